@@ -1,0 +1,317 @@
+"""Tensor-product multigrid preconditioned flexible CG (oracle).
+
+Paper: Section 3 (Algorithm 1, the TPMG V-cycle: pre-smoothing, residual,
+restriction, recursion from a zero guess, coarse-grid correction,
+post-smoothing), Section 4.1 (eq. BlockJacobi: vertical line relaxation with
+a tridiagonal solve per column by the Thomas algorithm), Section 5 (nu_pre =
+nu_post = 2, one smoother step on the coarsest grid, restriction of the
+cell-integral residual by summing the four children, linear interpolation
+for the prolongation, 4 - 7 levels).
+
+Readings (where the paper is silent or its implementation and theory differ):
+  * smoother: damped block-Jacobi with omega_J = 2/3 (the theory's weighted
+    block-Jacobi, Section 3.3.1) rather than sequential block-SOR, so the
+    sweep is order independent;
+  * Thomas algorithm tracked through the diagonal-dominance margin
+    s_k = p_k - m_k (p_k the pivot), so every addition is of positive terms;
+  * prolongation: least-squares linear reconstruction in the tangent plane
+    at the parent centre from the parent and its three neighbours, the same
+    gradient for all four children;
+  * coarsest grid: one damped sweep from a zero guess;
+  * outer solver: flexible CG with one-term orthogonalisation,
+    alpha = <r,z>/<p,q>, beta = -<z',q>/<p,q>, stopping when
+    ||r||_2 <= rtol ||f||_2 (the operator is SPD without advection,
+    Section 3.3.1);
+  * V-cycle rate: Richardson u <- u + M(f - A u) with f = 0, 12 cycles from
+    seeded U[-1,1], rate (||r_12|| / ||r_4||)^(1/8).
+
+Pins (tests/test_oracle_tpmg.py): Thomas vs dense LU; the smoother vs dense
+block inverses; conservation of the restriction; exactness of the
+prolongation on constants and O(h^2) on linear fields; the tensor-decoupling
+of the V-cycle spectrum (Section 3.3.1, eq. EigenvalueEquation); a V-cycle
+rate bounded in h and anisotropy; FCG == textbook CG (scipy) for M = I,
+one step for M = A^-1, == PCG (scipy) for a symmetric M; the solve ==
+scipy.sparse.linalg.spsolve.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import mesh as mesh_mod
+from . import operator as opmod
+
+
+# ---------------------------------------------------------------------------
+# column (Thomas) solve and the line smoother
+# ---------------------------------------------------------------------------
+
+
+def thomas_margin(l: np.ndarray, m: np.ndarray, e: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Solve A_T x = b for every column at once.
+
+    Row k of A_T: (e_k + l_k + m_k) x_k - l_k x_{k-1} - m_k x_{k+1} = b_k,
+    with l_0 = m_{nz-1} = 0 and e_k > 0 (arrays [n, nz]). Forward
+    elimination keeps the margin s_k = pivot_k - m_k:
+      s_0 = e_0,  s_k = e_k + l_k s_{k-1} / p_{k-1},  p_k = s_k + m_k,
+      d_k = (b_k + l_k d_{k-1}) / p_k;
+    back substitution x_{nz-1} = d_{nz-1}, x_k = d_k + (m_k / p_k) x_{k+1}.
+    """
+    n, nz = b.shape
+    p = np.empty_like(b)
+    d = np.empty_like(b)
+    s = e[:, 0]
+    p[:, 0] = s + m[:, 0]
+    d[:, 0] = b[:, 0] / p[:, 0]
+    for k in range(1, nz):
+        s = e[:, k] + l[:, k] * s / p[:, k - 1]
+        p[:, k] = s + m[:, k]
+        d[:, k] = (b[:, k] + l[:, k] * d[:, k - 1]) / p[:, k]
+    x = np.empty_like(b)
+    x[:, nz - 1] = d[:, nz - 1]
+    for k in range(nz - 2, -1, -1):
+        x[:, k] = d[:, k] + (m[:, k] / p[:, k]) * x[:, k + 1]
+    return x
+
+
+def smooth(op: opmod.LevelOperator, f: np.ndarray, u: np.ndarray, omega: float) -> np.ndarray:
+    """One damped block-Jacobi sweep u + omega A_T^-1 (f - A u)_T (eq. BlockJacobi)."""
+    l, m, e = opmod.column_bands(op)
+    r = f - opmod.apply(op, u)
+    return u + omega * thomas_margin(l, m, e, r)
+
+
+# ---------------------------------------------------------------------------
+# grid transfers
+# ---------------------------------------------------------------------------
+
+
+def restrict(r_fine: np.ndarray) -> np.ndarray:
+    """Sum of the four children 4P..4P+3 (cell integrals, Section 5)."""
+    n, nz = r_fine.shape
+    return r_fine.reshape(n // 4, 4, nz).sum(axis=1)
+
+
+def prolongation_weights(coarse: mesh_mod.Mesh, fine: mesh_mod.Mesh) -> np.ndarray:
+    """w[c, j] with e_c = e_P + sum_j w[c, j] (e_{N_j(P)} - e_P), P = c // 4.
+
+    Least-squares gradient G in the tangent plane at r_P from the offsets
+    d_j = Pi(r_{N_j} - r_P): G = argmin sum_j (d_j . G - (e_{N_j} - e_P))^2,
+    then e_c = e_P + G . delta_c with delta_c = Pi(r_c - r_P), Pi the
+    tangent-plane projection. Written in 2-D coordinates of the plane.
+    """
+    rp = coarse.centre                                        # [nc, 3]
+    nc = len(rp)
+
+    def proj(v):
+        return v - np.sum(v * rp, axis=-1, keepdims=True) * rp
+
+    # an orthonormal tangent basis (t1, t2) at each parent centre
+    helper = np.where(np.abs(rp[:, 2:3]) < 0.9, np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]]))
+    t1 = proj(helper)
+    t1 = t1 / np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(rp, t1)
+    D = np.zeros((nc, 3, 2))
+    for j in range(3):
+        d = proj(coarse.centre[coarse.nbr[:, j]] - rp)
+        D[:, j, 0] = np.sum(d * t1, axis=1)
+        D[:, j, 1] = np.sum(d * t2, axis=1)
+    normal = np.einsum("nji,njk->nik", D, D)                 # D^T D, [nc, 2, 2]
+    pinv = np.linalg.solve(normal, np.transpose(D, (0, 2, 1)))  # (D^T D)^-1 D^T, [nc, 2, 3]
+    w = np.zeros((fine.n, 3))
+    for i in range(4):
+        c = 4 * np.arange(nc) + i
+        delta = proj(fine.centre[c] - rp)
+        dl = np.stack([np.sum(delta * t1, axis=1), np.sum(delta * t2, axis=1)], axis=1)   # [nc, 2]
+        w[c] = np.einsum("ni,nij->nj", dl, pinv)
+    return w
+
+
+def prolong(e_coarse: np.ndarray, coarse_nbr: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Linear interpolation of a coarse correction to the fine grid."""
+    nf = w.shape[0]
+    parent = np.arange(nf) // 4
+    ep = e_coarse[parent]
+    out = ep.copy()
+    for j in range(3):
+        out = out + w[:, j:j + 1] * (e_coarse[coarse_nbr[parent, j]] - ep)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# hierarchy and V-cycle
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Hierarchy:
+    ops: list          # LevelOperator per level, 0 = coarsest
+    weights: list      # weights[l] prolongs level l-1 -> l (weights[0] unused)
+    meshes: list
+    vert: opmod.Vertical
+    nu_pre: int = 2
+    nu_post: int = 2
+    nu_coarse: int = 1
+    omega: float = 2.0 / 3.0
+    dtype: type = np.float64
+
+    @property
+    def finest(self) -> opmod.LevelOperator:
+        return self.ops[-1]
+
+    def astype(self, dtype) -> "Hierarchy":
+        return Hierarchy([o.astype(dtype) for o in self.ops], [None if w is None else w.astype(dtype) for w in self.weights],
+                         self.meshes, self.vert, self.nu_pre, self.nu_post, self.nu_coarse, self.omega, dtype)
+
+
+def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0,
+          meshes: list | None = None, vert: opmod.Vertical | None = None) -> Hierarchy:
+    """Meshes, coefficients and transfer weights for TPMG on refinement `refinement`.
+
+    profiles: object with alpha_r_v, alpha_s_v, beta_v and optional per-cell
+    finest-grid alpha_r_h, alpha_s_h, beta_h (None = 1). vert replaces the
+    radial factors derived from r_faces (used to pose the 2-D problems of the
+    tensor decoupling).
+    """
+    if n_levels <= 0:
+        n_levels = min(6, refinement + 1)
+    if n_levels > refinement + 1:
+        raise ValueError("more levels than refinements")
+    if meshes is None:
+        meshes = mesh_mod.hierarchy(refinement)
+    if vert is None:
+        vert = opmod.vertical(r_faces)
+    nz = vert.nz
+    if profiles is None:
+        ar_v, as_v, b_v = np.ones(nz + 1), np.ones(nz), np.ones(nz)
+        ar_h = as_h = b_h = None
+    else:
+        ar_v, as_v, b_v = profiles.alpha_r_v, profiles.alpha_s_v, profiles.beta_v
+        ar_h, as_h, b_h = profiles.alpha_r_h, profiles.alpha_s_h, profiles.beta_h
+    nf = meshes[refinement].n
+    h = [np.ones(nf) if x is None else np.asarray(x, dtype=np.float64) for x in (ar_h, as_h, b_h)]
+    levels = list(range(refinement - n_levels + 1, refinement + 1))
+    per_level = {refinement: h}
+    for ref in range(refinement, levels[0], -1):
+        fine_area = meshes[ref].area
+        per_level[ref - 1] = [opmod.restrict_cell_factor(x, fine_area) for x in per_level[ref]]
+    ops, weights, used = [], [None], []
+    for ref in levels:
+        ar, as_, b = per_level[ref]
+        ops.append(opmod.assemble(meshes[ref], vert, omega2, ar_v, as_v, b_v, ar, as_, b))
+        used.append(meshes[ref])
+    for i in range(1, len(levels)):
+        weights.append(prolongation_weights(used[i - 1], used[i]))
+    return Hierarchy(ops, weights, used, vert)
+
+
+def vcycle(h: Hierarchy, f: np.ndarray, level: int | None = None) -> np.ndarray:
+    """Algorithm 1 applied to f from a zero initial guess; returns u."""
+    if level is None:
+        level = len(h.ops) - 1
+    op = h.ops[level]
+    u = np.zeros_like(f)
+    if level == 0:
+        for _ in range(h.nu_coarse):
+            u = smooth(op, f, u, h.omega)
+        return u
+    for _ in range(h.nu_pre):
+        u = smooth(op, f, u, h.omega)
+    r = f - opmod.apply(op, u)
+    fc = restrict(r)
+    uc = vcycle(h, fc, level - 1)
+    u = u + prolong(uc, h.ops[level - 1].nbr, h.weights[level])
+    for _ in range(h.nu_post):
+        u = smooth(op, f, u, h.omega)
+    return u
+
+
+def make_preconditioner(h: Hierarchy, precision: str = "fp64"):
+    """One V-cycle as a preconditioner r -> z. "fp32": the whole V-cycle
+    (coefficients, smoother, Thomas, transfers) in float32; the input is
+    rounded to float32 and the output widened back to float64."""
+    if precision == "fp64":
+        return lambda r: vcycle(h, r)
+    h32 = h.astype(np.float32)
+    return lambda r: vcycle(h32, r.astype(np.float32)).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# flexible CG
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    status: str                        # "converged", "maxit", "breakdown"
+    history: list = field(default_factory=list)   # ||r_k|| / ||f|| after each iteration (index 0: initial)
+
+
+def fcg(apply_a, precond, f: np.ndarray, x0: np.ndarray | None = None, rtol: float = 1e-8,
+        maxit: int = 100) -> SolveResult:
+    """Flexible CG with one-term orthogonalisation (FCG(1)).
+
+    r0 = f - A x0, z0 = M r0, p0 = z0; per iteration: q = A p,
+    alpha = <r,z>/<p,q>, x += alpha p, r -= alpha q, stop if
+    ||r|| <= rtol ||f||, z' = M r, beta = -<z',q>/<p,q>, p = z' + beta p.
+    """
+    x = np.zeros_like(f) if x0 is None else x0.astype(np.float64).copy()
+    fnorm = math.sqrt(float(np.sum(f * f)))
+    r = f - apply_a(x)
+    rnorm = math.sqrt(float(np.sum(r * r)))
+    hist = [rnorm / fnorm if fnorm > 0 else 0.0]
+    if rnorm <= rtol * fnorm:
+        return SolveResult(x, 0, "converged", hist)
+    z = precond(r)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    for it in range(maxit):
+        q = apply_a(p)
+        pq = float(np.sum(p * q))
+        if not (pq > 0.0) or not math.isfinite(pq) or not math.isfinite(rz):
+            return SolveResult(x, it, "breakdown", hist)
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rnorm = math.sqrt(float(np.sum(r * r)))
+        hist.append(rnorm / fnorm)
+        if not math.isfinite(rnorm):
+            return SolveResult(x, it + 1, "breakdown", hist)
+        if rnorm <= rtol * fnorm:
+            return SolveResult(x, it + 1, "converged", hist)
+        z = precond(r)
+        zq = float(np.sum(z * q))
+        rz = float(np.sum(z * r))
+        beta = -zq / pq
+        p = z + beta * p
+    return SolveResult(x, maxit, "maxit", hist)
+
+
+def solve(h: Hierarchy, f: np.ndarray, x0=None, rtol=1e-8, maxit=100, precision="fp64") -> SolveResult:
+    """TPMG-preconditioned FCG on the finest level of h."""
+    op = h.finest
+    return fcg(lambda v: opmod.apply(op, v), make_preconditioner(h, precision), f, x0, rtol, maxit)
+
+
+def richardson_rate(h: Hierarchy, seed: int = 7, cycles: int = 12, skip: int = 4, precision="fp64") -> float:
+    """Asymptotic V-cycle factor of u <- u + M(f - A u) with f = 0."""
+    op = h.finest
+    m = make_preconditioner(h, precision)
+    u = np.random.default_rng(seed).uniform(-1.0, 1.0, size=(op.n, op.nz))
+    norms = []
+    for _ in range(cycles + 1):
+        r = -opmod.apply(op, u)
+        norms.append(math.sqrt(float(np.sum(r * r))))
+        u = u + m(r)
+    return (norms[cycles] / norms[skip]) ** (1.0 / (cycles - skip))
+
+
+def direct_solve(op: opmod.LevelOperator, f: np.ndarray) -> np.ndarray:
+    """u = A^-1 f with a sparse direct solver (the plain definition)."""
+    a = opmod.to_sparse(op).tocsc()
+    return spla.spsolve(a, f.ravel()).reshape(f.shape)
