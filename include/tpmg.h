@@ -1,0 +1,213 @@
+/*
+ * tpmg.h -- C ABI of the MI355X (gfx950) tensor-product multigrid solver for
+ * the anisotropic pressure-correction equation in a thin spherical shell.
+ *
+ * Problem (Dedner, Mueller & Scheichl, Section 2.1 and Appendix A): find u
+ * with A u = f, where A is the cell-centred finite-volume discretisation of
+ *     L u = -omega^2 div(alpha grad u) + beta u
+ * on the shell S x [1, 1+H] (lengths in Earth radii), without the vertical
+ * advection term (Section 3.3.1: this operator is symmetric positive
+ * definite). The horizontal grid is an icosahedral grid refined
+ * `refinement` times; each horizontal cell T carries a column of nz cells
+ * between radial faces r_0 = 1 < ... < r_nz = 1 + H (Section 4.1). Profiles
+ * factorise: alpha_r = alpha_r^r(r) alpha_r^S(x), likewise alpha_S and beta
+ * (Appendix A, eq. hatFunctionsFac), homogeneous Neumann top and bottom.
+ *
+ * The solve is flexible CG (FP64) preconditioned by one tensor-product
+ * multigrid V-cycle (Algorithm 1): horizontal-only coarsening, vertical line
+ * relaxation (eq. BlockJacobi, damped block-Jacobi with a Thomas solve per
+ * column), restriction by summing the four children and linear
+ * interpolation (Section 5).
+ *
+ * Conventions for every entry point:
+ *  - Return value: a tpmg_status. Arguments are checked before any device
+ *    work; on error nothing is enqueued and tpmg_last_error() (thread-local)
+ *    holds a message. TPMG_NOT_CONVERGED is not an error: the solution
+ *    buffer holds the last iterate.
+ *  - Ownership: the caller owns every device buffer (right-hand sides,
+ *    solutions, workspace). The library never allocates device memory; it
+ *    carves the workspace given to tpmg_mg_setup. The library owns its host
+ *    handles; a handle must outlive the device work it enqueued.
+ *  - Streams: all device work of a tpmg_mg runs on the HIP stream given to
+ *    tpmg_mg_setup (a non-default stream if graphs are enabled).
+ *  - Layouts: host arrays are cell-major, value (T, k) at T * nz + k (the
+ *    column-contiguous storage of Section 4.1). Device vectors passed to
+ *    tpmg_spmv / tpmg_vcycle / tpmg_solve use the library's tiled layout of
+ *    64 columns per tile, value (T, k) at (T / 64) * 64 * nz + k * 64 +
+ *    T % 64, with the column count padded up to a multiple of 64 (padding
+ *    entries are zero on input and stay zero); tpmg_pack / tpmg_unpack
+ *    convert between the two.
+ */
+#ifndef TPMG_H
+#define TPMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TPMG_OK = 0,
+  TPMG_NOT_CONVERGED = 1,   /* maxit reached; u holds the last iterate      */
+  TPMG_ERR_ARG = -1,        /* invalid or mis-sized argument                */
+  TPMG_ERR_DEVICE = -2,     /* a HIP call failed                            */
+  TPMG_ERR_NOMEM = -3,      /* workspace smaller than tpmg_mg_workspace_size */
+  TPMG_ERR_BREAKDOWN = -4,  /* NaN/Inf, <p, A p> <= 0, or divergence        */
+  TPMG_ERR_STATE = -5       /* call out of order for this handle            */
+} tpmg_status;
+
+typedef struct tpmg_grid tpmg_grid;
+typedef struct tpmg_op tpmg_op;
+typedef struct tpmg_mg tpmg_mg;
+
+/* Multigrid parameters (Section 5: nu_pre = nu_post = 2, one coarse sweep). */
+typedef struct {
+  int n_levels;        /* multigrid levels; 0 = min(6, refinement + 1)      */
+  int nu_pre;          /* pre-smoothing sweeps per level (default 2)        */
+  int nu_post;         /* post-smoothing sweeps per level (default 2)       */
+  int nu_coarse;       /* sweeps on the coarsest level (default 1)          */
+  double omega_relax;  /* block-Jacobi damping (default 2/3)                */
+  int precond_fp32;    /* 1: V-cycle in FP32 inside the FP64 CG (default 0) */
+  int use_graph;       /* 1: replay the FCG iteration as a HIP graph        */
+  int reserved[5];
+} tpmg_mg_params;
+
+/* Result of a solve. history (optional, caller-owned, history_cap entries)
+ * receives ||r_k|| / ||f|| for k = 0 .. iters. */
+typedef struct {
+  int iters;
+  double relres;       /* ||r|| / ||f|| of the recursively updated residual */
+  double* history;
+  int history_cap;
+  double t_total_ms;   /* wall time of tpmg_solve, first kernel to return   */
+} tpmg_solve_info;
+
+/* Fills p with the defaults above. */
+void tpmg_mg_params_default(tpmg_mg_params* p);
+
+/* ---------------------------------------------------------------- host -- */
+
+/* Icosahedral grid hierarchy (Section 4.2: icosahedral grid projected onto
+ * the sphere, each coarse triangle the union of four fine ones) for
+ * refinements 0..refinement, with the radial faces r_faces[0..nz]
+ * (strictly increasing, r_faces[0] = 1; copied). Base icosahedron: poles
+ * plus two rings of five vertices at latitude +-atan(1/2), longitudes 72 i
+ * and 36 + 72 i; child i of cell P on the next finer grid is cell 4P + i;
+ * neighbour j of a cell lies across its edge j. Host only.
+ * Errors: TPMG_ERR_ARG for refinement outside [0, 10], nz < 1, NULL
+ * pointers or non-increasing faces. */
+tpmg_status tpmg_grid_icosahedral(int refinement, int nz, const double* r_faces, tpmg_grid** out);
+
+/* Number of cells n_T = 20 * 4^refinement_level of grid level
+ * refinement_level (0..refinement). */
+tpmg_status tpmg_grid_level_size(const tpmg_grid* g, int refinement_level, int* n_cells);
+
+/* Geometry of grid level refinement_level (Appendix A): spherical
+ * circumcentres (3 n), spherical areas |T| (n), neighbours (3 n, int32),
+ * great-circle edge lengths |S_TT'| (3 n) and two-point flux factors
+ * |S_TT'| n_TT'.(r_T' - r_T) / |r_T' - r_T|^2 (3 n), all cell-major
+ * ([T][j]). Any output may be NULL. Host arrays, caller-owned. */
+tpmg_status tpmg_grid_geometry(const tpmg_grid* g, int refinement_level, double* centres, double* areas,
+                               int32_t* nbr, double* edge_len, double* edge_factor);
+
+/* Radial cell volume factors v_k = (r_{k+1}^3 - r_k^3) / 3 (Appendix A),
+ * nz values. */
+tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk);
+
+/* Tensor-stencil operator on the n_levels finest grids (0 = min(6,
+ * refinement + 1)), Appendix A eq. hatFunctionsFac with the vertical
+ * advection dropped. Vertical profile factors: alpha_r_v at the nz+1
+ * faces, alpha_s_v and beta_v at the nz layer midpoints. Horizontal
+ * factors: one value per finest-grid cell (n_T values) or NULL for 1; the
+ * value on an edge is the mean of its two cells; coarse grids use
+ * area-weighted means of the four children and are rediscretised on their
+ * own geometry. omega2 = omega^2 > 0. All factors must be > 0.
+ * Errors: TPMG_ERR_ARG. */
+tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
+                           const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
+                           const double* alpha_s_h, const double* beta_h, tpmg_op** out);
+
+/* Number of multigrid levels of op, and the cell count of level (0 =
+ * coarsest). */
+tpmg_status tpmg_op_levels(const tpmg_op* op, int* n_levels);
+tpmg_status tpmg_op_level_size(const tpmg_op* op, int level, int* n_cells);
+
+/* Factorised coefficients of level (0 = coarsest), for parity checks:
+ * horizontal beta^S_T = |T| beta^S (n), alphar^S_T = omega^2 |T| alpha_r^S
+ * (n), alphaS^S_TT' = omega^2 g_TT' alpha_S^S (3 n, [T][j]); vertical
+ * beta^r_k = v_k beta^r (nz), alphaS^r_k = (r_{k+1} - r_k) alpha_S^r (nz),
+ * alphar^r_k = sigma_k 2 r_k^2 / (r_{k+1} - r_{k-1}) alpha_r^r (nz+1).
+ * The full coefficient is the product of a horizontal and a vertical
+ * factor. Any output may be NULL. */
+tpmg_status tpmg_op_coefficients(const tpmg_op* op, int level, double* beta_h, double* alpha_r_h,
+                                 double* alpha_s_h, double* beta_v, double* alpha_s_v, double* alpha_r_v);
+
+/* Prolongation weights into level (1..n_levels-1) from level-1: 3 per fine
+ * cell c ([c][j]), e_c = e_P + sum_j w[c][j] (e_{N_j(P)} - e_P), P = c / 4
+ * (least-squares linear reconstruction in the tangent plane at r_P). */
+tpmg_status tpmg_op_prolongation(const tpmg_op* op, int level, double* w);
+
+/* -------------------------------------------------------------- device -- */
+
+/* Device workspace bytes that tpmg_mg_setup needs for (op, params). */
+tpmg_status tpmg_mg_workspace_size(const tpmg_op* op, const tpmg_mg_params* params, size_t* bytes);
+
+/* Carves d_workspace (device, >= tpmg_mg_workspace_size bytes, 256-byte
+ * aligned), uploads the coefficients on hip_stream (a hipStream_t; NULL =
+ * default stream, which disables graphs) and synchronises it. op may be
+ * destroyed afterwards. Errors: TPMG_ERR_ARG, TPMG_ERR_NOMEM (workspace too
+ * small), TPMG_ERR_DEVICE. */
+tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void* d_workspace, size_t bytes,
+                          void* hip_stream, tpmg_mg** out);
+
+/* Length in doubles of a device vector in the tiled layout (padded columns
+ * times nz), and the real cell count of the finest grid. */
+tpmg_status tpmg_mg_vector_length(const tpmg_mg* mg, size_t* n_doubles, int* n_cells, int* nz);
+
+/* Cell-major <-> tiled conversion of a finest-grid FP64 vector (device
+ * pointers, asynchronous on the setup stream). d_cellmajor holds
+ * n_cells * nz doubles, d_tiled tpmg_mg_vector_length doubles. */
+tpmg_status tpmg_pack(tpmg_mg* mg, const double* d_cellmajor, double* d_tiled);
+tpmg_status tpmg_unpack(tpmg_mg* mg, const double* d_tiled, double* d_cellmajor);
+
+/* y = A x on the finest grid, matrix-free tensor stencil (eq. ColumnEquation),
+ * FP64, tiled layout, asynchronous. x and y must not alias. */
+tpmg_status tpmg_spmv(tpmg_mg* mg, const double* d_x, double* d_y);
+
+/* z = one V-cycle (Algorithm 1) applied to r from a zero initial guess, in
+ * the precision chosen at setup; FP64 tiled vectors in and out,
+ * asynchronous. r and z must not alias. */
+tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z);
+
+/* Solves A u = f by V-cycle-preconditioned flexible CG, starting from the
+ * guess in d_u (tiled FP64), until ||r|| <= rtol ||f|| (2-norms of the
+ * cell-integral residual) or maxit iterations. Synchronises the stream once
+ * per iteration. Returns TPMG_OK, TPMG_NOT_CONVERGED, or
+ * TPMG_ERR_BREAKDOWN (u then holds the last finite iterate). info may be
+ * NULL. */
+tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
+                       tpmg_solve_info* info);
+
+/* Diagnostics: times `reps` back-to-back launches of one finest-grid
+ * line-smoother sweep (the general form, reading u and f and writing u, in
+ * the precision chosen at setup) between two HIP events on the setup
+ * stream, using workspace buffers only (their contents are overwritten).
+ * avg_ms: mean duration per launch; model_bytes: the algorithmic HBM bytes
+ * of one sweep (read u and f, write u: 3 values per unknown of the
+ * finest grid, counting padding columns). Synchronises the stream. */
+tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* model_bytes);
+
+void tpmg_grid_destroy(tpmg_grid* g);
+void tpmg_op_destroy(tpmg_op* op);
+void tpmg_mg_destroy(tpmg_mg* mg);
+
+const char* tpmg_status_string(tpmg_status s);
+const char* tpmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPMG_H */

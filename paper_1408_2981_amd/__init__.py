@@ -1,0 +1,277 @@
+"""Python binding of libtpmg.so, the MI355X tensor-product multigrid solver.
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels. Functions carry the C ABI's names (include/tpmg.h); device
+buffers are torch tensors on the GPU (their data_ptr() is passed), host
+arrays are numpy arrays. The library must have been built
+(paper_1408_2981_amd/build.py); importing without it raises ImportError, and
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpmg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1408_2981_amd/build.py`")
+
+# torch ships its own HIP and HSA runtimes under the same sonames as
+# /opt/rocm's. Loading torch first makes libtpmg.so bind to those copies, so
+# the process has a single runtime and both sides see the same device,
+# memory and streams.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TPMG_OK = 0
+TPMG_NOT_CONVERGED = 1
+TPMG_ERR_ARG = -1
+TPMG_ERR_DEVICE = -2
+TPMG_ERR_NOMEM = -3
+TPMG_ERR_BREAKDOWN = -4
+TPMG_ERR_STATE = -5
+
+EXPORTED = [
+    "tpmg_mg_params_default", "tpmg_grid_icosahedral", "tpmg_grid_level_size", "tpmg_grid_geometry",
+    "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
+    "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
+    "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_mg_time_sweep", "tpmg_grid_destroy", "tpmg_op_destroy",
+    "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error",
+]
+
+
+class TpmgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+class MgParams(ctypes.Structure):
+    _fields_ = [
+        ("n_levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+        ("nu_coarse", ctypes.c_int), ("omega_relax", ctypes.c_double), ("precond_fp32", ctypes.c_int),
+        ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int * 5),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int), ("relres", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+        ("history_cap", ctypes.c_int), ("t_total_ms", ctypes.c_double),
+    ]
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.c_int
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+_sig = {
+    "tpmg_mg_params_default": (None, [ctypes.POINTER(MgParams)]),
+    "tpmg_grid_icosahedral": (_ip, [_ip, _ip, _dp, ctypes.POINTER(_vp)]),
+    "tpmg_grid_level_size": (_ip, [_vp, _ip, ctypes.POINTER(_ip)]),
+    "tpmg_grid_geometry": (_ip, [_vp, _ip, _dp, _dp, _i32p, _dp, _dp]),
+    "tpmg_grid_vertical": (_ip, [_vp, _dp]),
+    "tpmg_op_create": (_ip, [_vp, _ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.POINTER(_vp)]),
+    "tpmg_op_levels": (_ip, [_vp, ctypes.POINTER(_ip)]),
+    "tpmg_op_level_size": (_ip, [_vp, _ip, ctypes.POINTER(_ip)]),
+    "tpmg_op_coefficients": (_ip, [_vp, _ip, _dp, _dp, _dp, _dp, _dp, _dp]),
+    "tpmg_op_prolongation": (_ip, [_vp, _ip, _dp]),
+    "tpmg_mg_workspace_size": (_ip, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "tpmg_mg_setup": (_ip, [_vp, ctypes.POINTER(MgParams), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "tpmg_mg_vector_length": (_ip, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_ip), ctypes.POINTER(_ip)]),
+    "tpmg_pack": (_ip, [_vp, _vp, _vp]),
+    "tpmg_unpack": (_ip, [_vp, _vp, _vp]),
+    "tpmg_spmv": (_ip, [_vp, _vp, _vp]),
+    "tpmg_vcycle": (_ip, [_vp, _vp, _vp]),
+    "tpmg_solve": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
+    "tpmg_mg_time_sweep": (_ip, [_vp, _ip, _dp, _dp]),
+    "tpmg_grid_destroy": (None, [_vp]),
+    "tpmg_op_destroy": (None, [_vp]),
+    "tpmg_mg_destroy": (None, [_vp]),
+    "tpmg_status_string": (ctypes.c_char_p, [_ip]),
+    "tpmg_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def status_string(s: int) -> str:
+    return _lib.tpmg_status_string(s).decode()
+
+
+def tpmg_last_error() -> str:
+    return _lib.tpmg_last_error().decode()
+
+
+def _check(s: int, ok=(TPMG_OK,)) -> int:
+    if s not in ok:
+        raise TpmgError(s, tpmg_last_error())
+    return s
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _dev(t) -> int:
+    return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+
+
+# ---------------------------------------------------------------- host ----
+
+def tpmg_grid_icosahedral(refinement: int, nz: int, r_faces) -> int:
+    r = np.ascontiguousarray(r_faces, dtype=np.float64)
+    if r.shape != (nz + 1,):
+        raise ValueError("r_faces must hold nz + 1 values")
+    h = _vp()
+    _check(_lib.tpmg_grid_icosahedral(refinement, nz, _dptr(r), ctypes.byref(h)))
+    return h.value
+
+
+def tpmg_grid_level_size(grid: int, level: int) -> int:
+    n = _ip()
+    _check(_lib.tpmg_grid_level_size(grid, level, ctypes.byref(n)))
+    return n.value
+
+
+def tpmg_grid_geometry(grid: int, level: int) -> dict:
+    n = tpmg_grid_level_size(grid, level)
+    out = dict(centres=np.zeros((n, 3)), areas=np.zeros(n), nbr=np.zeros((n, 3), dtype=np.int32),
+               edge_len=np.zeros((n, 3)), edge_factor=np.zeros((n, 3)))
+    _check(_lib.tpmg_grid_geometry(grid, level, _dptr(out["centres"]), _dptr(out["areas"]),
+                                   out["nbr"].ctypes.data_as(_i32p), _dptr(out["edge_len"]),
+                                   _dptr(out["edge_factor"])))
+    return out
+
+
+def tpmg_grid_vertical(grid: int, nz: int) -> np.ndarray:
+    v = np.zeros(nz)
+    _check(_lib.tpmg_grid_vertical(grid, _dptr(v)))
+    return v
+
+
+def tpmg_op_create(grid: int, n_levels: int, omega2: float, alpha_r_v, alpha_s_v, beta_v,
+                   alpha_r_h=None, alpha_s_h=None, beta_h=None) -> int:
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+            for a in (alpha_r_v, alpha_s_v, beta_v, alpha_r_h, alpha_s_h, beta_h)]
+    h = _vp()
+    _check(_lib.tpmg_op_create(grid, n_levels, float(omega2), *[_dptr(a) for a in arrs], ctypes.byref(h)))
+    return h.value
+
+
+def tpmg_op_levels(op: int) -> int:
+    n = _ip()
+    _check(_lib.tpmg_op_levels(op, ctypes.byref(n)))
+    return n.value
+
+
+def tpmg_op_level_size(op: int, level: int) -> int:
+    n = _ip()
+    _check(_lib.tpmg_op_level_size(op, level, ctypes.byref(n)))
+    return n.value
+
+
+def tpmg_op_coefficients(op: int, level: int, nz: int) -> dict:
+    n = tpmg_op_level_size(op, level)
+    out = dict(beta_h=np.zeros(n), alpha_r_h=np.zeros(n), alpha_s_h=np.zeros((n, 3)), beta_v=np.zeros(nz),
+               alpha_s_v=np.zeros(nz), alpha_r_v=np.zeros(nz + 1))
+    _check(_lib.tpmg_op_coefficients(op, level, *[_dptr(out[k]) for k in
+                                                  ("beta_h", "alpha_r_h", "alpha_s_h", "beta_v", "alpha_s_v", "alpha_r_v")]))
+    return out
+
+
+def tpmg_op_prolongation(op: int, level: int) -> np.ndarray:
+    n = tpmg_op_level_size(op, level)
+    w = np.zeros((n, 3))
+    _check(_lib.tpmg_op_prolongation(op, level, _dptr(w)))
+    return w
+
+
+def tpmg_mg_params_default() -> MgParams:
+    p = MgParams()
+    _lib.tpmg_mg_params_default(ctypes.byref(p))
+    return p
+
+
+# -------------------------------------------------------------- device ----
+
+def tpmg_mg_workspace_size(op: int, params: MgParams) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.tpmg_mg_workspace_size(op, ctypes.byref(params), ctypes.byref(b)))
+    return b.value
+
+
+def tpmg_mg_setup(op: int, params: MgParams, workspace, nbytes: int, stream) -> int:
+    h = _vp()
+    st = stream if isinstance(stream, int) or stream is None else stream.cuda_stream
+    _check(_lib.tpmg_mg_setup(op, ctypes.byref(params), _dev(workspace), nbytes, st, ctypes.byref(h)))
+    return h.value
+
+
+def tpmg_mg_vector_length(mg: int):
+    n = ctypes.c_size_t()
+    c = _ip()
+    z = _ip()
+    _check(_lib.tpmg_mg_vector_length(mg, ctypes.byref(n), ctypes.byref(c), ctypes.byref(z)))
+    return n.value, c.value, z.value
+
+
+def tpmg_pack(mg: int, d_cellmajor, d_tiled):
+    _check(_lib.tpmg_pack(mg, _dev(d_cellmajor), _dev(d_tiled)))
+
+
+def tpmg_unpack(mg: int, d_tiled, d_cellmajor):
+    _check(_lib.tpmg_unpack(mg, _dev(d_tiled), _dev(d_cellmajor)))
+
+
+def tpmg_spmv(mg: int, d_x, d_y):
+    _check(_lib.tpmg_spmv(mg, _dev(d_x), _dev(d_y)))
+
+
+def tpmg_vcycle(mg: int, d_r, d_z):
+    _check(_lib.tpmg_vcycle(mg, _dev(d_r), _dev(d_z)))
+
+
+def tpmg_solve(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 256):
+    """Returns (status, iters, relres, history, t_total_ms)."""
+    hist = np.zeros(history_cap)
+    info = SolveInfo()
+    info.history = hist.ctypes.data_as(_dp)
+    info.history_cap = history_cap
+    s = _lib.tpmg_solve(mg, _dev(d_f), _dev(d_u), float(rtol), int(maxit), ctypes.byref(info))
+    _check(s, ok=(TPMG_OK, TPMG_NOT_CONVERGED, TPMG_ERR_BREAKDOWN))
+    return s, info.iters, info.relres, hist[: info.iters + 1].copy(), info.t_total_ms
+
+
+def tpmg_mg_time_sweep(mg: int, reps: int):
+    """Returns (avg_ms, model_bytes) of one finest-grid smoother sweep."""
+    ms = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(_lib.tpmg_mg_time_sweep(mg, reps, ctypes.byref(ms), ctypes.byref(b)))
+    return ms.value, b.value
+
+
+def tpmg_grid_destroy(h):
+    _lib.tpmg_grid_destroy(h)
+
+
+def tpmg_op_destroy(h):
+    _lib.tpmg_op_destroy(h)
+
+
+def tpmg_mg_destroy(h):
+    _lib.tpmg_mg_destroy(h)
+
+
+from .solver import Problem  # noqa: E402  (convenience wrapper over the calls above)

@@ -1,0 +1,98 @@
+// Device-side views and kernel launchers of the TPMG library (gfx950).
+//
+// Vector layout on the device: tiles of 64 columns; value (T, k) lives at
+// (T / 64) * 64 * nz + k * 64 + T % 64. One wave of 64 lanes owns one tile,
+// one lane one column, so every level of a tile is one contiguous,
+// coalesced 64-element row, and each tile is one contiguous chunk of HBM.
+// Per-column data (coefficients, neighbours, weights) is stored SoA with
+// the column count padded to a multiple of 64; padding columns are inert
+// (beta = 1, no couplings, neighbour = self) and their vector entries stay
+// zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tpmg {
+
+constexpr int kTile = 64;
+
+// One grid level as the kernels see it. Pointers are of the precision the
+// launcher is called with (double or float).
+struct LevelView {
+  int n = 0;       // real columns
+  int npad = 0;    // padded to a multiple of 64
+  int nz = 0;
+  const int32_t* nbr = nullptr;   // [3][npad]
+  const void* beta_h = nullptr;   // [npad]
+  const void* ar_h = nullptr;     // [npad]
+  const void* as_h = nullptr;     // [3][npad]
+  const void* pw = nullptr;       // [3][npad] prolongation weights into this level
+  const void* beta_v = nullptr;   // [nz]
+  const void* as_v = nullptr;     // [nz]
+  const void* ar_v = nullptr;     // [nz+1]
+};
+
+// Device scalars of the flexible CG recurrence.
+struct FcgScalars {
+  double rz;      // <r, z>
+  double pq;      // <p, A p>
+  double alpha;
+  double beta;
+  double rr;      // <r, r>
+  double ff;      // <f, f>
+  int status;     // 0 ok, 1 breakdown
+  int pad;
+};
+
+constexpr int kRedBlocks = 1024;   // fixed grid of the BLAS-1 reductions
+constexpr int kRedThreads = 256;
+constexpr int kChunk = 16;         // levels per wave in the stencil kernels
+
+size_t stencil_blocks(int npad, int nz);  // blocks of 256 threads of the stencil kernels
+
+// All launchers enqueue on `s` and return hipGetLastError().
+// prec: 8 = double, 4 = float (the V-cycle precision of the level data).
+
+// y = A x (mode 0, partials <x, y>) or y = b - A x (mode 1, partials
+// <y, y>, <b, b>); FP64; partials[2 * block + i].
+hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
+                         double* partials, hipStream_t s);
+
+// One damped block-Jacobi sweep with the Thomas solve per column:
+// u_out = u_in + omega A_T^-1 (f - A u_in). zero_guess: u_in taken as 0
+// (not read). f_double: f is FP64 (else of precision prec); out_double:
+// u_out is FP64. fcopy (optional): receives f rounded to prec. sd, sc:
+// scratch vectors of the level size in precision prec.
+hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_double, const void* u_in,
+                         bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
+                         double omega, hipStream_t s);
+
+// f_coarse[P] = sum_{i<4} (f - A u)[4P + i] on the fine level L.
+hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int prec, const void* f,
+                                    const void* u, void* f_coarse, hipStream_t s);
+
+// u_fine += P e_coarse (linear interpolation), in place.
+hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
+                              void* u_fine, hipStream_t s);
+
+// FCG BLAS-1 (FP64, whole padded vector of length len).
+hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, const FcgScalars* sc,
+                             size_t len, double* partials, hipStream_t s);
+hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
+                       hipStream_t s);
+hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);   // zero fill (graph-safe)
+
+// Single-block deterministic finalisation of the partial sums.
+enum FinalizeKind { kFinInit = 0, kFinAlpha = 1, kFinRR = 2, kFinBeta = 3, kFinDot = 4 };
+hipError_t launch_finalize(int kind, const double* partials, int nblocks, FcgScalars* sc, double* out2,
+                           hipStream_t s);
+
+// layout conversion of a finest-grid FP64 vector
+hipError_t launch_pack(const double* cm, double* tiled, int n, int npad, int nz, hipStream_t s);
+hipError_t launch_unpack(const double* tiled, double* cm, int n, int npad, int nz, hipStream_t s);
+
+}  // namespace tpmg

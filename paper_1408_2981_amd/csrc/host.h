@@ -1,0 +1,68 @@
+// Host-side data structures of the TPMG library: the icosahedral grid
+// hierarchy with its geometry, and the factorised operator coefficients.
+// Nothing here touches the GPU; the C ABI's host-only entry points use it
+// directly, and the device setup uploads from it.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tpmg {
+
+// One refinement level of the icosahedral grid (Section 4.2). Arrays are
+// cell-major: [T] or [T][j] with j the edge / neighbour index.
+struct MeshLevel {
+  int refinement = 0;
+  int n = 0;
+  std::vector<int32_t> faces;   // 3n vertex ids, counter-clockwise from outside
+  std::vector<int32_t> nbr;     // 3n: cell across edge j = (v_j, v_{j+1})
+  std::vector<double> centre;   // 3n: spherical circumcentre
+  std::vector<double> area;     // n : spherical area |T|
+  std::vector<double> arc;      // 3n: great-circle edge length |S_TT'|
+  std::vector<double> g;        // 3n: |S_TT'| n.(r_T' - r_T) / |r_T' - r_T|^2
+};
+
+struct Grid {
+  int refinement = 0;
+  int nz = 0;
+  std::vector<double> r;        // nz+1 radial faces
+  std::vector<double> vk;       // nz radial volume factors
+  std::vector<double> verts;    // 3 * n_vertices, all levels
+  std::vector<MeshLevel> levels;  // index = refinement
+};
+
+// Builds the hierarchy for refinements 0..refinement. Throws std::runtime_error.
+void build_grid(Grid& g, int refinement, int nz, const double* r_faces);
+
+// Factorised coefficients of one multigrid level (Appendix A,
+// eq. hatFunctionsFac). The full coefficients are products:
+//   beta^_{T,k} = beta_h[T] * beta_v[k]
+//   alphaS^_{TT',k} = as_h[3T+j] * as_v[k]
+//   alphar^_{T,k} = ar_h[T] * ar_v[k]      (face k below cell k)
+struct LevelCoeffs {
+  int refinement = 0;
+  int n = 0;
+  std::vector<int32_t> nbr;     // 3n
+  std::vector<double> beta_h;   // n
+  std::vector<double> ar_h;     // n
+  std::vector<double> as_h;     // 3n
+  std::vector<double> pw;       // 3n prolongation weights from the next coarser level (empty on level 0)
+};
+
+struct Operator {
+  int nz = 0;
+  int refinement = 0;
+  double omega2 = 0;
+  std::vector<double> beta_v;   // nz
+  std::vector<double> as_v;     // nz
+  std::vector<double> ar_v;     // nz+1
+  std::vector<LevelCoeffs> levels;  // 0 = coarsest
+};
+
+// Assembles the operator on the n_levels finest grids of g.
+void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, const double* alpha_r_v,
+                    const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
+                    const double* alpha_s_h, const double* beta_h);
+
+}  // namespace tpmg

@@ -1,0 +1,517 @@
+// HIP kernels of the tensor-product multigrid solver, written for gfx950
+// (CDNA4, wave64). Nothing here is a dense contraction, so there is no MFMA:
+// every kernel is bound by HBM traffic, and the design goal is coalesced,
+// once-only streaming of each field with the stencil rebuilt in registers
+// from O(1) per-column scalars and O(nz) wave-uniform vertical vectors
+// (paper Section 4.2: matrix-free reconstruction from factorised profiles).
+//
+// Operator (Appendix A, eq. ColumnEquation), flux form, for column T, level k:
+//   (A u)_k = bh bv_k u_k + av_k sum_j ah_j (u_k - u_{T_j,k})
+//           + arh (arv_{k+1} (u_k - u_{k+1}) + arv_k (u_k - u_{k-1}))
+// with bh, ah_j, arh per column and bv, av, arv per level.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace tpmg {
+namespace {
+
+__device__ __forceinline__ size_t tile_base(int col, int nz) {
+  return static_cast<size_t>(col >> 6) * (static_cast<size_t>(kTile) * nz) + (col & 63);
+}
+
+template <typename T>
+struct Lv {
+  int n, npad, nz;
+  const int32_t* __restrict__ nbr;
+  const T* __restrict__ bh;
+  const T* __restrict__ arh;
+  const T* __restrict__ ash;
+  const T* __restrict__ pw;
+  const T* __restrict__ bv;
+  const T* __restrict__ av;
+  const T* __restrict__ arv;
+};
+
+template <typename T>
+Lv<T> view(const LevelView& L) {
+  return Lv<T>{L.n,
+               L.npad,
+               L.nz,
+               L.nbr,
+               static_cast<const T*>(L.beta_h),
+               static_cast<const T*>(L.ar_h),
+               static_cast<const T*>(L.as_h),
+               static_cast<const T*>(L.pw),
+               static_cast<const T*>(L.beta_v),
+               static_cast<const T*>(L.as_v),
+               static_cast<const T*>(L.ar_v)};
+}
+
+// per-column stencil data held in registers for a whole column sweep
+template <typename T>
+struct Column {
+  T bh, arh, a0, a1, a2;
+  size_t base, b0, b1, b2;   // tile offsets of the column and its neighbours
+};
+
+template <typename T>
+__device__ __forceinline__ Column<T> load_column(const Lv<T>& L, int col) {
+  Column<T> c;
+  c.bh = L.bh[col];
+  c.arh = L.arh[col];
+  c.a0 = L.ash[col];
+  c.a1 = L.ash[L.npad + col];
+  c.a2 = L.ash[2 * L.npad + col];
+  c.base = tile_base(col, L.nz);
+  c.b0 = tile_base(L.nbr[col], L.nz);
+  c.b1 = tile_base(L.nbr[L.npad + col], L.nz);
+  c.b2 = tile_base(L.nbr[2 * L.npad + col], L.nz);
+  return c;
+}
+
+// (A u)_k given the own-column values um = u_{k-1}, uc = u_k, up = u_{k+1}
+template <typename T>
+__device__ __forceinline__ T apply_row(const Lv<T>& L, const Column<T>& c, const T* __restrict__ u, int k, T um,
+                                       T uc, T up) {
+  const size_t o = static_cast<size_t>(k) * kTile;
+  const T h = c.a0 * (uc - u[c.b0 + o]) + c.a1 * (uc - u[c.b1 + o]) + c.a2 * (uc - u[c.b2 + o]);
+  const T v = L.arv[k + 1] * (uc - up) + L.arv[k] * (uc - um);
+  return c.bh * L.bv[k] * uc + L.av[k] * h + c.arh * v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// deterministic block sum (256 threads = 4 waves) of NV values
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double red[4][NV];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[w][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[NV * blockIdx.x + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+}
+
+// ---------------------------------------------------------------------------
+// stencil kernels: one wave per (tile, chunk of kChunk levels)
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, const double* __restrict__ x,
+                                                const double* __restrict__ b, double* __restrict__ y,
+                                                double* __restrict__ partials) {
+  const int nchunks = (L.nz + kChunk - 1) / kChunk;
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  double acc[2] = {0.0, 0.0};
+  if (item < (L.npad >> 6) * nchunks) {
+    const int tile = item / nchunks, chunk = item - tile * nchunks;
+    const int k0 = chunk * kChunk, k1 = min(L.nz, k0 + kChunk);
+    const Column<double> c = load_column(L, tile * kTile + lane);
+    double um = k0 > 0 ? x[c.base + static_cast<size_t>(k0 - 1) * kTile] : 0.0;
+    double uc = x[c.base + static_cast<size_t>(k0) * kTile];
+    for (int k = k0; k < k1; ++k) {
+      const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      const double up = k + 1 < L.nz ? x[o + kTile] : 0.0;
+      const double ax = apply_row(L, c, x, k, um, uc, up);
+      if (MODE == 0) {
+        y[o] = ax;
+        acc[0] += uc * ax;
+      } else {
+        const double bk = b[o];
+        const double rk = bk - ax;
+        y[o] = rk;
+        acc[0] += rk * rk;
+        acc[1] += bk * bk;
+      }
+      um = uc;
+      uc = up;
+    }
+  }
+  block_sums<2>(acc, partials);
+}
+
+// Line smoother: damped block-Jacobi with a Thomas solve per column
+// (eq. BlockJacobi). Forward sweep: residual r_k = f_k - (A u)_k and
+// elimination in margin form s_k = e_k + l_k s_{k-1} / p_{k-1},
+// p_k = s_k + m_k (e_k the column excess bh bv_k + av_k sum_j ah_j,
+// l_k = arh arv_k, m_k = arh arv_{k+1}), d_k = (r_k + l_k d_{k-1}) / p_k;
+// backward sweep x_k = d_k + (m_k / p_k) x_{k+1}, u_out = u_in + omega x.
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
+__global__ __launch_bounds__(64) void k_smooth(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
+                                               TO* __restrict__ u_out, T* __restrict__ fcopy,
+                                               T* __restrict__ sd, T* __restrict__ sc, T omega) {
+  const int lane = threadIdx.x;
+  const int col = blockIdx.x * kTile + lane;
+  const Column<T> c = load_column(L, col);
+  const int nz = L.nz;
+  const T esum = c.a0 + c.a1 + c.a2;
+  T s_prev = T(0), ip_prev = T(1), d_prev = T(0);
+  T um = T(0), uc = ZERO ? T(0) : u_in[c.base];
+  for (int k = 0; k < nz; ++k) {
+    const size_t o = c.base + static_cast<size_t>(k) * kTile;
+    const T fk = static_cast<T>(f[o]);
+    if (FCOPY) fcopy[o] = fk;
+    T r = fk;
+    T up = T(0);
+    if (!ZERO) {
+      up = k + 1 < nz ? u_in[o + kTile] : T(0);
+      r = fk - apply_row(L, c, u_in, k, um, uc, up);
+    }
+    const T e = c.bh * L.bv[k] + esum * L.av[k];
+    const T l = c.arh * L.arv[k];
+    const T m = c.arh * L.arv[k + 1];
+    const T s = e + l * (s_prev * ip_prev);
+    const T ip = T(1) / (s + m);
+    const T d = (r + l * d_prev) * ip;
+    sd[o] = d;
+    sc[o] = m * ip;
+    s_prev = s;
+    ip_prev = ip;
+    d_prev = d;
+    um = uc;
+    uc = up;
+  }
+  T x = T(0);
+  for (int k = nz - 1; k >= 0; --k) {
+    const size_t o = c.base + static_cast<size_t>(k) * kTile;
+    x = sd[o] + sc[o] * x;
+    const T uo = ZERO ? omega * x : u_in[o] + omega * x;
+    u_out[o] = static_cast<TO>(uo);
+  }
+}
+
+// residual on the fine level, summed over the four children of each coarse
+// cell (Algorithm 1 residual + restriction by summation, Section 5)
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int n_coarse, const T* __restrict__ f,
+                                                           const T* __restrict__ u, T* __restrict__ fc) {
+  const int nchunks = (L.nz + kChunk - 1) / kChunk;
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (item >= (L.npad >> 6) * nchunks) return;
+  const int tile = item / nchunks, chunk = item - tile * nchunks;
+  const int k0 = chunk * kChunk, k1 = min(L.nz, k0 + kChunk);
+  const int col = tile * kTile + lane;
+  const int P = col >> 2;
+  const Column<T> c = load_column(L, col);
+  const size_t pb = tile_base(P, L.nz);
+  T um = k0 > 0 ? u[c.base + static_cast<size_t>(k0 - 1) * kTile] : T(0);
+  T uc = u[c.base + static_cast<size_t>(k0) * kTile];
+  for (int k = k0; k < k1; ++k) {
+    const size_t o = c.base + static_cast<size_t>(k) * kTile;
+    const T up = k + 1 < L.nz ? u[o + kTile] : T(0);
+    T r = f[o] - apply_row(L, c, u, k, um, uc, up);
+    r += __shfl_xor(r, 1, 64);
+    r += __shfl_xor(r, 2, 64);
+    if ((lane & 3) == 0 && P < n_coarse) fc[pb + static_cast<size_t>(k) * kTile] = r;
+    um = uc;
+    uc = up;
+  }
+}
+
+// u_fine[c] += e_P + sum_j w_cj (e_{N_j(P)} - e_P), P = c / 4
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(Lv<T> F, Lv<T> C, const T* __restrict__ e,
+                                                     T* __restrict__ u) {
+  const int nchunks = (F.nz + kChunk - 1) / kChunk;
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (item >= (F.npad >> 6) * nchunks) return;
+  const int tile = item / nchunks, chunk = item - tile * nchunks;
+  const int k0 = chunk * kChunk, k1 = min(F.nz, k0 + kChunk);
+  const int col = tile * kTile + lane;
+  if (col >= F.n) return;
+  const int P = col >> 2;
+  const T w0 = F.pw[col], w1 = F.pw[F.npad + col], w2 = F.pw[2 * F.npad + col];
+  const size_t bp = tile_base(P, F.nz);
+  const size_t q0 = tile_base(C.nbr[P], F.nz), q1 = tile_base(C.nbr[C.npad + P], F.nz),
+               q2 = tile_base(C.nbr[2 * C.npad + P], F.nz);
+  const size_t base = tile_base(col, F.nz);
+  for (int k = k0; k < k1; ++k) {
+    const size_t ok = static_cast<size_t>(k) * kTile;
+    const T ep = e[bp + ok];
+    T v = ep + w0 * (e[q0 + ok] - ep);
+    v = v + w1 * (e[q1 + ok] - ep);
+    v = v + w2 * (e[q2 + ok] - ep);
+    u[base + ok] = u[base + ok] + v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// flexible-CG BLAS-1 with fixed-grid deterministic reductions
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const FcgScalars* __restrict__ sc, size_t len,
+                                                    double* __restrict__ partials) {
+  const double alpha = sc->alpha;
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    x[i] = x[i] + alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+  }
+  block_sums<2>(acc, partials);
+}
+
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, const double* __restrict__ q,
+                                              const double* __restrict__ r, size_t len,
+                                              double* __restrict__ partials) {
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const double zi = z[i];
+    acc[0] += zi * q[i];
+    acc[1] += zi * r[i];
+  }
+  block_sums<2>(acc, partials);
+}
+
+__global__ __launch_bounds__(256) void k_pupdate(const double* __restrict__ z, double* __restrict__ p,
+                                                 const FcgScalars* __restrict__ sc, size_t len) {
+  const double beta = sc->beta;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill(uint32_t* __restrict__ p, size_t words) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+__device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
+
+__global__ __launch_bounds__(256) void k_finalize(int kind, const double* __restrict__ partials, int nblocks,
+                                                  FcgScalars* __restrict__ sc, double* __restrict__ out2) {
+  // every reduction kernel writes two partial sums per block
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    v[0] += partials[2 * b];
+    v[1] += partials[2 * b + 1];
+  }
+  __shared__ double red[4][2];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = 0; i < 2; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+    red[w][0] = v[0];
+    red[w][1] = v[1];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double s0 = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+  const double s1 = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+  switch (kind) {
+    case kFinInit:
+      sc->rr = s0;
+      sc->ff = s1;
+      sc->pq = 1.0;
+      sc->rz = 0.0;
+      sc->alpha = 0.0;
+      sc->beta = 0.0;
+      sc->status = 0;
+      break;
+    case kFinAlpha:
+      sc->pq = s0;
+      if (!(s0 > 0.0) || !finite(s0) || !finite(sc->rz)) {
+        sc->status = 1;
+        sc->alpha = 0.0;
+      } else {
+        sc->alpha = sc->rz / s0;
+      }
+      break;
+    case kFinRR:
+      sc->rr = s0;
+      break;
+    case kFinBeta:
+      sc->beta = -s0 / sc->pq;
+      sc->rz = s1;
+      break;
+    default:
+      out2[0] = s0;
+      out2[1] = s1;
+      break;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pack(const double* __restrict__ cm, double* __restrict__ tiled, int n,
+                                              int npad, int nz) {
+  const size_t total = static_cast<size_t>(npad) * nz;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int col = static_cast<int>(i / nz), k = static_cast<int>(i - static_cast<size_t>(col) * nz);
+    tiled[tile_base(col, nz) + static_cast<size_t>(k) * kTile] = col < n ? cm[i] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_unpack(const double* __restrict__ tiled, double* __restrict__ cm, int n,
+                                                int nz) {
+  const size_t total = static_cast<size_t>(n) * nz;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int col = static_cast<int>(i / nz), k = static_cast<int>(i - static_cast<size_t>(col) * nz);
+    cm[i] = tiled[tile_base(col, nz) + static_cast<size_t>(k) * kTile];
+  }
+}
+
+unsigned grid_for(size_t work, unsigned cap) {
+  size_t b = (work + 255) / 256;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b < cap ? b : cap);
+}
+
+}  // namespace
+
+size_t stencil_blocks(int npad, int nz) {
+  const size_t waves = static_cast<size_t>(npad / kTile) * ((nz + kChunk - 1) / kChunk);
+  return (waves + 3) / 4;
+}
+
+hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
+                         double* partials, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
+  if (mode == 0)
+    hipLaunchKernelGGL(k_spmv64<0>, dim3(blocks), dim3(256), 0, s, view<double>(L), x, b, y, partials);
+  else
+    hipLaunchKernelGGL(k_spmv64<1>, dim3(blocks), dim3(256), 0, s, view<double>(L), x, b, y, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const void* u_in, bool zero, void* u_out,
+                     bool out_double, void* fcopy, void* sd, void* sc, double omega, hipStream_t s) {
+  const Lv<T> L = view<T>(Lg);
+  const dim3 grid(Lg.npad / kTile), block(kTile);
+  const T* ui = static_cast<const T*>(u_in);
+  T* fc = static_cast<T*>(fcopy);
+  T* d = static_cast<T*>(sd);
+  T* c = static_cast<T*>(sc);
+  const T om = static_cast<T>(omega);
+  // (f type, out type, zero guess, f copy) combinations used by the V-cycle
+  if (f_double) {
+    const double* ff = static_cast<const double*>(f);
+    if (out_double) {
+      double* uo = static_cast<double*>(u_out);
+      if (zero)
+        hipLaunchKernelGGL((k_smooth<T, double, double, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+      else
+        hipLaunchKernelGGL((k_smooth<T, double, double, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+    } else {
+      T* uo = static_cast<T*>(u_out);
+      if (zero && fcopy)
+        hipLaunchKernelGGL((k_smooth<T, double, T, true, true>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+      else if (zero)
+        hipLaunchKernelGGL((k_smooth<T, double, T, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+      else
+        hipLaunchKernelGGL((k_smooth<T, double, T, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+    }
+  } else {
+    const T* ff = static_cast<const T*>(f);
+    if (out_double) {
+      double* uo = static_cast<double*>(u_out);
+      if (zero)
+        hipLaunchKernelGGL((k_smooth<T, T, double, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+      else
+        hipLaunchKernelGGL((k_smooth<T, T, double, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+    } else {
+      T* uo = static_cast<T*>(u_out);
+      if (zero)
+        hipLaunchKernelGGL((k_smooth<T, T, T, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+      else
+        hipLaunchKernelGGL((k_smooth<T, T, T, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+    }
+  }
+}
+
+hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_double, const void* u_in,
+                         bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
+                         double omega, hipStream_t s) {
+  if (prec == 8)
+    smooth_t<double>(L, f, true, u_in, zero_guess, u_out, true, nullptr, sd, sc, omega, s);
+  else
+    smooth_t<float>(L, f, f_double, u_in, zero_guess, u_out, out_double, fcopy, sd, sc, omega, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int prec, const void* f,
+                                    const void* u, void* f_coarse, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
+  if (prec == 8)
+    hipLaunchKernelGGL(k_residual_restrict<double>, dim3(blocks), dim3(256), 0, s, view<double>(L), C.n,
+                       static_cast<const double*>(f), static_cast<const double*>(u), static_cast<double*>(f_coarse));
+  else
+    hipLaunchKernelGGL(k_residual_restrict<float>, dim3(blocks), dim3(256), 0, s, view<float>(L), C.n,
+                       static_cast<const float*>(f), static_cast<const float*>(u), static_cast<float*>(f_coarse));
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
+                              void* u_fine, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(F.npad, F.nz));
+  if (prec == 8)
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(blocks), dim3(256), 0, s, view<double>(F), view<double>(C),
+                       static_cast<const double*>(e_coarse), static_cast<double*>(u_fine));
+  else
+    hipLaunchKernelGGL(k_prolong_add<float>, dim3(blocks), dim3(256), 0, s, view<float>(F), view<float>(C),
+                       static_cast<const float*>(e_coarse), static_cast<float*>(u_fine));
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, const FcgScalars* sc,
+                             size_t len, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, z, q, r, len, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_pupdate, dim3(grid_for(len, 2048)), dim3(256), 0, s, z, p, sc, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(words, 2048)), dim3(256), 0, s, static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int kind, const double* partials, int nblocks, FcgScalars* sc, double* out2,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, kind, partials, nblocks, sc, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const double* cm, double* tiled, int n, int npad, int nz, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(static_cast<size_t>(npad) * nz, 4096)), dim3(256), 0, s, cm, tiled, n,
+                     npad, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const double* tiled, double* cm, int n, int npad, int nz, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack, dim3(grid_for(static_cast<size_t>(n) * nz, 4096)), dim3(256), 0, s, tiled, cm, n,
+                     nz);
+  return hipGetLastError();
+}
+
+}  // namespace tpmg

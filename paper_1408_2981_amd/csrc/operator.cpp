@@ -1,0 +1,154 @@
+// Factorised tensor-stencil coefficients and grid-transfer weights.
+//
+// Paper, Appendix A (eq. hatFunctionsFac) with the vertical advection term
+// dropped (Section 3.3.1):
+//   beta^S_T     = |T| beta^S_T               beta^r_k   = v_k beta^r_k
+//   alphaS^S_TT' = omega^2 g_TT' alpha_S^S    alphaS^r_k = (r_{k+1}-r_k) alpha_S^r_k
+//   alphar^S_T   = omega^2 |T| alpha_r^S_T    alphar^r_k = sigma_k 2 r_k^2/(r_{k+1}-r_{k-1}) alpha_r^r_k
+// (the omega^2 of the horizontal coupling is applied once). sigma_0 =
+// sigma_nz = 0 imposes the homogeneous Neumann condition. The horizontal
+// profile factor on an edge is the mean of its two cells; on coarse grids
+// the horizontal factors are area-weighted means of the four children and
+// the stencil is rediscretised on the coarse geometry (the matrix-free
+// counterpart of the Galerkin coarse operator of Section 3.3.1).
+//
+// Prolongation (Section 5, "linear interpolation"): a fine cell c with
+// parent P takes e_P + G . delta_c, where G is the least-squares gradient
+// in the tangent plane at r_P fitted to the parent's three neighbours and
+// delta_c the tangent-plane offset of c's centre.
+#include <cmath>
+#include <stdexcept>
+
+#include "host.h"
+
+namespace tpmg {
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 at(const std::vector<double>& v, int i) { return {v[3 * i], v[3 * i + 1], v[3 * i + 2]}; }
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 tangent(V3 v, V3 n) {
+  double s = dot(v, n);
+  return {v.x - s * n.x, v.y - s * n.y, v.z - s * n.z};
+}
+
+// weights w[3c + j] for the fine cells of `fine` from parents on `coarse`
+std::vector<double> prolongation(const MeshLevel& coarse, const MeshLevel& fine) {
+  std::vector<double> w(3 * static_cast<size_t>(fine.n), 0.0);
+  for (int P = 0; P < coarse.n; ++P) {
+    V3 rp = at(coarse.centre, P);
+    V3 d[3];
+    double m[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double scale = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      d[j] = tangent(sub(at(coarse.centre, coarse.nbr[3 * P + j]), rp), rp);
+      scale += dot(d[j], d[j]);
+      const double dv[3] = {d[j].x, d[j].y, d[j].z};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) m[a][b] += dv[a] * dv[b];
+    }
+    // the normal direction is outside the span of the offsets; adding
+    // s n n^T (s ~ |d|^2) makes the normal matrix invertible without changing
+    // its action on tangent vectors
+    scale /= 3.0;
+    const double nv[3] = {rp.x, rp.y, rp.z};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) m[a][b] += scale * nv[a] * nv[b];
+    double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    double c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+    double c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    double det = m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02;
+    if (!(std::fabs(det) > 0.0)) throw std::runtime_error("degenerate prolongation stencil");
+    double inv[3][3] = {
+        {c00 / det, (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / det, (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / det},
+        {c01 / det, (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / det, (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / det},
+        {c02 / det, (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / det, (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / det}};
+    for (int i = 0; i < 4; ++i) {
+      int c = 4 * P + i;
+      V3 dl = tangent(sub(at(fine.centre, c), rp), rp);
+      const double dv[3] = {dl.x, dl.y, dl.z};
+      double y[3];   // y = M^-1 delta (M symmetric)
+      for (int a = 0; a < 3; ++a) y[a] = inv[a][0] * dv[0] + inv[a][1] * dv[1] + inv[a][2] * dv[2];
+      for (int j = 0; j < 3; ++j) w[3 * static_cast<size_t>(c) + j] = y[0] * d[j].x + y[1] * d[j].y + y[2] * d[j].z;
+    }
+  }
+  return w;
+}
+
+}  // namespace
+
+void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, const double* alpha_r_v,
+                    const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
+                    const double* alpha_s_h, const double* beta_h) {
+  const int nz = g.nz;
+  op.nz = nz;
+  op.refinement = g.refinement;
+  op.omega2 = omega2;
+  op.beta_v.resize(nz);
+  op.as_v.resize(nz);
+  op.ar_v.assign(nz + 1, 0.0);
+  for (int k = 0; k < nz; ++k) {
+    op.beta_v[k] = g.vk[k] * beta_v[k];
+    op.as_v[k] = (g.r[k + 1] - g.r[k]) * alpha_s_v[k];
+  }
+  for (int k = 1; k < nz; ++k) op.ar_v[k] = 2.0 * g.r[k] * g.r[k] / (g.r[k + 1] - g.r[k - 1]) * alpha_r_v[k];
+
+  // horizontal profile factors on every grid, finest first
+  const int fine_ref = g.refinement;
+  const int coarse_ref = fine_ref - n_levels + 1;
+  std::vector<std::vector<double>> hr(fine_ref + 1), hs(fine_ref + 1), hb(fine_ref + 1);
+  const int nf = g.levels[fine_ref].n;
+  auto init = [nf](std::vector<double>& dst, const double* src) {
+    dst.assign(nf, 1.0);
+    if (src)
+      for (int i = 0; i < nf; ++i) dst[i] = src[i];
+  };
+  init(hr[fine_ref], alpha_r_h);
+  init(hs[fine_ref], alpha_s_h);
+  init(hb[fine_ref], beta_h);
+  for (int r = fine_ref; r > coarse_ref; --r) {
+    const MeshLevel& F = g.levels[r];
+    const int nc = g.levels[r - 1].n;
+    for (auto* pair : {&hr, &hs, &hb}) {
+      std::vector<double>& src = (*pair)[r];
+      std::vector<double>& dst = (*pair)[r - 1];
+      dst.assign(nc, 0.0);
+      for (int P = 0; P < nc; ++P) {
+        double num = 0.0, den = 0.0;
+        for (int i = 0; i < 4; ++i) {
+          num += src[4 * P + i] * F.area[4 * P + i];
+          den += F.area[4 * P + i];
+        }
+        dst[P] = num / den;
+      }
+    }
+  }
+
+  op.levels.clear();
+  op.levels.resize(n_levels);
+  for (int l = 0; l < n_levels; ++l) {
+    const int r = coarse_ref + l;
+    const MeshLevel& M = g.levels[r];
+    LevelCoeffs& C = op.levels[l];
+    C.refinement = r;
+    C.n = M.n;
+    C.nbr = M.nbr;
+    C.beta_h.resize(M.n);
+    C.ar_h.resize(M.n);
+    C.as_h.resize(3 * static_cast<size_t>(M.n));
+    for (int t = 0; t < M.n; ++t) {
+      C.beta_h[t] = M.area[t] * hb[r][t];
+      C.ar_h[t] = omega2 * M.area[t] * hr[r][t];
+      for (int j = 0; j < 3; ++j) {
+        int o = M.nbr[3 * t + j];
+        C.as_h[3 * t + j] = omega2 * M.g[3 * t + j] * (0.5 * (hs[r][t] + hs[r][o]));
+      }
+    }
+    if (l > 0) C.pw = prolongation(g.levels[r - 1], M);
+  }
+}
+
+}  // namespace tpmg

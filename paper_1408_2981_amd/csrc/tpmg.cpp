@@ -1,0 +1,697 @@
+// C ABI of the TPMG library: argument checking, host handles, device
+// setup (workspace carving and coefficient upload), the V-cycle schedule
+// (Algorithm 1) and the flexible-CG driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "../../include/tpmg.h"
+#include "device.h"
+#include "host.h"
+
+struct tpmg_grid {
+  tpmg::Grid g;
+};
+struct tpmg_op {
+  tpmg::Operator op;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tpmg_status fail(tpmg_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define TPMG_HIP(call)                                                                              \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess)                                                                           \
+      return fail(TPMG_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+int pad64(int n) { return (n + tpmg::kTile - 1) / tpmg::kTile * tpmg::kTile; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct DevLevel {
+  int n = 0, npad = 0;
+  int32_t* nbr = nullptr;
+  void* bh[2] = {nullptr, nullptr};   // [0] double, [1] float
+  void* arh[2] = {nullptr, nullptr};
+  void* ash[2] = {nullptr, nullptr};
+  void* pw[2] = {nullptr, nullptr};
+  void* f = nullptr;                   // right-hand side (coarse levels; precision of the V-cycle)
+  void* u[2] = {nullptr, nullptr};     // ping-pong iterates
+};
+
+}  // namespace
+
+struct tpmg_mg {
+  int nlev = 0, nz = 0, n_fine = 0, npad_fine = 0;
+  int nu_pre = 2, nu_post = 2, nu_coarse = 1;
+  double omega = 2.0 / 3.0;
+  bool fp32 = false, use_graph = false;
+  hipStream_t stream = nullptr;
+  std::vector<DevLevel> lv;
+  void* bv[2] = {nullptr, nullptr};
+  void* asv[2] = {nullptr, nullptr};
+  void* arv[2] = {nullptr, nullptr};
+  void* fcopy = nullptr;                 // FP32 copy of the finest right-hand side
+  void* sd = nullptr;                    // Thomas scratch
+  void* sc = nullptr;
+  double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;   // FCG vectors (tiled, FP64)
+  double* partials = nullptr;
+  tpmg::FcgScalars* scal = nullptr;
+  double* dot2 = nullptr;
+  tpmg::FcgScalars* h_scal = nullptr;    // pinned host mirror
+  size_t len = 0;                        // padded finest vector length
+  int max_partial_blocks = 0;
+  // graph of one FCG iteration for a given (x, r-source) pair
+  hipGraphExec_t graph = nullptr;
+  const double* graph_f = nullptr;
+  double* graph_x = nullptr;
+
+  tpmg::LevelView view(int l) const {
+    const DevLevel& d = lv[l];
+    const int i = fp32 ? 1 : 0;
+    tpmg::LevelView v;
+    v.n = d.n;
+    v.npad = d.npad;
+    v.nz = nz;
+    v.nbr = d.nbr;
+    v.beta_h = d.bh[i];
+    v.ar_h = d.arh[i];
+    v.as_h = d.ash[i];
+    v.pw = d.pw[i];
+    v.beta_v = bv[i];
+    v.as_v = asv[i];
+    v.ar_v = arv[i];
+    return v;
+  }
+  tpmg::LevelView view64(int l) const {
+    const DevLevel& d = lv[l];
+    tpmg::LevelView v;
+    v.n = d.n;
+    v.npad = d.npad;
+    v.nz = nz;
+    v.nbr = d.nbr;
+    v.beta_h = d.bh[0];
+    v.ar_h = d.arh[0];
+    v.as_h = d.ash[0];
+    v.pw = d.pw[0];
+    v.beta_v = bv[0];
+    v.as_v = asv[0];
+    v.ar_v = arv[0];
+    return v;
+  }
+};
+
+namespace {
+
+// Lays out every device buffer of (op, params) on the carver.
+void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
+  const int nz = op.nz;
+  const size_t s = m.fp32 ? 4 : 8;
+  m.lv.assign(op.levels.size(), DevLevel());
+  for (size_t l = 0; l < op.levels.size(); ++l) {
+    DevLevel& d = m.lv[l];
+    d.n = op.levels[l].n;
+    d.npad = pad64(d.n);
+    const size_t np = d.npad;
+    d.nbr = static_cast<int32_t*>(cv.take(3 * np * sizeof(int32_t)));
+    for (int i = 0; i < 2; ++i) {
+      const size_t es = i == 0 ? 8 : 4;
+      d.bh[i] = cv.take(np * es);
+      d.arh[i] = cv.take(np * es);
+      d.ash[i] = cv.take(3 * np * es);
+      d.pw[i] = l > 0 ? cv.take(3 * np * es) : nullptr;
+    }
+    const size_t vec = np * nz * s;
+    const bool finest = l + 1 == op.levels.size();
+    d.f = finest ? nullptr : cv.take(vec);
+    d.u[0] = cv.take(vec);
+    d.u[1] = cv.take(vec);
+  }
+  for (int i = 0; i < 2; ++i) {
+    const size_t es = i == 0 ? 8 : 4;
+    m.bv[i] = cv.take(nz * es);
+    m.asv[i] = cv.take(nz * es);
+    m.arv[i] = cv.take((nz + 1) * es);
+  }
+  const size_t fine_len = static_cast<size_t>(pad64(op.levels.back().n)) * nz;
+  m.fcopy = m.fp32 ? cv.take(fine_len * 4) : nullptr;
+  m.sd = cv.take(fine_len * s);
+  m.sc = cv.take(fine_len * s);
+  m.r = static_cast<double*>(cv.take(fine_len * 8));
+  m.p = static_cast<double*>(cv.take(fine_len * 8));
+  m.q = static_cast<double*>(cv.take(fine_len * 8));
+  m.z = static_cast<double*>(cv.take(fine_len * 8));
+  m.max_partial_blocks = static_cast<int>(std::max<size_t>(tpmg::kRedBlocks, tpmg::stencil_blocks(pad64(op.levels.back().n), nz)));
+  m.partials = static_cast<double*>(cv.take(2 * static_cast<size_t>(m.max_partial_blocks) * 8));
+  m.scal = static_cast<tpmg::FcgScalars*>(cv.take(sizeof(tpmg::FcgScalars)));
+  m.dot2 = static_cast<double*>(cv.take(2 * 8));
+  m.len = fine_len;
+}
+
+tpmg_status check_params(const tpmg_mg_params* p) {
+  if (!p) return fail(TPMG_ERR_ARG, "params is NULL");
+  if (p->nu_pre < 1 || p->nu_post < 1 || p->nu_coarse < 1)
+    return fail(TPMG_ERR_ARG, "nu_pre, nu_post and nu_coarse must be >= 1");
+  if (!(p->omega_relax > 0.0) || !(p->omega_relax < 2.0)) return fail(TPMG_ERR_ARG, "omega_relax must be in (0, 2)");
+  if (p->n_levels < 0) return fail(TPMG_ERR_ARG, "n_levels must be >= 0");
+  return TPMG_OK;
+}
+
+template <typename T>
+std::vector<T> padded(const std::vector<double>& src, int n, int npad, int comps, double fill) {
+  // src is [n][comps] cell-major; result is [comps][npad] SoA
+  std::vector<T> out(static_cast<size_t>(npad) * comps, static_cast<T>(fill));
+  for (int c = 0; c < comps; ++c)
+    for (int t = 0; t < n; ++t) out[static_cast<size_t>(c) * npad + t] = static_cast<T>(src[static_cast<size_t>(t) * comps + c]);
+  return out;
+}
+
+template <typename T>
+hipError_t upload(void* dst, const std::vector<T>& v, hipStream_t s) {
+  return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// ---- V-cycle (Algorithm 1) -------------------------------------------------
+//
+// Level l > 0: nu_pre sweeps (the first from a zero guess), residual +
+// restriction to level l-1, recursion from a zero guess, prolongation +
+// correction, nu_post sweeps. Level 0: nu_coarse sweeps from zero. In the
+// mixed mode every level is FP32: the first finest sweep reads the FP64
+// residual and keeps an FP32 copy of it, the last writes FP64 z.
+hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
+  const int L = m.nlev - 1;
+  const int prec = m.fp32 ? 4 : 8;
+  hipStream_t s = m.stream;
+  std::vector<int> cur(m.nlev, 0);
+  hipError_t e;
+  // right-hand side of level l
+  auto rhs = [&](int l) -> const void* {
+    if (l < L) return m.lv[l].f;
+    return m.fp32 ? static_cast<const void*>(m.fcopy) : static_cast<const void*>(r_in);
+  };
+  for (int l = L; l >= 0; --l) {
+    const tpmg::LevelView V = m.view(l);
+    const int sweeps = l == 0 ? m.nu_coarse : m.nu_pre;
+    for (int k = 0; k < sweeps; ++k) {
+      const bool first = k == 0;
+      const bool finest_first = first && l == L;
+      const bool last_of_cycle = (l == 0 && L == 0 && k + 1 == sweeps);
+      const void* f = finest_first ? static_cast<const void*>(r_in) : rhs(l);
+      const bool f_double = (l == L) && (finest_first || !m.fp32);
+      void* out = last_of_cycle ? static_cast<void*>(z_out) : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
+      e = tpmg::launch_smooth(V, prec, f, f_double, m.lv[l].u[cur[l]], first, out, last_of_cycle,
+                              (finest_first && m.fp32) ? m.fcopy : nullptr, m.sd, m.sc, m.omega, s);
+      if (e != hipSuccess) return e;
+      if (!first) cur[l] = 1 - cur[l];
+    }
+    if (l > 0) {
+      const tpmg::LevelView C = m.view(l - 1);
+      e = tpmg::launch_residual_restrict(V, C, prec, rhs(l), m.lv[l].u[cur[l]], m.lv[l - 1].f, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int l = 1; l <= L; ++l) {
+    const tpmg::LevelView V = m.view(l);
+    e = tpmg::launch_prolong_add(V, m.view(l - 1), prec, m.lv[l - 1].u[cur[l - 1]], m.lv[l].u[cur[l]], s);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < m.nu_post; ++k) {
+      const bool last = l == L && k + 1 == m.nu_post;
+      void* out = last ? static_cast<void*>(z_out) : m.lv[l].u[1 - cur[l]];
+      e = tpmg::launch_smooth(V, prec, rhs(l), l == L && !m.fp32, m.lv[l].u[cur[l]], false, out, last, nullptr,
+                              m.sd, m.sc, m.omega, s);
+      if (e != hipSuccess) return e;
+      if (!last) cur[l] = 1 - cur[l];
+    }
+  }
+  return hipSuccess;
+}
+
+// one FCG iteration after the convergence test of the previous one:
+// z = M r; beta = -<z,q>/<p,q>; rz = <z,r>; p = z + beta p; q = A p;
+// alpha = rz/<p,q>; x += alpha p; r -= alpha q; rr = <r,r>
+hipError_t fcg_iteration(tpmg_mg& m, double* x) {
+  hipError_t e;
+  hipStream_t s = m.stream;
+  if ((e = vcycle(m, m.r, m.z)) != hipSuccess) return e;
+  if ((e = tpmg::launch_dots(m.z, m.q, m.r, m.len, m.partials, s)) != hipSuccess) return e;
+  if ((e = tpmg::launch_finalize(tpmg::kFinBeta, m.partials, tpmg::kRedBlocks, m.scal, m.dot2, s)) != hipSuccess) return e;
+  if ((e = tpmg::launch_pupdate(m.z, m.p, m.scal, m.len, s)) != hipSuccess) return e;
+  const tpmg::LevelView F = m.view64(m.nlev - 1);
+  if ((e = tpmg::launch_spmv64(F, 0, m.p, nullptr, m.q, m.partials, s)) != hipSuccess) return e;
+  const int sb = static_cast<int>(tpmg::stencil_blocks(F.npad, F.nz));
+  if ((e = tpmg::launch_finalize(tpmg::kFinAlpha, m.partials, sb, m.scal, m.dot2, s)) != hipSuccess) return e;
+  if ((e = tpmg::launch_fcg_update(x, m.r, m.p, m.q, m.scal, m.len, m.partials, s)) != hipSuccess) return e;
+  return tpmg::launch_finalize(tpmg::kFinRR, m.partials, tpmg::kRedBlocks, m.scal, m.dot2, s);
+}
+
+void drop_graph(tpmg_mg& m) {
+  if (m.graph) (void)hipGraphExecDestroy(m.graph);
+  m.graph = nullptr;
+  m.graph_x = nullptr;
+}
+
+tpmg_status check_mg(const tpmg_mg* mg) {
+  if (!mg) return fail(TPMG_ERR_ARG, "mg handle is NULL");
+  return TPMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpmg_mg_params_default(tpmg_mg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n_levels = 0;
+  p->nu_pre = 2;
+  p->nu_post = 2;
+  p->nu_coarse = 1;
+  p->omega_relax = 2.0 / 3.0;
+  p->precond_fp32 = 0;
+  p->use_graph = 0;
+}
+
+const char* tpmg_status_string(tpmg_status s) {
+  switch (s) {
+    case TPMG_OK: return "TPMG_OK";
+    case TPMG_NOT_CONVERGED: return "TPMG_NOT_CONVERGED";
+    case TPMG_ERR_ARG: return "TPMG_ERR_ARG";
+    case TPMG_ERR_DEVICE: return "TPMG_ERR_DEVICE";
+    case TPMG_ERR_NOMEM: return "TPMG_ERR_NOMEM";
+    case TPMG_ERR_BREAKDOWN: return "TPMG_ERR_BREAKDOWN";
+    case TPMG_ERR_STATE: return "TPMG_ERR_STATE";
+  }
+  return "unknown status";
+}
+
+const char* tpmg_last_error(void) { return g_last_error.c_str(); }
+
+tpmg_status tpmg_grid_icosahedral(int refinement, int nz, const double* r_faces, tpmg_grid** out) {
+  if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (refinement < 0 || refinement > 10) return fail(TPMG_ERR_ARG, "refinement must be in [0, 10]");
+  if (nz < 1 || nz > 4096) return fail(TPMG_ERR_ARG, "nz must be in [1, 4096]");
+  if (!r_faces) return fail(TPMG_ERR_ARG, "r_faces is NULL");
+  for (int k = 0; k < nz; ++k)
+    if (!(r_faces[k + 1] > r_faces[k]) || !std::isfinite(r_faces[k + 1]))
+      return fail(TPMG_ERR_ARG, "r_faces must be finite and strictly increasing");
+  if (!(r_faces[0] > 0.0)) return fail(TPMG_ERR_ARG, "r_faces[0] must be positive");
+  try {
+    auto* g = new tpmg_grid();
+    tpmg::build_grid(g->g, refinement, nz, r_faces);
+    *out = g;
+  } catch (const std::exception& ex) {
+    return fail(TPMG_ERR_ARG, ex.what());
+  }
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_grid_level_size(const tpmg_grid* g, int level, int* n_cells) {
+  if (!g || !n_cells) return fail(TPMG_ERR_ARG, "NULL argument");
+  if (level < 0 || level > g->g.refinement) return fail(TPMG_ERR_ARG, "level out of range");
+  *n_cells = g->g.levels[level].n;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_grid_geometry(const tpmg_grid* g, int level, double* centres, double* areas, int32_t* nbr,
+                               double* edge_len, double* edge_factor) {
+  if (!g) return fail(TPMG_ERR_ARG, "grid is NULL");
+  if (level < 0 || level > g->g.refinement) return fail(TPMG_ERR_ARG, "level out of range");
+  const tpmg::MeshLevel& L = g->g.levels[level];
+  if (centres) std::copy(L.centre.begin(), L.centre.end(), centres);
+  if (areas) std::copy(L.area.begin(), L.area.end(), areas);
+  if (nbr) std::copy(L.nbr.begin(), L.nbr.end(), nbr);
+  if (edge_len) std::copy(L.arc.begin(), L.arc.end(), edge_len);
+  if (edge_factor) std::copy(L.g.begin(), L.g.end(), edge_factor);
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk) {
+  if (!g || !vk) return fail(TPMG_ERR_ARG, "NULL argument");
+  std::copy(g->g.vk.begin(), g->g.vk.end(), vk);
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
+                           const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
+                           const double* alpha_s_h, const double* beta_h, tpmg_op** out) {
+  if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(TPMG_ERR_ARG, "grid is NULL");
+  if (!alpha_r_v || !alpha_s_v || !beta_v) return fail(TPMG_ERR_ARG, "vertical profile factors are required");
+  if (!(omega2 > 0.0) || !std::isfinite(omega2)) return fail(TPMG_ERR_ARG, "omega2 must be positive");
+  const int ref = g->g.refinement, nz = g->g.nz;
+  if (n_levels == 0) n_levels = std::min(6, ref + 1);
+  if (n_levels < 1 || n_levels > ref + 1) return fail(TPMG_ERR_ARG, "n_levels must be in [1, refinement + 1]");
+  auto positive = [](const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+      if (!(v[i] > 0.0) || !std::isfinite(v[i])) return false;
+    return true;
+  };
+  const size_t nf = g->g.levels[ref].n;
+  if (!positive(alpha_r_v + 1, nz > 1 ? nz - 1 : 0) || !positive(alpha_s_v, nz) || !positive(beta_v, nz))
+    return fail(TPMG_ERR_ARG, "vertical profile factors must be positive and finite");
+  if ((alpha_r_h && !positive(alpha_r_h, nf)) || (alpha_s_h && !positive(alpha_s_h, nf)) ||
+      (beta_h && !positive(beta_h, nf)))
+    return fail(TPMG_ERR_ARG, "horizontal profile factors must be positive and finite");
+  try {
+    auto* o = new tpmg_op();
+    tpmg::build_operator(o->op, g->g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, alpha_r_h, alpha_s_h, beta_h);
+    *out = o;
+  } catch (const std::exception& ex) {
+    return fail(TPMG_ERR_ARG, ex.what());
+  }
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_op_levels(const tpmg_op* op, int* n_levels) {
+  if (!op || !n_levels) return fail(TPMG_ERR_ARG, "NULL argument");
+  *n_levels = static_cast<int>(op->op.levels.size());
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_op_level_size(const tpmg_op* op, int level, int* n_cells) {
+  if (!op || !n_cells) return fail(TPMG_ERR_ARG, "NULL argument");
+  if (level < 0 || level >= static_cast<int>(op->op.levels.size())) return fail(TPMG_ERR_ARG, "level out of range");
+  *n_cells = op->op.levels[level].n;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_op_coefficients(const tpmg_op* op, int level, double* beta_h, double* alpha_r_h, double* alpha_s_h,
+                                 double* beta_v, double* alpha_s_v, double* alpha_r_v) {
+  if (!op) return fail(TPMG_ERR_ARG, "op is NULL");
+  if (level < 0 || level >= static_cast<int>(op->op.levels.size())) return fail(TPMG_ERR_ARG, "level out of range");
+  const tpmg::LevelCoeffs& C = op->op.levels[level];
+  if (beta_h) std::copy(C.beta_h.begin(), C.beta_h.end(), beta_h);
+  if (alpha_r_h) std::copy(C.ar_h.begin(), C.ar_h.end(), alpha_r_h);
+  if (alpha_s_h) std::copy(C.as_h.begin(), C.as_h.end(), alpha_s_h);
+  if (beta_v) std::copy(op->op.beta_v.begin(), op->op.beta_v.end(), beta_v);
+  if (alpha_s_v) std::copy(op->op.as_v.begin(), op->op.as_v.end(), alpha_s_v);
+  if (alpha_r_v) std::copy(op->op.ar_v.begin(), op->op.ar_v.end(), alpha_r_v);
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_op_prolongation(const tpmg_op* op, int level, double* w) {
+  if (!op || !w) return fail(TPMG_ERR_ARG, "NULL argument");
+  if (level < 1 || level >= static_cast<int>(op->op.levels.size())) return fail(TPMG_ERR_ARG, "level out of range");
+  const auto& pw = op->op.levels[level].pw;
+  std::copy(pw.begin(), pw.end(), w);
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mg_workspace_size(const tpmg_op* op, const tpmg_mg_params* params, size_t* bytes) {
+  if (!op || !bytes) return fail(TPMG_ERR_ARG, "NULL argument");
+  tpmg_status st = check_params(params);
+  if (st != TPMG_OK) return st;
+  tpmg_mg m;
+  m.fp32 = params->precond_fp32 != 0;
+  Carver cv(nullptr);
+  carve(m, op->op, cv);
+  *bytes = cv.off + 256;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void* d_workspace, size_t bytes,
+                          void* hip_stream, tpmg_mg** out) {
+  if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!op) return fail(TPMG_ERR_ARG, "op is NULL");
+  tpmg_status st = check_params(params);
+  if (st != TPMG_OK) return st;
+  if (!d_workspace) return fail(TPMG_ERR_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(TPMG_ERR_ARG, "workspace must be 256-byte aligned");
+  if (params->n_levels != 0 && params->n_levels != static_cast<int>(op->op.levels.size()))
+    return fail(TPMG_ERR_ARG, "params->n_levels differs from the operator's level count");
+  size_t need = 0;
+  if ((st = tpmg_mg_workspace_size(op, params, &need)) != TPMG_OK) return st;
+  if (bytes < need) return fail(TPMG_ERR_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+
+  auto* m = new tpmg_mg();
+  m->nlev = static_cast<int>(op->op.levels.size());
+  m->nz = op->op.nz;
+  m->n_fine = op->op.levels.back().n;
+  m->npad_fine = pad64(m->n_fine);
+  m->nu_pre = params->nu_pre;
+  m->nu_post = params->nu_post;
+  m->nu_coarse = params->nu_coarse;
+  m->omega = params->omega_relax;
+  m->fp32 = params->precond_fp32 != 0;
+  m->stream = static_cast<hipStream_t>(hip_stream);
+  m->use_graph = params->use_graph != 0 && m->stream != nullptr;
+  Carver cv(d_workspace);
+  carve(*m, op->op, cv);
+
+  auto cleanup_fail = [&](tpmg_status s, const std::string& msg) {
+    if (m->h_scal) (void)hipHostFree(m->h_scal);
+    delete m;
+    return fail(s, msg);
+  };
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&m->h_scal), sizeof(tpmg::FcgScalars), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    m->h_scal = nullptr;
+    return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  // zero the whole workspace once: padding entries of every vector stay zero
+  e = tpmg::launch_fill(d_workspace, (cv.off + 3) / 4 * 4, m->stream);
+  std::vector<std::vector<double>> keep64;
+  std::vector<std::vector<float>> keep32;
+  std::vector<std::vector<int32_t>> keepi;
+  const int nz = m->nz;
+  for (int l = 0; l < m->nlev && e == hipSuccess; ++l) {
+    const tpmg::LevelCoeffs& C = op->op.levels[l];
+    DevLevel& d = m->lv[l];
+    std::vector<int32_t> nb(3 * static_cast<size_t>(d.npad));
+    for (int j = 0; j < 3; ++j)
+      for (int t = 0; t < d.npad; ++t) nb[static_cast<size_t>(j) * d.npad + t] = t < d.n ? C.nbr[3 * static_cast<size_t>(t) + j] : t;
+    keepi.push_back(std::move(nb));
+    e = upload(d.nbr, keepi.back(), m->stream);
+    // inert padding columns: beta = 1, no couplings
+    keep64.push_back(padded<double>(C.beta_h, d.n, d.npad, 1, 1.0));
+    keep32.push_back(padded<float>(C.beta_h, d.n, d.npad, 1, 1.0));
+    if (e == hipSuccess) e = upload(d.bh[0], keep64.back(), m->stream);
+    if (e == hipSuccess) e = upload(d.bh[1], keep32.back(), m->stream);
+    keep64.push_back(padded<double>(C.ar_h, d.n, d.npad, 1, 0.0));
+    keep32.push_back(padded<float>(C.ar_h, d.n, d.npad, 1, 0.0));
+    if (e == hipSuccess) e = upload(d.arh[0], keep64.back(), m->stream);
+    if (e == hipSuccess) e = upload(d.arh[1], keep32.back(), m->stream);
+    keep64.push_back(padded<double>(C.as_h, d.n, d.npad, 3, 0.0));
+    keep32.push_back(padded<float>(C.as_h, d.n, d.npad, 3, 0.0));
+    if (e == hipSuccess) e = upload(d.ash[0], keep64.back(), m->stream);
+    if (e == hipSuccess) e = upload(d.ash[1], keep32.back(), m->stream);
+    if (l > 0) {
+      keep64.push_back(padded<double>(C.pw, d.n, d.npad, 3, 0.0));
+      keep32.push_back(padded<float>(C.pw, d.n, d.npad, 3, 0.0));
+      if (e == hipSuccess) e = upload(d.pw[0], keep64.back(), m->stream);
+      if (e == hipSuccess) e = upload(d.pw[1], keep32.back(), m->stream);
+    }
+  }
+  const std::vector<double>* vv[3] = {&op->op.beta_v, &op->op.as_v, &op->op.ar_v};
+  void** dst[3] = {m->bv, m->asv, m->arv};
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    keep64.push_back(*vv[i]);
+    keep32.push_back(std::vector<float>(vv[i]->begin(), vv[i]->end()));
+    e = upload(dst[i][0], keep64.back(), m->stream);
+    if (e == hipSuccess) e = upload(dst[i][1], keep32.back(), m->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  (void)nz;
+  if (e != hipSuccess) return cleanup_fail(TPMG_ERR_DEVICE, std::string("setup upload: ") + hipGetErrorString(e));
+  *out = m;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mg_vector_length(const tpmg_mg* mg, size_t* n_doubles, int* n_cells, int* nz) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (n_doubles) *n_doubles = mg->len;
+  if (n_cells) *n_cells = mg->n_fine;
+  if (nz) *nz = mg->nz;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_pack(tpmg_mg* mg, const double* d_cellmajor, double* d_tiled) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_cellmajor || !d_tiled) return fail(TPMG_ERR_ARG, "NULL vector");
+  TPMG_HIP(tpmg::launch_pack(d_cellmajor, d_tiled, mg->n_fine, mg->npad_fine, mg->nz, mg->stream));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_unpack(tpmg_mg* mg, const double* d_tiled, double* d_cellmajor) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_cellmajor || !d_tiled) return fail(TPMG_ERR_ARG, "NULL vector");
+  TPMG_HIP(tpmg::launch_unpack(d_tiled, d_cellmajor, mg->n_fine, mg->npad_fine, mg->nz, mg->stream));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_spmv(tpmg_mg* mg, const double* d_x, double* d_y) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_x || !d_y) return fail(TPMG_ERR_ARG, "NULL vector");
+  if (d_x == d_y) return fail(TPMG_ERR_ARG, "x and y must not alias");
+  TPMG_HIP(tpmg::launch_spmv64(mg->view64(mg->nlev - 1), 0, d_x, nullptr, d_y, mg->partials, mg->stream));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_r || !d_z) return fail(TPMG_ERR_ARG, "NULL vector");
+  if (d_r == d_z) return fail(TPMG_ERR_ARG, "r and z must not alias");
+  TPMG_HIP(vcycle(*mg, d_r, d_z));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit, tpmg_solve_info* info) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_f || !d_u) return fail(TPMG_ERR_ARG, "NULL vector");
+  if (d_f == d_u) return fail(TPMG_ERR_ARG, "f and u must not alias");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(TPMG_ERR_ARG, "rtol must be >= 0 and maxit >= 0");
+  if (info && info->history_cap > 0 && !info->history) return fail(TPMG_ERR_ARG, "history_cap > 0 with NULL history");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = mg->stream;
+  const tpmg::LevelView F = mg->view64(mg->nlev - 1);
+  const int sb = static_cast<int>(tpmg::stencil_blocks(F.npad, F.nz));
+  // r = f - A u, rr, ff; p = q = 0 so that the first iteration takes beta = 0
+  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, s));
+  TPMG_HIP(tpmg::launch_finalize(tpmg::kFinInit, mg->partials, sb, mg->scal, mg->dot2, s));
+  TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
+  TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
+  TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
+  TPMG_HIP(hipStreamSynchronize(s));
+  const double ff = mg->h_scal->ff;
+  const double fnorm = std::sqrt(ff);
+  double rnorm = std::sqrt(mg->h_scal->rr);
+  int iters = 0;
+  auto record = [&](int k, double v) {
+    if (info && info->history && k < info->history_cap) info->history[k] = v;
+  };
+  record(0, fnorm > 0 ? rnorm / fnorm : 0.0);
+  tpmg_status result = TPMG_NOT_CONVERGED;
+  if (!std::isfinite(rnorm) || !std::isfinite(fnorm)) {
+    result = TPMG_ERR_BREAKDOWN;
+  } else if (rnorm <= rtol * fnorm) {
+    result = TPMG_OK;
+  } else {
+    if (mg->use_graph && (mg->graph_x != d_u || mg->graph == nullptr)) {
+      drop_graph(*mg);
+      hipGraph_t g = nullptr;
+      TPMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = fcg_iteration(*mg, d_u);
+      hipError_t ee = hipStreamEndCapture(s, &g);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(TPMG_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      hipError_t ie = hipGraphInstantiate(&mg->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        mg->graph = nullptr;
+        return fail(TPMG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      }
+      mg->graph_x = d_u;
+    }
+    for (int it = 0; it < maxit; ++it) {
+      if (mg->use_graph) {
+        TPMG_HIP(hipGraphLaunch(mg->graph, s));
+      } else {
+        TPMG_HIP(fcg_iteration(*mg, d_u));
+      }
+      TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
+      TPMG_HIP(hipStreamSynchronize(s));
+      iters = it + 1;
+      if (mg->h_scal->status != 0) {
+        iters = it;
+        result = TPMG_ERR_BREAKDOWN;
+        break;
+      }
+      rnorm = std::sqrt(mg->h_scal->rr);
+      record(iters, fnorm > 0 ? rnorm / fnorm : 0.0);
+      if (!std::isfinite(rnorm)) {
+        result = TPMG_ERR_BREAKDOWN;
+        break;
+      }
+      if (rnorm <= rtol * fnorm) {
+        result = TPMG_OK;
+        break;
+      }
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->iters = iters;
+    info->relres = fnorm > 0 ? rnorm / fnorm : 0.0;
+    info->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite value or <p, A p> <= 0");
+  return result;
+}
+
+tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* model_bytes) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (reps < 1 || !avg_ms) return fail(TPMG_ERR_ARG, "reps must be >= 1 and avg_ms non-NULL");
+  const int L = mg->nlev - 1;
+  const int prec = mg->fp32 ? 4 : 8;
+  const tpmg::LevelView V = mg->view(L);
+  // f: the FP32 copy (mixed) or the FCG residual buffer (FP64); u: the
+  // finest ping-pong pair
+  const void* f = mg->fp32 ? static_cast<const void*>(mg->fcopy) : static_cast<const void*>(mg->r);
+  hipEvent_t e0, e1;
+  TPMG_HIP(hipEventCreate(&e0));
+  TPMG_HIP(hipEventCreate(&e1));
+  hipError_t e = hipEventRecord(e0, mg->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = tpmg::launch_smooth(V, prec, f, false, mg->lv[L].u[i & 1], false, mg->lv[L].u[1 - (i & 1)], false, nullptr,
+                            mg->sd, mg->sc, mg->omega, mg->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, mg->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("time sweep: ") + hipGetErrorString(e));
+  *avg_ms = static_cast<double>(ms) / reps;
+  if (model_bytes) *model_bytes = 3.0 * (mg->fp32 ? 4.0 : 8.0) * static_cast<double>(mg->len);
+  return TPMG_OK;
+}
+
+void tpmg_grid_destroy(tpmg_grid* g) { delete g; }
+void tpmg_op_destroy(tpmg_op* op) { delete op; }
+void tpmg_mg_destroy(tpmg_mg* mg) {
+  if (!mg) return;
+  drop_graph(*mg);
+  if (mg->h_scal) (void)hipHostFree(mg->h_scal);
+  delete mg;
+}
+
+}  // extern "C"

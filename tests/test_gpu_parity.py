@@ -1,0 +1,149 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI):
+layout conversion, the matrix-free SpMV (eq. ColumnEquation), one V-cycle
+(Algorithm 1) in FP64 and FP32, and the full flexible-CG solve. FP64 bar:
+relative error <= 1e-10 and identical iteration counts; mixed bar: <= 1e-6
+against the oracle's FP64 solution."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import synth  # noqa: E402
+from oracle import operator as opm, tpmg as otpmg  # noqa: E402
+from gpu_common import CASES, make, rel  # noqa: E402
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_pack_unpack_roundtrip(case):
+    h, P, f = make(case)
+    t = P.pack(f)
+    back = P.unpack(t)
+    assert np.array_equal(back, f)
+    tiled = t.cpu().numpy()
+    assert np.count_nonzero(tiled) <= f.size
+    assert tiled.size == P.len and P.len % 64 == 0
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_spmv(case):
+    h, P, f = make(case)
+    x = np.random.default_rng(7).standard_normal(f.shape)
+    xd = P.pack(x)
+    yd = P.device_vector()
+    P.spmv(xd, yd)
+    P.synchronize()
+    y = P.unpack(yd)
+    ref = opm.apply(h.finest, x)
+    assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # padding entries stay zero
+    assert np.count_nonzero(yd.cpu().numpy()) <= y.size
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_vcycle_fp64(case):
+    h, P, f = make(case)
+    zd = P.device_vector()
+    P.vcycle(P.pack(f), zd)
+    P.synchronize()
+    z = P.unpack(zd)
+    ref = otpmg.vcycle(h, f)
+    print(f"{case}: FP64 V-cycle rel diff {rel(z, ref):.2e}")
+    assert rel(z, ref) <= 1e-10, rel(z, ref)
+
+
+def _anorm(op, v):
+    return float(np.sqrt(np.sum(v * opm.apply(op, v))))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_vcycle_fp32(case):
+    """The FP32 V-cycle is a different rounding of the same operator, and the
+    problem's conditioning amplifies FP32 rounding differently in different
+    norms. Bar: the GPU FP32 V-cycle is as close to the exact FP64 V-cycle as
+    the oracle's own FP32 V-cycle is (within 10x, plus 1e-7), in the l2 norm
+    and in the energy norm of A."""
+    h, P, f = make(case, precond_fp32=True)
+    zd = P.device_vector()
+    P.vcycle(P.pack(f), zd)
+    P.synchronize()
+    z = P.unpack(zd)
+    z64 = otpmg.vcycle(h, f)
+    z32 = otpmg.make_preconditioner(h, "fp32")(f)
+    op = h.finest
+    for name, norm in (("l2", np.linalg.norm), ("A", lambda v: _anorm(op, v))):
+        e_gpu = norm(z - z64) / norm(z64)
+        e_orc = norm(z32 - z64) / norm(z64)
+        print(f"{case}: FP32 V-cycle {name}-error vs FP64 V-cycle: GPU {e_gpu:.2e}, oracle FP32 {e_orc:.2e}")
+        assert e_gpu <= 10 * e_orc + 1e-7
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("graph", [False, True])
+def test_solve_fp64(case, graph):
+    h, P, f = make(case, use_graph=graph)
+    ref = otpmg.solve(h, f, rtol=1e-8)
+    ud = P.device_vector()
+    st, iters, relres, hist, _ = P.solve(P.pack(f), ud, rtol=1e-8, maxit=100)
+    u = P.unpack(ud)
+    print(f"{case} graph={graph}: iters {iters} (oracle {ref.iters}), rel err {rel(u, ref.x):.2e}")
+    assert st == 0 and ref.status == "converged"
+    assert iters == ref.iters
+    assert rel(u, ref.x) <= 1e-10
+    assert np.allclose(hist, ref.history, rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_solve_mixed(case):
+    """Mixed path (FP32 V-cycle in FP64 FCG). At rtol 1e-8 the error against
+    the exact solution is limited by the conditioning, for the FP64 path too
+    (the 20,480-unknown case: 7e-6), so the 1e-6 bar is applied at rtol 1e-11;
+    at 1e-8 the GPU's error must be within 10x of the oracle's mixed solve."""
+    h, P, f = make(case, precond_fp32=True, use_graph=True)
+    tight = otpmg.solve(h, f, rtol=1e-13, maxit=400)
+    ref32 = otpmg.solve(h, f, rtol=1e-8, precision="fp32")
+    fd = P.pack(f)
+    ud = P.device_vector()
+    st, iters, relres, hist, _ = P.solve(fd, ud, rtol=1e-8, maxit=100)
+    u = P.unpack(ud)
+    e_gpu, e_orc = rel(u, tight.x), rel(ref32.x, tight.x)
+    print(f"{case}: mixed rtol 1e-8: iters {iters} (oracle mixed {ref32.iters}); error vs exact: GPU {e_gpu:.2e}, "
+          f"oracle mixed {e_orc:.2e}")
+    assert st == 0 and relres <= 1e-8
+    assert abs(iters - ref32.iters) <= 1
+    assert e_gpu <= max(1e-6, 10 * e_orc)
+    ud2 = P.device_vector()
+    st, iters2, relres2, _, _ = P.solve(fd, ud2, rtol=1e-11, maxit=200)
+    e_tight = rel(P.unpack(ud2), tight.x)
+    print(f"{case}: mixed rtol 1e-11: iters {iters2}, error vs exact {e_tight:.2e}")
+    assert st == 0 and e_tight <= 1e-6
+
+
+def test_graph_replays_match_eager():
+    h, P, f = make("ico3_nz13_quad", use_graph=True)
+    _, Pe, _ = make("ico3_nz13_quad", use_graph=False)
+    fd, fe = P.pack(f), Pe.pack(f)
+    outs = []
+    for _ in range(3):
+        ud = P.device_vector()
+        P.solve(fd, ud, rtol=1e-8, maxit=100)
+        outs.append(P.unpack(ud))
+        torch.cuda.synchronize()
+        _ = (fd * 2).sum().item()          # unrelated eager work between replays
+    ue = Pe.device_vector()
+    Pe.solve(fe, ue, rtol=1e-8, maxit=100)
+    eager = Pe.unpack(ue)
+    for o in outs:
+        assert np.array_equal(o, eager)
+
+
+def test_deterministic_fp64():
+    h, P, f = make("ico4_nz32_quad")
+    fd = P.pack(f)
+    a, b = P.device_vector(), P.device_vector()
+    P.solve(fd, a, rtol=1e-8, maxit=100)
+    P.solve(fd, b, rtol=1e-8, maxit=100)
+    assert torch.equal(a, b)
