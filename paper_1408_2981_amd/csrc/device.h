@@ -70,6 +70,10 @@ hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_dou
                          bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
                          double omega, hipStream_t s);
 
+// Largest dynamic LDS a workgroup may use (set once from the device
+// properties); decides between the LDS-staged smoother and the fallback.
+hipError_t set_max_lds(size_t bytes);
+
 // f_coarse[P] = sum_{i<4} (f - A u)[4P + i] on the fine level L.
 hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int prec, const void* f,
                                     const void* u, void* f_coarse, hipStream_t s);

@@ -11,6 +11,8 @@
 // with bh, ah_j, arh per column and bv, av, arv per level.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 
 namespace tpmg {
@@ -189,6 +191,305 @@ __global__ __launch_bounds__(64) void k_smooth(Lv<T> L, const TF* __restrict__ f
     x = sd[o] + sc[o] * x;
     const T uo = ZERO ? omega * x : u_in[o] + omega * x;
     u_out[o] = static_cast<TO>(uo);
+  }
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; renumber them so that each
+// XCD walks one contiguous range of tiles and neighbour gathers across tile
+// edges hit in that XCD's own L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
+__device__ __forceinline__ float fast_rcp(float p) { return __builtin_amdgcn_rcpf(p); }
+__device__ __forceinline__ double fast_rcp(double p) {
+  // hardware estimate refined by two Newton steps (a few ulp at most)
+  double r = __builtin_amdgcn_rcp(p);
+  double e = __builtin_fma(-p, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-p, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Line smoother, LDS-staged form: one workgroup per tile of 64 columns.
+//  1. every wave computes the residual r = f - A u_in for its own range of
+//     levels (all loads independent, many in flight) into LDS;
+//  2. wave 0 runs the margin-form Thomas recurrence of each column out of
+//     LDS (forward: d_k and m_k / p_k; backward: x_k), in place, reading
+//     LDS and the vertical coefficients kBatch levels ahead of the chain;
+//  3. every wave writes u_out = u_in + omega x for its levels.
+// LDS: two [nz][64] arrays of T and the three vertical vectors.
+constexpr int kBatch = 8;
+
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
+__global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
+                                                     TO* __restrict__ u_out, T* __restrict__ fcopy, T omega) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nz = L.nz;
+  T* __restrict__ rb = reinterpret_cast<T*>(smem);
+  T* __restrict__ cb = rb + static_cast<size_t>(nz) * kTile;
+  T* __restrict__ vb = cb + static_cast<size_t>(nz) * kTile;   // bv[nz], av[nz], arv[nz+1]
+  T* __restrict__ va = vb + nz;
+  T* __restrict__ vr = va + nz;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int col = tile * kTile + lane;
+  const int kw = (nz + nw - 1) / nw;
+  const int k0 = min(nz, wave * kw), k1 = min(nz, k0 + kw);
+  const Column<T> c = load_column(L, col);
+  for (int i = threadIdx.x; i <= nz; i += blockDim.x) {
+    if (i < nz) {
+      vb[i] = L.bv[i];
+      va[i] = L.av[i];
+    }
+    vr[i] = L.arv[i];
+  }
+
+  if (ZERO) {
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) {
+      const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      const T fk = static_cast<T>(f[o]);
+      if (FCOPY) fcopy[o] = fk;
+      rb[k * kTile + lane] = fk;
+    }
+  } else {
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) {
+      const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      const T um = k > 0 ? u_in[o - kTile] : T(0);
+      const T uc = u_in[o];
+      const T up = k + 1 < nz ? u_in[o + kTile] : T(0);
+      const T fk = static_cast<T>(f[o]);
+      if (FCOPY) fcopy[o] = fk;
+      rb[k * kTile + lane] = fk - apply_row(L, c, u_in, k, um, uc, up);
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const T esum = c.a0 + c.a1 + c.a2;
+    T s_prev = T(0), ip_prev = T(1), d_prev = T(0);
+    for (int kb = 0; kb < nz; kb += kBatch) {
+      T rr[kBatch], ee[kBatch], ll[kBatch], mm[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int k = min(kb + i, nz - 1);
+        rr[i] = rb[k * kTile + lane];
+        ee[i] = c.bh * vb[k] + esum * va[k];
+        ll[i] = c.arh * vr[k];
+        mm[i] = c.arh * vr[k + 1];
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        if (kb + i < nz) {
+          const int k = kb + i;
+          const T s = ee[i] + ll[i] * (s_prev * ip_prev);
+          const T ip = fast_rcp(s + mm[i]);
+          const T d = (rr[i] + ll[i] * d_prev) * ip;
+          rb[k * kTile + lane] = d;
+          cb[k * kTile + lane] = mm[i] * ip;
+          s_prev = s;
+          ip_prev = ip;
+          d_prev = d;
+        }
+      }
+    }
+    T x = T(0);
+    for (int kt = nz; kt > 0; kt -= kBatch) {
+      T dd[kBatch], cc[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int k = max(kt - 1 - i, 0);
+        dd[i] = rb[k * kTile + lane];
+        cc[i] = cb[k * kTile + lane];
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        if (kt - 1 - i >= 0) {
+          x = dd[i] + cc[i] * x;
+          rb[(kt - 1 - i) * kTile + lane] = x;
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll 8
+  for (int k = k0; k < k1; ++k) {
+    const size_t o = c.base + static_cast<size_t>(k) * kTile;
+    const T x = rb[k * kTile + lane];
+    const T uo = ZERO ? omega * x : u_in[o] + omega * x;
+    u_out[o] = static_cast<TO>(uo);
+  }
+}
+
+// Line smoother, scan form (nz <= kScanWaves * kScanLevels): one workgroup
+// per tile of 64 columns, wave w owns the levels [w*kb, (w+1)*kb) of every
+// column and keeps them in registers. The column solve of the margin-form
+// Thomas algorithm is evaluated by three block scans over the waves:
+//  * pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) is a Moebius map,
+//    (P, Q) -> ((e_k + l_k) P + e_k l_k Q, P + l_k Q) with s = P / Q; the
+//    product of a block's 2x2 matrices (positive entries, rescaled by exact
+//    powers of two) gives each wave the margin s entering its block;
+//  * elimination: d_k = (l_k d_{k-1} + r_k) / p_k, an affine map in d;
+//  * back substitution: x_k = (m_k / p_k) x_{k+1} + d_k, affine in x.
+// Every wave composes its block's map, publishes it in LDS, and applies the
+// published maps of the blocks before (after) it to obtain its incoming value.
+// The chain is therefore kb + n_waves steps instead of nz, and the only
+// workgroup-wide data in LDS are the per-wave summaries.
+constexpr int kScanLevels = 8;
+constexpr int kScanWaves = 16;
+
+template <typename T>
+__device__ __forceinline__ void rescale2(T& a, T& b) {
+  // multiply both entries by the same power of two so the larger is O(1)
+  const int e = max(ilogb(a), ilogb(b));
+  a = scalbn(a, -e);
+  b = scalbn(b, -e);
+}
+
+template <typename T>
+__device__ __forceinline__ T rcp_of(T v) {
+  return fast_rcp(v);
+}
+
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
+__global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
+                                                      TO* __restrict__ u_out, T* __restrict__ fcopy, T omega) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nz = L.nz;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  // summaries: pivot map (4), elimination map (2), substitution map (2)
+  T* __restrict__ sm = reinterpret_cast<T*>(smem);
+  auto at = [&](int w, int q) -> T& { return sm[(static_cast<size_t>(w) * 8 + q) * kTile + lane]; };
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int col = tile * kTile + lane;
+  const int kb = (nz + nw - 1) / nw;
+  const int k0 = min(nz, wave * kb);
+  const int nb = min(nz, k0 + kb) - k0;
+  const Column<T> c = load_column(L, col);
+  const T esum = c.a0 + c.a1 + c.a2;
+
+  // ---- residual of the wave's levels, in registers
+  T r[kScanLevels], uu[kScanLevels], e[kScanLevels], l[kScanLevels], m[kScanLevels];
+#pragma unroll
+  for (int i = 0; i < kScanLevels; ++i) {
+    if (i < nb) {
+      const int k = k0 + i;
+      const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      const T fk = static_cast<T>(f[o]);
+      if (FCOPY) fcopy[o] = fk;
+      e[i] = c.bh * L.bv[k] + esum * L.av[k];
+      l[i] = c.arh * L.arv[k];
+      m[i] = c.arh * L.arv[k + 1];
+      if (ZERO) {
+        r[i] = fk;
+        uu[i] = T(0);
+      } else {
+        const T um = k > 0 ? u_in[o - kTile] : T(0);
+        const T uc = u_in[o];
+        const T up = k + 1 < nz ? u_in[o + kTile] : T(0);
+        uu[i] = uc;
+        r[i] = fk - apply_row(L, c, u_in, k, um, uc, up);
+      }
+    }
+  }
+
+  // ---- pivots: block product of the Moebius matrices [[e+l, e l'], [1, l']]
+  // (l' = l_k, or 1 on level 0 where l_0 = 0, so that (0, 1) -> (e_0, 1))
+  T p00 = T(1), p01 = T(0), p10 = T(0), p11 = T(1);
+#pragma unroll
+  for (int i = 0; i < kScanLevels; ++i) {
+    if (i < nb) {
+      const T lp = (k0 + i == 0) ? T(1) : l[i];
+      const T a = e[i] + l[i], b = e[i] * lp;
+      const T n00 = a * p00 + b * p10, n01 = a * p01 + b * p11;
+      const T n10 = p00 + lp * p10, n11 = p01 + lp * p11;
+      const T mx = max(max(n00, n01), max(n10, n11));
+      const int ex = ilogb(mx);
+      p00 = scalbn(n00, -ex);
+      p01 = scalbn(n01, -ex);
+      p10 = scalbn(n10, -ex);
+      p11 = scalbn(n11, -ex);
+    }
+  }
+  at(wave, 0) = p00;
+  at(wave, 1) = p01;
+  at(wave, 2) = p10;
+  at(wave, 3) = p11;
+  __syncthreads();
+  T P = T(0), Q = T(1);
+  for (int j = 0; j < wave; ++j) {
+    const T nP = at(j, 0) * P + at(j, 1) * Q;
+    const T nQ = at(j, 2) * P + at(j, 3) * Q;
+    P = nP;
+    Q = nQ;
+    rescale2(P, Q);
+  }
+  // local margins and pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k)
+  T ip[kScanLevels];
+  {
+    T s_prev = wave == 0 ? T(0) : P * rcp_of(Q);
+#pragma unroll
+    for (int i = 0; i < kScanLevels; ++i) {
+      if (i < nb) {
+        const T s = (k0 + i == 0) ? e[i] : e[i] + l[i] * s_prev * rcp_of(s_prev + l[i]);
+        ip[i] = rcp_of(s + m[i]);
+        s_prev = s;
+      }
+    }
+  }
+
+  // ---- elimination d_k = a_k d_{k-1} + b_k, a_k = l_k / p_k, b_k = r_k / p_k
+  T A = T(1), B = T(0);
+#pragma unroll
+  for (int i = 0; i < kScanLevels; ++i) {
+    if (i < nb) {
+      const T a = l[i] * ip[i];
+      A = a * A;
+      B = a * B + r[i] * ip[i];
+    }
+  }
+  at(wave, 4) = A;
+  at(wave, 5) = B;
+  __syncthreads();
+  T d = T(0);
+  for (int j = 0; j < wave; ++j) d = at(j, 4) * d + at(j, 5);
+#pragma unroll
+  for (int i = 0; i < kScanLevels; ++i) {
+    if (i < nb) {
+      d = l[i] * ip[i] * d + r[i] * ip[i];
+      r[i] = d;   // r now holds d
+    }
+  }
+
+  // ---- back substitution x_k = c_k x_{k+1} + d_k, c_k = m_k / p_k
+  T C = T(1), D = T(0);
+#pragma unroll
+  for (int i = kScanLevels - 1; i >= 0; --i) {
+    if (i < nb) {
+      const T cc = m[i] * ip[i];
+      C = cc * C;
+      D = cc * D + r[i];
+    }
+  }
+  at(wave, 6) = C;
+  at(wave, 7) = D;
+  __syncthreads();
+  T x = T(0);
+  for (int j = nw - 1; j > wave; --j) x = at(j, 6) * x + at(j, 7);
+#pragma unroll
+  for (int i = kScanLevels - 1; i >= 0; --i) {
+    if (i < nb) {
+      x = m[i] * ip[i] * x + r[i];
+      const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
+      const T uo = ZERO ? omega * x : uu[i] + omega * x;
+      u_out[o] = static_cast<TO>(uo);
+    }
   }
 }
 
@@ -393,11 +694,33 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
   return hipGetLastError();
 }
 
+// the LDS-staged kernel when its two [nz][64] arrays fit, else the
+// register/global-scratch kernel
+size_t g_max_lds = 65536;
+
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
+static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, T* d, T* c, T om, hipStream_t s) {
+  const unsigned ntiles = static_cast<unsigned>(L.npad / kTile);
+  const size_t lds = (2 * static_cast<size_t>(L.nz) * kTile + 3 * static_cast<size_t>(L.nz) + 1) * sizeof(T);
+  if (L.nz <= kScanLevels * kScanWaves) {
+    const int waves = (L.nz + kScanLevels - 1) / kScanLevels;
+    const size_t sl = static_cast<size_t>(waves) * 8 * kTile * sizeof(T);
+    hipLaunchKernelGGL((k_smooth_scan<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(64 * waves), sl, s, L, f, ui, uo, fc,
+                       om);
+  } else if (lds <= g_max_lds) {
+    // one wave per kBatch levels for the parallel phases, at most 16 waves
+    const unsigned waves = static_cast<unsigned>(std::min(16, std::max(1, (L.nz + kBatch - 1) / kBatch)));
+    hipLaunchKernelGGL((k_smooth_lds<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(64 * waves), lds, s, L, f, ui, uo, fc,
+                       om);
+  } else {
+    hipLaunchKernelGGL((k_smooth<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(kTile), 0, s, L, f, ui, uo, fc, d, c, om);
+  }
+}
+
 template <typename T>
 static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const void* u_in, bool zero, void* u_out,
                      bool out_double, void* fcopy, void* sd, void* sc, double omega, hipStream_t s) {
   const Lv<T> L = view<T>(Lg);
-  const dim3 grid(Lg.npad / kTile), block(kTile);
   const T* ui = static_cast<const T*>(u_in);
   T* fc = static_cast<T*>(fcopy);
   T* d = static_cast<T*>(sd);
@@ -409,32 +732,32 @@ static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const vo
     if (out_double) {
       double* uo = static_cast<double*>(u_out);
       if (zero)
-        hipLaunchKernelGGL((k_smooth<T, double, double, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, double, double, true, false>(L, ff, ui, uo, fc, d, c, om, s);
       else
-        hipLaunchKernelGGL((k_smooth<T, double, double, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, double, double, false, false>(L, ff, ui, uo, fc, d, c, om, s);
     } else {
       T* uo = static_cast<T*>(u_out);
       if (zero && fcopy)
-        hipLaunchKernelGGL((k_smooth<T, double, T, true, true>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, double, T, true, true>(L, ff, ui, uo, fc, d, c, om, s);
       else if (zero)
-        hipLaunchKernelGGL((k_smooth<T, double, T, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, double, T, true, false>(L, ff, ui, uo, fc, d, c, om, s);
       else
-        hipLaunchKernelGGL((k_smooth<T, double, T, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, double, T, false, false>(L, ff, ui, uo, fc, d, c, om, s);
     }
   } else {
     const T* ff = static_cast<const T*>(f);
     if (out_double) {
       double* uo = static_cast<double*>(u_out);
       if (zero)
-        hipLaunchKernelGGL((k_smooth<T, T, double, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, T, double, true, false>(L, ff, ui, uo, fc, d, c, om, s);
       else
-        hipLaunchKernelGGL((k_smooth<T, T, double, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, T, double, false, false>(L, ff, ui, uo, fc, d, c, om, s);
     } else {
       T* uo = static_cast<T*>(u_out);
       if (zero)
-        hipLaunchKernelGGL((k_smooth<T, T, T, true, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, T, T, true, false>(L, ff, ui, uo, fc, d, c, om, s);
       else
-        hipLaunchKernelGGL((k_smooth<T, T, T, false, false>), grid, block, 0, s, L, ff, ui, uo, fc, d, c, om);
+        smooth_one<T, T, T, false, false>(L, ff, ui, uo, fc, d, c, om, s);
     }
   }
 }
@@ -447,6 +770,11 @@ hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_dou
   else
     smooth_t<float>(L, f, f_double, u_in, zero_guess, u_out, out_double, fcopy, sd, sc, omega, s);
   return hipGetLastError();
+}
+
+hipError_t set_max_lds(size_t bytes) {
+  g_max_lds = bytes;
+  return hipSuccess;
 }
 
 hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int prec, const void* f,

@@ -473,7 +473,15 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
     delete m;
     return fail(s, msg);
   };
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&m->h_scal), sizeof(tpmg::FcgScalars), hipHostMallocDefault);
+  int dev = 0, max_lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) {
+    delete m;
+    return fail(TPMG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
+  }
+  tpmg::set_max_lds(static_cast<size_t>(max_lds));
+  e = hipHostMalloc(reinterpret_cast<void**>(&m->h_scal), sizeof(tpmg::FcgScalars), hipHostMallocDefault);
   if (e != hipSuccess) {
     m->h_scal = nullptr;
     return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
