@@ -31,43 +31,75 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, iters_fp64: int) -> dict:
-    """The CPU oracle (NumPy, FP64, 1 thread) on a bounded sample of the same
-    workload: its setup, the initial residual and one FCG iteration (one
-    SpMV + one V-cycle + BLAS-1) are timed; the solve time is extrapolated
-    with the iteration count the solve needs (the GPU FP64 count, which
-    parity tests pin to the oracle's)."""
+def measured_traffic():
+    """HBM bytes per finest-sweep dispatch from the committed counter summary,
+    or None when kernels.hip has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "smoother_ico6_nz128_counters.md")
+    src = os.path.join(ROOT, "paper_1408_2981_amd", "csrc", "kernels.hip")
+    try:
+        vals = dict(l.strip().split(": ", 1) for l in open(path) if l.strip().startswith(("traffic_", "kernels_hip_")))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if vals.get("kernels_hip_sha256") != digest:
+        return None
+    return float(vals["traffic_bytes_per_dispatch"])
+
+
+def cpu_baseline(w, iters_fp64: int, sample_iters: int = 3) -> dict:
+    """The CPU oracle (NumPy, FP64, one thread) on a bounded sample of the same
+    workload: its FCG solve is run for `sample_iters` iterations (initial
+    residual included) and timed, and the time is scaled to the iteration
+    count the full solve needs (the GPU FP64 count, which the parity tests pin
+    to the oracle's own)."""
     from threadpoolctl import threadpool_limits
 
-    import numpy as np
-
     import synth
-    from oracle import operator as opm, tpmg as otpmg
+    from oracle import tpmg as otpmg
 
     with threadpool_limits(limits=1):
         h = otpmg.build(w.refinement, w.r_faces(), w.omega2)
         fine = h.meshes[-1]
         f = synth.make_rhs(w, fine.centre, fine.area, h.vert.vk)
-        op = h.finest
         t0 = time.perf_counter()
-        r = f - opm.apply(op, np.zeros_like(f))
+        res = otpmg.solve(h, f, rtol=1e-8, maxit=sample_iters)
         t1 = time.perf_counter()
-        z = otpmg.vcycle(h, r)
-        q = opm.apply(op, z)
-        _ = float(np.sum(z * q)), float(np.sum(r * z))
-        x = 0.5 * z
-        r = r - 0.5 * q
-        _ = float(np.sum(r * r))
-        t2 = time.perf_counter()
-    t_solve = (t1 - t0) + iters_fp64 * (t2 - t1)
+    done = max(res.iters, 1)
+    t_solve = (t1 - t0) * iters_fp64 / done
     return {
         "value": w.unknowns / t_solve,
         "unit": "unknowns/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"oracle FP64 on {w.name}: initial residual + 1 FCG iteration timed "
-                  f"({t2 - t0:.1f} s), extrapolated to {iters_fp64} iterations",
+        "sample": f"oracle FP64 FCG on {w.name}, first {done} iterations timed ({t1 - t0:.1f} s), "
+                  f"scaled to the {iters_fp64} iterations of the full solve",
     }
+
+
+def profile_sweep(w, reps: int):
+    """Counter run: `reps` finest-grid FP32 sweeps, then one copy of 512 MiB
+    (a plain copy kernel of known size, to calibrate FETCH_SIZE and
+    WRITE_SIZE)."""
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=False)
+    geo = P.geometry()
+    f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
+    u = P.device_vector()
+    st, it, rr, _, _ = P.solve(f, u)            # leaves realistic data in the sweep buffers
+    ms, nbytes = T.tpmg_mg_time_sweep(P.mg, reps)
+    src = torch.ones(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"sweep_avg_us": ms * 1000.0, "sweep_model_bytes": nbytes, "sweep_dispatches": reps,
+                      "copy_bytes": 512 * 1024 * 1024, "solve_iters": it}), flush=True)
 
 
 def main():
@@ -78,6 +110,9 @@ def main():
     ap.add_argument("--workload", default="ico6_nz128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=50)
+    ap.add_argument("--profile-sweep", action="store_true",
+                    help="only the finest-grid sweep timing loop (mixed) and a 512 MiB calibration copy, "
+                         "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -96,6 +131,9 @@ def main():
 
     w = synth.workload(args.workload)
     log(f"workload {w.name}: {w.unknowns} unknowns, refinement {w.refinement}, nz {w.nz}")
+    if args.profile_sweep:
+        profile_sweep(w, args.sweep_reps)
+        return
     results = {}
     P64 = T.Problem(w.refinement, w.r_faces(), w.omega2)
     geo = P64.geometry()
@@ -160,7 +198,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic() if args.workload == "ico6_nz128" else None,
             "avg_launch_us": mixed["sweep_ms"] * 1000.0,
             "bytes_per_launch": mixed["sweep_bytes"],
         },

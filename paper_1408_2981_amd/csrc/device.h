@@ -49,26 +49,36 @@ struct FcgScalars {
 
 constexpr int kRedBlocks = 1024;   // fixed grid of the BLAS-1 reductions
 constexpr int kRedThreads = 256;
-constexpr int kChunk = 16;         // levels per wave in the stencil kernels
 
+// Where a reduction's last block applies its sums to the FCG scalars.
+enum FinalizeSite { kFinInit = 0, kFinAlpha = 1, kFinRR = 2, kFinBeta = 3, kFinNone = 4 };
+
+int stencil_chunk(int npad, int nz);      // levels per wave of the stencil kernels
 size_t stencil_blocks(int npad, int nz);  // blocks of 256 threads of the stencil kernels
 
 // All launchers enqueue on `s` and return hipGetLastError().
 // prec: 8 = double, 4 = float (the V-cycle precision of the level data).
+// Reductions write two partial sums per block to `partials`; a one-block
+// finalize kernel then sums them in a fixed order and applies them to the
+// FCG scalars at `site`.
 
-// y = A x (mode 0, partials <x, y>) or y = b - A x (mode 1, partials
-// <y, y>, <b, b>); FP64; partials[2 * block + i].
+// mode 0: y = A x (partials <x, y>, e.g. site kFinAlpha). mode 1: y = b - A x
+// (partials <y, y>, <b, b>; site kFinInit). FP64; x and y must not alias.
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, hipStream_t s);
+                         double* partials, int site, FcgScalars* sc, hipStream_t s);
 
 // One damped block-Jacobi sweep with the Thomas solve per column:
 // u_out = u_in + omega A_T^-1 (f - A u_in). zero_guess: u_in taken as 0
 // (not read). f_double: f is FP64 (else of precision prec); out_double:
 // u_out is FP64. fcopy (optional): receives f rounded to prec. sd, sc:
-// scratch vectors of the level size in precision prec.
+// scratch vectors of the level size (used only by the fallback kernel).
+// q non-NULL (FP64 f and output required): also reduces <u_out, q> and
+// <u_out, f> and applies them at site kFinBeta.
 hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_double, const void* u_in,
                          bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
-                         double omega, hipStream_t s);
+                         double omega, hipStream_t s, const double* q = nullptr, double* partials = nullptr,
+                         FcgScalars* scal = nullptr);
+bool smooth_supports_dots(int nz);
 
 // Largest dynamic LDS a workgroup may use (set once from the device
 // properties); decides between the LDS-staged smoother and the fallback.
@@ -82,18 +92,15 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
                               void* u_fine, hipStream_t s);
 
-// FCG BLAS-1 (FP64, whole padded vector of length len).
-hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, const FcgScalars* sc,
-                             size_t len, double* partials, hipStream_t s);
+// x += alpha p, r -= alpha q (site kFinRR: <r, r>), FP64, padded length len.
+hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, FcgScalars* sc, size_t len,
+                             double* partials, hipStream_t s);
+// <z, q>, <z, r> (site kFinBeta), for nz beyond the fused smoother's range.
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
-                       hipStream_t s);
+                       FcgScalars* sc, hipStream_t s);
+// p = z + beta p (beta from the scalars), in place.
 hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);   // zero fill (graph-safe)
-
-// Single-block deterministic finalisation of the partial sums.
-enum FinalizeKind { kFinInit = 0, kFinAlpha = 1, kFinRR = 2, kFinBeta = 3, kFinDot = 4 };
-hipError_t launch_finalize(int kind, const double* partials, int nblocks, FcgScalars* sc, double* out2,
-                           hipStream_t s);
 
 // layout conversion of a finest-grid FP64 vector
 hipError_t launch_pack(const double* cm, double* tiled, int n, int npad, int nz, hipStream_t s);

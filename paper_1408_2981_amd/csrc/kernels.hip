@@ -89,37 +89,109 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// deterministic block sum (256 threads = 4 waves) of NV values
-template <int NV>
-__device__ __forceinline__ void block_sums(double (&v)[NV], double* __restrict__ out) {
-  __shared__ double red[4][NV];
+// deterministic block sum of two values (blockDim.x a multiple of 64, at
+// most 16 waves); thread 0 writes out[2 * blockIdx.x + i]
+__device__ __forceinline__ void block_sums(double (&v)[2], double* __restrict__ out) {
+  __shared__ double red[16][2];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  v[0] = wave_sum(v[0]);
+  v[1] = wave_sum(v[1]);
+  if (lane == 0) {
+    red[w][0] = v[0];
+    red[w][1] = v[1];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nw; ++i) {
+      a += red[i][0];
+      b += red[i][1];
+    }
+    out[2 * blockIdx.x] = a;
+    out[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
+
+// Scalar updates of the flexible-CG recurrence, applied by the last block of
+// a reduction to the deterministic sums (s0, s1) of all blocks' partials.
+__device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restrict__ sc) {
+  switch (site) {
+    case kFinInit:
+      sc->rr = s0;
+      sc->ff = s1;
+      sc->pq = 1.0;
+      sc->rz = 0.0;
+      sc->alpha = 0.0;
+      sc->beta = 0.0;
+      sc->status = 0;
+      break;
+    case kFinAlpha:
+      sc->pq = s0;
+      if (!(s0 > 0.0) || !finite(s0) || !finite(sc->rz)) {
+        sc->status = 1;
+        sc->alpha = 0.0;
+      } else {
+        sc->alpha = sc->rz / s0;
+      }
+      break;
+    case kFinRR:
+      sc->rr = s0;
+      break;
+    case kFinBeta:
+      sc->beta = -s0 / sc->pq;
+      sc->rz = s1;
+      break;
+    default:
+      break;
+  }
+}
+
+// Single-block deterministic finalisation: sums the partials of nblocks
+// blocks in a fixed order and applies them to the FCG scalars. It runs as a
+// kernel of its own: on this GPU each XCD has its own L2, and a kernel
+// boundary is the cheap way to make all blocks' partials visible (a
+// device-scope fence per block would write back the whole L2).
+__global__ __launch_bounds__(256) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
+                                                  FcgScalars* __restrict__ sc) {
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    v[0] += partials[2 * b];
+    v[1] += partials[2 * b + 1];
+  }
+  __shared__ double red[4][2];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[w][i] = v[i];
+  v[0] = wave_sum(v[0]);
+  v[1] = wave_sum(v[1]);
+  if (lane == 0) {
+    red[w][0] = v[0];
+    red[w][1] = v[1];
+  }
   __syncthreads();
   if (threadIdx.x == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) out[NV * blockIdx.x + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+    fcg_scalars(site, (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]),
+                (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]), sc);
 }
 
 // ---------------------------------------------------------------------------
-// stencil kernels: one wave per (tile, chunk of kChunk levels)
+// stencil kernels: one wave per (tile, chunk of levels); the chunk length is
+// chosen per grid so that small grids still launch enough waves
 // ---------------------------------------------------------------------------
 
+// MODE 0: y = A x, partials <x, y>. MODE 1: y = b - A x, partials <y, y>,
+// <b, b>.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, const double* __restrict__ x,
+__global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const double* __restrict__ x,
                                                 const double* __restrict__ b, double* __restrict__ y,
                                                 double* __restrict__ partials) {
-  const int nchunks = (L.nz + kChunk - 1) / kChunk;
+  const int nchunks = (L.nz + chunk - 1) / chunk;
   const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   double acc[2] = {0.0, 0.0};
   if (item < (L.npad >> 6) * nchunks) {
-    const int tile = item / nchunks, chunk = item - tile * nchunks;
-    const int k0 = chunk * kChunk, k1 = min(L.nz, k0 + kChunk);
+    const int tile = item / nchunks, chunk_i = item - tile * nchunks;
+    const int k0 = chunk_i * chunk, k1 = min(L.nz, k0 + chunk);
     const Column<double> c = load_column(L, tile * kTile + lane);
     double um = k0 > 0 ? x[c.base + static_cast<size_t>(k0 - 1) * kTile] : 0.0;
     double uc = x[c.base + static_cast<size_t>(k0) * kTile];
@@ -141,7 +213,7 @@ __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, const double* __re
       uc = up;
     }
   }
-  block_sums<2>(acc, partials);
+  block_sums(acc, partials);
 }
 
 // Line smoother: damped block-Jacobi with a Thomas solve per column
@@ -355,9 +427,10 @@ __device__ __forceinline__ T rcp_of(T v) {
   return fast_rcp(v);
 }
 
-template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
 __global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
-                                                      TO* __restrict__ u_out, T* __restrict__ fcopy, T omega) {
+                                                      TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
+                                                      const double* __restrict__ q, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nz = L.nz;
   const int lane = threadIdx.x & 63;
@@ -376,11 +449,13 @@ __global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restr
 
   // ---- residual of the wave's levels, in registers
   T r[kScanLevels], uu[kScanLevels], e[kScanLevels], l[kScanLevels], m[kScanLevels];
+  double fd[DOTS ? kScanLevels : 1];
 #pragma unroll
   for (int i = 0; i < kScanLevels; ++i) {
     if (i < nb) {
       const int k = k0 + i;
       const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      if (DOTS) fd[i] = static_cast<double>(f[o]);
       const T fk = static_cast<T>(f[o]);
       if (FCOPY) fcopy[o] = fk;
       e[i] = c.bh * L.bv[k] + esum * L.av[k];
@@ -482,28 +557,35 @@ __global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restr
   __syncthreads();
   T x = T(0);
   for (int j = nw - 1; j > wave; --j) x = at(j, 6) * x + at(j, 7);
+  double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = kScanLevels - 1; i >= 0; --i) {
     if (i < nb) {
       x = m[i] * ip[i] * x + r[i];
       const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
       const T uo = ZERO ? omega * x : uu[i] + omega * x;
-      u_out[o] = static_cast<TO>(uo);
+      const TO zo = static_cast<TO>(uo);
+      u_out[o] = zo;
+      if (DOTS) {
+        acc[0] += static_cast<double>(zo) * q[o];
+        acc[1] += static_cast<double>(zo) * fd[i];
+      }
     }
   }
+  if (DOTS) block_sums(acc, partials);
 }
 
 // residual on the fine level, summed over the four children of each coarse
 // cell (Algorithm 1 residual + restriction by summation, Section 5)
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int n_coarse, const T* __restrict__ f,
+__global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int chunk, int n_coarse, const T* __restrict__ f,
                                                            const T* __restrict__ u, T* __restrict__ fc) {
-  const int nchunks = (L.nz + kChunk - 1) / kChunk;
+  const int nchunks = (L.nz + chunk - 1) / chunk;
   const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (item >= (L.npad >> 6) * nchunks) return;
-  const int tile = item / nchunks, chunk = item - tile * nchunks;
-  const int k0 = chunk * kChunk, k1 = min(L.nz, k0 + kChunk);
+  const int tile = item / nchunks, chunk_i = item - tile * nchunks;
+  const int k0 = chunk_i * chunk, k1 = min(L.nz, k0 + chunk);
   const int col = tile * kTile + lane;
   const int P = col >> 2;
   const Column<T> c = load_column(L, col);
@@ -524,14 +606,14 @@ __global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int n_coarse
 
 // u_fine[c] += e_P + sum_j w_cj (e_{N_j(P)} - e_P), P = c / 4
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(Lv<T> F, Lv<T> C, const T* __restrict__ e,
+__global__ __launch_bounds__(256) void k_prolong_add(Lv<T> F, Lv<T> C, int chunk, const T* __restrict__ e,
                                                      T* __restrict__ u) {
-  const int nchunks = (F.nz + kChunk - 1) / kChunk;
+  const int nchunks = (F.nz + chunk - 1) / chunk;
   const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (item >= (F.npad >> 6) * nchunks) return;
-  const int tile = item / nchunks, chunk = item - tile * nchunks;
-  const int k0 = chunk * kChunk, k1 = min(F.nz, k0 + kChunk);
+  const int tile = item / nchunks, chunk_i = item - tile * nchunks;
+  const int k0 = chunk_i * chunk, k1 = min(F.nz, k0 + chunk);
   const int col = tile * kTile + lane;
   if (col >= F.n) return;
   const int P = col >> 2;
@@ -567,12 +649,12 @@ __global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, doub
     r[i] = ri;
     acc[0] += ri * ri;
   }
-  block_sums<2>(acc, partials);
+  block_sums(acc, partials);
 }
 
+// <z, q>, <z, r> for the case where the smoother cannot fuse them
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, const double* __restrict__ q,
-                                              const double* __restrict__ r, size_t len,
-                                              double* __restrict__ partials) {
+                                              const double* __restrict__ r, size_t len, double* __restrict__ partials) {
   double acc[2] = {0.0, 0.0};
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -580,7 +662,7 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, cons
     acc[0] += zi * q[i];
     acc[1] += zi * r[i];
   }
-  block_sums<2>(acc, partials);
+  block_sums(acc, partials);
 }
 
 __global__ __launch_bounds__(256) void k_pupdate(const double* __restrict__ z, double* __restrict__ p,
@@ -595,60 +677,6 @@ __global__ __launch_bounds__(256) void k_fill(uint32_t* __restrict__ p, size_t w
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
        i += static_cast<size_t>(gridDim.x) * blockDim.x)
     p[i] = 0u;
-}
-
-__device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
-
-__global__ __launch_bounds__(256) void k_finalize(int kind, const double* __restrict__ partials, int nblocks,
-                                                  FcgScalars* __restrict__ sc, double* __restrict__ out2) {
-  // every reduction kernel writes two partial sums per block
-  double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-    v[0] += partials[2 * b];
-    v[1] += partials[2 * b + 1];
-  }
-  __shared__ double red[4][2];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = 0; i < 2; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0) {
-    red[w][0] = v[0];
-    red[w][1] = v[1];
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  const double s0 = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-  const double s1 = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
-  switch (kind) {
-    case kFinInit:
-      sc->rr = s0;
-      sc->ff = s1;
-      sc->pq = 1.0;
-      sc->rz = 0.0;
-      sc->alpha = 0.0;
-      sc->beta = 0.0;
-      sc->status = 0;
-      break;
-    case kFinAlpha:
-      sc->pq = s0;
-      if (!(s0 > 0.0) || !finite(s0) || !finite(sc->rz)) {
-        sc->status = 1;
-        sc->alpha = 0.0;
-      } else {
-        sc->alpha = sc->rz / s0;
-      }
-      break;
-    case kFinRR:
-      sc->rr = s0;
-      break;
-    case kFinBeta:
-      sc->beta = -s0 / sc->pq;
-      sc->rz = s1;
-      break;
-    default:
-      out2[0] = s0;
-      out2[1] = s1;
-      break;
-  }
 }
 
 __global__ __launch_bounds__(256) void k_pack(const double* __restrict__ cm, double* __restrict__ tiled, int n,
@@ -679,36 +707,62 @@ unsigned grid_for(size_t work, unsigned cap) {
 
 }  // namespace
 
+int stencil_chunk(int npad, int nz) {
+  // largest levels-per-wave that still gives >= 4096 waves (latency hiding on
+  // small grids), at most 16
+  const size_t tiles = static_cast<size_t>(npad / kTile);
+  for (int c = 16; c > 1; c >>= 1)
+    if (tiles * static_cast<size_t>((nz + c - 1) / c) >= 4096) return c;
+  return 1;
+}
+
 size_t stencil_blocks(int npad, int nz) {
-  const size_t waves = static_cast<size_t>(npad / kTile) * ((nz + kChunk - 1) / kChunk);
+  const int c = stencil_chunk(npad, nz);
+  const size_t waves = static_cast<size_t>(npad / kTile) * ((nz + c - 1) / c);
   return (waves + 3) / 4;
 }
 
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, hipStream_t s) {
+                         double* partials, int site, FcgScalars* sc, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
+  const int chunk = stencil_chunk(L.npad, L.nz);
+  const Lv<double> V = view<double>(L);
   if (mode == 0)
-    hipLaunchKernelGGL(k_spmv64<0>, dim3(blocks), dim3(256), 0, s, view<double>(L), x, b, y, partials);
+    hipLaunchKernelGGL(k_spmv64<0>, dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
   else
-    hipLaunchKernelGGL(k_spmv64<1>, dim3(blocks), dim3(256), 0, s, view<double>(L), x, b, y, partials);
+    hipLaunchKernelGGL(k_spmv64<1>, dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
+  if (site != kFinNone)
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc);
   return hipGetLastError();
 }
 
-// the LDS-staged kernel when its two [nz][64] arrays fit, else the
-// register/global-scratch kernel
+// the scan kernel for nz <= 128, else the LDS-staged kernel when its two
+// [nz][64] arrays fit, else the register/global-scratch kernel
 size_t g_max_lds = 65536;
 
-template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
-static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, T* d, T* c, T om, hipStream_t s) {
+struct DotArgs {
+  const double* q;
+  double* partials;
+  FcgScalars* sc;
+};
+
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, T* d, T* c, T om, const DotArgs& da,
+                       hipStream_t s) {
   const unsigned ntiles = static_cast<unsigned>(L.npad / kTile);
-  const size_t lds = (2 * static_cast<size_t>(L.nz) * kTile + 3 * static_cast<size_t>(L.nz) + 1) * sizeof(T);
   if (L.nz <= kScanLevels * kScanWaves) {
     const int waves = (L.nz + kScanLevels - 1) / kScanLevels;
     const size_t sl = static_cast<size_t>(waves) * 8 * kTile * sizeof(T);
-    hipLaunchKernelGGL((k_smooth_scan<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(64 * waves), sl, s, L, f, ui, uo, fc,
-                       om);
-  } else if (lds <= g_max_lds) {
-    // one wave per kBatch levels for the parallel phases, at most 16 waves
+    hipLaunchKernelGGL((k_smooth_scan<T, TF, TO, ZERO, FCOPY, DOTS>), dim3(ntiles), dim3(64 * waves), sl, s, L, f, ui,
+                       uo, fc, om, da.q, da.partials);
+    if (DOTS)
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), da.partials,
+                         static_cast<int>(ntiles), da.sc);
+    return;
+  }
+  // dots are only requested for nz within the scan kernel's range
+  const size_t lds = (2 * static_cast<size_t>(L.nz) * kTile + 3 * static_cast<size_t>(L.nz) + 1) * sizeof(T);
+  if (lds <= g_max_lds) {
     const unsigned waves = static_cast<unsigned>(std::min(16, std::max(1, (L.nz + kBatch - 1) / kBatch)));
     hipLaunchKernelGGL((k_smooth_lds<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(64 * waves), lds, s, L, f, ui, uo, fc,
                        om);
@@ -719,58 +773,67 @@ static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, 
 
 template <typename T>
 static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const void* u_in, bool zero, void* u_out,
-                     bool out_double, void* fcopy, void* sd, void* sc, double omega, hipStream_t s) {
+                     bool out_double, void* fcopy, void* sd, void* sc, double omega, const DotArgs& da, hipStream_t s) {
   const Lv<T> L = view<T>(Lg);
   const T* ui = static_cast<const T*>(u_in);
   T* fc = static_cast<T*>(fcopy);
   T* d = static_cast<T*>(sd);
   T* c = static_cast<T*>(sc);
   const T om = static_cast<T>(omega);
-  // (f type, out type, zero guess, f copy) combinations used by the V-cycle
+  const bool dots = da.q != nullptr;
+  // (f type, out type, zero guess, f copy, dots) combinations used by the V-cycle
   if (f_double) {
     const double* ff = static_cast<const double*>(f);
     if (out_double) {
       double* uo = static_cast<double*>(u_out);
-      if (zero)
-        smooth_one<T, double, double, true, false>(L, ff, ui, uo, fc, d, c, om, s);
+      if (dots && zero)
+        smooth_one<T, double, double, true, false, true>(L, ff, ui, uo, fc, d, c, om, da, s);
+      else if (dots)
+        smooth_one<T, double, double, false, false, true>(L, ff, ui, uo, fc, d, c, om, da, s);
+      else if (zero)
+        smooth_one<T, double, double, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
       else
-        smooth_one<T, double, double, false, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, double, double, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
     } else {
       T* uo = static_cast<T*>(u_out);
       if (zero && fcopy)
-        smooth_one<T, double, T, true, true>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, double, T, true, true, false>(L, ff, ui, uo, fc, d, c, om, da, s);
       else if (zero)
-        smooth_one<T, double, T, true, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, double, T, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
       else
-        smooth_one<T, double, T, false, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, double, T, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
     }
   } else {
     const T* ff = static_cast<const T*>(f);
     if (out_double) {
       double* uo = static_cast<double*>(u_out);
       if (zero)
-        smooth_one<T, T, double, true, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, T, double, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
       else
-        smooth_one<T, T, double, false, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, T, double, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
     } else {
       T* uo = static_cast<T*>(u_out);
       if (zero)
-        smooth_one<T, T, T, true, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, T, T, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
       else
-        smooth_one<T, T, T, false, false>(L, ff, ui, uo, fc, d, c, om, s);
+        smooth_one<T, T, T, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
     }
   }
 }
 
 hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_double, const void* u_in,
                          bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
-                         double omega, hipStream_t s) {
+                         double omega, hipStream_t s, const double* q, double* partials, FcgScalars* scal) {
+  if (q && L.nz > kScanLevels * kScanWaves) return hipErrorInvalidValue;
+  const DotArgs da{q, partials, scal};
   if (prec == 8)
-    smooth_t<double>(L, f, true, u_in, zero_guess, u_out, true, nullptr, sd, sc, omega, s);
+    smooth_t<double>(L, f, true, u_in, zero_guess, u_out, true, nullptr, sd, sc, omega, da, s);
   else
-    smooth_t<float>(L, f, f_double, u_in, zero_guess, u_out, out_double, fcopy, sd, sc, omega, s);
+    smooth_t<float>(L, f, f_double, u_in, zero_guess, u_out, out_double, fcopy, sd, sc, omega, da, s);
   return hipGetLastError();
 }
+
+bool smooth_supports_dots(int nz) { return nz <= kScanLevels * kScanWaves; }
 
 hipError_t set_max_lds(size_t bytes) {
   g_max_lds = bytes;
@@ -780,11 +843,12 @@ hipError_t set_max_lds(size_t bytes) {
 hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int prec, const void* f,
                                     const void* u, void* f_coarse, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
+  const int chunk = stencil_chunk(L.npad, L.nz);
   if (prec == 8)
-    hipLaunchKernelGGL(k_residual_restrict<double>, dim3(blocks), dim3(256), 0, s, view<double>(L), C.n,
+    hipLaunchKernelGGL(k_residual_restrict<double>, dim3(blocks), dim3(256), 0, s, view<double>(L), chunk, C.n,
                        static_cast<const double*>(f), static_cast<const double*>(u), static_cast<double*>(f_coarse));
   else
-    hipLaunchKernelGGL(k_residual_restrict<float>, dim3(blocks), dim3(256), 0, s, view<float>(L), C.n,
+    hipLaunchKernelGGL(k_residual_restrict<float>, dim3(blocks), dim3(256), 0, s, view<float>(L), chunk, C.n,
                        static_cast<const float*>(f), static_cast<const float*>(u), static_cast<float*>(f_coarse));
   return hipGetLastError();
 }
@@ -792,24 +856,27 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
                               void* u_fine, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(F.npad, F.nz));
+  const int chunk = stencil_chunk(F.npad, F.nz);
   if (prec == 8)
-    hipLaunchKernelGGL(k_prolong_add<double>, dim3(blocks), dim3(256), 0, s, view<double>(F), view<double>(C),
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(blocks), dim3(256), 0, s, view<double>(F), view<double>(C), chunk,
                        static_cast<const double*>(e_coarse), static_cast<double*>(u_fine));
   else
-    hipLaunchKernelGGL(k_prolong_add<float>, dim3(blocks), dim3(256), 0, s, view<float>(F), view<float>(C),
+    hipLaunchKernelGGL(k_prolong_add<float>, dim3(blocks), dim3(256), 0, s, view<float>(F), view<float>(C), chunk,
                        static_cast<const float*>(e_coarse), static_cast<float*>(u_fine));
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, const FcgScalars* sc,
-                             size_t len, double* partials, hipStream_t s) {
+hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, FcgScalars* sc, size_t len,
+                             double* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
-                       hipStream_t s) {
+                       FcgScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, z, q, r, len, partials);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc);
   return hipGetLastError();
 }
 
@@ -821,12 +888,6 @@ hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   hipLaunchKernelGGL(k_fill, dim3(grid_for(words, 2048)), dim3(256), 0, s, static_cast<uint32_t*>(p), words);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(int kind, const double* partials, int nblocks, FcgScalars* sc, double* out2,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, kind, partials, nblocks, sc, out2);
   return hipGetLastError();
 }
 

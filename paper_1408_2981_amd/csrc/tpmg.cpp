@@ -84,13 +84,11 @@ struct tpmg_mg {
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;   // FCG vectors (tiled, FP64)
   double* partials = nullptr;
   tpmg::FcgScalars* scal = nullptr;
-  double* dot2 = nullptr;
   tpmg::FcgScalars* h_scal = nullptr;    // pinned host mirror
   size_t len = 0;                        // padded finest vector length
   int max_partial_blocks = 0;
-  // graph of one FCG iteration for a given (x, r-source) pair
+  // graph of one FCG iteration for the solution vector graph_x
   hipGraphExec_t graph = nullptr;
-  const double* graph_f = nullptr;
   double* graph_x = nullptr;
 
   tpmg::LevelView view(int l) const {
@@ -168,10 +166,13 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
   m.p = static_cast<double*>(cv.take(fine_len * 8));
   m.q = static_cast<double*>(cv.take(fine_len * 8));
   m.z = static_cast<double*>(cv.take(fine_len * 8));
-  m.max_partial_blocks = static_cast<int>(std::max<size_t>(tpmg::kRedBlocks, tpmg::stencil_blocks(pad64(op.levels.back().n), nz)));
+  // reductions: stencil blocks of the finest grid, the BLAS grid, or one
+  // block per tile (the smoother with fused dots)
+  const size_t fine_npad = pad64(op.levels.back().n);
+  m.max_partial_blocks = static_cast<int>(
+      std::max({static_cast<size_t>(tpmg::kRedBlocks), tpmg::stencil_blocks(static_cast<int>(fine_npad), nz), fine_npad / 64}));
   m.partials = static_cast<double*>(cv.take(2 * static_cast<size_t>(m.max_partial_blocks) * 8));
   m.scal = static_cast<tpmg::FcgScalars*>(cv.take(sizeof(tpmg::FcgScalars)));
-  m.dot2 = static_cast<double*>(cv.take(2 * 8));
   m.len = fine_len;
 }
 
@@ -205,7 +206,7 @@ hipError_t upload(void* dst, const std::vector<T>& v, hipStream_t s) {
 // correction, nu_post sweeps. Level 0: nu_coarse sweeps from zero. In the
 // mixed mode every level is FP32: the first finest sweep reads the FP64
 // residual and keeps an FP32 copy of it, the last writes FP64 z.
-hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
+hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out, const double* q_dots = nullptr) {
   const int L = m.nlev - 1;
   const int prec = m.fp32 ? 4 : 8;
   hipStream_t s = m.stream;
@@ -226,8 +227,11 @@ hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
       const void* f = finest_first ? static_cast<const void*>(r_in) : rhs(l);
       const bool f_double = (l == L) && (finest_first || !m.fp32);
       void* out = last_of_cycle ? static_cast<void*>(z_out) : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
-      e = tpmg::launch_smooth(V, prec, f, f_double, m.lv[l].u[cur[l]], first, out, last_of_cycle,
-                              (finest_first && m.fp32) ? m.fcopy : nullptr, m.sd, m.sc, m.omega, s);
+      const bool dots = last_of_cycle && q_dots;
+      e = tpmg::launch_smooth(V, prec, dots ? static_cast<const void*>(r_in) : f, dots || f_double,
+                              m.lv[l].u[cur[l]], first, out, last_of_cycle,
+                              (finest_first && m.fp32) ? m.fcopy : nullptr, m.sd, m.sc, m.omega, s,
+                              dots ? q_dots : nullptr, m.partials, m.scal);
       if (e != hipSuccess) return e;
       if (!first) cur[l] = 1 - cur[l];
     }
@@ -244,8 +248,11 @@ hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
     for (int k = 0; k < m.nu_post; ++k) {
       const bool last = l == L && k + 1 == m.nu_post;
       void* out = last ? static_cast<void*>(z_out) : m.lv[l].u[1 - cur[l]];
-      e = tpmg::launch_smooth(V, prec, rhs(l), l == L && !m.fp32, m.lv[l].u[cur[l]], false, out, last, nullptr,
-                              m.sd, m.sc, m.omega, s);
+      // the last sweep reads the FP64 residual when it also forms <z, q>, <z, r>
+      const bool dots = last && q_dots;
+      e = tpmg::launch_smooth(V, prec, dots ? static_cast<const void*>(r_in) : rhs(l), dots || (l == L && !m.fp32),
+                              m.lv[l].u[cur[l]], false, out, last, nullptr, m.sd, m.sc, m.omega, s,
+                              dots ? q_dots : nullptr, m.partials, m.scal);
       if (e != hipSuccess) return e;
       if (!last) cur[l] = 1 - cur[l];
     }
@@ -253,22 +260,24 @@ hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
   return hipSuccess;
 }
 
-// one FCG iteration after the convergence test of the previous one:
-// z = M r; beta = -<z,q>/<p,q>; rz = <z,r>; p = z + beta p; q = A p;
-// alpha = rz/<p,q>; x += alpha p; r -= alpha q; rr = <r,r>
+// One FCG iteration after the convergence test of the previous one:
+//   z = M r, with beta = -<z,q>/<p,q> and rz = <z,r> formed by the last sweep;
+//   p = z + beta p; q = A p, alpha = rz/<p,q>;
+//   x += alpha p, r -= alpha q, rr = <r,r>.
 hipError_t fcg_iteration(tpmg_mg& m, double* x) {
   hipError_t e;
   hipStream_t s = m.stream;
-  if ((e = vcycle(m, m.r, m.z)) != hipSuccess) return e;
-  if ((e = tpmg::launch_dots(m.z, m.q, m.r, m.len, m.partials, s)) != hipSuccess) return e;
-  if ((e = tpmg::launch_finalize(tpmg::kFinBeta, m.partials, tpmg::kRedBlocks, m.scal, m.dot2, s)) != hipSuccess) return e;
+  if (tpmg::smooth_supports_dots(m.nz)) {
+    if ((e = vcycle(m, m.r, m.z, m.q)) != hipSuccess) return e;
+  } else {
+    if ((e = vcycle(m, m.r, m.z)) != hipSuccess) return e;
+    if ((e = tpmg::launch_dots(m.z, m.q, m.r, m.len, m.partials, m.scal, s)) != hipSuccess) return e;
+  }
   if ((e = tpmg::launch_pupdate(m.z, m.p, m.scal, m.len, s)) != hipSuccess) return e;
   const tpmg::LevelView F = m.view64(m.nlev - 1);
-  if ((e = tpmg::launch_spmv64(F, 0, m.p, nullptr, m.q, m.partials, s)) != hipSuccess) return e;
-  const int sb = static_cast<int>(tpmg::stencil_blocks(F.npad, F.nz));
-  if ((e = tpmg::launch_finalize(tpmg::kFinAlpha, m.partials, sb, m.scal, m.dot2, s)) != hipSuccess) return e;
-  if ((e = tpmg::launch_fcg_update(x, m.r, m.p, m.q, m.scal, m.len, m.partials, s)) != hipSuccess) return e;
-  return tpmg::launch_finalize(tpmg::kFinRR, m.partials, tpmg::kRedBlocks, m.scal, m.dot2, s);
+  if ((e = tpmg::launch_spmv64(F, 0, m.p, nullptr, m.q, m.partials, tpmg::kFinAlpha, m.scal, s)) != hipSuccess)
+    return e;
+  return tpmg::launch_fcg_update(x, m.r, m.p, m.q, m.scal, m.len, m.partials, s);
 }
 
 void drop_graph(tpmg_mg& m) {
@@ -565,7 +574,8 @@ tpmg_status tpmg_spmv(tpmg_mg* mg, const double* d_x, double* d_y) {
   if (st != TPMG_OK) return st;
   if (!d_x || !d_y) return fail(TPMG_ERR_ARG, "NULL vector");
   if (d_x == d_y) return fail(TPMG_ERR_ARG, "x and y must not alias");
-  TPMG_HIP(tpmg::launch_spmv64(mg->view64(mg->nlev - 1), 0, d_x, nullptr, d_y, mg->partials, mg->stream));
+  TPMG_HIP(tpmg::launch_spmv64(mg->view64(mg->nlev - 1), 0, d_x, nullptr, d_y, mg->partials, tpmg::kFinNone, mg->scal,
+                                mg->stream));
   return TPMG_OK;
 }
 
@@ -588,10 +598,8 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = mg->stream;
   const tpmg::LevelView F = mg->view64(mg->nlev - 1);
-  const int sb = static_cast<int>(tpmg::stencil_blocks(F.npad, F.nz));
   // r = f - A u, rr, ff; p = q = 0 so that the first iteration takes beta = 0
-  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, s));
-  TPMG_HIP(tpmg::launch_finalize(tpmg::kFinInit, mg->partials, sb, mg->scal, mg->dot2, s));
+  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s));
   TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
   TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
   TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
