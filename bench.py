@@ -102,6 +102,108 @@ def profile_sweep(w, reps: int):
                       "copy_bytes": 512 * 1024 * 1024, "solve_iters": it}), flush=True)
 
 
+def anisotropy_report(steps: int = 3):
+    """Refinement 7 x 128 quadratic levels (41,943,040 unknowns), H = ratio x h_7
+    for ratio 1e-1, 1e-2, 1e-3, seeded uniform right-hand side: V-cycle rate
+    (FP64 and mixed), mixed and FP64 solve time, finest-sweep bandwidth."""
+    import numpy as np
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    for ratio in ("0.1", "0.01", "0.001"):
+        w = synth.workload(f"ico7_nz128_ar{ratio}")
+        line = {"workload": w.name, "unknowns": w.unknowns, "thickness_km": w.thickness * synth.R_EARTH_M / 1e3}
+        for name, fp32 in (("fp64", False), ("mixed", True)):
+            P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=fp32, use_graph=True)
+            geo = P.geometry()
+            f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
+            u0 = P.pack(synth.uniform_noise(w.n, w.nz, 7))
+            rate, _ = T.tpmg_richardson_rate(P.mg, u0, 12, 4)
+            u = P.device_vector()
+            P.solve(f, u)
+            times = []
+            for _ in range(steps):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it, rr, _, _ = P.solve(f, u)
+                times.append(time.perf_counter() - t0)
+            ms = 1000.0 * float(np.median(times))
+            sweep_ms, sweep_b = T.tpmg_mg_time_sweep(P.mg, 20)
+            line[name] = {"vcycle_rate": rate, "iters": it, "status": int(st), "relres": rr, "ms_per_solve": ms,
+                          "unknowns_per_s": w.unknowns / (ms / 1000.0), "finest_sweep_us": sweep_ms * 1000.0,
+                          "finest_sweep_GBs": sweep_b / (sweep_ms / 1000.0) / 1e9}
+            P.close()
+            del P, f, u, u0
+            torch.cuda.empty_cache()
+        print(json.dumps(line), flush=True)
+
+
+def batch_report(steps: int = 3):
+    """Sixteen solves of uneven size (refinement 4/5/6 x nz 32/64/128,
+    quadratic grading, seeded uniform right-hand sides, mixed precision):
+    one batched solve vs a loop of the sixteen single solves."""
+    import numpy as np
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    stream = torch.cuda.Stream()
+    ws = synth.batch_list()
+    probs, fs = [], []
+    for w in ws:
+        P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True, stream=stream)
+        geo = P.geometry()
+        fs.append(P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk())))
+        probs.append(P)
+    unknowns = sum(w.unknowns for w in ws)
+    us = [P.device_vector() for P in probs]
+
+    def sequential():
+        its = []
+        for P, f, u in zip(probs, fs, us):
+            u.zero_()
+            torch.cuda.synchronize()
+            st, it, *_ = P.solve(f, u)
+            its.append(it)
+        return its
+
+    sequential()
+    t_seq = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        its_seq = sequential()
+        t_seq.append(time.perf_counter() - t0)
+    mgs = [P.mg for P in probs]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    wsp = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, wsp.data_ptr() + (-wsp.data_ptr()) % 256, nbytes)
+    t_bat = []
+    for k in range(steps + 1):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, per, _ = T.tpmg_batch_solve(batch, fs, us, 1e-8, 100)
+        if k:
+            t_bat.append(time.perf_counter() - t0)
+    its_bat = [p[0] for p in per]
+    T.tpmg_batch_destroy(batch)
+    line = {"workload": "batch16: refinements 4/5/6 x nz 32/64/128 quadratic, mixed, rtol 1e-8",
+            "unknowns": unknowns, "status": int(st),
+            "batched_ms": 1000.0 * float(np.median(t_bat)), "sequential_ms": 1000.0 * float(np.median(t_seq)),
+            "batched_unknowns_per_s": unknowns / float(np.median(t_bat)),
+            "iters_batched": its_bat, "iters_single": its_seq}
+    line["speedup"] = line["sequential_ms"] / line["batched_ms"]
+    print(json.dumps(line), flush=True)
+    for P in probs:
+        P.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +212,8 @@ def main():
     ap.add_argument("--workload", default="ico6_nz128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=50)
+    ap.add_argument("--report", action="store_true",
+                    help="also measure the anisotropy sweep on the refinement-7 grid (one JSON line per ratio)")
     ap.add_argument("--profile-sweep", action="store_true",
                     help="only the finest-grid sweep timing loop (mixed) and a 512 MiB calibration copy, "
                          "for hardware-counter runs")
@@ -207,6 +311,12 @@ def main():
         log("timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(w, fp64["iters"])
     print(json.dumps(out), flush=True)
+    if args.report:
+        for P in (P64, P32):
+            P.close()
+        torch.cuda.empty_cache()
+        batch_report()
+        anisotropy_report()
 
 
 if __name__ == "__main__":

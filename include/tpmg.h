@@ -61,6 +61,7 @@ typedef enum {
 typedef struct tpmg_grid tpmg_grid;
 typedef struct tpmg_op tpmg_op;
 typedef struct tpmg_mg tpmg_mg;
+typedef struct tpmg_batch tpmg_batch;
 
 /* Multigrid parameters (Section 5: nu_pre = nu_post = 2, one coarse sweep). */
 typedef struct {
@@ -189,6 +190,42 @@ tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z);
  * NULL. */
 tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
                        tpmg_solve_info* info);
+
+/* ----------------------------------------------------------- batched -- */
+
+/* Several independent solves of uneven size advanced together: every step
+ * of the FCG iteration (each smoother sweep, transfer and BLAS-1 operation
+ * of the V-cycle of Algorithm 1, taken level by level from the finest grid
+ * down) is one grouped launch over all problems, the whole iteration is
+ * replayed as one HIP graph, and each problem stops when its own relative
+ * residual meets rtol (tested on the device; a finished problem's work is
+ * skipped). Each problem is computed with the block decomposition of its
+ * own tpmg_solve, so its iterates and iteration count equal those of a
+ * single solve. The problems must share one non-default stream, the
+ * precision and the smoother parameters, and have at least two levels and
+ * nz <= 128. The batch workspace (device, 256-byte aligned) holds the
+ * per-problem scalars and the launch tables; problems must outlive the
+ * batch. Errors: TPMG_ERR_ARG, TPMG_ERR_NOMEM. */
+tpmg_status tpmg_batch_workspace_size(tpmg_mg* const* problems, int n, size_t* bytes);
+tpmg_status tpmg_batch_create(tpmg_mg* const* problems, int n, void* d_workspace, size_t bytes, tpmg_batch** out);
+
+/* Solves problem p from the guess in d_u[p] with right-hand side d_f[p]
+ * (tiled FP64, as tpmg_solve). infos (optional) holds n entries. Returns
+ * TPMG_OK when all converged, TPMG_NOT_CONVERGED if one reached maxit,
+ * TPMG_ERR_BREAKDOWN if one broke down (its u holds its last finite
+ * iterate). Synchronises the stream once per iteration. */
+tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* const* d_u, double rtol, int maxit,
+                             tpmg_solve_info* infos);
+void tpmg_batch_destroy(tpmg_batch* b);
+
+/* Asymptotic V-cycle convergence factor (Section 6.1: the rate of the
+ * V-cycle in the Richardson iteration): runs u <- u + M(f - A u) with f = 0
+ * from the start vector in d_u (tiled FP64, overwritten by the last
+ * iterate), records ||r_i|| = ||A u_i|| for i = 0..cycles in norms
+ * (optional, cycles + 1 values) and returns
+ * rate = (||r_cycles|| / ||r_skip||)^(1 / (cycles - skip)).
+ * Requires 0 <= skip < cycles. Synchronises the stream. */
+tpmg_status tpmg_richardson_rate(tpmg_mg* mg, double* d_u, int cycles, int skip, double* rate, double* norms);
 
 /* Diagnostics: times `reps` back-to-back launches of one finest-grid
  * line-smoother sweep (the general form, reading u and f and writing u, in

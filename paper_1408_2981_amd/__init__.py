@@ -40,7 +40,8 @@ EXPORTED = [
     "tpmg_mg_params_default", "tpmg_grid_icosahedral", "tpmg_grid_level_size", "tpmg_grid_geometry",
     "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
     "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
-    "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_mg_time_sweep", "tpmg_grid_destroy", "tpmg_op_destroy",
+    "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
+    "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_grid_destroy", "tpmg_op_destroy",
     "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error",
 ]
 
@@ -90,6 +91,12 @@ _sig = {
     "tpmg_spmv": (_ip, [_vp, _vp, _vp]),
     "tpmg_vcycle": (_ip, [_vp, _vp, _vp]),
     "tpmg_solve": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
+    "tpmg_batch_workspace_size": (_ip, [ctypes.POINTER(_vp), _ip, ctypes.POINTER(ctypes.c_size_t)]),
+    "tpmg_batch_create": (_ip, [ctypes.POINTER(_vp), _ip, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "tpmg_batch_solve": (_ip, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_double, _ip,
+                               ctypes.POINTER(SolveInfo)]),
+    "tpmg_batch_destroy": (None, [_vp]),
+    "tpmg_richardson_rate": (_ip, [_vp, _vp, _ip, _ip, _dp, _dp]),
     "tpmg_mg_time_sweep": (_ip, [_vp, _ip, _dp, _dp]),
     "tpmg_grid_destroy": (None, [_vp]),
     "tpmg_op_destroy": (None, [_vp]),
@@ -252,6 +259,48 @@ def tpmg_solve(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 25
     s = _lib.tpmg_solve(mg, _dev(d_f), _dev(d_u), float(rtol), int(maxit), ctypes.byref(info))
     _check(s, ok=(TPMG_OK, TPMG_NOT_CONVERGED, TPMG_ERR_BREAKDOWN))
     return s, info.iters, info.relres, hist[: info.iters + 1].copy(), info.t_total_ms
+
+
+def _ptrs(handles):
+    return (_vp * len(handles))(*[_dev(h) for h in handles])
+
+
+def tpmg_batch_workspace_size(mgs) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.tpmg_batch_workspace_size(_ptrs(mgs), len(mgs), ctypes.byref(b)))
+    return b.value
+
+
+def tpmg_batch_create(mgs, workspace, nbytes: int) -> int:
+    h = _vp()
+    _check(_lib.tpmg_batch_create(_ptrs(mgs), len(mgs), _dev(workspace), nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def tpmg_batch_solve(batch: int, fs, us, rtol: float, maxit: int, history_cap: int = 256):
+    """Returns (status, [(iters, relres, history)], t_total_ms)."""
+    n = len(fs)
+    hists = [np.zeros(history_cap) for _ in range(n)]
+    infos = (SolveInfo * n)()
+    for i in range(n):
+        infos[i].history = hists[i].ctypes.data_as(_dp)
+        infos[i].history_cap = history_cap
+    s = _lib.tpmg_batch_solve(batch, _ptrs(fs), _ptrs(us), float(rtol), int(maxit), infos)
+    _check(s, ok=(TPMG_OK, TPMG_NOT_CONVERGED, TPMG_ERR_BREAKDOWN))
+    per = [(infos[i].iters, infos[i].relres, hists[i][: infos[i].iters + 1].copy()) for i in range(n)]
+    return s, per, infos[0].t_total_ms if n else 0.0
+
+
+def tpmg_batch_destroy(h):
+    _lib.tpmg_batch_destroy(h)
+
+
+def tpmg_richardson_rate(mg: int, d_u, cycles: int = 12, skip: int = 4):
+    """Returns (rate, norms[cycles + 1]); d_u is overwritten."""
+    rate = ctypes.c_double()
+    norms = np.zeros(cycles + 1)
+    _check(_lib.tpmg_richardson_rate(mg, _dev(d_u), cycles, skip, ctypes.byref(rate), _dptr(norms)))
+    return rate.value, norms
 
 
 def tpmg_mg_time_sweep(mg: int, reps: int):

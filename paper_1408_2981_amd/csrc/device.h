@@ -43,9 +43,46 @@ struct FcgScalars {
   double beta;
   double rr;      // <r, r>
   double ff;      // <f, f>
+  double rtol;    // stopping tolerance (set at kFinInit)
   int status;     // 0 ok, 1 breakdown
+  int done;       // converged or broken down: batched launches skip the problem
+  int iters;      // completed iterations (maintained on the device)
   int pad;
 };
+
+// Operations of one FCG iteration, as grouped by the batched executor.
+enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize };
+
+// One problem's part of a grouped launch (device memory, sorted by start).
+struct Seg {
+  int start;        // first block of this segment in the grouped grid (multiple of 8)
+  int nblocks;      // blocks of the problem's own launch (reduction width for finalize)
+  int chunk;        // levels per wave of the stencil kernels
+  int site;         // finalize site
+  LevelView L;      // level (the fine level for restriction and prolongation)
+  LevelView C;      // coarse level (restriction, prolongation)
+  const void* in0;  // smoother: f; restriction: f; prolongation: e; spmv: x; pupdate: z; update: p
+  const void* in1;  // smoother: u_in; restriction: u; update: q
+  void* out0;       // smoother: u_out; restriction: f_coarse; prolongation, spmv: y; pupdate: p; update: x
+  void* out1;       // smoother: fcopy; update: r
+  const double* q;  // smoother with fused dots
+  double* partials;
+  FcgScalars* sc;
+  size_t len;       // BLAS-1 vector length
+};
+
+// A grouped launch over the segments of several problems.
+struct BatchLaunch {
+  int kind;         // OpKind
+  int prec;         // 8 or 4 (V-cycle precision)
+  bool f_double, out_double, zero, fcopy, dots;   // smoother variant
+  double omega;
+  unsigned grid, block;
+  size_t lds;
+  const Seg* segs;  // device
+  int nseg;
+};
+hipError_t launch_batched(const BatchLaunch& b, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;   // fixed grid of the BLAS-1 reductions
 constexpr int kRedThreads = 256;
@@ -55,6 +92,8 @@ enum FinalizeSite { kFinInit = 0, kFinAlpha = 1, kFinRR = 2, kFinBeta = 3, kFinN
 
 int stencil_chunk(int npad, int nz);      // levels per wave of the stencil kernels
 size_t stencil_blocks(int npad, int nz);  // blocks of 256 threads of the stencil kernels
+int scan_waves(int nz);                   // waves per tile of the scan smoother
+unsigned pupdate_blocks(size_t len);      // blocks of the p-update kernel
 
 // All launchers enqueue on `s` and return hipGetLastError().
 // prec: 8 = double, 4 = float (the V-cycle precision of the level data).
@@ -65,7 +104,9 @@ size_t stencil_blocks(int npad, int nz);  // blocks of 256 threads of the stenci
 // mode 0: y = A x (partials <x, y>, e.g. site kFinAlpha). mode 1: y = b - A x
 // (partials <y, y>, <b, b>; site kFinInit). FP64; x and y must not alias.
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, int site, FcgScalars* sc, hipStream_t s);
+                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol = 0.0);
+// one-block finalisation of nblocks partials at `site` (rtol used at kFinInit)
+hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s);
 
 // One damped block-Jacobi sweep with the Thomas solve per column:
 // u_out = u_in + omega A_T^-1 (f - A u_in). zero_guess: u_in taken as 0
@@ -100,6 +141,7 @@ hipError_t launch_dots(const double* z, const double* q, const double* r, size_t
                        FcgScalars* sc, hipStream_t s);
 // p = z + beta p (beta from the scalars), in place.
 hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s);
+hipError_t launch_add(double* x, const double* y, size_t len, hipStream_t s);   // x += y
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);   // zero fill (graph-safe)
 
 // layout conversion of a finest-grid FP64 vector

@@ -9,6 +9,13 @@
 //   (A u)_k = bh bv_k u_k + av_k sum_j ah_j (u_k - u_{T_j,k})
 //           + arh (arv_{k+1} (u_k - u_{k+1}) + arv_k (u_k - u_{k-1}))
 // with bh, ah_j, arh per column and bv, av, arv per level.
+//
+// Every kernel of the solve is written as a device body that takes its
+// block's index and the block count of its problem's launch (GridPos). A
+// single-problem kernel passes (blockIdx.x, gridDim.x); a batched kernel
+// decodes its block from a table of segments, one per problem, and passes the
+// problem-local values, so each problem of a batch is computed with exactly
+// the block decomposition, and therefore the rounding, of its own solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +43,7 @@ struct Lv {
 };
 
 template <typename T>
-Lv<T> view(const LevelView& L) {
+__host__ __device__ Lv<T> view(const LevelView& L) {
   return Lv<T>{L.n,
                L.npad,
                L.nz,
@@ -49,6 +56,14 @@ Lv<T> view(const LevelView& L) {
                static_cast<const T*>(L.as_v),
                static_cast<const T*>(L.ar_v)};
 }
+
+// this block's index and the number of blocks of its problem's launch
+struct GridPos {
+  int b;
+  int nb;
+};
+
+__device__ __forceinline__ GridPos whole_grid() { return GridPos{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)}; }
 
 // per-column stencil data held in registers for a whole column sweep
 template <typename T>
@@ -90,8 +105,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // deterministic block sum of two values (blockDim.x a multiple of 64, at
-// most 16 waves); thread 0 writes out[2 * blockIdx.x + i]
-__device__ __forceinline__ void block_sums(double (&v)[2], double* __restrict__ out) {
+// most 16 waves); thread 0 writes out[2 * b + i]
+__device__ __forceinline__ void block_sums(double (&v)[2], double* __restrict__ out, int b) {
   __shared__ double red[16][2];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   v[0] = wave_sum(v[0]);
@@ -102,21 +117,23 @@ __device__ __forceinline__ void block_sums(double (&v)[2], double* __restrict__ 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
+    double a = 0.0, c = 0.0;
     for (int i = 0; i < nw; ++i) {
       a += red[i][0];
-      b += red[i][1];
+      c += red[i][1];
     }
-    out[2 * blockIdx.x] = a;
-    out[2 * blockIdx.x + 1] = b;
+    out[2 * b] = a;
+    out[2 * b + 1] = c;
   }
 }
 
 __device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
 
-// Scalar updates of the flexible-CG recurrence, applied by the last block of
-// a reduction to the deterministic sums (s0, s1) of all blocks' partials.
-__device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restrict__ sc) {
+// Scalar updates of the flexible-CG recurrence from the deterministic sums
+// (s0, s1) of all blocks' partials. done/iters serve batched solves, which
+// test convergence on the device (||r|| <= rtol ||f||, as the host does for a
+// single solve).
+__device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restrict__ sc, double rtol) {
   switch (site) {
     case kFinInit:
       sc->rr = s0;
@@ -125,12 +142,16 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       sc->rz = 0.0;
       sc->alpha = 0.0;
       sc->beta = 0.0;
-      sc->status = 0;
+      sc->rtol = rtol;
+      sc->iters = 0;
+      sc->status = (finite(s0) && finite(s1)) ? 0 : 1;
+      sc->done = (sc->status != 0 || sqrt(s0) <= rtol * sqrt(s1)) ? 1 : 0;
       break;
     case kFinAlpha:
       sc->pq = s0;
       if (!(s0 > 0.0) || !finite(s0) || !finite(sc->rz)) {
         sc->status = 1;
+        sc->done = 1;
         sc->alpha = 0.0;
       } else {
         sc->alpha = sc->rz / s0;
@@ -138,6 +159,13 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       break;
     case kFinRR:
       sc->rr = s0;
+      if (sc->status == 0) sc->iters += 1;
+      if (!finite(s0)) {
+        sc->status = 1;
+        sc->done = 1;
+      } else if (sqrt(s0) <= sc->rtol * sqrt(sc->ff)) {
+        sc->done = 1;
+      }
       break;
     case kFinBeta:
       sc->beta = -s0 / sc->pq;
@@ -148,13 +176,13 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
   }
 }
 
-// Single-block deterministic finalisation: sums the partials of nblocks
-// blocks in a fixed order and applies them to the FCG scalars. It runs as a
-// kernel of its own: on this GPU each XCD has its own L2, and a kernel
-// boundary is the cheap way to make all blocks' partials visible (a
-// device-scope fence per block would write back the whole L2).
-__global__ __launch_bounds__(256) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
-                                                  FcgScalars* __restrict__ sc) {
+// One block: sums the partials of nblocks blocks in a fixed order and
+// applies them to the scalars. It runs as a kernel of its own: on this GPU
+// each XCD has its own L2, and a kernel boundary is the cheap way to make
+// all blocks' partials visible (a device-scope fence per block would write
+// back the whole L2).
+__device__ __forceinline__ void finalize_body(int site, const double* __restrict__ partials, int nblocks,
+                                              FcgScalars* __restrict__ sc, double rtol) {
   double v[2] = {0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     v[0] += partials[2 * b];
@@ -171,7 +199,7 @@ __global__ __launch_bounds__(256) void k_finalize(int site, const double* __rest
   __syncthreads();
   if (threadIdx.x == 0)
     fcg_scalars(site, (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]),
-                (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]), sc);
+                (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]), sc, rtol);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,11 +210,11 @@ __global__ __launch_bounds__(256) void k_finalize(int site, const double* __rest
 // MODE 0: y = A x, partials <x, y>. MODE 1: y = b - A x, partials <y, y>,
 // <b, b>.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const double* __restrict__ x,
-                                                const double* __restrict__ b, double* __restrict__ y,
-                                                double* __restrict__ partials) {
+__device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk, const double* __restrict__ x,
+                                          const double* __restrict__ b, double* __restrict__ y,
+                                          double* __restrict__ partials, GridPos g) {
   const int nchunks = (L.nz + chunk - 1) / chunk;
-  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   double acc[2] = {0.0, 0.0};
   if (item < (L.npad >> 6) * nchunks) {
@@ -213,7 +241,7 @@ __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const d
       uc = up;
     }
   }
-  block_sums(acc, partials);
+  block_sums(acc, partials, g.b);
 }
 
 // Line smoother: damped block-Jacobi with a Thomas solve per column
@@ -223,7 +251,7 @@ __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const d
 // l_k = arh arv_k, m_k = arh arv_{k+1}), d_k = (r_k + l_k d_{k-1}) / p_k;
 // backward sweep x_k = d_k + (m_k / p_k) x_{k+1}, u_out = u_in + omega x.
 template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY>
-__global__ __launch_bounds__(64) void k_smooth(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
+__global__ __launch_bounds__(64) void k_smooth_fallback(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
                                                TO* __restrict__ u_out, T* __restrict__ fcopy,
                                                T* __restrict__ sd, T* __restrict__ sc, T omega) {
   const int lane = threadIdx.x;
@@ -428,18 +456,20 @@ __device__ __forceinline__ T rcp_of(T v) {
 }
 
 template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
-                                                      TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
-                                                      const double* __restrict__ q, double* __restrict__ partials) {
+__device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __restrict__ f, const T* __restrict__ u_in,
+                                                 TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
+                                                 const double* __restrict__ q, double* __restrict__ partials,
+                                                 GridPos g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nz = L.nz;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nw = blockDim.x >> 6;
+  // waves that own levels; a batched launch may give the block more (idle) waves
+  const int nw = (nz + kScanLevels - 1) / kScanLevels;
   // summaries: pivot map (4), elimination map (2), substitution map (2)
   T* __restrict__ sm = reinterpret_cast<T*>(smem);
   auto at = [&](int w, int q) -> T& { return sm[(static_cast<size_t>(w) * 8 + q) * kTile + lane]; };
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = xcd_tile(g.b, g.nb);
   const int col = tile * kTile + lane;
   const int kb = (nz + nw - 1) / nw;
   const int k0 = min(nz, wave * kb);
@@ -572,16 +602,17 @@ __global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restr
       }
     }
   }
-  if (DOTS) block_sums(acc, partials);
+  if (DOTS) block_sums(acc, partials, g.b);
 }
 
 // residual on the fine level, summed over the four children of each coarse
 // cell (Algorithm 1 residual + restriction by summation, Section 5)
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int chunk, int n_coarse, const T* __restrict__ f,
-                                                           const T* __restrict__ u, T* __restrict__ fc) {
+__device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk, int n_coarse,
+                                                       const T* __restrict__ f, const T* __restrict__ u,
+                                                       T* __restrict__ fc, GridPos g) {
   const int nchunks = (L.nz + chunk - 1) / chunk;
-  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (item >= (L.npad >> 6) * nchunks) return;
   const int tile = item / nchunks, chunk_i = item - tile * nchunks;
@@ -606,10 +637,10 @@ __global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int chunk, i
 
 // u_fine[c] += e_P + sum_j w_cj (e_{N_j(P)} - e_P), P = c / 4
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(Lv<T> F, Lv<T> C, int chunk, const T* __restrict__ e,
-                                                     T* __restrict__ u) {
+__device__ __forceinline__ void prolong_add_body(const Lv<T>& F, const Lv<T>& C, int chunk, const T* __restrict__ e,
+                                                 T* __restrict__ u, GridPos g) {
   const int nchunks = (F.nz + chunk - 1) / chunk;
-  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (item >= (F.npad >> 6) * nchunks) return;
   const int tile = item / nchunks, chunk_i = item - tile * nchunks;
@@ -633,44 +664,104 @@ __global__ __launch_bounds__(256) void k_prolong_add(Lv<T> F, Lv<T> C, int chunk
 }
 
 // ---------------------------------------------------------------------------
-// flexible-CG BLAS-1 with fixed-grid deterministic reductions
+// flexible-CG BLAS-1: grid-stride loops over the padded vector with a fixed
+// block count, deterministic reductions
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ p, const double* __restrict__ q,
-                                                    const FcgScalars* __restrict__ sc, size_t len,
-                                                    double* __restrict__ partials) {
+__device__ __forceinline__ void fcg_update_body(double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ q,
+                                                const FcgScalars* __restrict__ sc, size_t len,
+                                                double* __restrict__ partials, GridPos g) {
   const double alpha = sc->alpha;
   double acc[2] = {0.0, 0.0};
-  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+  for (size_t i = static_cast<size_t>(g.b) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(g.nb) * blockDim.x) {
     x[i] = x[i] + alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     acc[0] += ri * ri;
   }
-  block_sums(acc, partials);
+  block_sums(acc, partials, g.b);
 }
 
 // <z, q>, <z, r> for the case where the smoother cannot fuse them
-__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, const double* __restrict__ q,
-                                              const double* __restrict__ r, size_t len, double* __restrict__ partials) {
+__device__ __forceinline__ void dots_body(const double* __restrict__ z, const double* __restrict__ q,
+                                          const double* __restrict__ r, size_t len, double* __restrict__ partials,
+                                          GridPos g) {
   double acc[2] = {0.0, 0.0};
-  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+  for (size_t i = static_cast<size_t>(g.b) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(g.nb) * blockDim.x) {
     const double zi = z[i];
     acc[0] += zi * q[i];
     acc[1] += zi * r[i];
   }
-  block_sums(acc, partials);
+  block_sums(acc, partials, g.b);
+}
+
+__device__ __forceinline__ void pupdate_body(const double* __restrict__ z, double* __restrict__ p,
+                                             const FcgScalars* __restrict__ sc, size_t len, GridPos g) {
+  const double beta = sc->beta;
+  for (size_t i = static_cast<size_t>(g.b) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(g.nb) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// single-problem kernels
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
+                                                  FcgScalars* __restrict__ sc, double rtol) {
+  finalize_body(site, partials, nblocks, sc, rtol);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const double* __restrict__ x,
+                                                const double* __restrict__ b, double* __restrict__ y,
+                                                double* __restrict__ partials) {
+  spmv_body<MODE>(L, chunk, x, b, y, partials, whole_grid());
+}
+
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+__global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
+                                                      TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
+                                                      const double* __restrict__ q, double* __restrict__ partials) {
+  smooth_scan_body<T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int chunk, int n_coarse, const T* __restrict__ f,
+                                                           const T* __restrict__ u, T* __restrict__ fc) {
+  residual_restrict_body<T>(L, chunk, n_coarse, f, u, fc, whole_grid());
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(Lv<T> F, Lv<T> C, int chunk, const T* __restrict__ e,
+                                                     T* __restrict__ u) {
+  prolong_add_body<T>(F, C, chunk, e, u, whole_grid());
+}
+
+__global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const FcgScalars* __restrict__ sc, size_t len,
+                                                    double* __restrict__ partials) {
+  fcg_update_body(x, r, p, q, sc, len, partials, whole_grid());
+}
+
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, const double* __restrict__ q,
+                                              const double* __restrict__ r, size_t len, double* __restrict__ partials) {
+  dots_body(z, q, r, len, partials, whole_grid());
 }
 
 __global__ __launch_bounds__(256) void k_pupdate(const double* __restrict__ z, double* __restrict__ p,
                                                  const FcgScalars* __restrict__ sc, size_t len) {
-  const double beta = sc->beta;
+  pupdate_body(z, p, sc, len, whole_grid());
+}
+
+__global__ __launch_bounds__(256) void k_add(double* __restrict__ x, const double* __restrict__ y, size_t len) {
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
        i += static_cast<size_t>(gridDim.x) * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+    x[i] = x[i] + y[i];
 }
 
 __global__ __launch_bounds__(256) void k_fill(uint32_t* __restrict__ p, size_t words) {
@@ -699,6 +790,85 @@ __global__ __launch_bounds__(256) void k_unpack(const double* __restrict__ tiled
   }
 }
 
+// ---------------------------------------------------------------------------
+// batched kernels: one grouped launch covers several problems. segs[] is
+// sorted by start; every segment starts at a multiple of 8 blocks, so the
+// XCD of a block (blockIdx.x mod 8) equals that of its problem-local index.
+// Problems whose scalars are marked done are skipped.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ const Seg* find_segment(const Seg* __restrict__ segs, int nseg, GridPos& g) {
+  const int b = blockIdx.x;
+  int s = 0;
+  for (int i = 1; i < nseg; ++i)
+    if (segs[i].start <= b) s = i;
+  const Seg* sg = &segs[s];
+  g.b = b - sg->start;
+  g.nb = sg->nblocks;
+  if (g.b >= g.nb) return nullptr;                      // alignment padding
+  if (sg->sc != nullptr && sg->sc->done) return nullptr;  // converged problem
+  return sg;
+}
+
+template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+__global__ __launch_bounds__(1024) void kb_smooth_scan(const Seg* __restrict__ segs, int nseg, double omega) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  smooth_scan_body<T, TF, TO, ZERO, FCOPY, DOTS>(view<T>(sg->L), static_cast<const TF*>(sg->in0),
+                                                 static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
+                                                 static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q,
+                                                 sg->partials, g);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_residual_restrict(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  residual_restrict_body<T>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
+                            static_cast<const T*>(sg->in1), static_cast<T*>(sg->out0), g);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_prolong_add(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  prolong_add_body<T>(view<T>(sg->L), view<T>(sg->C), sg->chunk, static_cast<const T*>(sg->in0),
+                      static_cast<T*>(sg->out0), g);
+}
+
+__global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  spmv_body<0>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
+               static_cast<double*>(sg->out0), sg->partials, g);
+}
+
+__global__ __launch_bounds__(256) void kb_pupdate(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  pupdate_body(static_cast<const double*>(sg->in0), static_cast<double*>(sg->out0), sg->sc, sg->len, g);
+}
+
+__global__ __launch_bounds__(256) void kb_fcg_update(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  fcg_update_body(static_cast<double*>(sg->out0), static_cast<double*>(sg->out1), static_cast<const double*>(sg->in0),
+                  static_cast<const double*>(sg->in1), sg->sc, sg->len, sg->partials, g);
+}
+
+// one block per problem
+__global__ __launch_bounds__(256) void kb_finalize(const Seg* __restrict__ segs, int nseg) {
+  const Seg* sg = &segs[blockIdx.x];
+  if (sg->sc->done) return;
+  finalize_body(sg->site, sg->partials, sg->nblocks, sg->sc, 0.0);
+}
+
 unsigned grid_for(size_t work, unsigned cap) {
   size_t b = (work + 255) / 256;
   if (b < 1) b = 1;
@@ -706,6 +876,10 @@ unsigned grid_for(size_t work, unsigned cap) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
 
 int stencil_chunk(int npad, int nz) {
   // largest levels-per-wave that still gives >= 4096 waves (latency hiding on
@@ -722,8 +896,17 @@ size_t stencil_blocks(int npad, int nz) {
   return (waves + 3) / 4;
 }
 
+int scan_waves(int nz) { return (nz + kScanLevels - 1) / kScanLevels; }
+bool smooth_supports_dots(int nz) { return nz <= kScanLevels * kScanWaves; }
+unsigned pupdate_blocks(size_t len) { return grid_for(len, 2048); }
+
+hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, nblocks, sc, rtol);
+  return hipGetLastError();
+}
+
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, int site, FcgScalars* sc, hipStream_t s) {
+                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol) {
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
   const int chunk = stencil_chunk(L.npad, L.nz);
   const Lv<double> V = view<double>(L);
@@ -732,7 +915,7 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
   else
     hipLaunchKernelGGL(k_spmv64<1>, dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
   if (site != kFinNone)
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol);
   return hipGetLastError();
 }
 
@@ -751,13 +934,13 @@ static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, 
                        hipStream_t s) {
   const unsigned ntiles = static_cast<unsigned>(L.npad / kTile);
   if (L.nz <= kScanLevels * kScanWaves) {
-    const int waves = (L.nz + kScanLevels - 1) / kScanLevels;
+    const int waves = scan_waves(L.nz);
     const size_t sl = static_cast<size_t>(waves) * 8 * kTile * sizeof(T);
     hipLaunchKernelGGL((k_smooth_scan<T, TF, TO, ZERO, FCOPY, DOTS>), dim3(ntiles), dim3(64 * waves), sl, s, L, f, ui,
                        uo, fc, om, da.q, da.partials);
     if (DOTS)
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), da.partials,
-                         static_cast<int>(ntiles), da.sc);
+                         static_cast<int>(ntiles), da.sc, 0.0);
     return;
   }
   // dots are only requested for nz within the scan kernel's range
@@ -767,10 +950,12 @@ static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, 
     hipLaunchKernelGGL((k_smooth_lds<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(64 * waves), lds, s, L, f, ui, uo, fc,
                        om);
   } else {
-    hipLaunchKernelGGL((k_smooth<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(kTile), 0, s, L, f, ui, uo, fc, d, c, om);
+    hipLaunchKernelGGL((k_smooth_fallback<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(kTile), 0, s, L, f, ui, uo, fc,
+                       d, c, om);
   }
 }
 
+// (f type, out type, zero guess, f copy, dots) combinations used by the V-cycle
 template <typename T>
 static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const void* u_in, bool zero, void* u_out,
                      bool out_double, void* fcopy, void* sd, void* sc, double omega, const DotArgs& da, hipStream_t s) {
@@ -781,7 +966,6 @@ static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const vo
   T* c = static_cast<T*>(sc);
   const T om = static_cast<T>(omega);
   const bool dots = da.q != nullptr;
-  // (f type, out type, zero guess, f copy, dots) combinations used by the V-cycle
   if (f_double) {
     const double* ff = static_cast<const double*>(f);
     if (out_double) {
@@ -833,8 +1017,6 @@ hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_dou
   return hipGetLastError();
 }
 
-bool smooth_supports_dots(int nz) { return nz <= kScanLevels * kScanWaves; }
-
 hipError_t set_max_lds(size_t bytes) {
   g_max_lds = bytes;
   return hipSuccess;
@@ -869,19 +1051,24 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, 
 hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, FcgScalars* sc, size_t len,
                              double* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0);
   return hipGetLastError();
 }
 
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, z, q, r, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0);
   return hipGetLastError();
 }
 
 hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s) {
-  hipLaunchKernelGGL(k_pupdate, dim3(grid_for(len, 2048)), dim3(256), 0, s, z, p, sc, len);
+  hipLaunchKernelGGL(k_pupdate, dim3(pupdate_blocks(len)), dim3(256), 0, s, z, p, sc, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(double* x, const double* y, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_add, dim3(grid_for(len, 2048)), dim3(256), 0, s, x, y, len);
   return hipGetLastError();
 }
 
@@ -900,6 +1087,79 @@ hipError_t launch_pack(const double* cm, double* tiled, int n, int npad, int nz,
 hipError_t launch_unpack(const double* tiled, double* cm, int n, int npad, int nz, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack, dim3(grid_for(static_cast<size_t>(n) * nz, 4096)), dim3(256), 0, s, tiled, cm, n,
                      nz);
+  return hipGetLastError();
+}
+
+// ---- batched launches -----------------------------------------------------
+
+template <typename T>
+static hipError_t batched_smooth_t(const BatchLaunch& b, hipStream_t s) {
+  const dim3 grid(b.grid), block(b.block);
+  const size_t lds = b.lds;
+  const double om = b.omega;
+  const bool zero = b.zero, fcopy = b.fcopy, dots = b.dots;
+  if (b.f_double && b.out_double) {
+    if (dots && zero)
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, true, false, true>), grid, block, lds, s, b.segs, b.nseg, om);
+    else if (dots)
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, false, false, true>), grid, block, lds, s, b.segs, b.nseg, om);
+    else if (zero)
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+    else
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+  } else if (b.f_double) {
+    if (zero && fcopy)
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, T, true, true, false>), grid, block, lds, s, b.segs, b.nseg, om);
+    else if (zero)
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, T, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+    else
+      hipLaunchKernelGGL((kb_smooth_scan<T, double, T, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+  } else if (b.out_double) {
+    if (zero)
+      hipLaunchKernelGGL((kb_smooth_scan<T, T, double, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+    else
+      hipLaunchKernelGGL((kb_smooth_scan<T, T, double, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+  } else {
+    if (zero)
+      hipLaunchKernelGGL((kb_smooth_scan<T, T, T, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+    else
+      hipLaunchKernelGGL((kb_smooth_scan<T, T, T, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
+  switch (b.kind) {
+    case kOpSmooth:
+      if (b.prec == 8) return batched_smooth_t<double>(b, s);
+      return batched_smooth_t<float>(b, s);
+    case kOpRestrict:
+      if (b.prec == 8)
+        hipLaunchKernelGGL(kb_residual_restrict<double>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      else
+        hipLaunchKernelGGL(kb_residual_restrict<float>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      break;
+    case kOpProlong:
+      if (b.prec == 8)
+        hipLaunchKernelGGL(kb_prolong_add<double>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      else
+        hipLaunchKernelGGL(kb_prolong_add<float>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      break;
+    case kOpSpmv:
+      hipLaunchKernelGGL(kb_spmv64, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      break;
+    case kOpPupdate:
+      hipLaunchKernelGGL(kb_pupdate, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      break;
+    case kOpUpdate:
+      hipLaunchKernelGGL(kb_fcg_update, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      break;
+    case kOpFinalize:
+      hipLaunchKernelGGL(kb_finalize, dim3(b.nseg), dim3(256), 0, s, b.segs, b.nseg);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

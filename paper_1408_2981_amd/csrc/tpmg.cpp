@@ -199,85 +199,389 @@ hipError_t upload(void* dst, const std::vector<T>& v, hipStream_t s) {
   return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
-// ---- V-cycle (Algorithm 1) -------------------------------------------------
+// ---- V-cycle (Algorithm 1) and the FCG iteration as lists of operations -----
 //
+// Each operation carries its place in the lockstep schedule (order), so the
+// same list serves a single solve (executed in program order) and a batch of
+// solves (operations of all problems with the same order become one grouped
+// launch).
+struct Op {
+  int order[4] = {0, 0, 0, 0};
+  int kind = tpmg::kOpSmooth;
+  int prec = 8;
+  bool f_double = false, zero = false, out_double = false, fcopy = false, dots = false;
+  double omega = 0.0;
+  tpmg::LevelView L, C;
+  const void* in0 = nullptr;
+  const void* in1 = nullptr;
+  void* out0 = nullptr;
+  void* out1 = nullptr;
+  const double* q = nullptr;
+  double* partials = nullptr;
+  tpmg::FcgScalars* sc = nullptr;
+  int site = tpmg::kFinNone;
+  size_t len = 0;
+  void* scratch_d = nullptr;   // fallback smoother only
+  void* scratch_c = nullptr;
+};
+
+bool order_less(const Op& a, const Op& b) {
+  for (int i = 0; i < 4; ++i)
+    if (a.order[i] != b.order[i]) return a.order[i] < b.order[i];
+  return false;
+}
+
 // Level l > 0: nu_pre sweeps (the first from a zero guess), residual +
 // restriction to level l-1, recursion from a zero guess, prolongation +
 // correction, nu_post sweeps. Level 0: nu_coarse sweeps from zero. In the
 // mixed mode every level is FP32: the first finest sweep reads the FP64
-// residual and keeps an FP32 copy of it, the last writes FP64 z.
-hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out, const double* q_dots = nullptr) {
+// residual and keeps an FP32 copy of it, the last writes FP64 z (and, when
+// q_dots is given, also forms <z, q> and <z, r>, applied at kFinBeta).
+void vcycle_ops(tpmg_mg& m, const double* r_in, double* z_out, const double* q_dots, tpmg::FcgScalars* sc,
+                std::vector<Op>& ops) {
   const int L = m.nlev - 1;
   const int prec = m.fp32 ? 4 : 8;
-  hipStream_t s = m.stream;
   std::vector<int> cur(m.nlev, 0);
-  hipError_t e;
-  // right-hand side of level l
   auto rhs = [&](int l) -> const void* {
     if (l < L) return m.lv[l].f;
     return m.fp32 ? static_cast<const void*>(m.fcopy) : static_cast<const void*>(r_in);
   };
+  auto sweep = [&](int o0, int o1, int o2, int o3, int l, const void* f, bool f_double, bool zero, void* out,
+                   bool out_double, bool fcopy, bool dots) {
+    Op op;
+    op.order[0] = o0;
+    op.order[1] = o1;
+    op.order[2] = o2;
+    op.order[3] = o3;
+    op.kind = tpmg::kOpSmooth;
+    op.prec = prec;
+    op.f_double = f_double;
+    op.zero = zero;
+    op.out_double = out_double;
+    op.fcopy = fcopy;
+    op.dots = dots;
+    op.omega = m.omega;
+    op.L = m.view(l);
+    op.in0 = f;
+    op.in1 = m.lv[l].u[cur[l]];
+    op.out0 = out;
+    op.out1 = fcopy ? m.fcopy : nullptr;
+    op.q = dots ? q_dots : nullptr;
+    op.partials = m.partials;
+    op.sc = sc;
+    op.site = dots ? tpmg::kFinBeta : tpmg::kFinNone;
+    op.scratch_d = m.sd;
+    op.scratch_c = m.sc;
+    ops.push_back(op);
+  };
   for (int l = L; l >= 0; --l) {
-    const tpmg::LevelView V = m.view(l);
+    const int j = L - l;
     const int sweeps = l == 0 ? m.nu_coarse : m.nu_pre;
     for (int k = 0; k < sweeps; ++k) {
       const bool first = k == 0;
       const bool finest_first = first && l == L;
       const bool last_of_cycle = (l == 0 && L == 0 && k + 1 == sweeps);
-      const void* f = finest_first ? static_cast<const void*>(r_in) : rhs(l);
-      const bool f_double = (l == L) && (finest_first || !m.fp32);
-      void* out = last_of_cycle ? static_cast<void*>(z_out) : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
       const bool dots = last_of_cycle && q_dots;
-      e = tpmg::launch_smooth(V, prec, dots ? static_cast<const void*>(r_in) : f, dots || f_double,
-                              m.lv[l].u[cur[l]], first, out, last_of_cycle,
-                              (finest_first && m.fp32) ? m.fcopy : nullptr, m.sd, m.sc, m.omega, s,
-                              dots ? q_dots : nullptr, m.partials, m.scal);
-      if (e != hipSuccess) return e;
+      const void* f = (finest_first || dots) ? static_cast<const void*>(r_in) : rhs(l);
+      const bool f_double = dots || ((l == L) && (finest_first || !m.fp32));
+      void* out = last_of_cycle ? static_cast<void*>(z_out) : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
+      sweep(0, j, 0, k, l, f, f_double, first, out, last_of_cycle, finest_first && m.fp32, dots);
       if (!first) cur[l] = 1 - cur[l];
     }
     if (l > 0) {
-      const tpmg::LevelView C = m.view(l - 1);
-      e = tpmg::launch_residual_restrict(V, C, prec, rhs(l), m.lv[l].u[cur[l]], m.lv[l - 1].f, s);
-      if (e != hipSuccess) return e;
+      Op op;
+      op.order[0] = 0;
+      op.order[1] = j;
+      op.order[2] = 1;
+      op.kind = tpmg::kOpRestrict;
+      op.prec = prec;
+      op.L = m.view(l);
+      op.C = m.view(l - 1);
+      op.in0 = rhs(l);
+      op.in1 = m.lv[l].u[cur[l]];
+      op.out0 = m.lv[l - 1].f;
+      ops.push_back(op);
     }
   }
   for (int l = 1; l <= L; ++l) {
-    const tpmg::LevelView V = m.view(l);
-    e = tpmg::launch_prolong_add(V, m.view(l - 1), prec, m.lv[l - 1].u[cur[l - 1]], m.lv[l].u[cur[l]], s);
-    if (e != hipSuccess) return e;
+    const int j = L - l;
+    Op op;
+    op.order[0] = 1;
+    op.order[1] = -j;
+    op.kind = tpmg::kOpProlong;
+    op.prec = prec;
+    op.L = m.view(l);
+    op.C = m.view(l - 1);
+    op.in0 = m.lv[l - 1].u[cur[l - 1]];
+    op.out0 = m.lv[l].u[cur[l]];
+    ops.push_back(op);
     for (int k = 0; k < m.nu_post; ++k) {
       const bool last = l == L && k + 1 == m.nu_post;
       void* out = last ? static_cast<void*>(z_out) : m.lv[l].u[1 - cur[l]];
       // the last sweep reads the FP64 residual when it also forms <z, q>, <z, r>
       const bool dots = last && q_dots;
-      e = tpmg::launch_smooth(V, prec, dots ? static_cast<const void*>(r_in) : rhs(l), dots || (l == L && !m.fp32),
-                              m.lv[l].u[cur[l]], false, out, last, nullptr, m.sd, m.sc, m.omega, s,
-                              dots ? q_dots : nullptr, m.partials, m.scal);
-      if (e != hipSuccess) return e;
+      sweep(1, -j, 1, k, l, dots ? static_cast<const void*>(r_in) : rhs(l), dots || (l == L && !m.fp32), false, out,
+            last, false, dots);
       if (!last) cur[l] = 1 - cur[l];
     }
   }
-  return hipSuccess;
 }
 
 // One FCG iteration after the convergence test of the previous one:
 //   z = M r, with beta = -<z,q>/<p,q> and rz = <z,r> formed by the last sweep;
 //   p = z + beta p; q = A p, alpha = rz/<p,q>;
 //   x += alpha p, r -= alpha q, rr = <r,r>.
-hipError_t fcg_iteration(tpmg_mg& m, double* x) {
-  hipError_t e;
-  hipStream_t s = m.stream;
-  if (tpmg::smooth_supports_dots(m.nz)) {
-    if ((e = vcycle(m, m.r, m.z, m.q)) != hipSuccess) return e;
-  } else {
-    if ((e = vcycle(m, m.r, m.z)) != hipSuccess) return e;
-    if ((e = tpmg::launch_dots(m.z, m.q, m.r, m.len, m.partials, m.scal, s)) != hipSuccess) return e;
+// With nz beyond the fused smoother's range the dots are a separate op
+// (kind -1, single solves only).
+void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) {
+  const bool fused = tpmg::smooth_supports_dots(m.nz);
+  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops);
+  if (!fused) {
+    Op d;
+    d.order[0] = 2;
+    d.kind = -1;
+    d.in0 = m.z;
+    d.in1 = m.q;
+    d.out0 = m.r;
+    d.partials = m.partials;
+    d.sc = sc;
+    d.len = m.len;
+    ops.push_back(d);
   }
-  if ((e = tpmg::launch_pupdate(m.z, m.p, m.scal, m.len, s)) != hipSuccess) return e;
-  const tpmg::LevelView F = m.view64(m.nlev - 1);
-  if ((e = tpmg::launch_spmv64(F, 0, m.p, nullptr, m.q, m.partials, tpmg::kFinAlpha, m.scal, s)) != hipSuccess)
-    return e;
-  return tpmg::launch_fcg_update(x, m.r, m.p, m.q, m.scal, m.len, m.partials, s);
+  Op pu;
+  pu.order[0] = 2;
+  pu.order[1] = 1;
+  pu.kind = tpmg::kOpPupdate;
+  pu.in0 = m.z;
+  pu.out0 = m.p;
+  pu.sc = sc;
+  pu.len = m.len;
+  ops.push_back(pu);
+  Op sp;
+  sp.order[0] = 2;
+  sp.order[1] = 2;
+  sp.kind = tpmg::kOpSpmv;
+  sp.L = m.view64(m.nlev - 1);
+  sp.in0 = m.p;
+  sp.out0 = m.q;
+  sp.partials = m.partials;
+  sp.sc = sc;
+  sp.site = tpmg::kFinAlpha;
+  ops.push_back(sp);
+  Op up;
+  up.order[0] = 2;
+  up.order[1] = 3;
+  up.kind = tpmg::kOpUpdate;
+  up.in0 = m.p;
+  up.in1 = m.q;
+  up.out0 = x;
+  up.out1 = m.r;
+  up.partials = m.partials;
+  up.sc = sc;
+  up.site = tpmg::kFinRR;
+  up.len = m.len;
+  ops.push_back(up);
+}
+
+// executes one operation with the single-problem launchers (which also run
+// the finalize kernel of a reducing operation)
+hipError_t exec_op(const Op& op, hipStream_t s) {
+  switch (op.kind) {
+    case tpmg::kOpSmooth:
+      return tpmg::launch_smooth(op.L, op.prec, op.in0, op.f_double, op.in1, op.zero, op.out0, op.out_double, op.out1,
+                                 op.scratch_d, op.scratch_c, op.omega, s, op.q, op.partials, op.sc);
+    case tpmg::kOpRestrict:
+      return tpmg::launch_residual_restrict(op.L, op.C, op.prec, op.in0, op.in1, op.out0, s);
+    case tpmg::kOpProlong:
+      return tpmg::launch_prolong_add(op.L, op.C, op.prec, op.in0, op.out0, s);
+    case tpmg::kOpPupdate:
+      return tpmg::launch_pupdate(static_cast<const double*>(op.in0), static_cast<double*>(op.out0), op.sc, op.len, s);
+    case tpmg::kOpSpmv:
+      return tpmg::launch_spmv64(op.L, 0, static_cast<const double*>(op.in0), nullptr, static_cast<double*>(op.out0),
+                                 op.partials, op.site, op.sc, s);
+    case tpmg::kOpUpdate:
+      return tpmg::launch_fcg_update(static_cast<double*>(op.out0), static_cast<double*>(op.out1),
+                                     static_cast<const double*>(op.in0), static_cast<const double*>(op.in1), op.sc,
+                                     op.len, op.partials, s);
+    case -1:
+      return tpmg::launch_dots(static_cast<const double*>(op.in0), static_cast<const double*>(op.in1),
+                               static_cast<const double*>(op.out0), op.len, op.partials, op.sc, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
+  std::vector<Op> ops;
+  vcycle_ops(m, r_in, z_out, nullptr, m.scal, ops);
+  for (const Op& op : ops) {
+    hipError_t e = exec_op(op, m.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t fcg_iteration(tpmg_mg& m, double* x) {
+  std::vector<Op> ops;
+  fcg_ops(m, x, m.scal, ops);
+  for (const Op& op : ops) {
+    hipError_t e = exec_op(op, m.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+struct tpmg_batch {
+  std::vector<tpmg_mg*> probs;
+  hipStream_t stream = nullptr;
+  tpmg::FcgScalars* scal = nullptr;     // device, one per problem
+  tpmg::FcgScalars* h_scal = nullptr;   // pinned host mirror
+  tpmg::Seg* segs = nullptr;            // device segment tables
+  size_t max_segs = 0;
+  std::vector<tpmg::BatchLaunch> plan;
+  std::vector<double*> plan_u;          // solution vectors the plan was built for
+  hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+// Groups the FCG-iteration operations of all problems by schedule position:
+// one grouped launch per position, followed by a grouped finalize where the
+// operation reduces. Returns the number of segments; with upload == false it
+// only counts them.
+hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* nsegs_out) {
+  struct Item {
+    Op op;
+    int prob;
+  };
+  std::vector<Item> items;
+  for (size_t p = 0; p < b.probs.size(); ++p) {
+    std::vector<Op> ops;
+    fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops);
+    for (const Op& op : ops) items.push_back({op, static_cast<int>(p)});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& c) { return order_less(a.op, c.op); });
+  std::vector<tpmg::Seg> host;
+  std::vector<tpmg::BatchLaunch> plan;
+  std::vector<size_t> seg_offset;   // first segment of each launch
+  size_t i = 0;
+  while (i < items.size()) {
+    size_t j = i;
+    while (j < items.size() && !order_less(items[i].op, items[j].op) && !order_less(items[j].op, items[i].op)) ++j;
+    const Op& o = items[i].op;
+    tpmg::BatchLaunch L{};
+    L.kind = o.kind;
+    L.prec = o.prec;
+    L.f_double = o.f_double;
+    L.out_double = o.out_double;
+    L.zero = o.zero;
+    L.fcopy = o.fcopy;
+    L.dots = o.dots;
+    L.omega = o.omega;
+    L.block = 256;
+    tpmg::BatchLaunch F{};
+    F.kind = tpmg::kOpFinalize;
+    const bool reduces = o.site != tpmg::kFinNone;
+    const size_t first = host.size();
+    std::vector<tpmg::Seg> fin;
+    unsigned start = 0;
+    for (size_t k = i; k < j; ++k) {
+      const Op& a = items[k].op;
+      if (a.kind != o.kind || a.prec != o.prec || a.f_double != o.f_double || a.out_double != o.out_double ||
+          a.zero != o.zero || a.fcopy != o.fcopy || a.dots != o.dots)
+        return hipErrorInvalidValue;   // problems disagree on the schedule
+      tpmg::Seg g{};
+      g.site = a.site;
+      g.L = a.L;
+      g.C = a.C;
+      g.in0 = a.in0;
+      g.in1 = a.in1;
+      g.out0 = a.out0;
+      g.out1 = a.out1;
+      g.q = a.q;
+      g.partials = a.partials;
+      g.sc = a.sc;
+      g.len = a.len;
+      int nb = 0;
+      switch (a.kind) {
+        case tpmg::kOpSmooth: {
+          nb = a.L.npad / tpmg::kTile;
+          const int waves = tpmg::scan_waves(a.L.nz);
+          L.block = std::max(L.block, static_cast<unsigned>(64 * waves));
+          break;
+        }
+        case tpmg::kOpRestrict:
+        case tpmg::kOpProlong:
+        case tpmg::kOpSpmv:
+          nb = static_cast<int>(tpmg::stencil_blocks(a.L.npad, a.L.nz));
+          g.chunk = tpmg::stencil_chunk(a.L.npad, a.L.nz);
+          break;
+        case tpmg::kOpPupdate:
+          nb = static_cast<int>(tpmg::pupdate_blocks(a.len));
+          break;
+        case tpmg::kOpUpdate:
+          nb = tpmg::kRedBlocks;
+          break;
+        default:
+          return hipErrorInvalidValue;   // unfused dots: nz beyond the scan smoother
+      }
+      g.start = static_cast<int>(start);
+      g.nblocks = nb;
+      start += (static_cast<unsigned>(nb) + 7u) / 8u * 8u;
+      host.push_back(g);
+      if (reduces) {
+        tpmg::Seg f = g;
+        f.start = static_cast<int>(fin.size());
+        fin.push_back(f);
+      }
+    }
+    L.grid = start;
+    L.nseg = static_cast<int>(j - i);
+    // every wave of the block, idle or not, publishes its 8 summaries
+    if (o.kind == tpmg::kOpSmooth) L.lds = static_cast<size_t>(L.block / 64) * 8 * tpmg::kTile * static_cast<size_t>(o.prec);
+    seg_offset.push_back(first);
+    plan.push_back(L);
+    if (reduces) {
+      F.nseg = static_cast<int>(fin.size());
+      F.grid = static_cast<unsigned>(fin.size());
+      F.block = 256;
+      seg_offset.push_back(host.size());
+      host.insert(host.end(), fin.begin(), fin.end());
+      plan.push_back(F);
+    }
+    i = j;
+  }
+  if (nsegs_out) *nsegs_out = host.size();
+  if (!upload) return hipSuccess;
+  if (host.size() > b.max_segs) return hipErrorInvalidValue;
+  for (size_t k = 0; k < plan.size(); ++k) plan[k].segs = b.segs + seg_offset[k];
+  hipError_t e = hipMemcpyAsync(b.segs, host.data(), host.size() * sizeof(tpmg::Seg), hipMemcpyHostToDevice, b.stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(b.stream);
+  if (e != hipSuccess) return e;
+  b.plan = std::move(plan);
+  return hipSuccess;
+}
+
+tpmg_status check_batch(tpmg_mg* const* problems, int n) {
+  if (!problems || n < 1) return fail(TPMG_ERR_ARG, "need at least one problem");
+  const tpmg_mg* a = problems[0];
+  for (int i = 0; i < n; ++i) {
+    const tpmg_mg* m = problems[i];
+    if (!m) return fail(TPMG_ERR_ARG, "NULL problem");
+    if (m->nlev < 2) return fail(TPMG_ERR_ARG, "batched problems need at least 2 multigrid levels");
+    if (!tpmg::smooth_supports_dots(m->nz)) return fail(TPMG_ERR_ARG, "batched problems need nz <= 128");
+    if (m->fp32 != a->fp32 || m->nu_pre != a->nu_pre || m->nu_post != a->nu_post || m->nu_coarse != a->nu_coarse ||
+        m->omega != a->omega)
+      return fail(TPMG_ERR_ARG, "batched problems must share precision and smoother parameters");
+    if (m->stream != a->stream || m->stream == nullptr)
+      return fail(TPMG_ERR_ARG, "batched problems must share one non-default stream");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == m) return fail(TPMG_ERR_ARG, "a problem appears twice in the batch");
+  }
+  return TPMG_OK;
 }
 
 void drop_graph(tpmg_mg& m) {
@@ -599,7 +903,7 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   hipStream_t s = mg->stream;
   const tpmg::LevelView F = mg->view64(mg->nlev - 1);
   // r = f - A u, rr, ff; p = q = 0 so that the first iteration takes beta = 0
-  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s));
+  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol));
   TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
   TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
   TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
@@ -672,6 +976,32 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   return result;
 }
 
+tpmg_status tpmg_richardson_rate(tpmg_mg* mg, double* d_u, int cycles, int skip, double* rate, double* norms) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_u || !rate) return fail(TPMG_ERR_ARG, "NULL argument");
+  if (skip < 0 || cycles <= skip) return fail(TPMG_ERR_ARG, "need 0 <= skip < cycles");
+  hipStream_t s = mg->stream;
+  const tpmg::LevelView F = mg->view64(mg->nlev - 1);
+  // p holds the zero right-hand side, r the residual -A u, z the correction
+  TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
+  std::vector<double> nrm(cycles + 1);
+  for (int i = 0; i <= cycles; ++i) {
+    TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, mg->p, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s));
+    TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
+    TPMG_HIP(hipStreamSynchronize(s));
+    nrm[i] = std::sqrt(mg->h_scal->rr);
+    if (i == cycles) break;
+    TPMG_HIP(vcycle(*mg, mg->r, mg->z));
+    TPMG_HIP(tpmg::launch_add(d_u, mg->z, mg->len, s));
+  }
+  if (norms) std::copy(nrm.begin(), nrm.end(), norms);
+  if (!(nrm[skip] > 0.0) || !std::isfinite(nrm[cycles]))
+    return fail(TPMG_ERR_BREAKDOWN, "residual norms not positive and finite");
+  *rate = std::pow(nrm[cycles] / nrm[skip], 1.0 / (cycles - skip));
+  return TPMG_OK;
+}
+
 tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* model_bytes) {
   tpmg_status st = check_mg(mg);
   if (st != TPMG_OK) return st;
@@ -699,6 +1029,143 @@ tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* mo
   *avg_ms = static_cast<double>(ms) / reps;
   if (model_bytes) *model_bytes = 3.0 * (mg->fp32 ? 4.0 : 8.0) * static_cast<double>(mg->len);
   return TPMG_OK;
+}
+
+tpmg_status tpmg_batch_workspace_size(tpmg_mg* const* problems, int n, size_t* bytes) {
+  if (!bytes) return fail(TPMG_ERR_ARG, "bytes is NULL");
+  tpmg_status st = check_batch(problems, n);
+  if (st != TPMG_OK) return st;
+  tpmg_batch b;
+  b.probs.assign(problems, problems + n);
+  size_t nseg = 0;
+  if (build_plan(b, nullptr, false, &nseg) != hipSuccess) return fail(TPMG_ERR_ARG, "problems disagree on the schedule");
+  Carver cv(nullptr);
+  cv.take(static_cast<size_t>(n) * sizeof(tpmg::FcgScalars));
+  cv.take(nseg * sizeof(tpmg::Seg));
+  *bytes = cv.off + 256;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_batch_create(tpmg_mg* const* problems, int n, void* d_workspace, size_t bytes, tpmg_batch** out) {
+  if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  tpmg_status st = tpmg_batch_workspace_size(problems, n, &need);
+  if (st != TPMG_OK) return st;
+  if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(TPMG_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (bytes < need) return fail(TPMG_ERR_NOMEM, "batch workspace too small: need " + std::to_string(need) + " bytes");
+  auto* b = new tpmg_batch();
+  b->probs.assign(problems, problems + n);
+  b->stream = problems[0]->stream;
+  Carver cv(d_workspace);
+  b->scal = static_cast<tpmg::FcgScalars*>(cv.take(static_cast<size_t>(n) * sizeof(tpmg::FcgScalars)));
+  b->max_segs = (need - 256 - (static_cast<size_t>(n) * sizeof(tpmg::FcgScalars) + 255) / 256 * 256) / sizeof(tpmg::Seg);
+  b->segs = static_cast<tpmg::Seg*>(cv.take(b->max_segs * sizeof(tpmg::Seg)));
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_scal), static_cast<size_t>(n) * sizeof(tpmg::FcgScalars),
+                               hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* const* d_u, double rtol, int maxit,
+                             tpmg_solve_info* infos) {
+  if (!b || !d_f || !d_u) return fail(TPMG_ERR_ARG, "NULL argument");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(TPMG_ERR_ARG, "rtol must be >= 0 and maxit >= 0");
+  const int n = static_cast<int>(b->probs.size());
+  for (int p = 0; p < n; ++p) {
+    if (!d_f[p] || !d_u[p] || d_f[p] == d_u[p]) return fail(TPMG_ERR_ARG, "NULL or aliasing f/u");
+    if (infos && infos[p].history_cap > 0 && !infos[p].history)
+      return fail(TPMG_ERR_ARG, "history_cap > 0 with NULL history");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = b->stream;
+  // per problem: r = f - A u, rr, ff (kFinInit also marks already-converged
+  // problems done); p = q = 0
+  for (int p = 0; p < n; ++p) {
+    tpmg_mg& m = *b->probs[p];
+    TPMG_HIP(tpmg::launch_spmv64(m.view64(m.nlev - 1), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit,
+                                  b->scal + p, s, rtol));
+    TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
+    TPMG_HIP(tpmg::launch_fill(m.q, m.len * 8, s));
+  }
+  const bool rebuild = b->plan_u.size() != static_cast<size_t>(n) || !std::equal(b->plan_u.begin(), b->plan_u.end(), d_u);
+  if (rebuild || b->graph == nullptr) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->plan_u.clear();
+    hipError_t e = build_plan(*b, d_u, true, nullptr);
+    if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("batch plan: ") + hipGetErrorString(e));
+    hipGraph_t g = nullptr;
+    TPMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (const tpmg::BatchLaunch& L : b->plan)
+      if ((ce = tpmg::launch_batched(L, s)) != hipSuccess) break;
+    hipError_t ee = hipStreamEndCapture(s, &g);
+    if (ce != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(TPMG_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      b->graph = nullptr;
+      return fail(TPMG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    b->plan_u.assign(d_u, d_u + n);
+  }
+  const size_t sbytes = static_cast<size_t>(n) * sizeof(tpmg::FcgScalars);
+  auto read_scalars = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(b->h_scal, b->scal, sbytes, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  TPMG_HIP(read_scalars());
+  std::vector<double> fnorm(n);
+  for (int p = 0; p < n; ++p) {
+    fnorm[p] = std::sqrt(b->h_scal[p].ff);
+    if (infos && infos[p].history && infos[p].history_cap > 0)
+      infos[p].history[0] = fnorm[p] > 0 ? std::sqrt(b->h_scal[p].rr) / fnorm[p] : 0.0;
+  }
+  auto all_done = [&]() {
+    for (int p = 0; p < n; ++p)
+      if (!b->h_scal[p].done) return false;
+    return true;
+  };
+  for (int it = 0; it < maxit && !all_done(); ++it) {
+    TPMG_HIP(hipGraphLaunch(b->graph, s));
+    TPMG_HIP(read_scalars());
+    for (int p = 0; p < n; ++p) {
+      const tpmg::FcgScalars& c = b->h_scal[p];
+      if (infos && infos[p].history && c.status == 0 && c.iters < infos[p].history_cap && c.iters == it + 1)
+        infos[p].history[c.iters] = fnorm[p] > 0 ? std::sqrt(c.rr) / fnorm[p] : 0.0;
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  tpmg_status worst = TPMG_OK;
+  for (int p = 0; p < n; ++p) {
+    const tpmg::FcgScalars& c = b->h_scal[p];
+    tpmg_status st = c.status ? TPMG_ERR_BREAKDOWN : (c.done ? TPMG_OK : TPMG_NOT_CONVERGED);
+    if (infos) {
+      infos[p].iters = c.iters;
+      infos[p].relres = fnorm[p] > 0 ? std::sqrt(c.rr) / fnorm[p] : 0.0;
+      infos[p].t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (st == TPMG_ERR_BREAKDOWN) worst = st;
+    else if (st == TPMG_NOT_CONVERGED && worst == TPMG_OK) worst = st;
+  }
+  if (worst == TPMG_ERR_BREAKDOWN) return fail(worst, "breakdown in at least one problem of the batch");
+  return worst;
+}
+
+void tpmg_batch_destroy(tpmg_batch* b) {
+  if (!b) return;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->h_scal) (void)hipHostFree(b->h_scal);
+  delete b;
 }
 
 void tpmg_grid_destroy(tpmg_grid* g) { delete g; }

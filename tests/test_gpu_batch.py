@@ -1,0 +1,75 @@
+"""Batched solves of uneven size (several problems advanced together by
+grouped launches and one graph per FCG iteration) against the single solves
+of the same problems: identical iteration counts and bitwise identical
+solutions, because each problem keeps the block decomposition of its own
+solve; and the oracle's solution within the FP64 bar."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1408_2981_amd as T  # noqa: E402
+import synth  # noqa: E402
+from oracle import tpmg as otpmg  # noqa: E402
+
+PROBS = [(2, 8, "uniform", 11), (3, 13, "quadratic", 12), (3, 16, "quadratic", 13), (4, 32, "quadratic", 14),
+         (2, 16, "uniform", 15)]
+
+
+def _setup(fp32, stream):
+    out = []
+    for ref, nz, grading, seed in PROBS:
+        r = synth.vertical_faces(nz, synth.H10KM, grading)
+        om2 = synth.omega_for(ref) ** 2
+        prof = synth.profiles_random(nz, synth.n_cells(ref), seed=seed + 100)
+        P = T.Problem(ref, r, om2, profiles=prof).setup(precond_fp32=fp32, use_graph=True, stream=stream)
+        geo = P.geometry()
+        f = synth.cell_integral(synth.uniform_noise(P.n, nz, seed), geo["areas"], P.vk())
+        out.append((P, f, (ref, r, om2, prof)))
+    return out
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_batch_equals_single_solves(fp32):
+    stream = torch.cuda.Stream()
+    probs = _setup(fp32, stream)
+    fs = [P.pack(f) for P, f, _ in probs]
+    singles = []
+    for (P, f, _), fd in zip(probs, fs):
+        u = P.device_vector()
+        st, iters, relres, hist, _ = P.solve(fd, u, rtol=1e-8, maxit=200)
+        assert st == T.TPMG_OK
+        singles.append((iters, P.unpack(u), hist))
+    mgs = [P.mg for P, _, _ in probs]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, ws.data_ptr() + off, nbytes)
+    for rep in range(2):   # second call replays the cached plan and graph
+        us = [P.device_vector() for P, _, _ in probs]
+        st, per, ms = T.tpmg_batch_solve(batch, fs, us, 1e-8, 200)
+        assert st == T.TPMG_OK
+        for (P, f, _), u, (iters, hist_b_unused, _h), (it_s, u_s, hist_s) in zip(probs, us, per, singles):
+            assert iters == it_s
+            assert np.array_equal(P.unpack(u), u_s)
+    if not fp32:
+        for (P, f, (ref, r, om2, prof)), (it_s, u_s, _) in zip(probs, singles):
+            h = otpmg.build(ref, r, om2, profiles=prof)
+            o = otpmg.solve(h, f, rtol=1e-8)
+            assert o.iters == it_s
+            assert np.linalg.norm(u_s - o.x) <= 1e-10 * np.linalg.norm(o.x)
+    T.tpmg_batch_destroy(batch)
+
+
+def test_batch_rejects_mixed_parameters():
+    stream = torch.cuda.Stream()
+    a = _setup(False, stream)[:1]
+    b = _setup(True, stream)[:1]
+    with pytest.raises(T.TpmgError) as e:
+        T.tpmg_batch_workspace_size([a[0][0].mg, b[0][0].mg])
+    assert e.value.status == T.TPMG_ERR_ARG
