@@ -477,8 +477,15 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   const Column<T> c = load_column(L, col);
   const T esum = c.a0 + c.a1 + c.a2;
 
+  // column coefficients of level k0 + i, rebuilt from the per-column scalars
+  // and the wave-uniform vertical vectors whenever needed (cheaper than
+  // holding them: registers decide how many tiles a CU keeps in flight)
+  auto e_of = [&](int i) -> T { return c.bh * L.bv[k0 + i] + esum * L.av[k0 + i]; };
+  auto l_of = [&](int i) -> T { return c.arh * L.arv[k0 + i]; };
+  auto m_of = [&](int i) -> T { return c.arh * L.arv[k0 + i + 1]; };
+
   // ---- residual of the wave's levels, in registers
-  T r[kScanLevels], uu[kScanLevels], e[kScanLevels], l[kScanLevels], m[kScanLevels];
+  T r[kScanLevels], uu[kScanLevels];
   double fd[DOTS ? kScanLevels : 1];
 #pragma unroll
   for (int i = 0; i < kScanLevels; ++i) {
@@ -488,9 +495,6 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
       if (DOTS) fd[i] = static_cast<double>(f[o]);
       const T fk = static_cast<T>(f[o]);
       if (FCOPY) fcopy[o] = fk;
-      e[i] = c.bh * L.bv[k] + esum * L.av[k];
-      l[i] = c.arh * L.arv[k];
-      m[i] = c.arh * L.arv[k + 1];
       if (ZERO) {
         r[i] = fk;
         uu[i] = T(0);
@@ -510,8 +514,9 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 #pragma unroll
   for (int i = 0; i < kScanLevels; ++i) {
     if (i < nb) {
-      const T lp = (k0 + i == 0) ? T(1) : l[i];
-      const T a = e[i] + l[i], b = e[i] * lp;
+      const T ei = e_of(i), li = l_of(i);
+      const T lp = (k0 + i == 0) ? T(1) : li;
+      const T a = ei + li, b = ei * lp;
       const T n00 = a * p00 + b * p10, n01 = a * p01 + b * p11;
       const T n10 = p00 + lp * p10, n11 = p01 + lp * p11;
       const T mx = max(max(n00, n01), max(n10, n11));
@@ -542,8 +547,9 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 #pragma unroll
     for (int i = 0; i < kScanLevels; ++i) {
       if (i < nb) {
-        const T s = (k0 + i == 0) ? e[i] : e[i] + l[i] * s_prev * rcp_of(s_prev + l[i]);
-        ip[i] = rcp_of(s + m[i]);
+        const T ei = e_of(i), li = l_of(i);
+        const T s = (k0 + i == 0) ? ei : ei + li * s_prev * rcp_of(s_prev + li);
+        ip[i] = rcp_of(s + m_of(i));
         s_prev = s;
       }
     }
@@ -554,7 +560,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 #pragma unroll
   for (int i = 0; i < kScanLevels; ++i) {
     if (i < nb) {
-      const T a = l[i] * ip[i];
+      const T a = l_of(i) * ip[i];
       A = a * A;
       B = a * B + r[i] * ip[i];
     }
@@ -567,7 +573,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 #pragma unroll
   for (int i = 0; i < kScanLevels; ++i) {
     if (i < nb) {
-      d = l[i] * ip[i] * d + r[i] * ip[i];
+      d = l_of(i) * ip[i] * d + r[i] * ip[i];
       r[i] = d;   // r now holds d
     }
   }
@@ -577,7 +583,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 #pragma unroll
   for (int i = kScanLevels - 1; i >= 0; --i) {
     if (i < nb) {
-      const T cc = m[i] * ip[i];
+      const T cc = m_of(i) * ip[i];
       C = cc * C;
       D = cc * D + r[i];
     }
@@ -591,7 +597,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 #pragma unroll
   for (int i = kScanLevels - 1; i >= 0; --i) {
     if (i < nb) {
-      x = m[i] * ip[i] * x + r[i];
+      x = m_of(i) * ip[i] * x + r[i];
       const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
       const T uo = ZERO ? omega * x : uu[i] + omega * x;
       const TO zo = static_cast<TO>(uo);
@@ -722,8 +728,10 @@ __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const d
   spmv_body<MODE>(L, chunk, x, b, y, partials, whole_grid());
 }
 
+// Occupancy: an FP32 sweep fits two 16-wave workgroups per CU (at most 64
+// VGPRs, 8 waves per SIMD); FP64 one.
 template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__(1024) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
+__global__ __launch_bounds__(1024, sizeof(T) == 4 ? 8 : 4) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
                                                       TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
                                                       const double* __restrict__ q, double* __restrict__ partials) {
   smooth_scan_body<T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
@@ -810,8 +818,10 @@ __device__ __forceinline__ const Seg* find_segment(const Seg* __restrict__ segs,
   return sg;
 }
 
+// (the segment lookup costs registers: the fused-dots variant keeps its
+// natural allocation rather than spilling under the FP32 bound)
 template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__(1024) void kb_smooth_scan(const Seg* __restrict__ segs, int nseg, double omega) {
+__global__ __launch_bounds__(1024, (sizeof(T) == 4 && !DOTS) ? 8 : 4) void kb_smooth_scan(const Seg* __restrict__ segs, int nseg, double omega) {
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
