@@ -72,7 +72,19 @@ typedef struct {
   double omega_relax;  /* block-Jacobi damping (default 2/3)                */
   int precond_fp32;    /* 1: V-cycle in FP32 inside the FP64 CG (default 0) */
   int use_graph;       /* 1: replay the FCG iteration as a HIP graph        */
-  int reserved[5];
+  /* Launch configuration (see "Launch tuning" below). 0 in any field keeps
+   * the built-in choice or, with autotune, lets the trials decide it. */
+  int autotune;        /* 0: built-in choices; 1: timed trials at setup,
+                          reusing the process-wide tuning cache; 2: timed
+                          trials that replace the cached entries          */
+  int smoother;        /* line-smoother kernel on every level: 1 = column in
+                          registers, solved by block scans over the waves
+                          (nz <= 16 * scan_levels, required for batches);
+                          2 = LDS-staged; 3 = global scratch (any nz)     */
+  int scan_levels;     /* levels per wave of the scan smoother: 4, 8, 16   */
+  int stencil_chunk;   /* levels per wave of the transfer kernels and the
+                          operator: 1 .. 256                              */
+  int reserved[1];
 } tpmg_mg_params;
 
 /* Result of a solve. history (optional, caller-owned, history_cap entries)
@@ -202,8 +214,8 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
  * skipped). Each problem is computed with the block decomposition of its
  * own tpmg_solve, so its iterates and iteration count equal those of a
  * single solve. The problems must share one non-default stream, the
- * precision and the smoother parameters, and have at least two levels and
- * nz <= 128. The batch workspace (device, 256-byte aligned) holds the
+ * precision and the smoother parameters, have at least two levels and use
+ * the scan smoother on every level (the default for nz <= 256). The batch workspace (device, 256-byte aligned) holds the
  * per-problem scalars and the launch tables; problems must outlive the
  * batch. Errors: TPMG_ERR_ARG, TPMG_ERR_NOMEM. */
 tpmg_status tpmg_batch_workspace_size(tpmg_mg* const* problems, int n, size_t* bytes);
@@ -235,6 +247,43 @@ tpmg_status tpmg_richardson_rate(tpmg_mg* mg, double* d_u, int cycles, int skip,
  * of one sweep (read u and f, write u: 3 values per unknown of the
  * finest grid, counting padding columns). Synchronises the stream. */
 tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* model_bytes);
+
+/* ------------------------------------------------------ launch tuning -- */
+
+/* The line-smoother kernel (how a column is held while its tridiagonal
+ * system is solved), the levels per wave of the scan smoother and the
+ * levels per wave of the stencil kernels (residual + restriction,
+ * prolongation + correction, the FP64 operator) are chosen per level and
+ * per precision at tpmg_mg_setup. With params->autotune the setup times
+ * each admissible candidate on the workspace (a few launches each) and
+ * keeps the fastest; the choice is stored in a process-wide cache keyed by
+ * device (architecture and compute-unit count), kernel, precision, padded
+ * column count and nz, so that later setups of the same shape run no trials.
+ * The smoother choice changes the rounding order of the column solve (the
+ * result stays within the FP64 parity bar of the same algorithm); the
+ * stencil chunks change no stencil output bit, only the summation order of
+ * the dot product fused into the operator. */
+
+/* Chosen configuration of level (0 = coarsest): smoother kind (1, 2, 3 as in
+ * tpmg_mg_params), scan levels per wave, and the stencil chunks of
+ * residual + restriction from this level, prolongation into this level and
+ * (finest level only) the FP64 operator. Any output may be NULL. */
+tpmg_status tpmg_mg_tuning(const tpmg_mg* mg, int level, int* smoother, int* scan_levels, int* chunk_restrict,
+                           int* chunk_prolong, int* chunk_spmv);
+
+/* Timed trials run by the setup of mg and their total device time. */
+tpmg_status tpmg_mg_autotune_stats(const tpmg_mg* mg, int* trials, double* trial_ms);
+
+/* Process-wide tuning cache, JSON text: one object whose keys name
+ * "device|kernel|precision|padded columns|nz" and whose values are
+ * [choice, scan levels] arrays. load merges a file into the cache
+ * (TPMG_ERR_ARG if it cannot be read or parsed; the cache is then
+ * unchanged), save writes the whole cache, clear empties it, entries counts
+ * it. Host only; thread-safe. */
+tpmg_status tpmg_tune_load(const char* path);
+tpmg_status tpmg_tune_save(const char* path);
+tpmg_status tpmg_tune_clear(void);
+tpmg_status tpmg_tune_entries(int* n);
 
 void tpmg_grid_destroy(tpmg_grid* g);
 void tpmg_op_destroy(tpmg_op* op);

@@ -41,7 +41,8 @@ EXPORTED = [
     "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
     "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
     "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
-    "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_grid_destroy", "tpmg_op_destroy",
+    "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
+    "tpmg_tune_save", "tpmg_tune_clear", "tpmg_tune_entries", "tpmg_grid_destroy", "tpmg_op_destroy",
     "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error",
 ]
 
@@ -56,8 +57,15 @@ class MgParams(ctypes.Structure):
     _fields_ = [
         ("n_levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
         ("nu_coarse", ctypes.c_int), ("omega_relax", ctypes.c_double), ("precond_fp32", ctypes.c_int),
-        ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int * 5),
+        ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int), ("smoother", ctypes.c_int),
+        ("scan_levels", ctypes.c_int), ("stencil_chunk", ctypes.c_int), ("reserved", ctypes.c_int * 1),
     ]
+
+
+# line-smoother kinds (tpmg_mg_params.smoother, tpmg_mg_tuning)
+SMOOTHER_SCAN = 1
+SMOOTHER_LDS = 2
+SMOOTHER_GLOBAL = 3
 
 
 class SolveInfo(ctypes.Structure):
@@ -98,6 +106,12 @@ _sig = {
     "tpmg_batch_destroy": (None, [_vp]),
     "tpmg_richardson_rate": (_ip, [_vp, _vp, _ip, _ip, _dp, _dp]),
     "tpmg_mg_time_sweep": (_ip, [_vp, _ip, _dp, _dp]),
+    "tpmg_mg_tuning": (_ip, [_vp, _ip] + [ctypes.POINTER(_ip)] * 5),
+    "tpmg_mg_autotune_stats": (_ip, [_vp, ctypes.POINTER(_ip), _dp]),
+    "tpmg_tune_load": (_ip, [ctypes.c_char_p]),
+    "tpmg_tune_save": (_ip, [ctypes.c_char_p]),
+    "tpmg_tune_clear": (_ip, []),
+    "tpmg_tune_entries": (_ip, [ctypes.POINTER(_ip)]),
     "tpmg_grid_destroy": (None, [_vp]),
     "tpmg_op_destroy": (None, [_vp]),
     "tpmg_mg_destroy": (None, [_vp]),
@@ -309,6 +323,41 @@ def tpmg_mg_time_sweep(mg: int, reps: int):
     b = ctypes.c_double()
     _check(_lib.tpmg_mg_time_sweep(mg, reps, ctypes.byref(ms), ctypes.byref(b)))
     return ms.value, b.value
+
+
+def tpmg_mg_tuning(mg: int, level: int) -> dict:
+    """Launch configuration of a level: smoother kind, scan levels per wave
+    and the stencil chunks (0 where a kernel does not run on the level)."""
+    v = [ctypes.c_int() for _ in range(5)]
+    _check(_lib.tpmg_mg_tuning(mg, level, *[ctypes.byref(x) for x in v]))
+    keys = ("smoother", "scan_levels", "chunk_restrict", "chunk_prolong", "chunk_spmv")
+    return {k: x.value for k, x in zip(keys, v)}
+
+
+def tpmg_mg_autotune_stats(mg: int):
+    """Returns (timed trials, their device milliseconds) of mg's setup."""
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(_lib.tpmg_mg_autotune_stats(mg, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def tpmg_tune_load(path: str) -> None:
+    _check(_lib.tpmg_tune_load(os.fsencode(path)))
+
+
+def tpmg_tune_save(path: str) -> None:
+    _check(_lib.tpmg_tune_save(os.fsencode(path)))
+
+
+def tpmg_tune_clear() -> None:
+    _check(_lib.tpmg_tune_clear())
+
+
+def tpmg_tune_entries() -> int:
+    n = ctypes.c_int()
+    _check(_lib.tpmg_tune_entries(ctypes.byref(n)))
+    return n.value
 
 
 def tpmg_grid_destroy(h):

@@ -19,6 +19,24 @@ namespace tpmg {
 
 constexpr int kTile = 64;
 
+// Where the line smoother keeps a column while it solves it.
+enum SmootherKind {
+  kSmScan = 0,    // registers, the column split over the waves of a workgroup and joined by block scans
+  kSmLds = 1,     // residual and Thomas factors staged in LDS, one wave runs the recurrence
+  kSmGlobal = 2,  // Thomas factors in global scratch (any nz)
+};
+
+// Launch configuration of one level, chosen at setup (defaults, caller
+// overrides or timed trials). The smoother choice changes the rounding of the
+// column solve; the stencil chunks only change how work is dealt to waves.
+struct LevelTune {
+  int smoother = kSmScan;
+  int scan_levels = 8;   // levels per wave of the scan smoother: 4, 8 or 16 (nz <= 16 * scan_levels)
+  int chunk_rr = 0;      // levels per wave of residual + restriction from this level (0: heuristic)
+  int chunk_pr = 0;      // levels per wave of prolongation + correction into this level
+  int chunk_spmv = 0;    // levels per wave of the FP64 operator (finest level)
+};
+
 // One grid level as the kernels see it. Pointers are of the precision the
 // launcher is called with (double or float).
 struct LevelView {
@@ -33,6 +51,7 @@ struct LevelView {
   const void* beta_v = nullptr;   // [nz]
   const void* as_v = nullptr;     // [nz]
   const void* ar_v = nullptr;     // [nz+1]
+  LevelTune tune;
 };
 
 // Device scalars of the flexible CG recurrence.
@@ -75,6 +94,7 @@ struct Seg {
 struct BatchLaunch {
   int kind;         // OpKind
   int prec;         // 8 or 4 (V-cycle precision)
+  int scan_levels;  // smoother: levels per wave (the same for every segment of the launch)
   bool f_double, out_double, zero, fcopy, dots;   // smoother variant
   double omega;
   unsigned grid, block;
@@ -90,9 +110,15 @@ constexpr int kRedThreads = 256;
 // Where a reduction's last block applies its sums to the FCG scalars.
 enum FinalizeSite { kFinInit = 0, kFinAlpha = 1, kFinRR = 2, kFinBeta = 3, kFinNone = 4 };
 
-int stencil_chunk(int npad, int nz);      // levels per wave of the stencil kernels
-size_t stencil_blocks(int npad, int nz);  // blocks of 256 threads of the stencil kernels
-int scan_waves(int nz);                   // waves per tile of the scan smoother
+int stencil_chunk(int npad, int nz);   // heuristic levels per wave of the stencil kernels
+int effective_chunk(int tuned, int npad, int nz);   // tuned if set, else the heuristic
+size_t stencil_blocks(int npad, int nz, int chunk);  // blocks of 256 threads of a stencil kernel
+constexpr int kScanWavesMax = 16;
+int scan_waves(int nz, int scan_levels);   // waves per tile of the scan smoother
+// whether the smoother kind (with scan_levels for kSmScan) can run a level of nz
+// levels in precision prec (LDS limits included)
+bool smoother_fits(int kind, int scan_levels, int nz, int prec);
+LevelTune default_tune(int nz, int prec);
 unsigned pupdate_blocks(size_t len);      // blocks of the p-update kernel
 
 // All launchers enqueue on `s` and return hipGetLastError().
@@ -109,20 +135,20 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s);
 
 // One damped block-Jacobi sweep with the Thomas solve per column:
-// u_out = u_in + omega A_T^-1 (f - A u_in). zero_guess: u_in taken as 0
-// (not read). f_double: f is FP64 (else of precision prec); out_double:
-// u_out is FP64. fcopy (optional): receives f rounded to prec. sd, sc:
-// scratch vectors of the level size (used only by the fallback kernel).
-// q non-NULL (FP64 f and output required): also reduces <u_out, q> and
-// <u_out, f> and applies them at site kFinBeta.
+// u_out = u_in + omega A_T^-1 (f - A u_in), with the kernel L.tune selects.
+// zero_guess: u_in taken as 0 (not read). f_double: f is FP64 (else of
+// precision prec); out_double: u_out is FP64. fcopy (optional): receives f
+// rounded to prec. sd, sc: scratch vectors of the level size (used only by
+// the global-scratch kernel). q non-NULL (FP64 f and output and the scan
+// kernel required): also reduces <u_out, q> and <u_out, f> and applies them
+// at site kFinBeta. hipErrorInvalidValue if the tuned kernel cannot run.
 hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_double, const void* u_in,
                          bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
                          double omega, hipStream_t s, const double* q = nullptr, double* partials = nullptr,
                          FcgScalars* scal = nullptr);
-bool smooth_supports_dots(int nz);
 
 // Largest dynamic LDS a workgroup may use (set once from the device
-// properties); decides between the LDS-staged smoother and the fallback.
+// properties); bounds the LDS-staged smoother.
 hipError_t set_max_lds(size_t bytes);
 
 // f_coarse[P] = sum_{i<4} (f - A u)[4P + i] on the fine level L.

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device.h"
 
@@ -425,9 +426,9 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
   }
 }
 
-// Line smoother, scan form (nz <= kScanWaves * kScanLevels): one workgroup
-// per tile of 64 columns, wave w owns the levels [w*kb, (w+1)*kb) of every
-// column and keeps them in registers. The column solve of the margin-form
+// Line smoother, scan form (nz <= kScanWavesMax * KB): one workgroup per
+// tile of 64 columns, wave w owns the levels [w*kb, (w+1)*kb) (kb <= KB) of
+// every column and keeps them in registers. The column solve of the margin-form
 // Thomas algorithm is evaluated by three block scans over the waves:
 //  * pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) is a Moebius map,
 //    (P, Q) -> ((e_k + l_k) P + e_k l_k Q, P + l_k Q) with s = P / Q; the
@@ -439,9 +440,6 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
 // published maps of the blocks before (after) it to obtain its incoming value.
 // The chain is therefore kb + n_waves steps instead of nz, and the only
 // workgroup-wide data in LDS are the per-wave summaries.
-constexpr int kScanLevels = 8;
-constexpr int kScanWaves = 16;
-
 template <typename T>
 __device__ __forceinline__ void rescale2(T& a, T& b) {
   // multiply both entries by the same power of two so the larger is O(1)
@@ -455,7 +453,7 @@ __device__ __forceinline__ T rcp_of(T v) {
   return fast_rcp(v);
 }
 
-template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
 __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __restrict__ f, const T* __restrict__ u_in,
                                                  TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
                                                  const double* __restrict__ q, double* __restrict__ partials,
@@ -465,7 +463,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // waves that own levels; a batched launch may give the block more (idle) waves
-  const int nw = (nz + kScanLevels - 1) / kScanLevels;
+  const int nw = (nz + KB - 1) / KB;
   // summaries: pivot map (4), elimination map (2), substitution map (2)
   T* __restrict__ sm = reinterpret_cast<T*>(smem);
   auto at = [&](int w, int q) -> T& { return sm[(static_cast<size_t>(w) * 8 + q) * kTile + lane]; };
@@ -485,10 +483,10 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   auto m_of = [&](int i) -> T { return c.arh * L.arv[k0 + i + 1]; };
 
   // ---- residual of the wave's levels, in registers
-  T r[kScanLevels], uu[kScanLevels];
-  double fd[DOTS ? kScanLevels : 1];
+  T r[KB], uu[KB];
+  double fd[DOTS ? KB : 1];
 #pragma unroll
-  for (int i = 0; i < kScanLevels; ++i) {
+  for (int i = 0; i < KB; ++i) {
     if (i < nb) {
       const int k = k0 + i;
       const size_t o = c.base + static_cast<size_t>(k) * kTile;
@@ -512,7 +510,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // (l' = l_k, or 1 on level 0 where l_0 = 0, so that (0, 1) -> (e_0, 1))
   T p00 = T(1), p01 = T(0), p10 = T(0), p11 = T(1);
 #pragma unroll
-  for (int i = 0; i < kScanLevels; ++i) {
+  for (int i = 0; i < KB; ++i) {
     if (i < nb) {
       const T ei = e_of(i), li = l_of(i);
       const T lp = (k0 + i == 0) ? T(1) : li;
@@ -541,11 +539,11 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     rescale2(P, Q);
   }
   // local margins and pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k)
-  T ip[kScanLevels];
+  T ip[KB];
   {
     T s_prev = wave == 0 ? T(0) : P * rcp_of(Q);
 #pragma unroll
-    for (int i = 0; i < kScanLevels; ++i) {
+    for (int i = 0; i < KB; ++i) {
       if (i < nb) {
         const T ei = e_of(i), li = l_of(i);
         const T s = (k0 + i == 0) ? ei : ei + li * s_prev * rcp_of(s_prev + li);
@@ -558,7 +556,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // ---- elimination d_k = a_k d_{k-1} + b_k, a_k = l_k / p_k, b_k = r_k / p_k
   T A = T(1), B = T(0);
 #pragma unroll
-  for (int i = 0; i < kScanLevels; ++i) {
+  for (int i = 0; i < KB; ++i) {
     if (i < nb) {
       const T a = l_of(i) * ip[i];
       A = a * A;
@@ -571,7 +569,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   T d = T(0);
   for (int j = 0; j < wave; ++j) d = at(j, 4) * d + at(j, 5);
 #pragma unroll
-  for (int i = 0; i < kScanLevels; ++i) {
+  for (int i = 0; i < KB; ++i) {
     if (i < nb) {
       d = l_of(i) * ip[i] * d + r[i] * ip[i];
       r[i] = d;   // r now holds d
@@ -581,7 +579,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // ---- back substitution x_k = c_k x_{k+1} + d_k, c_k = m_k / p_k
   T C = T(1), D = T(0);
 #pragma unroll
-  for (int i = kScanLevels - 1; i >= 0; --i) {
+  for (int i = KB - 1; i >= 0; --i) {
     if (i < nb) {
       const T cc = m_of(i) * ip[i];
       C = cc * C;
@@ -595,7 +593,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   for (int j = nw - 1; j > wave; --j) x = at(j, 6) * x + at(j, 7);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
-  for (int i = kScanLevels - 1; i >= 0; --i) {
+  for (int i = KB - 1; i >= 0; --i) {
     if (i < nb) {
       x = m_of(i) * ip[i] * x + r[i];
       const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
@@ -728,13 +726,24 @@ __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const d
   spmv_body<MODE>(L, chunk, x, b, y, partials, whole_grid());
 }
 
-// Occupancy: an FP32 sweep fits two 16-wave workgroups per CU (at most 64
-// VGPRs, 8 waves per SIMD); FP64 one.
-template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__(1024, sizeof(T) == 4 ? 8 : 4) void k_smooth_scan(Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in,
-                                                      TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
-                                                      const double* __restrict__ q, double* __restrict__ partials) {
-  smooth_scan_body<T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
+// Occupancy: an FP32 sweep with up to 8 levels per wave fits two 16-wave
+// workgroups per CU (at most 64 VGPRs, 8 waves per SIMD); otherwise one.
+// FP64 with 16 levels per wave needs more than 128 VGPRs and is limited to
+// 8 waves (nz <= 128).
+template <int KB, typename T>
+constexpr int scan_waves_per_simd(bool dots) {
+  return (sizeof(T) == 4 && KB <= 8 && !dots) ? 8 : (sizeof(T) == 8 && KB == 16) ? 2 : 4;
+}
+template <int KB, typename T>
+constexpr int scan_max_threads() {
+  return 64 * ((sizeof(T) == 8 && KB == 16) ? 8 : kScanWavesMax);
+}
+
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+__global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd<KB, T>(false))) void k_smooth_scan(
+    Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in, TO* __restrict__ u_out, T* __restrict__ fcopy,
+    T omega, const double* __restrict__ q, double* __restrict__ partials) {
+  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
 }
 
 template <typename T>
@@ -820,12 +829,13 @@ __device__ __forceinline__ const Seg* find_segment(const Seg* __restrict__ segs,
 
 // (the segment lookup costs registers: the fused-dots variant keeps its
 // natural allocation rather than spilling under the FP32 bound)
-template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__(1024, (sizeof(T) == 4 && !DOTS) ? 8 : 4) void kb_smooth_scan(const Seg* __restrict__ segs, int nseg, double omega) {
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+__global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd<KB, T>(DOTS))) void kb_smooth_scan(const Seg* __restrict__ segs,
+                                                                                        int nseg, double omega) {
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  smooth_scan_body<T, TF, TO, ZERO, FCOPY, DOTS>(view<T>(sg->L), static_cast<const TF*>(sg->in0),
+  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(view<T>(sg->L), static_cast<const TF*>(sg->in0),
                                                  static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
                                                  static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q,
                                                  sg->partials, g);
@@ -900,14 +910,54 @@ int stencil_chunk(int npad, int nz) {
   return 1;
 }
 
-size_t stencil_blocks(int npad, int nz) {
-  const int c = stencil_chunk(npad, nz);
+int effective_chunk(int tuned, int npad, int nz) { return tuned > 0 ? tuned : stencil_chunk(npad, nz); }
+
+size_t stencil_blocks(int npad, int nz, int chunk) {
+  const int c = effective_chunk(chunk, npad, nz);
   const size_t waves = static_cast<size_t>(npad / kTile) * ((nz + c - 1) / c);
   return (waves + 3) / 4;
 }
 
-int scan_waves(int nz) { return (nz + kScanLevels - 1) / kScanLevels; }
-bool smooth_supports_dots(int nz) { return nz <= kScanLevels * kScanWaves; }
+int scan_waves(int nz, int scan_levels) { return (nz + scan_levels - 1) / scan_levels; }
+
+// the scan kernel for nz <= 16 * KB; the LDS-staged kernel while its two
+// [nz][64] arrays fit; the global-scratch kernel for any nz
+size_t g_max_lds = 65536;
+
+size_t lds_smoother_bytes(int nz, int prec) {
+  return (2 * static_cast<size_t>(nz) * kTile + 3 * static_cast<size_t>(nz) + 1) * static_cast<size_t>(prec);
+}
+
+bool smoother_fits(int kind, int scan_levels, int nz, int prec) {
+  switch (kind) {
+    case kSmScan:
+      return (scan_levels == 4 || scan_levels == 8 || scan_levels == 16) &&
+             scan_waves(nz, scan_levels) <= ((prec == 8 && scan_levels == 16) ? 8 : kScanWavesMax);
+    case kSmLds:
+      return lds_smoother_bytes(nz, prec) <= g_max_lds;
+    case kSmGlobal:
+      return true;
+    default:
+      return false;
+  }
+}
+
+LevelTune default_tune(int nz, int prec) {
+  LevelTune t;
+  if (smoother_fits(kSmScan, 8, nz, prec)) {
+    t.smoother = kSmScan;
+    t.scan_levels = 8;
+  } else if (smoother_fits(kSmScan, 16, nz, prec)) {
+    t.smoother = kSmScan;
+    t.scan_levels = 16;
+  } else if (smoother_fits(kSmLds, 0, nz, prec)) {
+    t.smoother = kSmLds;
+  } else {
+    t.smoother = kSmGlobal;
+  }
+  return t;
+}
+
 unsigned pupdate_blocks(size_t len) { return grid_for(len, 2048); }
 
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s) {
@@ -917,8 +967,8 @@ hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgSca
 
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
                          double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol) {
-  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
-  const int chunk = stencil_chunk(L.npad, L.nz);
+  const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
   if (mode == 0)
     hipLaunchKernelGGL(k_spmv64<0>, dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
@@ -929,102 +979,136 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
   return hipGetLastError();
 }
 
-// the scan kernel for nz <= 128, else the LDS-staged kernel when its two
-// [nz][64] arrays fit, else the register/global-scratch kernel
-size_t g_max_lds = 65536;
-
-struct DotArgs {
-  const double* q;
-  double* partials;
-  FcgScalars* sc;
+template <typename X>
+struct Type {
+  using type = X;
 };
+template <bool B>
+using Bool = std::integral_constant<bool, B>;
 
-template <typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-static void smooth_one(const Lv<T>& L, const TF* f, const T* ui, TO* uo, T* fc, T* d, T* c, T om, const DotArgs& da,
-                       hipStream_t s) {
-  const unsigned ntiles = static_cast<unsigned>(L.npad / kTile);
-  if (L.nz <= kScanLevels * kScanWaves) {
-    const int waves = scan_waves(L.nz);
-    const size_t sl = static_cast<size_t>(waves) * 8 * kTile * sizeof(T);
-    hipLaunchKernelGGL((k_smooth_scan<T, TF, TO, ZERO, FCOPY, DOTS>), dim3(ntiles), dim3(64 * waves), sl, s, L, f, ui,
-                       uo, fc, om, da.q, da.partials);
-    if (DOTS)
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), da.partials,
-                         static_cast<int>(ntiles), da.sc, 0.0);
-    return;
-  }
-  // dots are only requested for nz within the scan kernel's range
-  const size_t lds = (2 * static_cast<size_t>(L.nz) * kTile + 3 * static_cast<size_t>(L.nz) + 1) * sizeof(T);
-  if (lds <= g_max_lds) {
-    const unsigned waves = static_cast<unsigned>(std::min(16, std::max(1, (L.nz + kBatch - 1) / kBatch)));
-    hipLaunchKernelGGL((k_smooth_lds<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(64 * waves), lds, s, L, f, ui, uo, fc,
-                       om);
+// Calls fn(Type<TF>, Type<TO>, Bool<ZERO>, Bool<FCOPY>, Bool<DOTS>) for the
+// smoother variant of the flags; these are the combinations the V-cycle uses
+// (T: precision of the level data).
+template <typename T, typename Fn>
+void smoother_variant(bool f_double, bool out_double, bool zero, bool fcopy, bool dots, Fn&& fn) {
+  using D = Type<double>;
+  using P = Type<T>;
+  if (f_double && out_double) {
+    if (dots && zero)
+      fn(D{}, D{}, Bool<true>{}, Bool<false>{}, Bool<true>{});
+    else if (dots)
+      fn(D{}, D{}, Bool<false>{}, Bool<false>{}, Bool<true>{});
+    else if (zero)
+      fn(D{}, D{}, Bool<true>{}, Bool<false>{}, Bool<false>{});
+    else
+      fn(D{}, D{}, Bool<false>{}, Bool<false>{}, Bool<false>{});
+  } else if (f_double) {
+    if (zero && fcopy)
+      fn(D{}, P{}, Bool<true>{}, Bool<true>{}, Bool<false>{});
+    else if (zero)
+      fn(D{}, P{}, Bool<true>{}, Bool<false>{}, Bool<false>{});
+    else
+      fn(D{}, P{}, Bool<false>{}, Bool<false>{}, Bool<false>{});
+  } else if (out_double) {
+    if (zero)
+      fn(P{}, D{}, Bool<true>{}, Bool<false>{}, Bool<false>{});
+    else
+      fn(P{}, D{}, Bool<false>{}, Bool<false>{}, Bool<false>{});
   } else {
-    hipLaunchKernelGGL((k_smooth_fallback<T, TF, TO, ZERO, FCOPY>), dim3(ntiles), dim3(kTile), 0, s, L, f, ui, uo, fc,
-                       d, c, om);
+    if (zero)
+      fn(P{}, P{}, Bool<true>{}, Bool<false>{}, Bool<false>{});
+    else
+      fn(P{}, P{}, Bool<false>{}, Bool<false>{}, Bool<false>{});
   }
 }
 
-// (f type, out type, zero guess, f copy, dots) combinations used by the V-cycle
+// Calls fn(std::integral_constant<int, KB>) for a valid levels-per-wave value.
+template <typename Fn>
+void scan_levels_variant(int kb, Fn&& fn) {
+  if (kb == 4)
+    fn(std::integral_constant<int, 4>{});
+  else if (kb == 16)
+    fn(std::integral_constant<int, 16>{});
+  else
+    fn(std::integral_constant<int, 8>{});
+}
+
+struct SmoothArgs {
+  const void* f;
+  const void* u_in;
+  void* u_out;
+  void* fcopy;
+  void* sd;
+  void* sc;
+  double omega;
+  const double* q;
+  double* partials;
+  FcgScalars* scal;
+};
+
 template <typename T>
-static void smooth_t(const LevelView& Lg, const void* f, bool f_double, const void* u_in, bool zero, void* u_out,
-                     bool out_double, void* fcopy, void* sd, void* sc, double omega, const DotArgs& da, hipStream_t s) {
+static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool out_double, const SmoothArgs& a,
+                           hipStream_t s) {
   const Lv<T> L = view<T>(Lg);
-  const T* ui = static_cast<const T*>(u_in);
-  T* fc = static_cast<T*>(fcopy);
-  T* d = static_cast<T*>(sd);
-  T* c = static_cast<T*>(sc);
-  const T om = static_cast<T>(omega);
-  const bool dots = da.q != nullptr;
-  if (f_double) {
-    const double* ff = static_cast<const double*>(f);
-    if (out_double) {
-      double* uo = static_cast<double*>(u_out);
-      if (dots && zero)
-        smooth_one<T, double, double, true, false, true>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else if (dots)
-        smooth_one<T, double, double, false, false, true>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else if (zero)
-        smooth_one<T, double, double, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else
-        smooth_one<T, double, double, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-    } else {
-      T* uo = static_cast<T*>(u_out);
-      if (zero && fcopy)
-        smooth_one<T, double, T, true, true, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else if (zero)
-        smooth_one<T, double, T, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else
-        smooth_one<T, double, T, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-    }
-  } else {
-    const T* ff = static_cast<const T*>(f);
-    if (out_double) {
-      double* uo = static_cast<double*>(u_out);
-      if (zero)
-        smooth_one<T, T, double, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else
-        smooth_one<T, T, double, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-    } else {
-      T* uo = static_cast<T*>(u_out);
-      if (zero)
-        smooth_one<T, T, T, true, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-      else
-        smooth_one<T, T, T, false, false, false>(L, ff, ui, uo, fc, d, c, om, da, s);
-    }
+  const LevelTune& tn = Lg.tune;
+  const bool dots = a.q != nullptr;
+  const bool fcopy = a.fcopy != nullptr;
+  const int prec = static_cast<int>(sizeof(T));
+  const unsigned ntiles = static_cast<unsigned>(L.npad / kTile);
+  const T* ui = static_cast<const T*>(a.u_in);
+  T* fc = static_cast<T*>(a.fcopy);
+  const T om = static_cast<T>(a.omega);
+  if (!smoother_fits(tn.smoother, tn.scan_levels, L.nz, prec)) return hipErrorInvalidValue;
+  if (tn.smoother == kSmScan) {
+    const int waves = scan_waves(L.nz, tn.scan_levels);
+    const size_t sl = static_cast<size_t>(waves) * 8 * kTile * sizeof(T);
+    scan_levels_variant(tn.scan_levels, [&](auto kbc) {
+      constexpr int KB = decltype(kbc)::value;
+      smoother_variant<T>(f_double, out_double, zero, fcopy, dots, [&](auto tf, auto to, auto z, auto fcp, auto dt) {
+        using TF = typename decltype(tf)::type;
+        using TO = typename decltype(to)::type;
+        hipLaunchKernelGGL((k_smooth_scan<KB, T, TF, TO, decltype(z)::value, decltype(fcp)::value, decltype(dt)::value>),
+                           dim3(ntiles), dim3(64 * waves), sl, s, L, static_cast<const TF*>(a.f), ui,
+                           static_cast<TO*>(a.u_out), fc, om, a.q, a.partials);
+      });
+    });
+    if (dots)
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), a.partials,
+                         static_cast<int>(ntiles), a.scal, 0.0);
+    return hipGetLastError();
   }
+  if (dots) return hipErrorInvalidValue;   // only the scan kernel forms the dots
+  if (tn.smoother == kSmLds) {
+    const size_t lds = lds_smoother_bytes(L.nz, prec);
+    const unsigned waves = static_cast<unsigned>(std::min(16, std::max(1, (L.nz + kBatch - 1) / kBatch)));
+    smoother_variant<T>(f_double, out_double, zero, fcopy, false, [&](auto tf, auto to, auto z, auto fcp, auto) {
+      using TF = typename decltype(tf)::type;
+      using TO = typename decltype(to)::type;
+      hipLaunchKernelGGL((k_smooth_lds<T, TF, TO, decltype(z)::value, decltype(fcp)::value>), dim3(ntiles),
+                         dim3(64 * waves), lds, s, L, static_cast<const TF*>(a.f), ui, static_cast<TO*>(a.u_out), fc,
+                         om);
+    });
+  } else {
+    smoother_variant<T>(f_double, out_double, zero, fcopy, false, [&](auto tf, auto to, auto z, auto fcp, auto) {
+      using TF = typename decltype(tf)::type;
+      using TO = typename decltype(to)::type;
+      hipLaunchKernelGGL((k_smooth_fallback<T, TF, TO, decltype(z)::value, decltype(fcp)::value>), dim3(ntiles),
+                         dim3(kTile), 0, s, L, static_cast<const TF*>(a.f), ui, static_cast<TO*>(a.u_out), fc,
+                         static_cast<T*>(a.sd), static_cast<T*>(a.sc), om);
+    });
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_smooth(const LevelView& L, int prec, const void* f, bool f_double, const void* u_in,
                          bool zero_guess, void* u_out, bool out_double, void* fcopy, void* sd, void* sc,
                          double omega, hipStream_t s, const double* q, double* partials, FcgScalars* scal) {
-  if (q && L.nz > kScanLevels * kScanWaves) return hipErrorInvalidValue;
-  const DotArgs da{q, partials, scal};
-  if (prec == 8)
-    smooth_t<double>(L, f, true, u_in, zero_guess, u_out, true, nullptr, sd, sc, omega, da, s);
-  else
-    smooth_t<float>(L, f, f_double, u_in, zero_guess, u_out, out_double, fcopy, sd, sc, omega, da, s);
-  return hipGetLastError();
+  if (prec == 8) {
+    const SmoothArgs a{f, u_in, u_out, nullptr, sd, sc, omega, q, partials, scal};
+    return smooth_t<double>(L, true, zero_guess, true, a, s);
+  }
+  const SmoothArgs a{f, u_in, u_out, fcopy, sd, sc, omega, q, partials, scal};
+  return smooth_t<float>(L, f_double, zero_guess, out_double, a, s);
 }
 
 hipError_t set_max_lds(size_t bytes) {
@@ -1034,8 +1118,8 @@ hipError_t set_max_lds(size_t bytes) {
 
 hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int prec, const void* f,
                                     const void* u, void* f_coarse, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz));
-  const int chunk = stencil_chunk(L.npad, L.nz);
+  const int chunk = effective_chunk(L.tune.chunk_rr, L.npad, L.nz);
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   if (prec == 8)
     hipLaunchKernelGGL(k_residual_restrict<double>, dim3(blocks), dim3(256), 0, s, view<double>(L), chunk, C.n,
                        static_cast<const double*>(f), static_cast<const double*>(u), static_cast<double*>(f_coarse));
@@ -1047,8 +1131,8 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
 
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
                               void* u_fine, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(stencil_blocks(F.npad, F.nz));
-  const int chunk = stencil_chunk(F.npad, F.nz);
+  const int chunk = effective_chunk(F.tune.chunk_pr, F.npad, F.nz);
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(F.npad, F.nz, chunk));
   if (prec == 8)
     hipLaunchKernelGGL(k_prolong_add<double>, dim3(blocks), dim3(256), 0, s, view<double>(F), view<double>(C), chunk,
                        static_cast<const double*>(e_coarse), static_cast<double*>(u_fine));
@@ -1105,36 +1189,16 @@ hipError_t launch_unpack(const double* tiled, double* cm, int n, int npad, int n
 template <typename T>
 static hipError_t batched_smooth_t(const BatchLaunch& b, hipStream_t s) {
   const dim3 grid(b.grid), block(b.block);
-  const size_t lds = b.lds;
-  const double om = b.omega;
-  const bool zero = b.zero, fcopy = b.fcopy, dots = b.dots;
-  if (b.f_double && b.out_double) {
-    if (dots && zero)
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, true, false, true>), grid, block, lds, s, b.segs, b.nseg, om);
-    else if (dots)
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, false, false, true>), grid, block, lds, s, b.segs, b.nseg, om);
-    else if (zero)
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-    else
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, double, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-  } else if (b.f_double) {
-    if (zero && fcopy)
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, T, true, true, false>), grid, block, lds, s, b.segs, b.nseg, om);
-    else if (zero)
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, T, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-    else
-      hipLaunchKernelGGL((kb_smooth_scan<T, double, T, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-  } else if (b.out_double) {
-    if (zero)
-      hipLaunchKernelGGL((kb_smooth_scan<T, T, double, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-    else
-      hipLaunchKernelGGL((kb_smooth_scan<T, T, double, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-  } else {
-    if (zero)
-      hipLaunchKernelGGL((kb_smooth_scan<T, T, T, true, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-    else
-      hipLaunchKernelGGL((kb_smooth_scan<T, T, T, false, false, false>), grid, block, lds, s, b.segs, b.nseg, om);
-  }
+  if (!smoother_fits(kSmScan, b.scan_levels, 1, static_cast<int>(sizeof(T)))) return hipErrorInvalidValue;
+  scan_levels_variant(b.scan_levels, [&](auto kbc) {
+    constexpr int KB = decltype(kbc)::value;
+    smoother_variant<T>(b.f_double, b.out_double, b.zero, b.fcopy, b.dots, [&](auto tf, auto to, auto z, auto fcp, auto dt) {
+      using TF = typename decltype(tf)::type;
+      using TO = typename decltype(to)::type;
+      hipLaunchKernelGGL((kb_smooth_scan<KB, T, TF, TO, decltype(z)::value, decltype(fcp)::value, decltype(dt)::value>),
+                         grid, block, b.lds, s, b.segs, b.nseg, b.omega);
+    });
+  });
   return hipGetLastError();
 }
 

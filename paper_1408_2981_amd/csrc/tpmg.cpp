@@ -4,11 +4,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cctype>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -90,6 +97,10 @@ struct tpmg_mg {
   // graph of one FCG iteration for the solution vector graph_x
   hipGraphExec_t graph = nullptr;
   double* graph_x = nullptr;
+  // launch configuration per level, and the cost of choosing it
+  std::vector<tpmg::LevelTune> tune;
+  int tune_trials = 0;
+  double tune_ms = 0.0;
 
   tpmg::LevelView view(int l) const {
     const DevLevel& d = lv[l];
@@ -106,6 +117,7 @@ struct tpmg_mg {
     v.beta_v = bv[i];
     v.as_v = asv[i];
     v.ar_v = arv[i];
+    if (!tune.empty()) v.tune = tune[l];
     return v;
   }
   tpmg::LevelView view64(int l) const {
@@ -122,6 +134,7 @@ struct tpmg_mg {
     v.beta_v = bv[0];
     v.as_v = asv[0];
     v.ar_v = arv[0];
+    if (!tune.empty()) v.tune = tune[l];
     return v;
   }
 };
@@ -166,11 +179,11 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
   m.p = static_cast<double*>(cv.take(fine_len * 8));
   m.q = static_cast<double*>(cv.take(fine_len * 8));
   m.z = static_cast<double*>(cv.take(fine_len * 8));
-  // reductions: stencil blocks of the finest grid, the BLAS grid, or one
-  // block per tile (the smoother with fused dots)
+  // reductions: stencil blocks of the finest grid (at most: one level per
+  // wave), the BLAS grid, or one block per tile (the smoother with fused dots)
   const size_t fine_npad = pad64(op.levels.back().n);
-  m.max_partial_blocks = static_cast<int>(
-      std::max({static_cast<size_t>(tpmg::kRedBlocks), tpmg::stencil_blocks(static_cast<int>(fine_npad), nz), fine_npad / 64}));
+  m.max_partial_blocks = static_cast<int>(std::max(
+      {static_cast<size_t>(tpmg::kRedBlocks), tpmg::stencil_blocks(static_cast<int>(fine_npad), nz, 1), fine_npad / 64}));
   m.partials = static_cast<double*>(cv.take(2 * static_cast<size_t>(m.max_partial_blocks) * 8));
   m.scal = static_cast<tpmg::FcgScalars*>(cv.take(sizeof(tpmg::FcgScalars)));
   m.len = fine_len;
@@ -182,6 +195,13 @@ tpmg_status check_params(const tpmg_mg_params* p) {
     return fail(TPMG_ERR_ARG, "nu_pre, nu_post and nu_coarse must be >= 1");
   if (!(p->omega_relax > 0.0) || !(p->omega_relax < 2.0)) return fail(TPMG_ERR_ARG, "omega_relax must be in (0, 2)");
   if (p->n_levels < 0) return fail(TPMG_ERR_ARG, "n_levels must be >= 0");
+  if (p->autotune < 0 || p->autotune > 2) return fail(TPMG_ERR_ARG, "autotune must be 0, 1 or 2");
+  if (p->smoother < 0 || p->smoother > 3) return fail(TPMG_ERR_ARG, "smoother must be 0 (auto), 1, 2 or 3");
+  if (p->scan_levels != 0 && p->scan_levels != 4 && p->scan_levels != 8 && p->scan_levels != 16)
+    return fail(TPMG_ERR_ARG, "scan_levels must be 0, 4, 8 or 16");
+  if (p->scan_levels != 0 && p->smoother > 1)
+    return fail(TPMG_ERR_ARG, "scan_levels applies to the scan smoother only");
+  if (p->stencil_chunk < 0 || p->stencil_chunk > 256) return fail(TPMG_ERR_ARG, "stencil_chunk must be in 0..256");
   return TPMG_OK;
 }
 
@@ -334,7 +354,7 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, double* z_out, const double* q_d
 // With nz beyond the fused smoother's range the dots are a separate op
 // (kind -1, single solves only).
 void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) {
-  const bool fused = tpmg::smooth_supports_dots(m.nz);
+  const bool fused = m.tune.back().smoother == tpmg::kSmScan;
   vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops);
   if (!fused) {
     Op d;
@@ -462,18 +482,28 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
     fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops);
     for (const Op& op : ops) items.push_back({op, static_cast<int>(p)});
   }
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& c) { return order_less(a.op, c.op); });
+  // smoother sweeps of one position are grouped by levels per wave (one
+  // kernel instance per launch)
+  auto kb_of = [](const Op& o) { return o.kind == tpmg::kOpSmooth ? o.L.tune.scan_levels : 0; };
+  auto group_less = [&](const Op& a, const Op& c) {
+    if (order_less(a, c)) return true;
+    if (order_less(c, a)) return false;
+    return kb_of(a) < kb_of(c);
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const Item& a, const Item& c) { return group_less(a.op, c.op); });
   std::vector<tpmg::Seg> host;
   std::vector<tpmg::BatchLaunch> plan;
   std::vector<size_t> seg_offset;   // first segment of each launch
   size_t i = 0;
   while (i < items.size()) {
     size_t j = i;
-    while (j < items.size() && !order_less(items[i].op, items[j].op) && !order_less(items[j].op, items[i].op)) ++j;
+    while (j < items.size() && !group_less(items[i].op, items[j].op) && !group_less(items[j].op, items[i].op)) ++j;
     const Op& o = items[i].op;
     tpmg::BatchLaunch L{};
     L.kind = o.kind;
     L.prec = o.prec;
+    L.scan_levels = kb_of(o);
     L.f_double = o.f_double;
     L.out_double = o.out_double;
     L.zero = o.zero;
@@ -507,17 +537,22 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
       int nb = 0;
       switch (a.kind) {
         case tpmg::kOpSmooth: {
+          if (a.L.tune.smoother != tpmg::kSmScan) return hipErrorInvalidValue;
           nb = a.L.npad / tpmg::kTile;
-          const int waves = tpmg::scan_waves(a.L.nz);
+          const int waves = tpmg::scan_waves(a.L.nz, a.L.tune.scan_levels);
           L.block = std::max(L.block, static_cast<unsigned>(64 * waves));
           break;
         }
         case tpmg::kOpRestrict:
         case tpmg::kOpProlong:
-        case tpmg::kOpSpmv:
-          nb = static_cast<int>(tpmg::stencil_blocks(a.L.npad, a.L.nz));
-          g.chunk = tpmg::stencil_chunk(a.L.npad, a.L.nz);
+        case tpmg::kOpSpmv: {
+          const int tuned = a.kind == tpmg::kOpRestrict  ? a.L.tune.chunk_rr
+                            : a.kind == tpmg::kOpProlong ? a.L.tune.chunk_pr
+                                                         : a.L.tune.chunk_spmv;
+          g.chunk = tpmg::effective_chunk(tuned, a.L.npad, a.L.nz);
+          nb = static_cast<int>(tpmg::stencil_blocks(a.L.npad, a.L.nz, g.chunk));
           break;
+        }
         case tpmg::kOpPupdate:
           nb = static_cast<int>(tpmg::pupdate_blocks(a.len));
           break;
@@ -572,7 +607,9 @@ tpmg_status check_batch(tpmg_mg* const* problems, int n) {
     const tpmg_mg* m = problems[i];
     if (!m) return fail(TPMG_ERR_ARG, "NULL problem");
     if (m->nlev < 2) return fail(TPMG_ERR_ARG, "batched problems need at least 2 multigrid levels");
-    if (!tpmg::smooth_supports_dots(m->nz)) return fail(TPMG_ERR_ARG, "batched problems need nz <= 128");
+    for (const tpmg::LevelTune& t : m->tune)
+      if (t.smoother != tpmg::kSmScan)
+        return fail(TPMG_ERR_ARG, "batched problems need the scan smoother on every level (params.smoother = 1)");
     if (m->fp32 != a->fp32 || m->nu_pre != a->nu_pre || m->nu_post != a->nu_post || m->nu_coarse != a->nu_coarse ||
         m->omega != a->omega)
       return fail(TPMG_ERR_ARG, "batched problems must share precision and smoother parameters");
@@ -592,6 +629,269 @@ void drop_graph(tpmg_mg& m) {
 
 tpmg_status check_mg(const tpmg_mg* mg) {
   if (!mg) return fail(TPMG_ERR_ARG, "mg handle is NULL");
+  return TPMG_OK;
+}
+
+// ---- launch tuning -----------------------------------------------------------
+
+// Process-wide cache of tuned choices: key "device|kernel|precision|npad|nz",
+// value {choice, scan levels}.
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::string, std::array<int, 2>> map;
+};
+
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+std::string tune_key(const std::string& dev, const char* kernel, int prec, int npad, int nz) {
+  return dev + "|" + kernel + "|" + std::to_string(prec) + "|" + std::to_string(npad) + "|" + std::to_string(nz);
+}
+
+// Parses the cache format: {"key": [int, int], ...} (keys without quotes or
+// backslashes). Returns false on any deviation.
+bool parse_tune_json(const std::string& text, std::map<std::string, std::array<int, 2>>& out) {
+  size_t i = 0;
+  auto ws = [&]() {
+    while (i < text.size() && std::isspace(static_cast<unsigned char>(text[i]))) ++i;
+  };
+  auto eat = [&](char ch) {
+    ws();
+    if (i < text.size() && text[i] == ch) {
+      ++i;
+      return true;
+    }
+    return false;
+  };
+  auto integer = [&](int& v) {
+    ws();
+    const size_t b = i;
+    if (i < text.size() && text[i] == '-') ++i;
+    while (i < text.size() && std::isdigit(static_cast<unsigned char>(text[i]))) ++i;
+    if (i == b || (i == b + 1 && text[b] == '-') || i - b > 10) return false;
+    const long long x = std::stoll(text.substr(b, i - b));
+    if (x < -1000000 || x > 1000000) return false;
+    v = static_cast<int>(x);
+    return true;
+  };
+  if (!eat('{')) return false;
+  if (eat('}')) {
+    ws();
+    return i == text.size();
+  }
+  for (;;) {
+    if (!eat('"')) return false;
+    const size_t b = i;
+    while (i < text.size() && text[i] != '"' && text[i] != '\\') ++i;
+    if (i >= text.size() || text[i] != '"' || i == b) return false;
+    const std::string key = text.substr(b, i - b);
+    ++i;
+    std::array<int, 2> v{};
+    if (!eat(':') || !eat('[') || !integer(v[0]) || !eat(',') || !integer(v[1]) || !eat(']')) return false;
+    out[key] = v;
+    if (eat(',')) continue;
+    if (!eat('}')) return false;
+    ws();
+    return i == text.size();
+  }
+}
+
+std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string arch(prop.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return arch + ":" + std::to_string(prop.multiProcessorCount);
+}
+
+// Mean device time per launch of `launch`: two warm-up launches, then the
+// better of two timed groups of `reps` launches between events.
+hipError_t time_launches(hipStream_t s, int reps, const std::function<hipError_t()>& launch, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch();
+  double best = 1e300;
+  for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+    e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (e == hipSuccess) best = std::min(best, static_cast<double>(t) / reps);
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  *ms = best;
+  return e;
+}
+
+// Picks, among candidates, the one with the smallest time; the first
+// candidate (the built-in choice) is kept unless another is 2% faster.
+template <typename C>
+hipError_t pick(tpmg_mg& m, const std::vector<C>& cands, const std::function<hipError_t(const C&)>& launch,
+                size_t* best_index) {
+  double best_t = 0.0;
+  *best_index = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    double t = 0.0;
+    hipError_t e = time_launches(m.stream, 8, [&]() { return launch(cands[i]); }, &t);
+    if (e != hipSuccess) return e;
+    m.tune_trials += 1;
+    m.tune_ms += t * (8 * 2 + 2);
+    if (i == 0 || t < 0.98 * best_t) {
+      best_t = t;
+      *best_index = i;
+    }
+  }
+  return hipSuccess;
+}
+
+tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p);
+
+// Sets m.tune from the defaults and the caller's overrides (trials ==
+// false, before any device work), or refines it by timed trials on the
+// workspace (trials == true), whose vectors hold zeros at that point and
+// still hold zeros afterwards (every trial maps zero data to zero data).
+tpmg_status choose_tuning(tpmg_mg& m, const tpmg_mg_params& p, bool trials) {
+  const int prec = m.fp32 ? 4 : 8;
+  const int L = m.nlev - 1;
+  if (trials) {
+    if (p.autotune == 0) return TPMG_OK;
+    return autotune(m, p);
+  }
+  m.tune.assign(m.nlev, tpmg::default_tune(m.nz, prec));
+  for (int l = 0; l <= L; ++l) {
+    tpmg::LevelTune& t = m.tune[l];
+    if (p.smoother != 0) {
+      t.smoother = p.smoother - 1;
+      if (t.smoother == tpmg::kSmScan && !tpmg::smoother_fits(tpmg::kSmScan, t.scan_levels, m.nz, prec))
+        t.scan_levels = 16;
+    }
+    if (p.scan_levels != 0) {
+      t.smoother = tpmg::kSmScan;
+      t.scan_levels = p.scan_levels;
+    }
+    if (p.stencil_chunk != 0) t.chunk_rr = t.chunk_pr = t.chunk_spmv = p.stencil_chunk;
+    if (!tpmg::smoother_fits(t.smoother, t.scan_levels, m.nz, prec))
+      return fail(TPMG_ERR_ARG, "the requested line smoother cannot run nz = " + std::to_string(m.nz) +
+                                    " (scan form: nz <= 16 * scan_levels; LDS form: two [nz][64] arrays in LDS)");
+  }
+  return TPMG_OK;
+}
+
+tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p) {
+  const int prec = m.fp32 ? 4 : 8;
+  const int L = m.nlev - 1;
+  const std::string dev = device_tag();
+  TuneCache& cache = tune_cache();
+  auto lookup = [&](const std::string& key, std::array<int, 2>* v) {
+    if (p.autotune == 2) return false;
+    std::lock_guard<std::mutex> lk(cache.mu);
+    auto it = cache.map.find(key);
+    if (it == cache.map.end()) return false;
+    *v = it->second;
+    return true;
+  };
+  auto store = [&](const std::string& key, std::array<int, 2> v) {
+    std::lock_guard<std::mutex> lk(cache.mu);
+    cache.map[key] = v;
+  };
+  const bool tune_smoother = p.smoother == 0 && p.scan_levels == 0;
+  const bool tune_scan_levels = p.smoother == 1 && p.scan_levels == 0;
+  const bool tune_chunks = p.stencil_chunk == 0;
+  std::vector<int> chunks;
+  for (int c = 1; c <= 16; c *= 2)
+    if (c <= m.nz) chunks.push_back(c);
+  auto chunk_cands = [&](int npad) {
+    // the heuristic first
+    std::vector<int> v{tpmg::stencil_chunk(npad, m.nz)};
+    for (int c : chunks)
+      if (c != v[0]) v.push_back(c);
+    return v;
+  };
+
+  for (int l = 0; l <= L; ++l) {
+    tpmg::LevelTune& t = m.tune[l];
+    const int npad = m.lv[l].npad;
+    const void* f = l < L ? m.lv[l].f : (m.fp32 ? static_cast<const void*>(m.fcopy) : static_cast<const void*>(m.r));
+    if (tune_smoother || tune_scan_levels) {
+      const std::string key = tune_key(dev, tune_smoother ? "smooth" : "smooth_scan", prec, npad, m.nz);
+      std::array<int, 2> v{};
+      if (lookup(key, &v) && tpmg::smoother_fits(v[0], v[1], m.nz, prec)) {
+        t.smoother = v[0];
+        t.scan_levels = v[1];
+      } else {
+        std::vector<std::array<int, 2>> cands{{t.smoother, t.scan_levels}};
+        for (int kb : {4, 8, 16})
+          if (tpmg::smoother_fits(tpmg::kSmScan, kb, m.nz, prec) && !(t.smoother == tpmg::kSmScan && t.scan_levels == kb))
+            cands.push_back({tpmg::kSmScan, kb});
+        if (tune_smoother)
+          for (int kind : {tpmg::kSmLds, tpmg::kSmGlobal})
+            if (tpmg::smoother_fits(kind, 8, m.nz, prec) && t.smoother != kind) cands.push_back({kind, 8});
+        size_t best = 0;
+        std::function<hipError_t(const std::array<int, 2>&)> run = [&](const std::array<int, 2>& c) {
+          tpmg::LevelView v = m.view(l);
+          v.tune.smoother = c[0];
+          v.tune.scan_levels = c[1];
+          return tpmg::launch_smooth(v, prec, f, prec == 8, m.lv[l].u[0], false, m.lv[l].u[1], prec == 8, nullptr,
+                                     m.sd, m.sc, m.omega, m.stream);
+        };
+        hipError_t e = pick(m, cands, run, &best);
+        if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("autotune (smoother): ") + hipGetErrorString(e));
+        t.smoother = cands[best][0];
+        t.scan_levels = cands[best][1];
+        store(key, cands[best]);
+      }
+    }
+    if (!tune_chunks) continue;
+    const std::vector<int> cc = chunk_cands(npad);
+    auto tune_chunk = [&](const char* kernel, int kprec, int* field,
+                          const std::function<hipError_t(int)>& launch) -> tpmg_status {
+      const std::string key = tune_key(dev, kernel, kprec, npad, m.nz);
+      std::array<int, 2> v{};
+      if (lookup(key, &v) && v[0] >= 1 && v[0] <= 256) {
+        *field = v[0];
+        return TPMG_OK;
+      }
+      size_t best = 0;
+      std::function<hipError_t(const int&)> run = [&](const int& c) { return launch(c); };
+      hipError_t e = pick(m, cc, run, &best);
+      if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("autotune (") + kernel + "): " + hipGetErrorString(e));
+      *field = cc[best];
+      store(key, {cc[best], 0});
+      return TPMG_OK;
+    };
+    tpmg_status st = TPMG_OK;
+    if (l > 0) {
+      st = tune_chunk("restrict", prec, &t.chunk_rr, [&](int c) {
+        tpmg::LevelView F = m.view(l);
+        F.tune.chunk_rr = c;
+        return tpmg::launch_residual_restrict(F, m.view(l - 1), prec, f, m.lv[l].u[0], m.lv[l - 1].f, m.stream);
+      });
+      if (st == TPMG_OK)
+        st = tune_chunk("prolong", prec, &t.chunk_pr, [&](int c) {
+          tpmg::LevelView F = m.view(l);
+          F.tune.chunk_pr = c;
+          return tpmg::launch_prolong_add(F, m.view(l - 1), prec, m.lv[l - 1].u[0], m.lv[l].u[0], m.stream);
+        });
+    }
+    if (st == TPMG_OK && l == L)
+      st = tune_chunk("spmv", 8, &t.chunk_spmv, [&](int c) {
+        tpmg::LevelView V = m.view64(l);
+        V.tune.chunk_spmv = c;
+        hipError_t e = tpmg::launch_spmv64(V, 0, m.p, nullptr, m.q, m.partials, tpmg::kFinNone, m.scal, m.stream);
+        if (e != hipSuccess) return e;
+        return tpmg::launch_finalize(tpmg::kFinNone, m.partials,
+                                     static_cast<int>(tpmg::stencil_blocks(V.npad, V.nz, c)), m.scal, 0.0, m.stream);
+      });
+    if (st != TPMG_OK) return st;
+  }
   return TPMG_OK;
 }
 
@@ -794,6 +1094,10 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
     return fail(TPMG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
   }
   tpmg::set_max_lds(static_cast<size_t>(max_lds));
+  if ((st = choose_tuning(*m, *params, false)) != TPMG_OK) {
+    delete m;
+    return st;
+  }
   e = hipHostMalloc(reinterpret_cast<void**>(&m->h_scal), sizeof(tpmg::FcgScalars), hipHostMallocDefault);
   if (e != hipSuccess) {
     m->h_scal = nullptr;
@@ -844,7 +1148,84 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   (void)nz;
   if (e != hipSuccess) return cleanup_fail(TPMG_ERR_DEVICE, std::string("setup upload: ") + hipGetErrorString(e));
+  if ((st = choose_tuning(*m, *params, true)) != TPMG_OK) {
+    const std::string msg = g_last_error;
+    return cleanup_fail(st, msg);
+  }
   *out = m;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mg_tuning(const tpmg_mg* mg, int level, int* smoother, int* scan_levels, int* chunk_restrict,
+                           int* chunk_prolong, int* chunk_spmv) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (level < 0 || level >= mg->nlev) return fail(TPMG_ERR_ARG, "level out of range");
+  const tpmg::LevelTune& t = mg->tune[level];
+  const int npad = mg->lv[level].npad;
+  if (smoother) *smoother = t.smoother + 1;
+  if (scan_levels) *scan_levels = t.scan_levels;
+  if (chunk_restrict) *chunk_restrict = level > 0 ? tpmg::effective_chunk(t.chunk_rr, npad, mg->nz) : 0;
+  if (chunk_prolong) *chunk_prolong = level > 0 ? tpmg::effective_chunk(t.chunk_pr, npad, mg->nz) : 0;
+  if (chunk_spmv) *chunk_spmv = level + 1 == mg->nlev ? tpmg::effective_chunk(t.chunk_spmv, npad, mg->nz) : 0;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mg_autotune_stats(const tpmg_mg* mg, int* trials, double* trial_ms) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (trials) *trials = mg->tune_trials;
+  if (trial_ms) *trial_ms = mg->tune_ms;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_tune_load(const char* path) {
+  if (!path) return fail(TPMG_ERR_ARG, "path is NULL");
+  std::ifstream in(path, std::ios::binary);
+  if (!in) return fail(TPMG_ERR_ARG, std::string("cannot read ") + path);
+  std::stringstream ss;
+  ss << in.rdbuf();
+  std::map<std::string, std::array<int, 2>> parsed;
+  if (!parse_tune_json(ss.str(), parsed)) return fail(TPMG_ERR_ARG, std::string("malformed tuning file ") + path);
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (const auto& kv : parsed) c.map[kv.first] = kv.second;
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_tune_save(const char* path) {
+  if (!path) return fail(TPMG_ERR_ARG, "path is NULL");
+  std::string text = "{\n";
+  {
+    TuneCache& c = tune_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    size_t i = 0;
+    for (const auto& kv : c.map) {
+      text += "  \"" + kv.first + "\": [" + std::to_string(kv.second[0]) + ", " + std::to_string(kv.second[1]) + "]";
+      text += ++i < c.map.size() ? ",\n" : "\n";
+    }
+  }
+  text += "}\n";
+  std::ofstream out(path, std::ios::binary | std::ios::trunc);
+  if (!out) return fail(TPMG_ERR_ARG, std::string("cannot write ") + path);
+  out << text;
+  out.close();
+  if (!out) return fail(TPMG_ERR_ARG, std::string("write failed: ") + path);
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_tune_clear(void) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.map.clear();
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_tune_entries(int* n) {
+  if (!n) return fail(TPMG_ERR_ARG, "n is NULL");
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  *n = static_cast<int>(c.map.size());
   return TPMG_OK;
 }
 

@@ -11,6 +11,7 @@ from . import (
     tpmg_grid_icosahedral, tpmg_grid_geometry, tpmg_grid_vertical, tpmg_op_create, tpmg_op_levels,
     tpmg_mg_params_default, tpmg_mg_workspace_size, tpmg_mg_setup, tpmg_mg_vector_length, tpmg_pack,
     tpmg_unpack, tpmg_spmv, tpmg_vcycle, tpmg_solve, tpmg_grid_destroy, tpmg_op_destroy, tpmg_mg_destroy,
+    tpmg_mg_tuning,
 )
 
 
@@ -100,6 +101,10 @@ class Problem:
     def solve(self, f_tiled, u_tiled, rtol: float = 1e-8, maxit: int = 100):
         """Synchronous; returns (status, iters, relres, history, t_total_ms)."""
         return tpmg_solve(self.mg, f_tiled, u_tiled, rtol, maxit)
+
+    def tuning(self):
+        """Launch configuration chosen at setup, one dict per level (0 = coarsest)."""
+        return [tpmg_mg_tuning(self.mg, lvl) for lvl in range(tpmg_op_levels(self.op))]
 
     def synchronize(self):
         self.stream.synchronize()

@@ -87,3 +87,63 @@ def test_host_geometry_and_coefficients_match_oracle(ref, nz, grading, seed):
             assert np.allclose(T.tpmg_op_prolongation(P.op, lvl), h.weights[lvl], rtol=0, atol=1e-13)
     assert np.allclose(P.vk(), h.vert.vk, rtol=1e-15, atol=0)
     P.close()
+
+
+def test_tuning_parameter_errors():
+    """Launch-tuning fields of tpmg_mg_params are range-checked on the host."""
+    r = synth.vertical_faces(4, 0.01)
+    g = T.tpmg_grid_icosahedral(2, 4, r)
+    op = T.tpmg_op_create(g, 0, 1.0, np.ones(5), np.ones(4), np.ones(4))
+    good = T.tpmg_mg_params_default()
+    assert (good.autotune, good.smoother, good.scan_levels, good.stencil_chunk) == (0, 0, 0, 0)
+    base = T.tpmg_mg_workspace_size(op, good)
+    for field, value in (("autotune", 3), ("autotune", -1), ("smoother", 4), ("scan_levels", 5),
+                         ("scan_levels", 32), ("stencil_chunk", -1), ("stencil_chunk", 257)):
+        p = T.tpmg_mg_params_default()
+        setattr(p, field, value)
+        with pytest.raises(T.TpmgError) as e:
+            T.tpmg_mg_workspace_size(op, p)
+        assert e.value.status == T.TPMG_ERR_ARG, (field, value)
+    p = T.tpmg_mg_params_default()
+    p.smoother, p.scan_levels = T.SMOOTHER_LDS, 8        # levels per wave only apply to the scan kernel
+    with pytest.raises(T.TpmgError):
+        T.tpmg_mg_workspace_size(op, p)
+    p = T.tpmg_mg_params_default()
+    p.autotune, p.smoother, p.scan_levels, p.stencil_chunk = 2, T.SMOOTHER_SCAN, 16, 256
+    assert T.tpmg_mg_workspace_size(op, p) == base       # tuning does not change the workspace
+
+
+def test_tune_cache_file_roundtrip(tmp_path):
+    """The process-wide tuning cache: JSON load merges, save writes every
+    entry, a malformed or missing file is rejected and leaves the cache
+    unchanged."""
+    T.tpmg_tune_clear()
+    assert T.tpmg_tune_entries() == 0
+    src = tmp_path / "in.json"
+    src.write_text('{ "gfx950:256|smooth|4|81920|128": [0, 8],\n  "gfx950:256|spmv|8|81920|128": [4, 0] }\n')
+    T.tpmg_tune_load(str(src))
+    assert T.tpmg_tune_entries() == 2
+    out = tmp_path / "out.json"
+    T.tpmg_tune_save(str(out))
+    text = out.read_text()
+    assert '"gfx950:256|smooth|4|81920|128": [0, 8]' in text and '"gfx950:256|spmv|8|81920|128": [4, 0]' in text
+    for bad in ('{"a": [1, 2]', '{"a": [1]}', '{"a\\\\b": [1, 2]}', '{"a": [1, 2]} x', '{"a": [x, 2]}', '[]',
+                '{"": [1, 2]}'):
+        p = tmp_path / "bad.json"
+        p.write_text(bad)
+        with pytest.raises(T.TpmgError) as e:
+            T.tpmg_tune_load(str(p))
+        assert e.value.status == T.TPMG_ERR_ARG, bad
+        assert T.tpmg_tune_entries() == 2
+    with pytest.raises(T.TpmgError):
+        T.tpmg_tune_load(str(tmp_path / "missing.json"))
+    T.tpmg_tune_clear()
+    assert T.tpmg_tune_entries() == 0
+    T.tpmg_tune_load(str(out))
+    assert T.tpmg_tune_entries() == 2
+    (tmp_path / "empty.json").write_text("{}")
+    T.tpmg_tune_load(str(tmp_path / "empty.json"))
+    assert T.tpmg_tune_entries() == 2
+    T.tpmg_tune_save(str(tmp_path / "again.json"))
+    assert (tmp_path / "again.json").read_text() == text
+    T.tpmg_tune_clear()
