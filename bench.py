@@ -87,7 +87,7 @@ def profile_sweep(w, reps: int):
     import paper_1408_2981_amd as T
     import synth
 
-    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=False)
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=False, autotune=1)
     geo = P.geometry()
     f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
     u = P.device_vector()
@@ -155,7 +155,8 @@ def batch_report(steps: int = 3):
     ws = synth.batch_list()
     probs, fs = [], []
     for w in ws:
-        P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True, stream=stream)
+        P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True, stream=stream,
+                                                                 smoother=T.SMOOTHER_SCAN, autotune=1)
         geo = P.geometry()
         fs.append(P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk())))
         probs.append(P)
@@ -193,11 +194,17 @@ def batch_report(steps: int = 3):
             t_bat.append(time.perf_counter() - t0)
     its_bat = [p[0] for p in per]
     T.tpmg_batch_destroy(batch)
+    chosen = {}
+    for w, P in zip(ws, probs):
+        fine = P.tuning()[-1]
+        chosen[f"ref{w.refinement}_nz{w.nz}"] = {"scan_levels": fine["scan_levels"],
+                                                "chunk_restrict": fine["chunk_restrict"],
+                                                "chunk_spmv": fine["chunk_spmv"]}
     line = {"workload": "batch16: refinements 4/5/6 x nz 32/64/128 quadratic, mixed, rtol 1e-8",
             "unknowns": unknowns, "status": int(st),
             "batched_ms": 1000.0 * float(np.median(t_bat)), "sequential_ms": 1000.0 * float(np.median(t_seq)),
             "batched_unknowns_per_s": unknowns / float(np.median(t_bat)),
-            "iters_batched": its_bat, "iters_single": its_seq}
+            "iters_batched": its_bat, "iters_single": its_seq, "tuned_finest_level": chosen}
     line["speedup"] = line["sequential_ms"] / line["batched_ms"]
     print(json.dumps(line), flush=True)
     for P in probs:
@@ -212,6 +219,8 @@ def main():
     ap.add_argument("--workload", default="ico6_nz128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=50)
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+                    help="choose kernels by timed trials at setup (excluded from the timed solves)")
     ap.add_argument("--report", action="store_true",
                     help="also measure the anisotropy sweep on the refinement-7 grid (one JSON line per ratio)")
     ap.add_argument("--profile-sweep", action="store_true",
@@ -244,7 +253,8 @@ def main():
     f_host = synth.make_rhs(w, geo["centres"], geo["areas"], P64.vk())
     P32 = T.Problem(w.refinement, w.r_faces(), w.omega2)
     for name, P, fp32 in (("fp64", P64, False), ("mixed", P32, True)):
-        P.setup(precond_fp32=fp32, use_graph=True)
+        P.setup(precond_fp32=fp32, use_graph=True, autotune=args.autotune)
+        log(f"{name}: tuning (coarsest first) {P.tuning()}")
         f = P.pack(f_host)
         u = P.device_vector()
         for _ in range(args.warmup):
@@ -294,6 +304,8 @@ def main():
             "fp64_iters": fp64["iters"],
             "mixed_speedup_vs_fp64": fp64["ms"] / mixed["ms"],
             "fp64_sweep_GBs": fp64["sweep_bytes"] / (fp64["sweep_ms"] / 1000.0) / 1e9,
+            "autotune": args.autotune,
+            "finest_tuning_mixed": P32.tuning()[-1],
         },
         "roofline": {
             "kernel": "finest-grid line-smoother sweep (FP32, mixed solve)",
