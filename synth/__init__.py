@@ -293,6 +293,9 @@ def workload(name: str) -> Workload:
     if name == "ico6_nz64_seq":  # learned-guess sequence
         return Workload(name, 6, 64, "quadratic", H10KM, omega_for(6) ** 2, "smooth_sequence", 50)
     m = name.split("_")
+    if m[0] == "seq":            # seq_<ref>_<nz>: a smaller smooth sequence (seeds 50 and 51)
+        ref, nz = int(m[1]), int(m[2])
+        return Workload(name, ref, nz, "quadratic", H10KM, omega_for(ref) ** 2, "smooth_sequence", 50)
     if m[0] == "test":           # test_<ref>_<nz>_<grading>_<seed>
         ref, nz, grading, seed = int(m[1]), int(m[2]), m[3], int(m[4])
         return Workload(name, ref, nz, grading, H10KM, omega_for(ref) ** 2, "uniform", seed)
@@ -307,6 +310,20 @@ def batch_list():
         nz = [32, 64, 128][(i // 3) % 3]
         out.append(Workload(f"batch{i}", ref, nz, "quadratic", H10KM, omega_for(ref) ** 2, "uniform", 40 + i))
     return out
+
+
+def sequence_rhs(w: Workload, centres: np.ndarray, areas: np.ndarray, vk: np.ndarray, t) -> np.ndarray:
+    """Right-hand side number t of a smooth sequence: the cell integral of
+    f_0 + 0.05 t g, with f_0 and g smooth seeded fields (seeds w.seed and
+    w.seed + 1) sampled at the cell centres and layer midpoints. t may be a
+    scalar or a sequence (then the result is [len(t), n, nz])."""
+    r = w.r_faces()
+    r_mid = 0.5 * (r[:-1] + r[1:])
+    f0 = smooth_random_field(centres, r_mid, w.thickness, w.seed)
+    g = smooth_random_field(centres, r_mid, w.thickness, w.seed + 1)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    out = np.stack([cell_integral(f0 + 0.05 * tt * g, areas, vk) for tt in ts])
+    return out if np.ndim(t) else out[0]
 
 
 def make_rhs(w: Workload, centres: np.ndarray, areas: np.ndarray, vk: np.ndarray) -> np.ndarray:
@@ -325,4 +342,6 @@ def make_rhs(w: Workload, centres: np.ndarray, areas: np.ndarray, vk: np.ndarray
         return fm + 0.1 * rms * uniform_noise(len(areas), w.nz, w.seed) * vol
     if w.rhs == "uniform":
         return cell_integral(uniform_noise(len(areas), w.nz, w.seed), areas, vk)
+    if w.rhs == "smooth_sequence":
+        return sequence_rhs(w, centres, areas, vk, 1)
     raise ValueError(w.rhs)
