@@ -190,3 +190,12 @@ def predict(p: dict, s: Scaling, f_cols: np.ndarray, nbr: np.ndarray, act_bf16: 
     """Initial guess [n, nz] for the right-hand side f_cols [n, nz]."""
     y, _ = forward(p, standardise_x(s, features(f_cols, nbr)), act_bf16)
     return y * s.sd_y + s.mu_y
+
+
+def guess(p: dict, s: Scaling, f_cols: np.ndarray, nbr: np.ndarray, op, act_bf16: bool = True) -> np.ndarray:
+    """The network's prediction followed by one undamped line-relaxation
+    sweep, u_hat + A_T^-1 (f - A u_hat) (the block-Jacobi column solve of
+    Section 5 with damping 1), on the operator op of the grid."""
+    from . import tpmg as tp
+
+    return tp.smooth(op, f_cols, predict(p, s, f_cols, nbr, act_bf16), 1.0)

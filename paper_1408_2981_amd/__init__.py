@@ -43,6 +43,10 @@ EXPORTED = [
     "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
     "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
     "tpmg_tune_save", "tpmg_tune_clear", "tpmg_tune_entries", "tpmg_grid_destroy", "tpmg_op_destroy",
+    "tpmg_mlp_param_count", "tpmg_mlp_workspace_size", "tpmg_mlp_create", "tpmg_mlp_set_params", "tpmg_mlp_get_params",
+    "tpmg_mlp_set_scaling", "tpmg_mlp_get_scaling", "tpmg_mlp_fit_scaling", "tpmg_mlp_features", "tpmg_mlp_targets",
+    "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_infer", "tpmg_mlp_save",
+    "tpmg_mlp_load", "tpmg_mlp_destroy",
     "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error",
 ]
 
@@ -78,6 +82,7 @@ class SolveInfo(ctypes.Structure):
 _vp = ctypes.c_void_p
 _ip = ctypes.c_int
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
 _sig = {
@@ -112,6 +117,23 @@ _sig = {
     "tpmg_tune_save": (_ip, [ctypes.c_char_p]),
     "tpmg_tune_clear": (_ip, []),
     "tpmg_tune_entries": (_ip, [ctypes.POINTER(_ip)]),
+    "tpmg_mlp_param_count": (_ip, [_ip, _ip, ctypes.POINTER(ctypes.c_size_t)]),
+    "tpmg_mlp_workspace_size": (_ip, [_ip, _ip, _ip, ctypes.POINTER(ctypes.c_size_t)]),
+    "tpmg_mlp_create": (_ip, [_ip, _ip, _ip, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "tpmg_mlp_set_params": (_ip, [_vp, _fp]),
+    "tpmg_mlp_get_params": (_ip, [_vp, _fp]),
+    "tpmg_mlp_set_scaling": (_ip, [_vp, _dp, _dp, _dp, _dp]),
+    "tpmg_mlp_get_scaling": (_ip, [_vp, _dp, _dp, _dp, _dp]),
+    "tpmg_mlp_fit_scaling": (_ip, [_vp, _vp, _vp, ctypes.c_size_t]),
+    "tpmg_mlp_features": (_ip, [_vp, _vp, _vp, _vp]),
+    "tpmg_mlp_targets": (_ip, [_vp, _vp, _vp, _vp]),
+    "tpmg_mlp_forward": (_ip, [_vp, _vp, _ip, _vp]),
+    "tpmg_mlp_gradients": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, _fp, _fp]),
+    "tpmg_mlp_train_step": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, ctypes.c_float, _fp]),
+    "tpmg_mlp_infer": (_ip, [_vp, _vp, _vp, _ip, _vp]),
+    "tpmg_mlp_save": (_ip, [_vp, ctypes.c_char_p]),
+    "tpmg_mlp_load": (_ip, [_vp, ctypes.c_char_p]),
+    "tpmg_mlp_destroy": (None, [_vp]),
     "tpmg_grid_destroy": (None, [_vp]),
     "tpmg_op_destroy": (None, [_vp]),
     "tpmg_mg_destroy": (None, [_vp]),
@@ -372,4 +394,101 @@ def tpmg_mg_destroy(h):
     _lib.tpmg_mg_destroy(h)
 
 
+# ------------------------------------------------------ learned guess ----
+
+def tpmg_mlp_param_count(nz: int, hidden: int) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.tpmg_mlp_param_count(nz, hidden, ctypes.byref(n)))
+    return n.value
+
+
+def tpmg_mlp_workspace_size(nz: int, hidden: int, max_rows: int) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.tpmg_mlp_workspace_size(nz, hidden, max_rows, ctypes.byref(n)))
+    return n.value
+
+
+def tpmg_mlp_create(nz: int, hidden: int, max_rows: int, workspace, nbytes: int, stream) -> int:
+    h = _vp()
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(_lib.tpmg_mlp_create(nz, hidden, max_rows, _dev(workspace), nbytes, s, ctypes.byref(h)))
+    return h.value
+
+
+def _fptr(a):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_fp)
+
+
+def tpmg_mlp_set_params(m: int, params) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.tpmg_mlp_set_params(m, _fptr(p)))
+
+
+def tpmg_mlp_get_params(m: int, n: int) -> np.ndarray:
+    p = np.zeros(n, dtype=np.float32)
+    _check(_lib.tpmg_mlp_get_params(m, _fptr(p)))
+    return p
+
+
+def tpmg_mlp_set_scaling(m: int, mu_x, sd_x, mu_y, sd_y) -> None:
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (mu_x, sd_x, mu_y, sd_y)]
+    _check(_lib.tpmg_mlp_set_scaling(m, *[_dptr(a) for a in arrs]))
+
+
+def tpmg_mlp_get_scaling(m: int, n_in: int, nz: int):
+    out = [np.zeros(n_in), np.zeros(n_in), np.zeros(nz), np.zeros(nz)]
+    _check(_lib.tpmg_mlp_get_scaling(m, *[_dptr(a) for a in out]))
+    return out
+
+
+def tpmg_mlp_fit_scaling(m: int, d_x, d_y, rows: int) -> None:
+    _check(_lib.tpmg_mlp_fit_scaling(m, _dev(d_x), _dev(d_y), rows))
+
+
+def tpmg_mlp_features(m: int, mg: int, d_f, d_x) -> None:
+    _check(_lib.tpmg_mlp_features(m, mg, _dev(d_f), _dev(d_x)))
+
+
+def tpmg_mlp_targets(m: int, mg: int, d_u, d_y) -> None:
+    _check(_lib.tpmg_mlp_targets(m, mg, _dev(d_u), _dev(d_y)))
+
+
+def tpmg_mlp_forward(m: int, d_x, rows: int, d_y) -> None:
+    _check(_lib.tpmg_mlp_forward(m, _dev(d_x), rows, _dev(d_y)))
+
+
+def tpmg_mlp_gradients(m: int, d_x, d_y, rows_total: int, d_rows, batch: int, n_params: int):
+    """Returns (loss, grads[n_params]) of the batch; synchronous."""
+    loss = ctypes.c_float()
+    g = np.zeros(n_params, dtype=np.float32)
+    _check(_lib.tpmg_mlp_gradients(m, _dev(d_x), _dev(d_y), rows_total, _dev(d_rows), batch, ctypes.byref(loss),
+                                   _fptr(g)))
+    return loss.value, g
+
+
+def tpmg_mlp_train_step(m: int, d_x, d_y, rows_total: int, d_rows, batch: int, lr: float, want_loss: bool = False):
+    loss = ctypes.c_float()
+    _check(_lib.tpmg_mlp_train_step(m, _dev(d_x), _dev(d_y), rows_total, _dev(d_rows), batch, lr,
+                                    ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def tpmg_mlp_infer(m: int, mg: int, d_f, d_u0, relax: int = 1) -> None:
+    _check(_lib.tpmg_mlp_infer(m, mg, _dev(d_f), relax, _dev(d_u0)))
+
+
+def tpmg_mlp_save(m: int, path: str) -> None:
+    _check(_lib.tpmg_mlp_save(m, os.fsencode(path)))
+
+
+def tpmg_mlp_load(m: int, path: str) -> None:
+    _check(_lib.tpmg_mlp_load(m, os.fsencode(path)))
+
+
+def tpmg_mlp_destroy(m: int) -> None:
+    _lib.tpmg_mlp_destroy(m)
+
+
 from .solver import Problem  # noqa: E402  (convenience wrapper over the calls above)
+from .learned_guess import ColumnMLP  # noqa: E402

@@ -37,20 +37,23 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in ("mesh.cpp", "operator.cpp"):
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *HOST_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    obj = os.path.join(BUILD, "tpmg.cpp.o")
-    _run([HIPCC, "-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-I", INCLUDE, "-c",
-          os.path.join(CSRC, "tpmg.cpp"), "-o", obj])
-    objs.append(obj)
+        jobs.append((["g++", *HOST_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    for src in ("tpmg.cpp", "mlp.cpp"):
+        obj = os.path.join(BUILD, src + ".o")
+        jobs.append(([HIPCC, "-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-I", INCLUDE, "-c",
+                      os.path.join(CSRC, src), "-o", obj], obj))
     for src in sorted(f for f in os.listdir(CSRC) if f.endswith(".hip")):
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *DEVICE_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append(([HIPCC, *DEVICE_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = OUT + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs])
     os.replace(tmp, OUT)

@@ -170,8 +170,27 @@ hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size
 hipError_t launch_add(double* x, const double* y, size_t len, hipStream_t s);   // x += y
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);   // zero fill (graph-safe)
 
+// Finest grid of a set-up solver, for the kernels that read its vectors
+// directly (the learned initial guess).
+struct FineGrid {
+  int n = 0, npad = 0, nz = 0;
+  const int32_t* nbr = nullptr;   // [3][npad]
+  hipStream_t stream = nullptr;
+};
+
 // layout conversion of a finest-grid FP64 vector
 hipError_t launch_pack(const double* cm, double* tiled, int n, int npad, int nz, hipStream_t s);
 hipError_t launch_unpack(const double* tiled, double* cm, int n, int npad, int nz, hipStream_t s);
 
 }  // namespace tpmg
+
+struct tpmg_mg;
+// Finest grid of mg (defined next to the solver's handle).
+bool tpmg_fine_grid(const tpmg_mg* mg, tpmg::FineGrid* out);
+// Sets the thread's message returned by tpmg_last_error().
+void tpmg_set_last_error(const char* msg);
+// One line-relaxation sweep on mg's finest grid in FP64, u_out = u_in +
+// omega A_T^-1 (f - A u_in) (tiled vectors, u_in and u_out distinct; sd, sc:
+// FP64 scratch vectors of the finest length), enqueued on s.
+hipError_t tpmg_relax_finest(const tpmg_mg* mg, const double* f, const double* u_in, double* u_out, double* sd,
+                             double* sc, double omega, hipStream_t s);

@@ -1,0 +1,94 @@
+// Device side of the per-column MLP (learned initial guess): launchers of
+// the gfx950 kernels. Matrices are row-major; bf16 is the 16-bit brain
+// float; every launcher enqueues on `s` and returns hipGetLastError() or
+// hipErrorInvalidValue for a shape it does not support.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "device.h"
+
+namespace tpmg {
+
+using bf16 = __bf16;
+
+// C[m][n] = sum_k A(m, k) B(n, k) for m < M, n < N, k < K, with
+// A(m, k) = ta ? A[k * lda + m] : A[m * lda + k] and likewise B. Products of
+// bf16 on the matrix cores, FP32 sums. Requirements (checked): lda, ldb
+// multiples of 8, 16-byte aligned A and B; not transposed: K a multiple of
+// 8, lda >= K (ldb >= K); transposed: lda >= M rounded up to 8 (ldb >= N),
+// the entries between M and that bound are read but reach only discarded
+// outputs.
+enum GemmEpilogue {
+  kEpiBiasReluBf16 = 0,  // out_bf16[m ldc + n] = bf16(max(C + bias[n], 0))
+  kEpiBiasF32 = 1,       // out_f32[m ldc + n] = C + bias[n]
+  kEpiMaskBf16 = 2,      // out_bf16[m ldc + n] = mask[m ldc + n] > 0 ? bf16(C) : 0
+  kEpiPartialF32 = 3,    // out_f32[z M N + m N + n] = C over the z-th slice of ksplit values of k
+  kEpiInferTiled = 4,    // out_f64 tiled (column m, level n) = (C + bias[n]) sd[n] + mu[n]
+};
+
+struct GemmArgs {
+  const bf16* A = nullptr;
+  const bf16* B = nullptr;
+  int lda = 0, ldb = 0;
+  int M = 0, N = 0, K = 0;
+  int ksplit = 0;            // kEpiPartialF32: k values per slice (multiple of 32); else K
+  bool ta = false, tb = false;
+  int epi = kEpiBiasF32;
+  const float* bias = nullptr;
+  const bf16* mask = nullptr;
+  bf16* out_bf16 = nullptr;
+  float* out_f32 = nullptr;
+  int ldc = 0;
+  double* out_f64 = nullptr;  // kEpiInferTiled: tiled FP64 vector with nz = N levels
+  const float* mu = nullptr;
+  const float* sd = nullptr;
+};
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+
+// x[T][j]: the column's right-hand side (j < nz) and the vertical means of
+// neighbours 0..2 (j = nz + i), from a tiled FP64 vector.
+hipError_t launch_mlp_features(const FineGrid& g, const double* f, float* x, hipStream_t s);
+// y[T][k] = u(T, k), FP32.
+hipError_t launch_mlp_targets(const FineGrid& g, const double* u, float* y, hipStream_t s);
+
+// Gathers rows (rows == nullptr: rows 0..n-1), standardises and rounds:
+// xb[r][j] = bf16((x[row][j] - mu_x[j]) / sd_x[j]) for j < n_in, 0 up to kp;
+// yt (optional) [r][k] = (y[row][k] - mu_y[k]) / sd_y[k]. An index outside
+// [0, rows_total) is not read: its row becomes zeros and *bad_row is set.
+hipError_t launch_mlp_prep(const float* x, const float* y, const int32_t* rows, size_t rows_total, int* bad_row,
+                           int n, int n_in, int kp, int nz, const float* mu_x, const float* sd_x, const float* mu_y,
+                           const float* sd_y, bf16* xb, float* yt, hipStream_t s);
+
+// d = y - yt; dy = bf16(scale d); loss_partials[b] = sum of d^2 per block
+// (FP64), then loss[0] = sum over blocks / (n nz), FP32.
+hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* dy, double* partials,
+                          float* loss, hipStream_t s);
+int mlp_mse_blocks(int n, int nz);
+
+// out_part[c][j] = sum of a[r][j] over the c-th chunk of 256 rows (FP32).
+hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_part, hipStream_t s);
+int colsum_chunks(int rows);
+// out[i] = sum_p part[p * len + i] (fixed order), FP32.
+hipError_t launch_sum_parts(const float* part, int nparts, size_t len, float* out, hipStream_t s);
+
+// Adam over n parameters (moments m, v; step t >= 1), FP32.
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s);
+
+// bf16 copies of the weights: w1b [hidden][kp] (zero beyond n_in), w2b, w3b,
+// and the transposes w2t [hidden][hidden], w3t [hidden][nz].
+hipError_t launch_refresh_weights(const float* params, int n_in, int hidden, int nz, int kp, bf16* w1b, bf16* w2b,
+                                  bf16* w3b, bf16* w2t, bf16* w3t, hipStream_t s);
+
+// Per-column sums over rows of a [rows][cols] FP32 matrix, in FP64:
+// partials [chunks][cols] of a (mean == nullptr) or of (a - mean)^2, chunk c
+// covering rows [c chunk_rows, (c + 1) chunk_rows).
+constexpr int kMomentChunksMax = 2048;
+size_t moment_chunk_rows(size_t rows);
+hipError_t launch_moment_partials(const float* a, size_t rows, int cols, const double* mean, double* part,
+                                  hipStream_t s);
+
+}  // namespace tpmg

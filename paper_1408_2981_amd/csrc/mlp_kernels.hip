@@ -1,0 +1,455 @@
+// gfx950 kernels of the per-column MLP (learned initial guess): a bf16
+// matrix-core GEMM with fused epilogues, and the small elementwise and
+// reduction kernels around it (features, standardisation, loss, bias
+// gradients, Adam, weight copies, scaling moments).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "mlp_device.h"
+
+namespace tpmg {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ size_t tiled_index(int col, int k, int nz) {
+  return static_cast<size_t>(col >> 6) * 64 * nz + static_cast<size_t>(k) * 64 + (col & 63);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: one workgroup of 4 waves computes a (64 WM) x (64 WN) tile of C; each
+// wave a 64 x 64 block as 2 x 2 matrix-core products of 32 x 32 x 16 (bf16
+// operands, FP32 accumulators). K advances in steps of 32 through LDS
+// (rows padded by 8 bf16 so the 16-byte operand reads spread over the banks).
+// Operand layout of the 32 x 32 x 16 product: lane l supplies row l % 32 of A
+// (column l % 32 of B) at k = 8 (l / 32) .. 8 (l / 32) + 7; accumulator r of
+// lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+// ---------------------------------------------------------------------------
+constexpr int kBK = 32;
+constexpr int kLdsRow = kBK + 8;
+
+// Stages rows [r0, r0 + ROWS) x k [k0, k0 + 32) of a K-contiguous (T false)
+// or R-contiguous (T true) operand into LDS as [row][k]; entries outside
+// r < R, k < kend are zero.
+template <int ROWS, bool T>
+__device__ __forceinline__ void stage(const bf16* __restrict__ src, int ld, int r0, int R, int k0, int kend,
+                                      bf16 (*dst)[kLdsRow]) {
+  constexpr int kChunks = ROWS * kBK / 8;   // 16-byte chunks of 8 bf16
+#pragma unroll
+  for (int c = threadIdx.x; c < kChunks; c += 256) {
+    if (!T) {
+      const int row = c >> 2, kc = (c & 3) * 8;
+      const int r = r0 + row, k = k0 + kc;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (r < R && k < kend) v = *reinterpret_cast<const uint4*>(src + static_cast<size_t>(r) * ld + k);
+      *reinterpret_cast<uint4*>(&dst[row][kc]) = v;
+    } else {
+      constexpr int kPerK = ROWS / 8;
+      const int kk = c / kPerK, rc = (c - kk * kPerK) * 8;
+      const int k = k0 + kk, r = r0 + rc;
+      union {
+        uint4 u;
+        bf16 h[8];
+      } v;
+      v.u = make_uint4(0u, 0u, 0u, 0u);
+      if (k < kend && r < R) v.u = *reinterpret_cast<const uint4*>(src + static_cast<size_t>(k) * ld + r);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dst[rc + i][kk] = v.h[i];
+    }
+  }
+}
+
+template <int WM, int WN, bool TR, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  constexpr int BM = 64 * WM, BN = 64 * WN;
+  __shared__ __align__(16) bf16 As[BM][kLdsRow];
+  __shared__ __align__(16) bf16 Bs[BN][kLdsRow];
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int kbeg = blockIdx.z * g.ksplit;
+  const int kend = min(g.K, kbeg + g.ksplit);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave / WN) * 64, wn = (wave % WN) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  const int lr = lane & 31, lk = 8 * (lane >> 5);
+  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+    stage<BM, TR>(g.A, g.lda, m0, g.M, k0, kend, As);
+    stage<BN, TR>(g.B, g.ldb, n0, g.N, k0, kend, Bs);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kBK; ks += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + lr][ks + lk]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 32 * j + lr][ks + lk]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int n = n0 + wn + 32 * j + lr;
+        if (m >= g.M || n >= g.N) continue;
+        const float c = acc[i][j][r];
+        const size_t o = static_cast<size_t>(m) * g.ldc + n;
+        if (EPI == kEpiBiasReluBf16) {
+          g.out_bf16[o] = static_cast<bf16>(fmaxf(c + g.bias[n], 0.0f));
+        } else if (EPI == kEpiBiasF32) {
+          g.out_f32[o] = c + g.bias[n];
+        } else if (EPI == kEpiMaskBf16) {
+          g.out_bf16[o] = static_cast<float>(g.mask[o]) > 0.0f ? static_cast<bf16>(c) : static_cast<bf16>(0.0f);
+        } else if (EPI == kEpiPartialF32) {
+          g.out_f32[static_cast<size_t>(blockIdx.z) * g.M * g.N + static_cast<size_t>(m) * g.N + n] = c;
+        } else {
+          g.out_f64[tiled_index(m, n, g.N)] = static_cast<double>((c + g.bias[n]) * g.sd[n] + g.mu[n]);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// features, targets, standardisation
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_mlp_features(FineGrid g, const double* __restrict__ f, float* __restrict__ x) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n) return;
+  const int nz = g.nz, nin = nz + 3;
+  float* row = x + static_cast<size_t>(t) * nin;
+  for (int k = 0; k < nz; ++k) row[k] = static_cast<float>(f[tiled_index(t, k, nz)]);
+  for (int j = 0; j < 3; ++j) {
+    const int nb = g.nbr[static_cast<size_t>(j) * g.npad + t];
+    double s = 0.0;
+    for (int k = 0; k < nz; ++k) s += f[tiled_index(nb, k, nz)];
+    row[nz + j] = static_cast<float>(s / nz);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_targets(FineGrid g, const double* __restrict__ u, float* __restrict__ y) {
+  const size_t total = static_cast<size_t>(g.n) * g.nz;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int t = static_cast<int>(i / g.nz), k = static_cast<int>(i - static_cast<size_t>(t) * g.nz);
+    y[i] = static_cast<float>(u[tiled_index(t, k, g.nz)]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_prep(const float* __restrict__ x, const float* __restrict__ y,
+                                                  const int32_t* __restrict__ rows, size_t rows_total,
+                                                  int* __restrict__ bad_row, int n, int nin, int kp, int nz,
+                                                  const float* __restrict__ mu_x, const float* __restrict__ sd_x,
+                                                  const float* __restrict__ mu_y, const float* __restrict__ sd_y,
+                                                  bf16* __restrict__ xb, float* __restrict__ yt) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  const size_t first = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  // source row of batch row r, or -1 for an index outside [0, rows_total)
+  auto source = [&](int r) -> long long {
+    if (!rows) return r;
+    const long long v = rows[r];
+    if (v < 0 || static_cast<size_t>(v) >= rows_total) {
+      *bad_row = 1;
+      return -1;
+    }
+    return v;
+  };
+  const size_t tx = static_cast<size_t>(n) * kp;
+  for (size_t i = first; i < tx; i += stride) {
+    const int r = static_cast<int>(i / kp), j = static_cast<int>(i - static_cast<size_t>(r) * kp);
+    const long long row = source(r);
+    float v = 0.0f;
+    if (j < nin && row >= 0) v = (x[static_cast<size_t>(row) * nin + j] - mu_x[j]) / sd_x[j];
+    xb[i] = static_cast<bf16>(v);
+  }
+  if (!yt) return;
+  const size_t ty = static_cast<size_t>(n) * nz;
+  for (size_t i = first; i < ty; i += stride) {
+    const int r = static_cast<int>(i / nz), k = static_cast<int>(i - static_cast<size_t>(r) * nz);
+    const long long row = source(r);
+    yt[i] = row >= 0 ? (y[static_cast<size_t>(row) * nz + k] - mu_y[k]) / sd_y[k] : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// loss, bias gradients, partial sums
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_mse(const float* __restrict__ y, const float* __restrict__ yt, size_t total,
+                                                 float scale, bf16* __restrict__ dy, double* __restrict__ partials) {
+  double s = 0.0;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float d = y[i] - yt[i];
+    dy[i] = static_cast<bf16>(scale * d);
+    s += static_cast<double>(d) * d;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_loss(const double* __restrict__ partials, int nblocks, double inv_total,
+                                                  float* __restrict__ loss) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partials[b];
+  s = block_sum(s);
+  if (threadIdx.x == 0) loss[0] = static_cast<float>(s * inv_total);
+}
+
+__global__ __launch_bounds__(256) void k_colsum_partial(const bf16* __restrict__ a, int rows, int cols,
+                                                        float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  const int r0 = blockIdx.y * 256, r1 = min(rows, r0 + 256);
+  float s = 0.0f;
+  for (int r = r0; r < r1; ++r) s += static_cast<float>(a[static_cast<size_t>(r) * cols + j]);
+  out[static_cast<size_t>(blockIdx.y) * cols + j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nparts, size_t len,
+                                                   float* __restrict__ out) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    float s = 0.0f;
+    for (int p = 0; p < nparts; ++p) s += part[static_cast<size_t>(p) * len + i];
+    out[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// optimiser and weight copies
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, size_t n, float lr, float bc1, float bc2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_refresh_weights(const float* __restrict__ params, int nin, int h, int nz,
+                                                         int kp, bf16* __restrict__ w1b, bf16* __restrict__ w2b,
+                                                         bf16* __restrict__ w3b, bf16* __restrict__ w2t,
+                                                         bf16* __restrict__ w3t) {
+  const float* W1 = params;
+  const float* W2 = W1 + static_cast<size_t>(h) * nin + h;
+  const float* W3 = W2 + static_cast<size_t>(h) * h + h;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  const size_t first = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (size_t i = first; i < static_cast<size_t>(h) * kp; i += stride) {
+    const int o = static_cast<int>(i / kp), k = static_cast<int>(i - static_cast<size_t>(o) * kp);
+    w1b[i] = static_cast<bf16>(k < nin ? W1[static_cast<size_t>(o) * nin + k] : 0.0f);
+  }
+  for (size_t i = first; i < static_cast<size_t>(h) * h; i += stride) {
+    const int r = static_cast<int>(i / h), c = static_cast<int>(i - static_cast<size_t>(r) * h);
+    const bf16 w = static_cast<bf16>(W2[i]);
+    w2b[i] = w;
+    w2t[static_cast<size_t>(c) * h + r] = w;
+  }
+  for (size_t i = first; i < static_cast<size_t>(nz) * h; i += stride) {
+    const int r = static_cast<int>(i / h), c = static_cast<int>(i - static_cast<size_t>(r) * h);
+    const bf16 w = static_cast<bf16>(W3[i]);
+    w3b[i] = w;
+    w3t[static_cast<size_t>(c) * nz + r] = w;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_moment_partials(const float* __restrict__ a, size_t rows, int cols,
+                                                         size_t chunk_rows, const double* __restrict__ mean,
+                                                         double* __restrict__ part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  const size_t r0 = static_cast<size_t>(blockIdx.y) * chunk_rows;
+  const size_t r1 = std::min(rows, r0 + chunk_rows);
+  double s = 0.0;
+  if (mean) {
+    const double mu = mean[j];
+    for (size_t r = r0; r < r1; ++r) {
+      const double d = static_cast<double>(a[r * cols + j]) - mu;
+      s += d * d;
+    }
+  } else {
+    for (size_t r = r0; r < r1; ++r) s += static_cast<double>(a[r * cols + j]);
+  }
+  part[static_cast<size_t>(blockIdx.y) * cols + j] = s;
+}
+
+unsigned grid_of(size_t work, unsigned cap = 4096) {
+  const size_t b = (work + 255) / 256;
+  return static_cast<unsigned>(std::max<size_t>(1, std::min<size_t>(b, cap)));
+}
+
+template <int WM, int WN, bool TR>
+hipError_t gemm_tile(const GemmArgs& g, hipStream_t s) {
+  const dim3 grid((g.M + 64 * WM - 1) / (64 * WM), (g.N + 64 * WN - 1) / (64 * WN), (g.K + g.ksplit - 1) / g.ksplit);
+  switch (g.epi) {
+    case kEpiBiasReluBf16:
+      hipLaunchKernelGGL((k_gemm<WM, WN, TR, kEpiBiasReluBf16>), grid, dim3(256), 0, s, g);
+      break;
+    case kEpiBiasF32:
+      hipLaunchKernelGGL((k_gemm<WM, WN, TR, kEpiBiasF32>), grid, dim3(256), 0, s, g);
+      break;
+    case kEpiMaskBf16:
+      hipLaunchKernelGGL((k_gemm<WM, WN, TR, kEpiMaskBf16>), grid, dim3(256), 0, s, g);
+      break;
+    case kEpiPartialF32:
+      hipLaunchKernelGGL((k_gemm<WM, WN, TR, kEpiPartialF32>), grid, dim3(256), 0, s, g);
+      break;
+    case kEpiInferTiled:
+      hipLaunchKernelGGL((k_gemm<WM, WN, TR, kEpiInferTiled>), grid, dim3(256), 0, s, g);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
+  GemmArgs g = g0;
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0 || !g.A || !g.B) return hipErrorInvalidValue;
+  if (g.ta != g.tb) return hipErrorInvalidValue;   // both operands K-contiguous, or both transposed
+  if ((!g.ta && g.K % 8) || g.lda % 8 || g.ldb % 8) return hipErrorInvalidValue;
+  if ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) % 16) return hipErrorInvalidValue;
+  auto up8 = [](int v) { return (v + 7) / 8 * 8; };
+  if (!g.ta && (g.lda < g.K || g.ldb < g.K)) return hipErrorInvalidValue;
+  if (g.ta && (g.lda < up8(g.M) || g.ldb < up8(g.N))) return hipErrorInvalidValue;
+  if (g.epi == kEpiPartialF32) {
+    if (g.ksplit <= 0 || g.ksplit % kBK) return hipErrorInvalidValue;
+  } else {
+    g.ksplit = (g.K + kBK - 1) / kBK * kBK;
+  }
+  switch (g.epi) {
+    case kEpiBiasReluBf16:
+    case kEpiMaskBf16:
+      if (!g.out_bf16 || g.ldc < g.N) return hipErrorInvalidValue;
+      if (g.epi == kEpiBiasReluBf16 && !g.bias) return hipErrorInvalidValue;
+      if (g.epi == kEpiMaskBf16 && !g.mask) return hipErrorInvalidValue;
+      break;
+    case kEpiBiasF32:
+      if (!g.out_f32 || !g.bias || g.ldc < g.N) return hipErrorInvalidValue;
+      break;
+    case kEpiPartialF32:
+      if (!g.out_f32) return hipErrorInvalidValue;
+      break;
+    case kEpiInferTiled:
+      if (!g.out_f64 || !g.bias || !g.mu || !g.sd) return hipErrorInvalidValue;
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  const bool tr = g.ta;
+  if (g.N <= 64) return tr ? gemm_tile<4, 1, true>(g, s) : gemm_tile<4, 1, false>(g, s);
+  if (g.M <= 64) return tr ? gemm_tile<1, 4, true>(g, s) : gemm_tile<1, 4, false>(g, s);
+  return tr ? gemm_tile<2, 2, true>(g, s) : gemm_tile<2, 2, false>(g, s);
+}
+
+hipError_t launch_mlp_features(const FineGrid& g, const double* f, float* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_features, dim3((g.n + 255) / 256), dim3(256), 0, s, g, f, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_targets(const FineGrid& g, const double* u, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_targets, dim3(grid_of(static_cast<size_t>(g.n) * g.nz)), dim3(256), 0, s, g, u, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_prep(const float* x, const float* y, const int32_t* rows, size_t rows_total, int* bad_row,
+                           int n, int n_in, int kp, int nz, const float* mu_x, const float* sd_x, const float* mu_y,
+                           const float* sd_y, bf16* xb, float* yt, hipStream_t s) {
+  if (rows && !bad_row) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mlp_prep, dim3(grid_of(static_cast<size_t>(n) * kp)), dim3(256), 0, s, x, y, rows, rows_total,
+                     bad_row, n, n_in, kp, nz, mu_x, sd_x, mu_y, sd_y, xb, yt);
+  return hipGetLastError();
+}
+
+int mlp_mse_blocks(int n, int nz) { return static_cast<int>(grid_of(static_cast<size_t>(n) * nz, 1024)); }
+
+hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* dy, double* partials, float* loss,
+                          hipStream_t s) {
+  const size_t total = static_cast<size_t>(n) * nz;
+  const int nb = mlp_mse_blocks(n, nz);
+  hipLaunchKernelGGL(k_mlp_mse, dim3(nb), dim3(256), 0, s, y, yt, total, 2.0f / static_cast<float>(total), dy,
+                     partials);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, partials, nb, 1.0 / static_cast<double>(total), loss);
+  return hipGetLastError();
+}
+
+int colsum_chunks(int rows) { return (rows + 255) / 256; }
+
+hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_part, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 255) / 256, colsum_chunks(rows)), dim3(256), 0, s, a, rows, cols,
+                     out_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const float* part, int nparts, size_t len, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(grid_of(len)), dim3(256), 0, s, part, nparts, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s) {
+  const double bc1 = 1.0 / (1.0 - std::pow(0.9, t));
+  const double bc2 = 1.0 / (1.0 - std::pow(0.999, t));
+  hipLaunchKernelGGL(k_adam, dim3(grid_of(n)), dim3(256), 0, s, p, g, m, v, n, lr, static_cast<float>(bc1),
+                     static_cast<float>(bc2));
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_weights(const float* params, int n_in, int hidden, int nz, int kp, bf16* w1b, bf16* w2b,
+                                  bf16* w3b, bf16* w2t, bf16* w3t, hipStream_t s) {
+  const size_t work = std::max({static_cast<size_t>(hidden) * kp, static_cast<size_t>(hidden) * hidden,
+                                static_cast<size_t>(nz) * hidden});
+  hipLaunchKernelGGL(k_refresh_weights, dim3(grid_of(work)), dim3(256), 0, s, params, n_in, hidden, nz, kp, w1b, w2b,
+                     w3b, w2t, w3t);
+  return hipGetLastError();
+}
+
+size_t moment_chunk_rows(size_t rows) {
+  const size_t chunks = std::min<size_t>(kMomentChunksMax, std::max<size_t>(1, (rows + 255) / 256));
+  return (rows + chunks - 1) / chunks;
+}
+
+hipError_t launch_moment_partials(const float* a, size_t rows, int cols, const double* mean, double* part,
+                                  hipStream_t s) {
+  const size_t cr = moment_chunk_rows(rows);
+  const unsigned chunks = static_cast<unsigned>((rows + cr - 1) / cr);
+  hipLaunchKernelGGL(k_moment_partials, dim3((cols + 255) / 256, chunks), dim3(256), 0, s, a, rows, cols, cr, mean,
+                     part);
+  return hipGetLastError();
+}
+
+}  // namespace tpmg

@@ -1559,3 +1559,24 @@ void tpmg_mg_destroy(tpmg_mg* mg) {
 }
 
 }  // extern "C"
+
+bool tpmg_fine_grid(const tpmg_mg* mg, tpmg::FineGrid* out) {
+  if (!mg || !out) return false;
+  const DevLevel& d = mg->lv[mg->nlev - 1];
+  out->n = d.n;
+  out->npad = d.npad;
+  out->nz = mg->nz;
+  out->nbr = d.nbr;
+  out->stream = mg->stream;
+  return true;
+}
+
+void tpmg_set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+hipError_t tpmg_relax_finest(const tpmg_mg* mg, const double* f, const double* u_in, double* u_out, double* sd,
+                             double* sc, double omega, hipStream_t s) {
+  if (!mg || !f || !u_in || !u_out || u_in == u_out) return hipErrorInvalidValue;
+  tpmg::LevelView v = mg->view64(mg->nlev - 1);
+  v.tune = tpmg::default_tune(mg->nz, 8);
+  return tpmg::launch_smooth(v, 8, f, true, u_in, false, u_out, true, nullptr, sd, sc, omega, s);
+}

@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tp
 
 
 def test_all_header_symbols_exported():
-    text = open(HEADER).read()
+    inc = os.path.dirname(HEADER)
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     declared = set(re.findall(r"\b(tpmg_[a-z0-9_]+)\s*\(", text))
     assert len(declared) >= 20
     lib = ctypes.CDLL(T.LIB_PATH)
