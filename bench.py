@@ -141,6 +141,120 @@ def anisotropy_report(steps: int = 3):
         print(json.dumps(line), flush=True)
 
 
+def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
+    """Learned initial guess on the sequence f_t = f_0 + 0.05 t g (refinement 6
+    x 64 quadratic levels, 5,242,880 unknowns, smooth seeded fields): solve
+    t = 1..n_train from zero (mixed, rtol 1e-8), train the per-column MLP on
+    those solutions (GPU, bf16 matrix cores, Adam, batch 4096), then solve
+    t = n_train+1..n_total from four guesses: zero, the previous solution,
+    the network (+ one line-relaxation sweep) and the two-step extrapolation
+    2 u_{t-1} - u_{t-2}. Times include producing the guess."""
+    import numpy as np
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    w = synth.workload("ico6_nz64_seq")
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True, autotune=1)
+    geo = P.geometry()
+    vk = P.vk()
+    f0 = P.pack(synth.sequence_rhs(w, geo["centres"], geo["areas"], vk, 0))
+    g = P.pack(synth.sequence_rhs(w, geo["centres"], geo["areas"], vk, 1)) - f0   # 0.05 g as a cell integral
+    torch.cuda.synchronize()
+
+    def rhs(t):
+        f = f0 + float(t) * g
+        torch.cuda.synchronize()
+        return f
+
+    net = T.ColumnMLP(w.nz, 256, max(4096, P.n), stream=P.stream)
+    rng_params = np.random.default_rng(0)
+    n_in, h = w.nz + 3, 256
+    he = lambda fan_in, shape: (rng_params.standard_normal(shape) * math.sqrt(2.0 / fan_in)).astype(np.float32)
+    net.set_params(np.concatenate([he(n_in, (h, n_in)).ravel(), np.zeros(h, np.float32), he(h, (h, h)).ravel(),
+                                   np.zeros(h, np.float32), he(h, (w.nz, h)).ravel(), np.zeros(w.nz, np.float32)]))
+    X = torch.empty((n_train * P.n, n_in), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n_train * P.n, w.nz), dtype=torch.float32, device="cuda")
+    sols = {}
+    t0 = time.perf_counter()
+    for t in range(1, n_train + 1):
+        f = rhs(t)
+        u = P.device_vector()
+        st, it, *_ = P.solve(f, u)
+        net.features(P, f, X[(t - 1) * P.n:t * P.n])
+        net.targets(P, u, Y[(t - 1) * P.n:t * P.n])
+        if t >= n_train - 1:
+            sols[t] = u
+    net.synchronize()
+    t_data = time.perf_counter() - t0
+    log(f"sequence: {n_train} training solves and features in {t_data:.1f} s")
+    net.fit_scaling(X, Y)
+    t0 = time.perf_counter()
+    losses = net.train(X, Y, epochs=epochs, batch=4096, lr=1e-3, seed=0)
+    t_train = time.perf_counter() - t0
+    log(f"sequence: trained {epochs} epochs in {t_train:.1f} s, epoch losses {losses}")
+    steps = epochs * (X.shape[0] // 4096)
+    flop_step = 6.0 * 4096 * (n_in * h + h * h + h * w.nz)
+    del X, Y
+    torch.cuda.empty_cache()
+
+    # inference timing (device events on the shared stream)
+    f = rhs(n_train + 1)
+    u = P.device_vector()
+    infer_ms = {}
+    for relax in (0, 1):
+        for _ in range(3):
+            net.infer(P, f, u, relax)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
+        for _ in range(20):
+            net.infer(P, f, u, relax)
+        e1.record(P.stream)
+        e1.synchronize()
+        infer_ms[relax] = e0.elapsed_time(e1) / 20
+    flop_inf = 2.0 * P.n * (n_in * h + h * h + h * w.nz)
+
+    res = {k: {"iters": [], "ms": []} for k in ("zero", "previous", "network", "extrapolation")}
+    for t in range(n_train + 1, n_total + 1):
+        f = rhs(t)
+        for kind in res:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if kind == "zero":
+                u = P.device_vector()
+            elif kind == "previous":
+                u = sols[t - 1].clone()
+            elif kind == "extrapolation":
+                u = 2.0 * sols[t - 1] - sols[t - 2]
+            else:
+                u = P.device_vector()
+                net.infer(P, f, u, 1)
+            torch.cuda.synchronize()
+            st, it, *_ = P.solve(f, u)
+            res[kind]["ms"].append(1000.0 * (time.perf_counter() - t1))
+            res[kind]["iters"].append(it)
+            if kind == "zero":
+                sol = u
+        sols[t] = sol
+        sols.pop(t - 2, None)
+    line = {"workload": f"{w.name}: f_t = f_0 + 0.05 t g, refinement 6 x nz 64 quadratic, {w.unknowns} unknowns, "
+                        f"mixed, rtol 1e-8; train t=1..{n_train}, evaluate t={n_train + 1}..{n_total}",
+            "train": {"samples": n_train * P.n, "epochs": epochs, "steps": steps, "batch": 4096,
+                      "epoch_loss": losses, "seconds": t_train, "data_seconds": t_data,
+                      "TFLOPs_per_s": flop_step * steps / t_train / 1e12},
+            "inference": {"ms_network": infer_ms[0], "ms_with_relaxation": infer_ms[1], "GFLOP": flop_inf / 1e9,
+                          "TFLOPs_per_s": flop_inf / (infer_ms[0] / 1000.0) / 1e12,
+                          "mfma_bf16_peak_TFLOPs": 2500.0,
+                          "frac": flop_inf / (infer_ms[0] / 1000.0) / 1e12 / 2500.0}}
+    for kind, r in res.items():
+        line[kind] = {"mean_iters": float(np.mean(r["iters"])), "max_iters": int(np.max(r["iters"])),
+                      "mean_ms_incl_guess": float(np.mean(r["ms"]))}
+    print(json.dumps(line), flush=True)
+    net.close()
+    P.close()
+
+
 def batch_report(steps: int = 3):
     """Sixteen solves of uneven size (refinement 4/5/6 x nz 32/64/128,
     quadratic grading, seeded uniform right-hand sides, mixed precision):
@@ -219,6 +333,9 @@ def main():
     ap.add_argument("--workload", default="ico6_nz128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=50)
+    ap.add_argument("--sequence", action="store_true",
+                    help="only the learned-initial-guess sequence report (refinement 6 x nz 64, 200 solves)")
+    ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
                     help="choose kernels by timed trials at setup (excluded from the timed solves)")
     ap.add_argument("--report", action="store_true",
@@ -246,6 +363,9 @@ def main():
     log(f"workload {w.name}: {w.unknowns} unknowns, refinement {w.refinement}, nz {w.nz}")
     if args.profile_sweep:
         profile_sweep(w, args.sweep_reps)
+        return
+    if args.sequence:
+        sequence_report(epochs=args.epochs)
         return
     results = {}
     P64 = T.Problem(w.refinement, w.r_faces(), w.omega2)
@@ -328,6 +448,7 @@ def main():
             P.close()
         torch.cuda.empty_cache()
         batch_report()
+        sequence_report()
         anisotropy_report()
 
 

@@ -256,7 +256,8 @@ tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* mo
  * prolongation + correction, the FP64 operator) are chosen per level and
  * per precision at tpmg_mg_setup. With params->autotune the setup times
  * each admissible candidate on the workspace (a few launches each) and
- * keeps the fastest; the choice is stored in a process-wide cache keyed by
+ * keeps the fastest (the built-in choice unless another is 5% faster); the
+ * choice is stored in a process-wide cache keyed by
  * device (architecture and compute-unit count), kernel, precision, padded
  * column count and nz, so that later setups of the same shape run no trials.
  * The smoother choice changes the rounding order of the column solve (the

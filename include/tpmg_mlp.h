@@ -76,7 +76,8 @@ tpmg_status tpmg_mlp_fit_scaling(tpmg_mlp* m, const float* d_x, const float* d_y
 /* Features of every finest-grid column of mg from a right-hand side d_f
  * (tiled FP64, as tpmg_solve), written to d_x [n_cells][nz + 3]; targets
  * from a solution d_u, written to d_y [n_cells][nz]. mg's nz must equal the
- * network's. Asynchronous on the network's stream. */
+ * network's and (features) n_cells <= max_rows. Asynchronous on the
+ * network's stream. */
 tpmg_status tpmg_mlp_features(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, float* d_x);
 tpmg_status tpmg_mlp_targets(tpmg_mlp* m, const tpmg_mg* mg, const double* d_u, float* d_y);
 

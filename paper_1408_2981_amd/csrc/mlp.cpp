@@ -40,7 +40,7 @@ struct Carve {
   }
 };
 
-constexpr int kSplitMax = 16;   // K slices of the weight-gradient products
+constexpr int kSplitMax = 128;   // K slices of the weight-gradient products
 constexpr uint32_t kFileMagic = 0x504c4d54u;   // file tag of saved networks
 
 size_t param_count(int nz, int h) {
@@ -71,7 +71,7 @@ struct tpmg_mlp {
   std::vector<double> h_mu_x, h_sd_x, h_mu_y, h_sd_y;
   // activations of up to max_rows rows
   bf16 *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *dh2 = nullptr, *dh1 = nullptr;
-  float *y = nullptr, *yt = nullptr, *xraw = nullptr;
+  float *y = nullptr, *yt = nullptr;
   // reductions
   float* gpart = nullptr;     // kSplitMax x largest weight matrix
   float* cpart = nullptr;     // column-sum chunks x hidden
@@ -82,6 +82,7 @@ struct tpmg_mlp {
   int* bad_row = nullptr;     // set by a batch that names a row outside [0, rows_total)
   // inference before line relaxation, and the relaxation's scratch (tiled FP64)
   double *guess = nullptr, *rsd = nullptr, *rsc = nullptr;
+  double* colmean = nullptr;  // column means of a right-hand side (features)
 
   // parameter offsets in the packed array
   size_t oW1() const { return 0; }
@@ -118,7 +119,6 @@ void carve(tpmg_mlp& m, Carve& c) {
   m.dh1 = c.take<bf16>(R * m.h);
   m.y = c.take<float>(R * m.nz);
   m.yt = c.take<float>(R * m.nz);
-  m.xraw = c.take<float>(R * m.nin);
   const size_t wmax = std::max({static_cast<size_t>(m.h) * m.nin, static_cast<size_t>(m.h) * m.h,
                                 static_cast<size_t>(m.nz) * m.h});
   m.gpart = c.take<float>(kSplitMax * wmax);
@@ -132,6 +132,7 @@ void carve(tpmg_mlp& m, Carve& c) {
   m.guess = c.take<double>(tiled);
   m.rsd = c.take<double>(tiled);
   m.rsc = c.take<double>(tiled);
+  m.colmean = c.take<double>(m.max_rows);
 }
 
 tpmg_status check(const tpmg_mlp* m) {
@@ -213,7 +214,10 @@ hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out) {
 // row-major [batch][lda] and [batch][ldc], written to grads + off
 hipError_t weight_grad(tpmg_mlp& m, const bf16* a, int lda, int M, const bf16* c, int ldc, int N, int batch,
                        size_t off) {
-  int ksplit = (batch + kSplitMax - 1) / kSplitMax;
+  // slices of the batch: about 256 workgroups in all, at least 32 rows each
+  const long tiles = std::max(1L, (static_cast<long>(M) * N) / (128L * 128L));
+  const int want = static_cast<int>(std::min<long>(kSplitMax, std::max(1L, 256L / tiles)));
+  int ksplit = (batch + want - 1) / want;
   ksplit = std::max(32, (ksplit + 31) / 32 * 32);
   const int nsplit = (batch + ksplit - 1) / ksplit;
   tpmg::GemmArgs g;
@@ -467,7 +471,8 @@ tpmg_status tpmg_mlp_features(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f,
   tpmg::FineGrid g;
   if ((st = check_grid(m, mg, &g)) != TPMG_OK) return st;
   if (!d_f || !d_x) return fail(TPMG_ERR_ARG, "NULL device buffer");
-  MLP_HIP(tpmg::launch_mlp_features(g, d_f, d_x, m->stream));
+  if (g.n > m->max_rows) return fail(TPMG_ERR_ARG, "the grid has more columns than max_rows");
+  MLP_HIP(tpmg::launch_mlp_features(g, d_f, m->colmean, d_x, m->stream));
   return TPMG_OK;
 }
 
@@ -532,9 +537,7 @@ tpmg_status tpmg_mlp_infer(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, in
   if (g.n > m->max_rows) return fail(TPMG_ERR_ARG, "the grid has more columns than max_rows");
   if (relax != 0 && relax != 1) return fail(TPMG_ERR_ARG, "relax must be 0 or 1");
   if (g.stream != m->stream) return fail(TPMG_ERR_ARG, "the network and mg must share one stream");
-  MLP_HIP(tpmg::launch_mlp_features(g, d_f, m->xraw, m->stream));
-  MLP_HIP(tpmg::launch_mlp_prep(m->xraw, nullptr, nullptr, 0, nullptr, g.n, m->nin, m->kp, m->nz, m->mu_x, m->sd_x,
-                                m->mu_y, m->sd_y, m->xb, nullptr, m->stream));
+  MLP_HIP(tpmg::launch_mlp_features_bf16(g, d_f, m->colmean, m->mu_x, m->sd_x, m->kp, m->xb, m->stream));
   if (!relax) {
     MLP_HIP(forward(*m, g.n, tpmg::kEpiInferTiled, nullptr, d_u0));
     return TPMG_OK;

@@ -50,8 +50,12 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 
 // x[T][j]: the column's right-hand side (j < nz) and the vertical means of
-// neighbours 0..2 (j = nz + i), from a tiled FP64 vector.
-hipError_t launch_mlp_features(const FineGrid& g, const double* f, float* x, hipStream_t s);
+// neighbours 0..2 (j = nz + i), from a tiled FP64 vector; means: scratch of
+// n doubles (the column means). The _bf16 form writes the standardised,
+// bf16-rounded rows xb[T][kp] instead (zeros beyond nz + 3).
+hipError_t launch_mlp_features(const FineGrid& g, const double* f, double* means, float* x, hipStream_t s);
+hipError_t launch_mlp_features_bf16(const FineGrid& g, const double* f, double* means, const float* mu_x,
+                                    const float* sd_x, int kp, bf16* xb, hipStream_t s);
 // y[T][k] = u(T, k), FP32.
 hipError_t launch_mlp_targets(const FineGrid& g, const double* u, float* y, hipStream_t s);
 
@@ -69,7 +73,7 @@ hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* 
                           float* loss, hipStream_t s);
 int mlp_mse_blocks(int n, int nz);
 
-// out_part[c][j] = sum of a[r][j] over the c-th chunk of 256 rows (FP32).
+// out_part[c][j] = sum of a[r][j] over the c-th chunk of 64 rows (FP32).
 hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_part, hipStream_t s);
 int colsum_chunks(int rows);
 // out[i] = sum_p part[p * len + i] (fixed order), FP32.

@@ -15,6 +15,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+constexpr int kTileCols = 64;
+
 __device__ __forceinline__ size_t tiled_index(int col, int k, int nz) {
   return static_cast<size_t>(col >> 6) * 64 * nz + static_cast<size_t>(k) * 64 + (col & 63);
 }
@@ -129,26 +131,57 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // features, targets, standardisation
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_mlp_features(FineGrid g, const double* __restrict__ f, float* __restrict__ x) {
+// mean over the levels of every real column of a tiled FP64 vector (FP64)
+__global__ __launch_bounds__(256) void k_col_means(FineGrid g, const double* __restrict__ v, double* __restrict__ means) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.n) return;
-  const int nz = g.nz, nin = nz + 3;
-  float* row = x + static_cast<size_t>(t) * nin;
-  for (int k = 0; k < nz; ++k) row[k] = static_cast<float>(f[tiled_index(t, k, nz)]);
-  for (int j = 0; j < 3; ++j) {
-    const int nb = g.nbr[static_cast<size_t>(j) * g.npad + t];
-    double s = 0.0;
-    for (int k = 0; k < nz; ++k) s += f[tiled_index(nb, k, nz)];
-    row[nz + j] = static_cast<float>(s / nz);
-  }
+  double s = 0.0;
+  for (int k = 0; k < g.nz; ++k) s += v[tiled_index(t, k, g.nz)];
+  means[t] = s / g.nz;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_targets(FineGrid g, const double* __restrict__ u, float* __restrict__ y) {
-  const size_t total = static_cast<size_t>(g.n) * g.nz;
-  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int t = static_cast<int>(i / g.nz), k = static_cast<int>(i - static_cast<size_t>(t) * g.nz);
-    y[i] = static_cast<float>(u[tiled_index(t, k, g.nz)]);
+// One tile of 64 columns per block: the tile's values (level-major, one
+// coalesced row of 64 per level) are staged in LDS column-major with an odd
+// stride, completed by the neighbour means, and written out as contiguous
+// rows. MODE 0: raw features x[T][nz + 3]; MODE 1: standardised bf16 features
+// xb[T][kp] (zeros beyond nz + 3); MODE 2: values y[T][nz].
+template <int MODE>
+__global__ __launch_bounds__(256) void k_columns_to_rows(FineGrid g, const double* __restrict__ v,
+                                                         const double* __restrict__ means,
+                                                         const float* __restrict__ mu, const float* __restrict__ sd,
+                                                         int kp, void* __restrict__ out) {
+  extern __shared__ float lds[];
+  const int nz = g.nz;
+  const int w = MODE == 2 ? nz : nz + 3;    // row length
+  const int ws = MODE == 2 ? nz + 1 : nz + 3;   // LDS stride (odd: nz is a multiple of 8)
+  const int tile = blockIdx.x;
+  const size_t base = static_cast<size_t>(tile) * kTileCols * nz;
+  for (int i = threadIdx.x; i < kTileCols * nz; i += blockDim.x) {
+    const int k = i >> 6, c = i & 63;
+    lds[c * ws + k] = static_cast<float>(v[base + i]);
+  }
+  const int cnt = min(kTileCols, g.n - tile * kTileCols);
+  if (MODE != 2) {
+    for (int i = threadIdx.x; i < kTileCols * 3; i += blockDim.x) {
+      const int c = i / 3, j = i - 3 * c;
+      const int t = tile * kTileCols + c;
+      lds[c * ws + nz + j] = c < cnt ? static_cast<float>(means[g.nbr[static_cast<size_t>(j) * g.npad + t]]) : 0.0f;
+    }
+  }
+  __syncthreads();
+  if (MODE == 1) {
+    bf16* xb = static_cast<bf16*>(out) + static_cast<size_t>(tile) * kTileCols * kp;
+    for (int i = threadIdx.x; i < cnt * kp; i += blockDim.x) {
+      const int c = i / kp, j = i - c * kp;
+      const float val = j < w ? (lds[c * ws + j] - mu[j]) / sd[j] : 0.0f;
+      xb[i] = static_cast<bf16>(val);
+    }
+  } else {
+    float* o = static_cast<float*>(out) + static_cast<size_t>(tile) * kTileCols * w;
+    for (int i = threadIdx.x; i < cnt * w; i += blockDim.x) {
+      const int c = i / w, j = i - c * w;
+      o[i] = lds[c * ws + j];
+    }
   }
 }
 
@@ -221,14 +254,25 @@ __global__ __launch_bounds__(256) void k_mlp_loss(const double* __restrict__ par
   if (threadIdx.x == 0) loss[0] = static_cast<float>(s * inv_total);
 }
 
-__global__ __launch_bounds__(256) void k_colsum_partial(const bf16* __restrict__ a, int rows, int cols,
+// partial column sums of 64 rows per chunk: 64 columns x 4 row groups per block
+__global__ __launch_bounds__(256) void k_colsum_partial(const bf16* __restrict__ a, int rows, int cols, int chunks,
                                                         float* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
-  const int r0 = blockIdx.y * 256, r1 = min(rows, r0 + 256);
-  float s = 0.0f;
-  for (int r = r0; r < r1; ++r) s += static_cast<float>(a[static_cast<size_t>(r) * cols + j]);
-  out[static_cast<size_t>(blockIdx.y) * cols + j] = s;
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  for (int chunk = blockIdx.y; chunk < chunks; chunk += gridDim.y) {
+    const int r0 = chunk * 64;
+    float s = 0.0f;
+    if (j < cols)
+      for (int i = 0; i < 16; ++i) {
+        const int r = r0 + grp + 4 * i;
+        if (r < rows) s += static_cast<float>(a[static_cast<size_t>(r) * cols + j]);
+      }
+    red[grp][c] = s;
+    __syncthreads();
+    if (grp == 0 && j < cols) out[static_cast<size_t>(chunk) * cols + j] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nparts, size_t len,
@@ -377,14 +421,33 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
   return tr ? gemm_tile<2, 2, true>(g, s) : gemm_tile<2, 2, false>(g, s);
 }
 
-hipError_t launch_mlp_features(const FineGrid& g, const double* f, float* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_features, dim3((g.n + 255) / 256), dim3(256), 0, s, g, f, x);
+static hipError_t columns_to_rows(int mode, const FineGrid& g, const double* v, const double* means,
+                                  const float* mu, const float* sd, int kp, void* out, hipStream_t s) {
+  const int ws = mode == 2 ? g.nz + 1 : g.nz + 3;
+  const size_t lds = static_cast<size_t>(kTileCols) * ws * sizeof(float);
+  const dim3 grid(g.npad / kTileCols);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_columns_to_rows<0>, grid, dim3(256), lds, s, g, v, means, mu, sd, kp, out);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_columns_to_rows<1>, grid, dim3(256), lds, s, g, v, means, mu, sd, kp, out);
+  else
+    hipLaunchKernelGGL(k_columns_to_rows<2>, grid, dim3(256), lds, s, g, v, means, mu, sd, kp, out);
   return hipGetLastError();
 }
 
+hipError_t launch_mlp_features(const FineGrid& g, const double* f, double* means, float* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_means, dim3((g.n + 255) / 256), dim3(256), 0, s, g, f, means);
+  return columns_to_rows(0, g, f, means, nullptr, nullptr, 0, x, s);
+}
+
+hipError_t launch_mlp_features_bf16(const FineGrid& g, const double* f, double* means, const float* mu_x,
+                                    const float* sd_x, int kp, bf16* xb, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_means, dim3((g.n + 255) / 256), dim3(256), 0, s, g, f, means);
+  return columns_to_rows(1, g, f, means, mu_x, sd_x, kp, xb, s);
+}
+
 hipError_t launch_mlp_targets(const FineGrid& g, const double* u, float* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_targets, dim3(grid_of(static_cast<size_t>(g.n) * g.nz)), dim3(256), 0, s, g, u, y);
-  return hipGetLastError();
+  return columns_to_rows(2, g, u, nullptr, nullptr, nullptr, 0, y, s);
 }
 
 hipError_t launch_mlp_prep(const float* x, const float* y, const int32_t* rows, size_t rows_total, int* bad_row,
@@ -408,11 +471,12 @@ hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* 
   return hipGetLastError();
 }
 
-int colsum_chunks(int rows) { return (rows + 255) / 256; }
+int colsum_chunks(int rows) { return (rows + 63) / 64; }
 
 hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 255) / 256, colsum_chunks(rows)), dim3(256), 0, s, a, rows, cols,
-                     out_part);
+  const int chunks = colsum_chunks(rows);
+  hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 63) / 64, std::min(chunks, 65535)), dim3(256), 0, s, a, rows, cols,
+                     chunks, out_part);
   return hipGetLastError();
 }
 

@@ -46,17 +46,22 @@ class ColumnMLP:
 
     # data ---------------------------------------------------------------------
     def _ready(self, *tensors) -> None:
-        """Tensors made on torch's stream must be complete before the library's stream reads them."""
+        """Tensors made on torch's stream must be complete before the library's
+        stream reads them, and must not be recycled by torch's allocator while
+        the library's stream may still use them (record_stream)."""
         import torch
 
         torch.cuda.current_stream().synchronize()
+        for t in tensors:
+            if hasattr(t, "record_stream") and hasattr(self.stream, "cuda_stream"):
+                t.record_stream(self.stream)
 
     def features(self, problem, f_tiled, out=None):
         import torch
 
         if out is None:
             out = torch.empty((problem.n, self.n_in), dtype=torch.float32, device="cuda")
-        self._ready()
+        self._ready(f_tiled, out)
         tpmg_mlp_features(self.h, problem.mg, f_tiled, out)
         return out
 
@@ -65,7 +70,7 @@ class ColumnMLP:
 
         if out is None:
             out = torch.empty((problem.n, self.nz), dtype=torch.float32, device="cuda")
-        self._ready()
+        self._ready(u_tiled, out)
         tpmg_mlp_targets(self.h, problem.mg, u_tiled, out)
         return out
 
@@ -73,16 +78,17 @@ class ColumnMLP:
         import torch
 
         y = torch.empty((x.shape[0], self.nz), dtype=torch.float32, device="cuda")
-        self._ready()
+        self._ready(x, y)
         tpmg_mlp_forward(self.h, x, x.shape[0], y)
         self.stream.synchronize()
         return y
 
     def gradients(self, x, y, rows):
-        self._ready()
+        self._ready(x, y, rows)
         return tpmg_mlp_gradients(self.h, x, y, x.shape[0], rows, rows.shape[0], self.n_params)
 
     def train_step(self, x, y, rows, lr: float, want_loss: bool = False):
+        self._ready(x, y, rows)
         return tpmg_mlp_train_step(self.h, x, y, x.shape[0], rows, rows.shape[0], lr, want_loss)
 
     def train(self, x, y, epochs: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0, loss_every: int = 50):
@@ -93,10 +99,10 @@ class ColumnMLP:
         rows_total = x.shape[0]
         rng = np.random.default_rng(seed)
         per_epoch = []
-        self._ready()
+        self._ready(x, y)
         for _ in range(epochs):
             perm = torch.from_numpy(rng.permutation(rows_total).astype(np.int32)).to("cuda")
-            torch.cuda.current_stream().synchronize()
+            self._ready(perm)
             losses = []
             nb = rows_total // batch
             for b in range(nb):
@@ -111,6 +117,7 @@ class ColumnMLP:
     def infer(self, problem, f_tiled, u0_tiled, relax: int = 1) -> None:
         """u0_tiled (a zeroed tiled vector of problem) receives the guess, followed by
         one line-relaxation sweep when relax = 1; asynchronous on the shared stream."""
+        self._ready(f_tiled, u0_tiled)
         tpmg_mlp_infer(self.h, problem.mg, f_tiled, u0_tiled, relax)
 
     def save(self, path: str) -> None:

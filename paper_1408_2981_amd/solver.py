@@ -92,10 +92,18 @@ class Problem:
 
     # The calls below run on the library's stream; their tensors must be
     # complete on torch's stream first (device_vector / pack guarantee that).
+    def _uses(self, *tensors):
+        """Keeps torch's allocator from recycling tensors the library's stream may still read or write."""
+        for t in tensors:
+            if hasattr(t, "record_stream") and hasattr(self.stream, "cuda_stream"):
+                t.record_stream(self.stream)
+
     def spmv(self, x_tiled, y_tiled):
+        self._uses(x_tiled, y_tiled)
         tpmg_spmv(self.mg, x_tiled, y_tiled)
 
     def vcycle(self, r_tiled, z_tiled):
+        self._uses(r_tiled, z_tiled)
         tpmg_vcycle(self.mg, r_tiled, z_tiled)
 
     def solve(self, f_tiled, u_tiled, rtol: float = 1e-8, maxit: int = 100):

@@ -63,8 +63,9 @@ def test_features_and_targets_match_oracle():
     f = synth.sequence_rhs(w, fine.centre, fine.area, h.vert.vk, 3)
     u = np.random.default_rng(2).standard_normal(f.shape)
     net = T.ColumnMLP(w.nz, 64, 4096, stream=P.stream)
-    x = net.features(P, P.pack(f))
-    y = net.targets(P, P.pack(u))
+    fd, ud = P.pack(f), P.pack(u)
+    x = net.features(P, fd)
+    y = net.targets(P, ud)
     net.synchronize()
     xo = omlp.features(f, fine.nbr)
     assert x.shape == xo.shape
