@@ -31,19 +31,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(scan_levels: int):
     """HBM bytes per finest-sweep dispatch from the committed counter summary,
-    or None when kernels.hip has changed since the counters were taken."""
+    or None when kernels.hip has changed since the counters were taken or the
+    timed sweep uses another levels-per-wave instance than the one counted."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "smoother_ico6_nz128_counters.md")
     src = os.path.join(ROOT, "paper_1408_2981_amd", "csrc", "kernels.hip")
     try:
-        vals = dict(l.strip().split(": ", 1) for l in open(path) if l.strip().startswith(("traffic_", "kernels_hip_")))
+        vals = dict(l.strip().split(": ", 1) for l in open(path)
+                    if l.strip().startswith(("traffic_", "kernels_hip_", "scan_levels")))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if vals.get("kernels_hip_sha256") != digest:
+    if vals.get("kernels_hip_sha256") != digest or vals.get("scan_levels") != str(scan_levels):
         return None
     return float(vals["traffic_bytes_per_dispatch"])
 
@@ -434,7 +436,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic() if args.workload == "ico6_nz128" else None,
+            "traffic": measured_traffic(P32.tuning()[-1]["scan_levels"]) if args.workload == "ico6_nz128" else None,
             "avg_launch_us": mixed["sweep_ms"] * 1000.0,
             "bytes_per_launch": mixed["sweep_bytes"],
         },
