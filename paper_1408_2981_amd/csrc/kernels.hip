@@ -429,23 +429,33 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
 // Line smoother, scan form (nz <= kScanWavesMax * KB): one workgroup per
 // tile of 64 columns, wave w owns the levels [w*kb, (w+1)*kb) (kb <= KB) of
 // every column and keeps them in registers. The column solve of the margin-form
-// Thomas algorithm is evaluated by three block scans over the waves:
-//  * pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) is a Moebius map,
-//    (P, Q) -> ((e_k + l_k) P + e_k l_k Q, P + l_k Q) with s = P / Q; the
-//    product of a block's 2x2 matrices (positive entries, rescaled by exact
-//    powers of two) gives each wave the margin s entering its block;
-//  * elimination: d_k = (l_k d_{k-1} + r_k) / p_k, an affine map in d;
-//  * back substitution: x_k = (m_k / p_k) x_{k+1} + d_k, affine in x.
-// Every wave composes its block's map, publishes it in LDS, and applies the
-// published maps of the blocks before (after) it to obtain its incoming value.
-// The chain is therefore kb + n_waves steps instead of nz, and the only
-// workgroup-wide data in LDS are the per-wave summaries.
+// Thomas algorithm is evaluated in two rounds of block scans over the waves:
+//  1. pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) is a Moebius map,
+//     (P, Q) -> ((e_k + l_k) P + e_k l_k Q, P + l_k Q) with s = P / Q; each
+//     wave forms its block's product of 2x2 matrices (positive entries,
+//     rescaled by exact powers of two) and publishes it in LDS; wave 0 runs
+//     the products up the column and hands every block its incoming margin;
+//  2. the elimination d_k = (l_k d_{k-1} + r_k) / p_k and the back
+//     substitution x_k = (m_k / p_k) x_{k+1} + d_k are affine; each block's
+//     composition is summarised as d_last = A d_in + B and
+//     x_first = C x_in + Dd d_in + Db, so wave 0 finds every block's d_in
+//     (bottom up) and then x_in (top down) in one round.
+// The chain is kb + 2 n_waves steps instead of 2 nz, only wave 0 runs the
+// across-block chains, and the only workgroup-wide data in LDS are the
+// per-wave summaries.
+
+// binary exponent e with v = m 2^e, 0.5 <= m < 1 (v > 0), and v 2^-e
+__device__ __forceinline__ int exp_of(float v) { return __builtin_amdgcn_frexp_expf(v); }
+__device__ __forceinline__ int exp_of(double v) { return __builtin_amdgcn_frexp_exp(v); }
+__device__ __forceinline__ float scale2(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
+__device__ __forceinline__ double scale2(double v, int e) { return __builtin_amdgcn_ldexp(v, e); }
+
 template <typename T>
 __device__ __forceinline__ void rescale2(T& a, T& b) {
   // multiply both entries by the same power of two so the larger is O(1)
-  const int e = max(ilogb(a), ilogb(b));
-  a = scalbn(a, -e);
-  b = scalbn(b, -e);
+  const int e = exp_of(max(a, b));
+  a = scale2(a, -e);
+  b = scale2(b, -e);
 }
 
 template <typename T>
@@ -506,8 +516,10 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     }
   }
 
-  // ---- pivots: block product of the Moebius matrices [[e+l, e l'], [1, l']]
-  // (l' = l_k, or 1 on level 0 where l_0 = 0, so that (0, 1) -> (e_0, 1))
+  // ---- round 1, pivot margins: block product of the Moebius matrices
+  // [[e+l, e l'], [1, l']] (l' = l_k, or 1 on level 0 where l_0 = 0, so that
+  // (0, 1) -> (e_0, 1)); wave 0 turns the blocks' products into each block's
+  // incoming margin s_in = P / Q
   T p00 = T(1), p01 = T(0), p10 = T(0), p11 = T(1);
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
@@ -517,12 +529,11 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
       const T a = ei + li, b = ei * lp;
       const T n00 = a * p00 + b * p10, n01 = a * p01 + b * p11;
       const T n10 = p00 + lp * p10, n11 = p01 + lp * p11;
-      const T mx = max(max(n00, n01), max(n10, n11));
-      const int ex = ilogb(mx);
-      p00 = scalbn(n00, -ex);
-      p01 = scalbn(n01, -ex);
-      p10 = scalbn(n10, -ex);
-      p11 = scalbn(n11, -ex);
+      const int ex = exp_of(max(max(n00, n01), max(n10, n11)));
+      p00 = scale2(n00, -ex);
+      p01 = scale2(n01, -ex);
+      p10 = scale2(n10, -ex);
+      p11 = scale2(n11, -ex);
     }
   }
   at(wave, 0) = p00;
@@ -530,72 +541,101 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   at(wave, 2) = p10;
   at(wave, 3) = p11;
   __syncthreads();
-  T P = T(0), Q = T(1);
-  for (int j = 0; j < wave; ++j) {
-    const T nP = at(j, 0) * P + at(j, 1) * Q;
-    const T nQ = at(j, 2) * P + at(j, 3) * Q;
-    P = nP;
-    Q = nQ;
-    rescale2(P, Q);
+  if (wave == 0) {
+    T P = T(0), Q = T(1);
+    for (int j = 0; j < nw; ++j) {
+      const T a00 = at(j, 0), a01 = at(j, 1), a10 = at(j, 2), a11 = at(j, 3);
+      at(j, 0) = P;
+      at(j, 1) = Q;
+      const T nP = a00 * P + a01 * Q;
+      const T nQ = a10 * P + a11 * Q;
+      P = nP;
+      Q = nQ;
+      rescale2(P, Q);
+    }
   }
-  // local margins and pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k)
-  T ip[KB];
+  __syncthreads();
+
+  // local pivots p_k = s_k + m_k with s_k = e_k + l_k s_{k-1} / p_{k-1} (one
+  // reciprocal per level; p_{k0-1} = s_in + m_{k0-1}, m_{k0-1} = l_{k0}); keep
+  // the elimination factor l_k / p_k, the substitution factor m_k / p_k and
+  // r_k / p_k
+  T la[KB], mc[KB];
   {
-    T s_prev = wave == 0 ? T(0) : P * rcp_of(Q);
+    T s_prev = T(0), ip_prev = T(0);
+    if (wave > 0) {
+      s_prev = at(wave, 0) * rcp_of(at(wave, 1));
+      ip_prev = rcp_of(s_prev + l_of(0));
+    }
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
       if (i < nb) {
-        const T ei = e_of(i), li = l_of(i);
-        const T s = (k0 + i == 0) ? ei : ei + li * s_prev * rcp_of(s_prev + li);
-        ip[i] = rcp_of(s + m_of(i));
+        const T ei = e_of(i), li = l_of(i), mi = m_of(i);
+        const T s = (k0 + i == 0) ? ei : ei + li * s_prev * ip_prev;
+        const T ip = rcp_of(s + mi);
+        la[i] = li * ip;
+        mc[i] = mi * ip;
+        r[i] *= ip;
         s_prev = s;
+        ip_prev = ip;
       }
     }
   }
 
-  // ---- elimination d_k = a_k d_{k-1} + b_k, a_k = l_k / p_k, b_k = r_k / p_k
-  T A = T(1), B = T(0);
+  // ---- round 2: the block's elimination d_k = la_k d_{k-1} + r_k and back
+  // substitution x_k = mc_k x_{k+1} + d_k as affine maps of the incoming
+  // d_in (from the block below) and x_in (from the block above):
+  //   d_last = A d_in + B,  x_first = C x_in + Dd d_in + Db
+  T A = T(1), B = T(0), C = T(1), Dd = T(0), Db = T(0);
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     if (i < nb) {
-      const T a = l_of(i) * ip[i];
-      A = a * A;
-      B = a * B + r[i] * ip[i];
+      A = la[i] * A;
+      B = la[i] * B + r[i];
+      Dd += C * A;
+      Db += C * B;
+      C *= mc[i];
     }
   }
-  at(wave, 4) = A;
-  at(wave, 5) = B;
+  // (each wave overwrites only its own slots, which wave 0 filled before the
+  // last barrier and this wave has read)
+  at(wave, 0) = A;
+  at(wave, 1) = B;
+  at(wave, 2) = C;
+  at(wave, 3) = Dd;
+  at(wave, 4) = Db;
   __syncthreads();
-  T d = T(0);
-  for (int j = 0; j < wave; ++j) d = at(j, 4) * d + at(j, 5);
-#pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    if (i < nb) {
-      d = l_of(i) * ip[i] * d + r[i] * ip[i];
-      r[i] = d;   // r now holds d
+  if (wave == 0) {
+    T d = T(0);
+    for (int j = 0; j < nw; ++j) {   // d_in of each block, bottom up
+      const T aj = at(j, 0), bj = at(j, 1);
+      at(j, 5) = d;
+      d = aj * d + bj;
+    }
+    T x = T(0);
+    for (int j = nw - 1; j >= 0; --j) {   // x_in of each block, top down
+      const T din = at(j, 5);
+      at(j, 6) = x;
+      x = at(j, 2) * x + at(j, 3) * din + at(j, 4);
     }
   }
-
-  // ---- back substitution x_k = c_k x_{k+1} + d_k, c_k = m_k / p_k
-  T C = T(1), D = T(0);
-#pragma unroll
-  for (int i = KB - 1; i >= 0; --i) {
-    if (i < nb) {
-      const T cc = m_of(i) * ip[i];
-      C = cc * C;
-      D = cc * D + r[i];
-    }
-  }
-  at(wave, 6) = C;
-  at(wave, 7) = D;
   __syncthreads();
-  T x = T(0);
-  for (int j = nw - 1; j > wave; --j) x = at(j, 6) * x + at(j, 7);
+  {
+    T d = at(wave, 5);
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      if (i < nb) {
+        d = la[i] * d + r[i];
+        r[i] = d;   // r now holds d
+      }
+    }
+  }
+  T x = at(wave, 6);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = KB - 1; i >= 0; --i) {
     if (i < nb) {
-      x = m_of(i) * ip[i] * x + r[i];
+      x = mc[i] * x + r[i];
       const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
       const T uo = ZERO ? omega * x : uu[i] + omega * x;
       const TO zo = static_cast<TO>(uo);
