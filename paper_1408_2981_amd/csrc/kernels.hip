@@ -492,26 +492,52 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   auto l_of = [&](int i) -> T { return c.arh * L.arv[k0 + i]; };
   auto m_of = [&](int i) -> T { return c.arh * L.arv[k0 + i + 1]; };
 
-  // ---- residual of the wave's levels, in registers
+  // ---- residual of the wave's levels, in registers. All loads are issued
+  // before any is used: their level indices are clamped into the column (the
+  // value of a clamped load is discarded), so no branch separates them and
+  // the wave waits for memory once, not once per level.
   T r[KB], uu[KB];
   double fd[DOTS ? KB : 1];
+  {
+    TF fv[KB];
+    T n0[ZERO ? 1 : KB], n1[ZERO ? 1 : KB], n2[ZERO ? 1 : KB];
+    T below = T(0), above = T(0);
 #pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    if (i < nb) {
-      const int k = k0 + i;
-      const size_t o = c.base + static_cast<size_t>(k) * kTile;
-      if (DOTS) fd[i] = static_cast<double>(f[o]);
-      const T fk = static_cast<T>(f[o]);
-      if (FCOPY) fcopy[o] = fk;
-      if (ZERO) {
-        r[i] = fk;
-        uu[i] = T(0);
-      } else {
-        const T um = k > 0 ? u_in[o - kTile] : T(0);
-        const T uc = u_in[o];
-        const T up = k + 1 < nz ? u_in[o + kTile] : T(0);
-        uu[i] = uc;
-        r[i] = fk - apply_row(L, c, u_in, k, um, uc, up);
+    for (int i = 0; i < KB; ++i) {
+      const size_t ok = static_cast<size_t>(min(k0 + i, nz - 1)) * kTile;
+      fv[i] = f[c.base + ok];
+      if (!ZERO) {
+        uu[i] = u_in[c.base + ok];
+        n0[i] = u_in[c.b0 + ok];
+        n1[i] = u_in[c.b1 + ok];
+        n2[i] = u_in[c.b2 + ok];
+      }
+    }
+    if (!ZERO) {
+      const T b = u_in[c.base + static_cast<size_t>(max(k0 - 1, 0)) * kTile];
+      const T a = u_in[c.base + static_cast<size_t>(min(k0 + nb, nz - 1)) * kTile];
+      below = k0 > 0 ? b : T(0);
+      above = k0 + nb < nz ? a : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      if (i < nb) {
+        const int k = k0 + i;
+        if (DOTS) fd[i] = static_cast<double>(fv[i]);
+        const T fk = static_cast<T>(fv[i]);
+        if (FCOPY) fcopy[c.base + static_cast<size_t>(k) * kTile] = fk;
+        if (ZERO) {
+          r[i] = fk;
+          uu[i] = T(0);
+        } else {
+          const T uc = uu[i];
+          const T um = i == 0 ? below : uu[i > 0 ? i - 1 : 0];
+          const T next = i + 1 < KB ? uu[i + 1 < KB ? i + 1 : KB - 1] : above;
+          const T up = i + 1 < nb ? next : above;
+          const T h = c.a0 * (uc - n0[i]) + c.a1 * (uc - n1[i]) + c.a2 * (uc - n2[i]);
+          const T v = L.arv[k + 1] * (uc - up) + L.arv[k] * (uc - um);
+          r[i] = fk - (c.bh * L.bv[k] * uc + L.av[k] * h + c.arh * v);
+        }
       }
     }
   }
@@ -774,6 +800,11 @@ template <int KB, typename T>
 constexpr int scan_waves_per_simd(bool dots) {
   return (sizeof(T) == 4 && KB <= 8 && !dots) ? 8 : (sizeof(T) == 8 && KB == 16) ? 2 : 4;
 }
+// the batched form also holds its segment's pointers: no FP32 bound beyond 4
+template <int KB, typename T>
+constexpr int scan_waves_per_simd_batched() {
+  return (sizeof(T) == 8 && KB == 16) ? 2 : 4;
+}
 template <int KB, typename T>
 constexpr int scan_max_threads() {
   return 64 * ((sizeof(T) == 8 && KB == 16) ? 8 : kScanWavesMax);
@@ -870,15 +901,15 @@ __device__ __forceinline__ const Seg* find_segment(const Seg* __restrict__ segs,
 // (the segment lookup costs registers: the fused-dots variant keeps its
 // natural allocation rather than spilling under the FP32 bound)
 template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd<KB, T>(DOTS))) void kb_smooth_scan(const Seg* __restrict__ segs,
+__global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd_batched<KB, T>())) void kb_smooth_scan(const Seg* __restrict__ segs,
                                                                                         int nseg, double omega) {
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(view<T>(sg->L), static_cast<const TF*>(sg->in0),
-                                                 static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
-                                                 static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q,
-                                                 sg->partials, g);
+                                                     static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
+                                                     static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q,
+                                                     sg->partials, g);
 }
 
 template <typename T>
