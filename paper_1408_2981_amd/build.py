@@ -55,7 +55,7 @@ def build(verbose: bool = False) -> str:
         list(ex.map(lambda j: _run(j[0]), jobs))
     objs = [obj for _, obj in jobs]
     tmp = OUT + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-Wl,--no-undefined", "-o", tmp, *objs])
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)

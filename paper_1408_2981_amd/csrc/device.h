@@ -165,8 +165,8 @@ hipError_t launch_fcg_update(double* x, double* r, const double* p, const double
 // <z, q>, <z, r> (site kFinBeta), for nz beyond the fused smoother's range.
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s);
-// p = z + beta p (beta from the scalars), in place.
-hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s);
+// p = z + beta p (beta from the scalars), in place; z FP64 or FP32.
+hipError_t launch_pupdate(const void* z, bool z_double, double* p, const FcgScalars* sc, size_t len, hipStream_t s);
 hipError_t launch_add(double* x, const double* y, size_t len, hipStream_t s);   // x += y
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);   // zero fill (graph-safe)
 

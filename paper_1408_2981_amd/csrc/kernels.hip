@@ -768,12 +768,13 @@ __device__ __forceinline__ void dots_body(const double* __restrict__ z, const do
   block_sums(acc, partials, g.b);
 }
 
-__device__ __forceinline__ void pupdate_body(const double* __restrict__ z, double* __restrict__ p,
+template <typename TZ>
+__device__ __forceinline__ void pupdate_body(const TZ* __restrict__ z, double* __restrict__ p,
                                              const FcgScalars* __restrict__ sc, size_t len, GridPos g) {
   const double beta = sc->beta;
   for (size_t i = static_cast<size_t>(g.b) * blockDim.x + threadIdx.x; i < len;
        i += static_cast<size_t>(g.nb) * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+    p[i] = static_cast<double>(z[i]) + beta * p[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -841,7 +842,8 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, cons
   dots_body(z, q, r, len, partials, whole_grid());
 }
 
-__global__ __launch_bounds__(256) void k_pupdate(const double* __restrict__ z, double* __restrict__ p,
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_pupdate(const TZ* __restrict__ z, double* __restrict__ p,
                                                  const FcgScalars* __restrict__ sc, size_t len) {
   pupdate_body(z, p, sc, len, whole_grid());
 }
@@ -938,11 +940,12 @@ __global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, i
                static_cast<double*>(sg->out0), sg->partials, g);
 }
 
+template <typename TZ>
 __global__ __launch_bounds__(256) void kb_pupdate(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  pupdate_body(static_cast<const double*>(sg->in0), static_cast<double*>(sg->out0), sg->sc, sg->len, g);
+  pupdate_body(static_cast<const TZ*>(sg->in0), static_cast<double*>(sg->out0), sg->sc, sg->len, g);
 }
 
 __global__ __launch_bounds__(256) void kb_fcg_update(const Seg* __restrict__ segs, int nseg) {
@@ -1074,7 +1077,11 @@ void smoother_variant(bool f_double, bool out_double, bool zero, bool fcopy, boo
     else
       fn(D{}, D{}, Bool<false>{}, Bool<false>{}, Bool<false>{});
   } else if (f_double) {
-    if (zero && fcopy)
+    if (dots && zero)
+      fn(D{}, P{}, Bool<true>{}, Bool<false>{}, Bool<true>{});
+    else if (dots)
+      fn(D{}, P{}, Bool<false>{}, Bool<false>{}, Bool<true>{});
+    else if (zero && fcopy)
       fn(D{}, P{}, Bool<true>{}, Bool<true>{}, Bool<false>{});
     else if (zero)
       fn(D{}, P{}, Bool<true>{}, Bool<false>{}, Bool<false>{});
@@ -1227,8 +1234,13 @@ hipError_t launch_dots(const double* z, const double* q, const double* r, size_t
   return hipGetLastError();
 }
 
-hipError_t launch_pupdate(const double* z, double* p, const FcgScalars* sc, size_t len, hipStream_t s) {
-  hipLaunchKernelGGL(k_pupdate, dim3(pupdate_blocks(len)), dim3(256), 0, s, z, p, sc, len);
+hipError_t launch_pupdate(const void* z, bool z_double, double* p, const FcgScalars* sc, size_t len, hipStream_t s) {
+  if (z_double)
+    hipLaunchKernelGGL(k_pupdate<double>, dim3(pupdate_blocks(len)), dim3(256), 0, s, static_cast<const double*>(z), p,
+                       sc, len);
+  else
+    hipLaunchKernelGGL(k_pupdate<float>, dim3(pupdate_blocks(len)), dim3(256), 0, s, static_cast<const float*>(z), p,
+                       sc, len);
   return hipGetLastError();
 }
 
@@ -1294,7 +1306,10 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
       hipLaunchKernelGGL(kb_spmv64, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       break;
     case kOpPupdate:
-      hipLaunchKernelGGL(kb_pupdate, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      if (b.f_double)
+        hipLaunchKernelGGL(kb_pupdate<double>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      else
+        hipLaunchKernelGGL(kb_pupdate<float>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       break;
     case kOpUpdate:
       hipLaunchKernelGGL(kb_fcg_update, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);

@@ -257,8 +257,8 @@ bool order_less(const Op& a, const Op& b) {
 // mixed mode every level is FP32: the first finest sweep reads the FP64
 // residual and keeps an FP32 copy of it, the last writes FP64 z (and, when
 // q_dots is given, also forms <z, q> and <z, r>, applied at kFinBeta).
-void vcycle_ops(tpmg_mg& m, const double* r_in, double* z_out, const double* q_dots, tpmg::FcgScalars* sc,
-                std::vector<Op>& ops) {
+void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dots, tpmg::FcgScalars* sc,
+                std::vector<Op>& ops, bool z_float = false) {
   const int L = m.nlev - 1;
   const int prec = m.fp32 ? 4 : 8;
   std::vector<int> cur(m.nlev, 0);
@@ -304,8 +304,8 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, double* z_out, const double* q_d
       const bool dots = last_of_cycle && q_dots;
       const void* f = (finest_first || dots) ? static_cast<const void*>(r_in) : rhs(l);
       const bool f_double = dots || ((l == L) && (finest_first || !m.fp32));
-      void* out = last_of_cycle ? static_cast<void*>(z_out) : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
-      sweep(0, j, 0, k, l, f, f_double, first, out, last_of_cycle, finest_first && m.fp32, dots);
+      void* out = last_of_cycle ? z_out : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
+      sweep(0, j, 0, k, l, f, f_double, first, out, last_of_cycle && !z_float, finest_first && m.fp32, dots);
       if (!first) cur[l] = 1 - cur[l];
     }
     if (l > 0) {
@@ -337,11 +337,11 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, double* z_out, const double* q_d
     ops.push_back(op);
     for (int k = 0; k < m.nu_post; ++k) {
       const bool last = l == L && k + 1 == m.nu_post;
-      void* out = last ? static_cast<void*>(z_out) : m.lv[l].u[1 - cur[l]];
+      void* out = last ? z_out : m.lv[l].u[1 - cur[l]];
       // the last sweep reads the FP64 residual when it also forms <z, q>, <z, r>
       const bool dots = last && q_dots;
       sweep(1, -j, 1, k, l, dots ? static_cast<const void*>(r_in) : rhs(l), dots || (l == L && !m.fp32), false, out,
-            last, false, dots);
+            last && !z_float, false, dots);
       if (!last) cur[l] = 1 - cur[l];
     }
   }
@@ -355,7 +355,10 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, double* z_out, const double* q_d
 // (kind -1, single solves only).
 void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) {
   const bool fused = m.tune.back().smoother == tpmg::kSmScan;
-  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops);
+  // z of an FP32 V-cycle is an FP32 value: kept in FP32 when the last sweep
+  // also forms the dots (nothing else reads it in FP64)
+  const bool z_float = fused && m.fp32;
+  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops, z_float);
   if (!fused) {
     Op d;
     d.order[0] = 2;
@@ -372,6 +375,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) 
   pu.order[0] = 2;
   pu.order[1] = 1;
   pu.kind = tpmg::kOpPupdate;
+  pu.f_double = !z_float;
   pu.in0 = m.z;
   pu.out0 = m.p;
   pu.sc = sc;
@@ -415,7 +419,7 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
     case tpmg::kOpProlong:
       return tpmg::launch_prolong_add(op.L, op.C, op.prec, op.in0, op.out0, s);
     case tpmg::kOpPupdate:
-      return tpmg::launch_pupdate(static_cast<const double*>(op.in0), static_cast<double*>(op.out0), op.sc, op.len, s);
+      return tpmg::launch_pupdate(op.in0, op.f_double, static_cast<double*>(op.out0), op.sc, op.len, s);
     case tpmg::kOpSpmv:
       return tpmg::launch_spmv64(op.L, 0, static_cast<const double*>(op.in0), nullptr, static_cast<double*>(op.out0),
                                  op.partials, op.site, op.sc, s);
