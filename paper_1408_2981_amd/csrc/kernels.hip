@@ -88,15 +88,53 @@ __device__ __forceinline__ Column<T> load_column(const Lv<T>& L, int col) {
   return c;
 }
 
-// (A u)_k given the own-column values um = u_{k-1}, uc = u_k, up = u_{k+1}
+// (A u)_k in flux form from the own-column values um = u_{k-1}, uc = u_k,
+// up = u_{k+1} and the neighbour-column values n0, n1, n2 at level k (every
+// kernel evaluates a row through this one expression)
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// The fused multiply-adds are written out, so the rounding of a row does not
+// depend on how a kernel's instance happens to be compiled.
+template <typename T>
+__device__ __forceinline__ T row_flux(const Lv<T>& L, const Column<T>& c, int k, T um, T uc, T up, T n0, T n1, T n2) {
+  const T h = fma_t(c.a2, uc - n2, fma_t(c.a1, uc - n1, c.a0 * (uc - n0)));
+  const T v = fma_t(L.arv[k], uc - um, L.arv[k + 1] * (uc - up));
+  return fma_t(c.arh, v, fma_t(L.av[k], h, (c.bh * L.bv[k]) * uc));
+}
+
 template <typename T>
 __device__ __forceinline__ T apply_row(const Lv<T>& L, const Column<T>& c, const T* __restrict__ u, int k, T um,
                                        T uc, T up) {
   const size_t o = static_cast<size_t>(k) * kTile;
-  const T h = c.a0 * (uc - u[c.b0 + o]) + c.a1 * (uc - u[c.b1 + o]) + c.a2 * (uc - u[c.b2 + o]);
-  const T v = L.arv[k + 1] * (uc - up) + L.arv[k] * (uc - um);
-  return c.bh * L.bv[k] * uc + L.av[k] * h + c.arh * v;
+  return row_flux(L, c, k, um, uc, up, u[c.b0 + o], u[c.b1 + o], u[c.b2 + o]);
 }
+
+// Values of a column at levels k0-1 .. k0+CH and of its neighbours at
+// k0 .. k0+CH-1, all loaded before any is used (indices clamped into the
+// column; the callers ignore the clamped entries)
+template <typename T, int CH>
+struct ChunkLoads {
+  T xv[CH + 2], n0[CH], n1[CH], n2[CH];
+  __device__ __forceinline__ void load(const Column<T>& c, const T* __restrict__ u, int k0, int nz) {
+#pragma unroll
+    for (int i = 0; i < CH + 2; ++i) xv[i] = u[c.base + static_cast<size_t>(min(max(k0 - 1 + i, 0), nz - 1)) * kTile];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const size_t ok = static_cast<size_t>(min(k0 + i, nz - 1)) * kTile;
+      n0[i] = u[c.b0 + ok];
+      n1[i] = u[c.b1 + ok];
+      n2[i] = u[c.b2 + ok];
+    }
+  }
+  // (A u)_{k0+i} for k0 + i < nz
+  __device__ __forceinline__ T row(const Lv<T>& L, const Column<T>& c, int k0, int i) const {
+    const int k = k0 + i;
+    const T um = k > 0 ? xv[i] : T(0);
+    const T up = k + 1 < L.nz ? xv[i + 2] : T(0);
+    return row_flux(L, c, k, um, xv[i + 1], up, n0[i], n1[i], n2[i]);
+  }
+};
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -210,10 +248,11 @@ __device__ __forceinline__ void finalize_body(int site, const double* __restrict
 
 // MODE 0: y = A x, partials <x, y>. MODE 1: y = b - A x, partials <y, y>,
 // <b, b>.
-template <int MODE>
-__device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk, const double* __restrict__ x,
+template <int MODE, int CH>
+__device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, const double* __restrict__ x,
                                           const double* __restrict__ b, double* __restrict__ y,
                                           double* __restrict__ partials, GridPos g) {
+  const int chunk = CH > 0 ? CH : chunk_rt;
   const int nchunks = (L.nz + chunk - 1) / chunk;
   const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -222,24 +261,39 @@ __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk, const 
     const int tile = item / nchunks, chunk_i = item - tile * nchunks;
     const int k0 = chunk_i * chunk, k1 = min(L.nz, k0 + chunk);
     const Column<double> c = load_column(L, tile * kTile + lane);
-    double um = k0 > 0 ? x[c.base + static_cast<size_t>(k0 - 1) * kTile] : 0.0;
-    double uc = x[c.base + static_cast<size_t>(k0) * kTile];
-    for (int k = k0; k < k1; ++k) {
+    auto emit = [&](int k, double uc, double ax, double bk) {
       const size_t o = c.base + static_cast<size_t>(k) * kTile;
-      const double up = k + 1 < L.nz ? x[o + kTile] : 0.0;
-      const double ax = apply_row(L, c, x, k, um, uc, up);
       if (MODE == 0) {
         y[o] = ax;
         acc[0] += uc * ax;
       } else {
-        const double bk = b[o];
         const double rk = bk - ax;
         y[o] = rk;
         acc[0] += rk * rk;
         acc[1] += bk * bk;
       }
-      um = uc;
-      uc = up;
+    };
+    if constexpr (CH > 0) {
+      ChunkLoads<double, CH> ld;
+      ld.load(c, x, k0, L.nz);
+      double bb[MODE == 1 ? CH : 1];
+      if (MODE == 1) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) bb[MODE == 1 ? i : 0] = b[c.base + static_cast<size_t>(min(k0 + i, L.nz - 1)) * kTile];
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (k0 + i < k1) emit(k0 + i, ld.xv[i + 1], ld.row(L, c, k0, i), MODE == 1 ? bb[MODE == 1 ? i : 0] : 0.0);
+    } else {
+      double um = k0 > 0 ? x[c.base + static_cast<size_t>(k0 - 1) * kTile] : 0.0;
+      double uc = x[c.base + static_cast<size_t>(k0) * kTile];
+      for (int k = k0; k < k1; ++k) {
+        const size_t o = c.base + static_cast<size_t>(k) * kTile;
+        const double up = k + 1 < L.nz ? x[o + kTile] : 0.0;
+        emit(k, uc, apply_row(L, c, x, k, um, uc, up), MODE == 1 ? b[o] : 0.0);
+        um = uc;
+        uc = up;
+      }
     }
   }
   block_sums(acc, partials, g.b);
@@ -534,9 +588,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
           const T um = i == 0 ? below : uu[i > 0 ? i - 1 : 0];
           const T next = i + 1 < KB ? uu[i + 1 < KB ? i + 1 : KB - 1] : above;
           const T up = i + 1 < nb ? next : above;
-          const T h = c.a0 * (uc - n0[i]) + c.a1 * (uc - n1[i]) + c.a2 * (uc - n2[i]);
-          const T v = L.arv[k + 1] * (uc - up) + L.arv[k] * (uc - um);
-          r[i] = fk - (c.bh * L.bv[k] * uc + L.av[k] * h + c.arh * v);
+          r[i] = fk - row_flux(L, c, k, um, uc, up, n0[i], n1[i], n2[i]);
         }
       }
     }
@@ -677,10 +729,11 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 
 // residual on the fine level, summed over the four children of each coarse
 // cell (Algorithm 1 residual + restriction by summation, Section 5)
-template <typename T>
-__device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk, int n_coarse,
+template <typename T, int CH>
+__device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk_rt, int n_coarse,
                                                        const T* __restrict__ f, const T* __restrict__ u,
                                                        T* __restrict__ fc, GridPos g) {
+  const int chunk = CH > 0 ? CH : chunk_rt;
   const int nchunks = (L.nz + chunk - 1) / chunk;
   const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -691,17 +744,30 @@ __device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk
   const int P = col >> 2;
   const Column<T> c = load_column(L, col);
   const size_t pb = tile_base(P, L.nz);
-  T um = k0 > 0 ? u[c.base + static_cast<size_t>(k0 - 1) * kTile] : T(0);
-  T uc = u[c.base + static_cast<size_t>(k0) * kTile];
-  for (int k = k0; k < k1; ++k) {
-    const size_t o = c.base + static_cast<size_t>(k) * kTile;
-    const T up = k + 1 < L.nz ? u[o + kTile] : T(0);
-    T r = f[o] - apply_row(L, c, u, k, um, uc, up);
+  auto emit = [&](int k, T r) {
     r += __shfl_xor(r, 1, 64);
     r += __shfl_xor(r, 2, 64);
     if ((lane & 3) == 0 && P < n_coarse) fc[pb + static_cast<size_t>(k) * kTile] = r;
-    um = uc;
-    uc = up;
+  };
+  if constexpr (CH > 0) {
+    ChunkLoads<T, CH> ld;
+    ld.load(c, u, k0, L.nz);
+    T fv[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) fv[i] = f[c.base + static_cast<size_t>(min(k0 + i, L.nz - 1)) * kTile];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (k0 + i < k1) emit(k0 + i, fv[i] - ld.row(L, c, k0, i));
+  } else {
+    T um = k0 > 0 ? u[c.base + static_cast<size_t>(k0 - 1) * kTile] : T(0);
+    T uc = u[c.base + static_cast<size_t>(k0) * kTile];
+    for (int k = k0; k < k1; ++k) {
+      const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      const T up = k + 1 < L.nz ? u[o + kTile] : T(0);
+      emit(k, f[o] - apply_row(L, c, u, k, um, uc, up));
+      um = uc;
+      uc = up;
+    }
   }
 }
 
@@ -786,11 +852,11 @@ __global__ __launch_bounds__(256) void k_finalize(int site, const double* __rest
   finalize_body(site, partials, nblocks, sc, rtol);
 }
 
-template <int MODE>
+template <int MODE, int CH>
 __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const double* __restrict__ x,
                                                 const double* __restrict__ b, double* __restrict__ y,
                                                 double* __restrict__ partials) {
-  spmv_body<MODE>(L, chunk, x, b, y, partials, whole_grid());
+  spmv_body<MODE, CH>(L, chunk, x, b, y, partials, whole_grid());
 }
 
 // Occupancy: an FP32 sweep with up to 8 levels per wave fits two 16-wave
@@ -818,10 +884,10 @@ __global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd<K
   smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
 }
 
-template <typename T>
+template <typename T, int CH>
 __global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int chunk, int n_coarse, const T* __restrict__ f,
                                                            const T* __restrict__ u, T* __restrict__ fc) {
-  residual_restrict_body<T>(L, chunk, n_coarse, f, u, fc, whole_grid());
+  residual_restrict_body<T, CH>(L, chunk, n_coarse, f, u, fc, whole_grid());
 }
 
 template <typename T>
@@ -919,7 +985,7 @@ __global__ __launch_bounds__(256) void kb_residual_restrict(const Seg* __restric
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  residual_restrict_body<T>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
+  residual_restrict_body<T, 0>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
                             static_cast<const T*>(sg->in1), static_cast<T*>(sg->out0), g);
 }
 
@@ -936,7 +1002,7 @@ __global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, i
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  spmv_body<0>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
+  spmv_body<0, 0>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
                static_cast<double*>(sg->out0), sg->partials, g);
 }
 
@@ -1039,15 +1105,32 @@ hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgSca
   return hipGetLastError();
 }
 
+// Calls fn(std::integral_constant<int, CH>): CH = chunk for the unrolled
+// instances 1, 2, 4, 8, 16, else 0 (the loop over a runtime chunk).
+template <typename Fn>
+void chunk_variant(int chunk, Fn&& fn) {
+  switch (chunk) {
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    case 8: fn(std::integral_constant<int, 8>{}); break;
+    case 16: fn(std::integral_constant<int, 16>{}); break;
+    default: fn(std::integral_constant<int, 0>{}); break;
+  }
+}
+
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
                          double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol) {
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
-  if (mode == 0)
-    hipLaunchKernelGGL(k_spmv64<0>, dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
-  else
-    hipLaunchKernelGGL(k_spmv64<1>, dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
+  chunk_variant(chunk, [&](auto chc) {
+    constexpr int CH = decltype(chc)::value;
+    if (mode == 0)
+      hipLaunchKernelGGL((k_spmv64<0, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
+    else
+      hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
+  });
   if (site != kFinNone)
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol);
   return hipGetLastError();
@@ -1198,12 +1281,15 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
                                     const void* u, void* f_coarse, hipStream_t s) {
   const int chunk = effective_chunk(L.tune.chunk_rr, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
-  if (prec == 8)
-    hipLaunchKernelGGL(k_residual_restrict<double>, dim3(blocks), dim3(256), 0, s, view<double>(L), chunk, C.n,
-                       static_cast<const double*>(f), static_cast<const double*>(u), static_cast<double*>(f_coarse));
-  else
-    hipLaunchKernelGGL(k_residual_restrict<float>, dim3(blocks), dim3(256), 0, s, view<float>(L), chunk, C.n,
-                       static_cast<const float*>(f), static_cast<const float*>(u), static_cast<float*>(f_coarse));
+  chunk_variant(chunk, [&](auto chc) {
+    constexpr int CH = decltype(chc)::value;
+    if (prec == 8)
+      hipLaunchKernelGGL((k_residual_restrict<double, CH>), dim3(blocks), dim3(256), 0, s, view<double>(L), chunk, C.n,
+                         static_cast<const double*>(f), static_cast<const double*>(u), static_cast<double*>(f_coarse));
+    else
+      hipLaunchKernelGGL((k_residual_restrict<float, CH>), dim3(blocks), dim3(256), 0, s, view<float>(L), chunk, C.n,
+                         static_cast<const float*>(f), static_cast<const float*>(u), static_cast<float*>(f_coarse));
+  });
   return hipGetLastError();
 }
 
