@@ -131,13 +131,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // features, targets, standardisation
 // ---------------------------------------------------------------------------
 
-// mean over the levels of every real column of a tiled FP64 vector (FP64)
+// mean over the levels of every real column of a tiled FP64 vector (FP64):
+// one block per tile, four groups of levels per column summed apart (each
+// load a coalesced 64-wide row) and combined in a fixed order
 __global__ __launch_bounds__(256) void k_col_means(FineGrid g, const double* __restrict__ v, double* __restrict__ means) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.n) return;
+  __shared__ double part[4][kTileCols];
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int t = blockIdx.x * kTileCols + c;
+  const size_t base = static_cast<size_t>(blockIdx.x) * kTileCols * g.nz + c;
   double s = 0.0;
-  for (int k = 0; k < g.nz; ++k) s += v[tiled_index(t, k, g.nz)];
-  means[t] = s / g.nz;
+  for (int k = grp; k < g.nz; k += 4) s += v[base + static_cast<size_t>(k) * kTileCols];
+  part[grp][c] = s;
+  __syncthreads();
+  if (grp == 0 && t < g.n) means[t] = ((part[0][c] + part[1][c]) + (part[2][c] + part[3][c])) / g.nz;
 }
 
 // One tile of 64 columns per block: the tile's values (level-major, one
@@ -275,13 +281,21 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const bf16* __restrict__
   }
 }
 
+// out[i] = sum over p of part[p][i]: 64 elements x 4 groups of parts per
+// block, the groups combined in a fixed order
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nparts, size_t len,
                                                    float* __restrict__ out) {
-  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+  __shared__ float red[4][64];
+  const int e = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  for (size_t i0 = static_cast<size_t>(blockIdx.x) * 64; i0 < len; i0 += static_cast<size_t>(gridDim.x) * 64) {
+    const size_t i = i0 + e;
     float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += part[static_cast<size_t>(p) * len + i];
-    out[i] = s;
+    if (i < len)
+      for (int p = grp; p < nparts; p += 4) s += part[static_cast<size_t>(p) * len + i];
+    red[grp][e] = s;
+    __syncthreads();
+    if (grp == 0 && i < len) out[i] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+    __syncthreads();
   }
 }
 
@@ -436,13 +450,13 @@ static hipError_t columns_to_rows(int mode, const FineGrid& g, const double* v, 
 }
 
 hipError_t launch_mlp_features(const FineGrid& g, const double* f, double* means, float* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_means, dim3((g.n + 255) / 256), dim3(256), 0, s, g, f, means);
+  hipLaunchKernelGGL(k_col_means, dim3(g.npad / kTileCols), dim3(256), 0, s, g, f, means);
   return columns_to_rows(0, g, f, means, nullptr, nullptr, 0, x, s);
 }
 
 hipError_t launch_mlp_features_bf16(const FineGrid& g, const double* f, double* means, const float* mu_x,
                                     const float* sd_x, int kp, bf16* xb, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_means, dim3((g.n + 255) / 256), dim3(256), 0, s, g, f, means);
+  hipLaunchKernelGGL(k_col_means, dim3(g.npad / kTileCols), dim3(256), 0, s, g, f, means);
   return columns_to_rows(1, g, f, means, mu_x, sd_x, kp, xb, s);
 }
 
@@ -481,7 +495,8 @@ hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_p
 }
 
 hipError_t launch_sum_parts(const float* part, int nparts, size_t len, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_parts, dim3(grid_of(len)), dim3(256), 0, s, part, nparts, len, out);
+  hipLaunchKernelGGL(k_sum_parts, dim3(static_cast<unsigned>(std::min<size_t>((len + 63) / 64, 4096))), dim3(256), 0, s,
+                     part, nparts, len, out);
   return hipGetLastError();
 }
 
