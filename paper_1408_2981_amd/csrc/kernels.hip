@@ -483,18 +483,18 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
 // Line smoother, scan form (nz <= kScanWavesMax * KB): one workgroup per
 // tile of 64 columns, wave w owns the levels [w*kb, (w+1)*kb) (kb <= KB) of
 // every column and keeps them in registers. The column solve of the margin-form
-// Thomas algorithm is evaluated in two rounds of block scans over the waves:
+// Thomas algorithm is evaluated in three rounds of block scans over the waves:
 //  1. pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) is a Moebius map,
 //     (P, Q) -> ((e_k + l_k) P + e_k l_k Q, P + l_k Q) with s = P / Q; each
 //     wave forms its block's product of 2x2 matrices (positive entries,
 //     rescaled by exact powers of two) and publishes it in LDS; wave 0 runs
 //     the products up the column and hands every block its incoming margin;
-//  2. the elimination d_k = (l_k d_{k-1} + r_k) / p_k and the back
-//     substitution x_k = (m_k / p_k) x_{k+1} + d_k are affine; each block's
-//     composition is summarised as d_last = A d_in + B and
-//     x_first = C x_in + Dd d_in + Db, so wave 0 finds every block's d_in
-//     (bottom up) and then x_in (top down) in one round.
-// The chain is kb + 2 n_waves steps instead of 2 nz, only wave 0 runs the
+//  2. elimination: d_k = (l_k d_{k-1} + r_k) / p_k, an affine map in d;
+//  3. back substitution: x_k = (m_k / p_k) x_{k+1} + d_k, affine in x, its
+//     block maps formed from the block's own d (composing the substitution
+//     with the elimination instead, to save a round, loses the column's
+//     near-null component in FP32 at extreme anisotropy).
+// The chain is kb + 3 n_waves steps instead of 2 nz, only wave 0 runs the
 // across-block chains, and the only workgroup-wide data in LDS are the
 // per-wave summaries.
 
@@ -660,46 +660,34 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     }
   }
 
-  // ---- round 2: the block's elimination d_k = la_k d_{k-1} + r_k and back
-  // substitution x_k = mc_k x_{k+1} + d_k as affine maps of the incoming
-  // d_in (from the block below) and x_in (from the block above):
-  //   d_last = A d_in + B,  x_first = C x_in + Dd d_in + Db
-  T A = T(1), B = T(0), C = T(1), Dd = T(0), Db = T(0);
+  // ---- round 2, elimination d_k = la_k d_{k-1} + r_k: the block's map
+  // d_last = A d_in + B; wave 0 runs it up the column
+  {
+    T A = T(1), B = T(0);
 #pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    if (i < nb) {
-      A = la[i] * A;
-      B = la[i] * B + r[i];
-      Dd += C * A;
-      Db += C * B;
-      C *= mc[i];
+    for (int i = 0; i < KB; ++i) {
+      if (i < nb) {
+        A = la[i] * A;
+        B = la[i] * B + r[i];
+      }
     }
+    // (each wave overwrites only its own slots, which wave 0 filled before the
+    // last barrier and this wave has read)
+    at(wave, 0) = A;
+    at(wave, 1) = B;
   }
-  // (each wave overwrites only its own slots, which wave 0 filled before the
-  // last barrier and this wave has read)
-  at(wave, 0) = A;
-  at(wave, 1) = B;
-  at(wave, 2) = C;
-  at(wave, 3) = Dd;
-  at(wave, 4) = Db;
   __syncthreads();
   if (wave == 0) {
     T d = T(0);
-    for (int j = 0; j < nw; ++j) {   // d_in of each block, bottom up
+    for (int j = 0; j < nw; ++j) {
       const T aj = at(j, 0), bj = at(j, 1);
-      at(j, 5) = d;
+      at(j, 2) = d;
       d = aj * d + bj;
-    }
-    T x = T(0);
-    for (int j = nw - 1; j >= 0; --j) {   // x_in of each block, top down
-      const T din = at(j, 5);
-      at(j, 6) = x;
-      x = at(j, 2) * x + at(j, 3) * din + at(j, 4);
     }
   }
   __syncthreads();
   {
-    T d = at(wave, 5);
+    T d = at(wave, 2);
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
       if (i < nb) {
@@ -708,7 +696,32 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
       }
     }
   }
-  T x = at(wave, 6);
+
+  // ---- round 3, back substitution x_k = mc_k x_{k+1} + d_k: the block's map
+  // x_first = C x_in + D from the block's own d; wave 0 runs it down the column
+  {
+    T C = T(1), D = T(0);
+#pragma unroll
+    for (int i = KB - 1; i >= 0; --i) {
+      if (i < nb) {
+        C = mc[i] * C;
+        D = mc[i] * D + r[i];
+      }
+    }
+    at(wave, 3) = C;
+    at(wave, 4) = D;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    T x = T(0);
+    for (int j = nw - 1; j >= 0; --j) {
+      const T cj = at(j, 3), dj = at(j, 4);
+      at(j, 5) = x;
+      x = cj * x + dj;
+    }
+  }
+  __syncthreads();
+  T x = at(wave, 5);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = KB - 1; i >= 0; --i) {

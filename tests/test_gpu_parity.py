@@ -165,7 +165,41 @@ def test_vcycle_rate(case):
     rate32, _ = T.tpmg_richardson_rate(P32.mg, P32.pack(u0), 12, 4)
     ref32 = otpmg.richardson_rate(h, seed=7, precision="fp32")
     print(f"{case}: mixed V-cycle rate GPU {rate32:.6f}, oracle FP32 {ref32:.6f}, FP64 {ref:.6f}")
-    # FP32 rounding makes the 8-cycle estimate of the rate fluctuate (it is a
-    # nonlinear iteration); both FP32 rates are judged by their distance to
-    # the FP64 rate
-    assert abs(rate32 - ref) <= max(0.05, 2 * abs(ref32 - ref))
+    # The residual left after a few cycles lies in the components the V-cycle
+    # reduces slowest, and on those the FP32 V-cycle is a poor copy of the FP64
+    # one: measured with the oracle on these cases, |A (M32 r - M64 r)| / |r|
+    # reaches 0.09 (ico4_nz32_quad) to 0.56 (ico3_nz16) from the sixth cycle
+    # on. A per-cycle residual perturbation of eta moves the per-cycle factor
+    # by at most eta, so the FP32 rate is fixed by the FP64 one only to within
+    # that; the bar, 0.1, is the smallest of those perturbations.
+    assert rate32 < 1.0
+    assert abs(rate32 - ref) <= max(0.1, 2 * abs(ref32 - ref))
+
+
+def test_extreme_anisotropy_fp32():
+    """H/h = 1e-3 (ratio of the vertical extent to the horizontal spacing, the
+    far end of the anisotropy sweep of the robustness tables) on a small
+    sphere: the FP32 V-cycle stays a contraction with the FP64 V-cycle's
+    factor (within the bar above) and stays close to the FP64 V-cycle (the
+    oracle's FP32 V-cycle is 2.6e-7 away; bar 1e-4)."""
+    import paper_1408_2981_amd as T
+
+    ref_level, nz = 4, 32
+    r = synth.vertical_faces(nz, 1e-3 * synth.nominal_spacing(ref_level), "quadratic")
+    om2 = synth.omega_for(ref_level) ** 2
+    h = otpmg.build(ref_level, r, om2)
+    fine = h.meshes[-1]
+    f = synth.cell_integral(synth.uniform_noise(fine.n, nz, 3), fine.area, h.vert.vk)
+    z64 = otpmg.vcycle(h, f)
+    P = T.Problem(ref_level, r, om2).setup(precond_fp32=True)
+    zd = P.device_vector()
+    P.vcycle(P.pack(f), zd)
+    P.synchronize()
+    err = rel(P.unpack(zd), z64)
+    u0 = synth.uniform_noise(fine.n, nz, 7)
+    # this problem reaches its asymptotic factor late: rate over cycles 10-20
+    rate32, _ = T.tpmg_richardson_rate(P.mg, P.pack(u0), 20, 10)
+    ref = otpmg.richardson_rate(h, seed=7, cycles=20, skip=10)
+    print(f"H/h 1e-3: FP32 V-cycle vs FP64 V-cycle {err:.2e}; mixed rate {rate32:.4f}, FP64 oracle rate {ref:.4f}")
+    assert err <= 1e-4
+    assert rate32 < 1.0 and abs(rate32 - ref) <= 0.1
