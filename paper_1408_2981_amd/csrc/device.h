@@ -66,8 +66,22 @@ struct FcgScalars {
   int status;     // 0 ok, 1 breakdown
   int done;       // converged or broken down: batched launches skip the problem
   int iters;      // completed iterations (maintained on the device)
-  int pad;
+  int seq;        // records published so far (single solves)
 };
+
+// What a single solve's host loop needs of one FCG iteration, published by
+// the iteration's last kernel into pinned host memory (a ring of kRecords
+// slots, slot seq % kRecords), so that the host can wait for iteration k while
+// iteration k+1 is already queued.
+struct FcgRecord {
+  double rr;
+  int status;
+  int done;
+  int iters;
+  int seq;        // written last: 0 until the slot holds a record
+  int pad[2];
+};
+constexpr int kRecords = 4;
 
 // Operations of one FCG iteration, as grouped by the batched executor.
 enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize };
@@ -159,9 +173,11 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
                               void* u_fine, hipStream_t s);
 
-// x += alpha p, r -= alpha q (site kFinRR: <r, r>), FP64, padded length len.
+// Skipped once the scalars say done (an iteration queued after convergence
+// leaves x, r and the scalars alone); with ring != nullptr the finalize then
+// publishes the iteration's record.
 hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, FcgScalars* sc, size_t len,
-                             double* partials, hipStream_t s);
+                             double* partials, FcgRecord* ring, hipStream_t s);
 // <z, q>, <z, r> (site kFinBeta), for nz beyond the fused smoother's range.
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s);

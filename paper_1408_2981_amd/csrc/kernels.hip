@@ -183,6 +183,7 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       sc->beta = 0.0;
       sc->rtol = rtol;
       sc->iters = 0;
+      sc->seq = 0;
       sc->status = (finite(s0) && finite(s1)) ? 0 : 1;
       sc->done = (sc->status != 0 || sqrt(s0) <= rtol * sqrt(s1)) ? 1 : 0;
       break;
@@ -860,9 +861,26 @@ __device__ __forceinline__ void pupdate_body(const TZ* __restrict__ z, double* _
 // single-problem kernels
 // ---------------------------------------------------------------------------
 
+// Single solves: the sites of an iteration leave the scalars alone once
+// they say done (an iteration queued ahead of the host's convergence test
+// then changes nothing the solve returns); the kFinRR site publishes the
+// iteration's record to the host ring when one is given.
 __global__ __launch_bounds__(256) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
-                                                  FcgScalars* __restrict__ sc, double rtol) {
-  finalize_body(site, partials, nblocks, sc, rtol);
+                                                  FcgScalars* __restrict__ sc, double rtol,
+                                                  FcgRecord* __restrict__ ring) {
+  const bool iter_site = site == kFinAlpha || site == kFinRR || site == kFinBeta;
+  if (!(iter_site && sc->done)) finalize_body(site, partials, nblocks, sc, rtol);
+  if (site == kFinRR && ring != nullptr && threadIdx.x == 0) {
+    const int seq = sc->seq + 1;
+    sc->seq = seq;
+    FcgRecord* slot = ring + (seq % kRecords);
+    slot->rr = sc->rr;
+    slot->status = sc->status;
+    slot->done = sc->done;
+    slot->iters = sc->iters;
+    __threadfence_system();   // the payload is visible before the sequence number
+    slot->seq = seq;
+  }
 }
 
 template <int MODE, int CH>
@@ -913,6 +931,7 @@ __global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, doub
                                                     const double* __restrict__ p, const double* __restrict__ q,
                                                     const FcgScalars* __restrict__ sc, size_t len,
                                                     double* __restrict__ partials) {
+  if (sc->done) return;
   fcg_update_body(x, r, p, q, sc, len, partials, whole_grid());
 }
 
@@ -1114,7 +1133,7 @@ LevelTune default_tune(int nz, int prec) {
 unsigned pupdate_blocks(size_t len) { return grid_for(len, 2048); }
 
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, nblocks, sc, rtol);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, nblocks, sc, rtol, nullptr);
   return hipGetLastError();
 }
 
@@ -1145,7 +1164,7 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
       hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
   });
   if (site != kFinNone)
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, nullptr);
   return hipGetLastError();
 }
 
@@ -1248,7 +1267,7 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
     });
     if (dots)
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), a.partials,
-                         static_cast<int>(ntiles), a.scal, 0.0);
+                         static_cast<int>(ntiles), a.scal, 0.0, nullptr);
     return hipGetLastError();
   }
   if (dots) return hipErrorInvalidValue;   // only the scan kernel forms the dots
@@ -1320,16 +1339,17 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, 
 }
 
 hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, FcgScalars* sc, size_t len,
-                             double* partials, hipStream_t s) {
+                             double* partials, FcgRecord* ring, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
+                     ring);
   return hipGetLastError();
 }
 
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, z, q, r, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0, nullptr);
   return hipGetLastError();
 }
 

@@ -92,6 +92,8 @@ struct tpmg_mg {
   double* partials = nullptr;
   tpmg::FcgScalars* scal = nullptr;
   tpmg::FcgScalars* h_scal = nullptr;    // pinned host mirror
+  tpmg::FcgRecord* ring = nullptr;       // pinned ring of iteration records (host address)
+  tpmg::FcgRecord* ring_dev = nullptr;   // the same memory as the device addresses it
   size_t len = 0;                        // padded finest vector length
   int max_partial_blocks = 0;
   // graph of one FCG iteration for the solution vector graph_x
@@ -243,6 +245,7 @@ struct Op {
   size_t len = 0;
   void* scratch_d = nullptr;   // fallback smoother only
   void* scratch_c = nullptr;
+  tpmg::FcgRecord* ring = nullptr;   // update of a single solve: record ring
 };
 
 bool order_less(const Op& a, const Op& b) {
@@ -404,6 +407,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) 
   up.sc = sc;
   up.site = tpmg::kFinRR;
   up.len = m.len;
+  up.ring = m.ring_dev;
   ops.push_back(up);
 }
 
@@ -426,7 +430,7 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
     case tpmg::kOpUpdate:
       return tpmg::launch_fcg_update(static_cast<double*>(op.out0), static_cast<double*>(op.out1),
                                      static_cast<const double*>(op.in0), static_cast<const double*>(op.in1), op.sc,
-                                     op.len, op.partials, s);
+                                     op.len, op.partials, op.ring, s);
     case -1:
       return tpmg::launch_dots(static_cast<const double*>(op.in0), static_cast<const double*>(op.in1),
                                static_cast<const double*>(op.out0), op.len, op.partials, op.sc, s);
@@ -1088,6 +1092,7 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
 
   auto cleanup_fail = [&](tpmg_status s, const std::string& msg) {
     if (m->h_scal) (void)hipHostFree(m->h_scal);
+    if (m->ring) (void)hipHostFree(m->ring);
     delete m;
     return fail(s, msg);
   };
@@ -1108,6 +1113,15 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
     m->h_scal = nullptr;
     return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
+  e = hipHostMalloc(reinterpret_cast<void**>(&m->ring), tpmg::kRecords * sizeof(tpmg::FcgRecord),
+                    hipHostMallocDefault);
+  if (e != hipSuccess) {
+    m->ring = nullptr;
+    return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  std::memset(m->ring, 0, tpmg::kRecords * sizeof(tpmg::FcgRecord));
+  e = hipHostGetDevicePointer(reinterpret_cast<void**>(&m->ring_dev), m->ring, 0);
+  if (e != hipSuccess) return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
   // zero the whole workspace once: padding entries of every vector stay zero
   e = tpmg::launch_fill(d_workspace, (cv.off + 3) / 4 * 4, m->stream);
   std::vector<std::vector<double>> keep64;
@@ -1278,6 +1292,33 @@ tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z) {
   return TPMG_OK;
 }
 
+namespace {
+
+// Waits until the record with sequence number seq is in the ring (spinning on
+// the pinned slot; the stream is asked from time to time whether it failed or
+// went idle without publishing it).
+hipError_t wait_record(const tpmg::FcgRecord* ring, int seq, hipStream_t s, tpmg::FcgRecord* out) {
+  const tpmg::FcgRecord* slot = ring + (seq % tpmg::kRecords);
+  for (unsigned spin = 1;; ++spin) {
+    if (__atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if ((spin & 1023u) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return q;
+      if (__atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE) == seq) break;
+      return hipErrorUnknown;   // idle stream, record never published
+    }
+  }
+  out->rr = slot->rr;
+  out->status = slot->status;
+  out->done = slot->done;
+  out->iters = slot->iters;
+  out->seq = seq;
+  return hipSuccess;
+}
+
+}  // namespace
+
 tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit, tpmg_solve_info* info) {
   tpmg_status st = check_mg(mg);
   if (st != TPMG_OK) return st;
@@ -1326,31 +1367,48 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
       }
       mg->graph_x = d_u;
     }
+    // Iteration it+1 is queued before the host waits for iteration it's
+    // record unless the residual norms so far suggest that iteration it may
+    // converge: a queued iteration after convergence is left without effect
+    // (the update and the scalars skip once done) but costs its time.
+    std::memset(mg->ring, 0, tpmg::kRecords * sizeof(tpmg::FcgRecord));
+    int launched = 0;
+    auto launch_next = [&]() -> hipError_t {
+      ++launched;
+      return mg->use_graph ? hipGraphLaunch(mg->graph, s) : fcg_iteration(*mg, d_u);
+    };
+    const double target = rtol * fnorm;
+    double prev = rnorm;   // norm before the last known one (ratio estimate)
+    hipError_t werr = hipSuccess;
     for (int it = 0; it < maxit; ++it) {
-      if (mg->use_graph) {
-        TPMG_HIP(hipGraphLaunch(mg->graph, s));
-      } else {
-        TPMG_HIP(fcg_iteration(*mg, d_u));
-      }
-      TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
-      TPMG_HIP(hipStreamSynchronize(s));
+      if (launched == it) TPMG_HIP(launch_next());
+      const double ratio = prev > 0.0 ? std::min(1.0, rnorm / prev) : 1.0;
+      const bool ahead = it + 1 < maxit && rnorm * (it == 0 ? 1.0 : ratio) > 3.0 * target;
+      if (ahead && launched == it + 1) TPMG_HIP(launch_next());
+      tpmg::FcgRecord rec;
+      if ((werr = wait_record(mg->ring, it + 1, s, &rec)) != hipSuccess) break;
       iters = it + 1;
-      if (mg->h_scal->status != 0) {
+      if (rec.status != 0) {
         iters = it;
         result = TPMG_ERR_BREAKDOWN;
         break;
       }
-      rnorm = std::sqrt(mg->h_scal->rr);
+      prev = rnorm;
+      rnorm = std::sqrt(rec.rr);
       record(iters, fnorm > 0 ? rnorm / fnorm : 0.0);
       if (!std::isfinite(rnorm)) {
         result = TPMG_ERR_BREAKDOWN;
         break;
       }
-      if (rnorm <= rtol * fnorm) {
+      if (rnorm <= target) {
         result = TPMG_OK;
         break;
       }
     }
+    // drains an iteration queued ahead; reports the first device error
+    const hipError_t se = hipStreamSynchronize(s);
+    if (werr != hipSuccess || se != hipSuccess)
+      return fail(TPMG_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(werr != hipSuccess ? werr : se));
   }
   const auto t1 = std::chrono::steady_clock::now();
   if (info) {
@@ -1560,6 +1618,7 @@ void tpmg_mg_destroy(tpmg_mg* mg) {
   if (!mg) return;
   drop_graph(*mg);
   if (mg->h_scal) (void)hipHostFree(mg->h_scal);
+  if (mg->ring) (void)hipHostFree(mg->ring);
   delete mg;
 }
 

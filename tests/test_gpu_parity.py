@@ -149,6 +149,29 @@ def test_deterministic_fp64():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_iteration_queued_after_convergence_changes_nothing(graph):
+    """The solve queues iteration k+1 before it has read iteration k's
+    residual norm. The same solve stopped by maxit at the converged iteration
+    count (nothing queued beyond it) returns the same bits, and so does a run
+    whose maxit leaves it one iteration short (status: not converged)."""
+    import paper_1408_2981_amd as T
+
+    h, P, f = make("ico4_nz32_quad", use_graph=graph)
+    fd = P.pack(f)
+    a = P.device_vector()
+    st, iters, _, hist_a, _ = P.solve(fd, a, rtol=1e-8, maxit=100)
+    assert st == T.TPMG_OK
+    b = P.device_vector()
+    st_b, iters_b, _, hist_b, _ = P.solve(fd, b, rtol=1e-8, maxit=iters)
+    assert st_b == T.TPMG_OK and iters_b == iters
+    assert torch.equal(a, b) and np.array_equal(hist_a, hist_b)
+    c = P.device_vector()
+    st_c, iters_c, _, _, _ = P.solve(fd, c, rtol=1e-8, maxit=iters - 1)
+    assert st_c == T.TPMG_NOT_CONVERGED and iters_c == iters - 1
+    assert not torch.equal(a, c)
+
+
 @pytest.mark.parametrize("case", ["ico2_nz8_rand", "ico3_nz16", "ico4_nz32_quad"])
 def test_vcycle_rate(case):
     """V-cycle convergence factor in the Richardson iteration (f = 0, seeded
