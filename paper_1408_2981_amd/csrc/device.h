@@ -18,6 +18,13 @@
 namespace tpmg {
 
 constexpr int kTile = 64;
+// waves per block of the stencil kernels (SpMV, residual + restriction)
+constexpr int kStencilWaves = 4;
+// LDS of a scan-smoother block of `waves` waves in precision prec: eight
+// summary slots and a two-tile neighbour exchange slice per wave
+constexpr size_t scan_lds_bytes(int waves, int prec) {
+  return static_cast<size_t>(waves) * (8 + 2) * kTile * static_cast<size_t>(prec);
+}
 
 // Where the line smoother keeps a column while it solves it.
 enum SmootherKind {
@@ -44,6 +51,13 @@ struct LevelView {
   int npad = 0;    // padded to a multiple of 64
   int nz = 0;
   const int32_t* nbr = nullptr;   // [3][npad]
+  // where a stencil kernel finds neighbour j of a column at the level its
+  // wave holds: byte j of code[col] is the neighbour's lane in the column's
+  // own tile (< 64), or 64 + its slot in the tile's halo, the list of
+  // out-of-tile neighbour columns halo[64 t + slot] (unused slots: the slot's
+  // own column)
+  const int32_t* code = nullptr;  // [npad]
+  const int32_t* halo = nullptr;  // [npad]
   const void* beta_h = nullptr;   // [npad]
   const void* ar_h = nullptr;     // [npad]
   const void* as_h = nullptr;     // [3][npad]
@@ -191,6 +205,13 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);   // zero fill (gr
 struct FineGrid {
   int n = 0, npad = 0, nz = 0;
   const int32_t* nbr = nullptr;   // [3][npad]
+  // where a stencil kernel finds neighbour j of a column at the level its
+  // wave holds: byte j of code[col] is the neighbour's lane in the column's
+  // own tile (< 64), or 64 + its slot in the tile's halo, the list of
+  // out-of-tile neighbour columns halo[64 t + slot] (unused slots: the slot's
+  // own column)
+  const int32_t* code = nullptr;  // [npad]
+  const int32_t* halo = nullptr;  // [npad]
   hipStream_t stream = nullptr;
 };
 

@@ -34,6 +34,8 @@ template <typename T>
 struct Lv {
   int n, npad, nz;
   const int32_t* __restrict__ nbr;
+  const int32_t* __restrict__ code;
+  const int32_t* __restrict__ halo;
   const T* __restrict__ bh;
   const T* __restrict__ arh;
   const T* __restrict__ ash;
@@ -49,6 +51,8 @@ __host__ __device__ Lv<T> view(const LevelView& L) {
                L.npad,
                L.nz,
                L.nbr,
+               L.code,
+               L.halo,
                static_cast<const T*>(L.beta_h),
                static_cast<const T*>(L.ar_h),
                static_cast<const T*>(L.as_h),
@@ -71,6 +75,8 @@ template <typename T>
 struct Column {
   T bh, arh, a0, a1, a2;
   size_t base, b0, b1, b2;   // tile offsets of the column and its neighbours
+  size_t hb;                 // tile offset of the column's halo slot
+  uint32_t code;             // where the wave finds each neighbour (see LevelView)
 };
 
 template <typename T>
@@ -85,8 +91,28 @@ __device__ __forceinline__ Column<T> load_column(const Lv<T>& L, int col) {
   c.b0 = tile_base(L.nbr[col], L.nz);
   c.b1 = tile_base(L.nbr[L.npad + col], L.nz);
   c.b2 = tile_base(L.nbr[2 * L.npad + col], L.nz);
+  c.hb = tile_base(L.halo[col], L.nz);
+  c.code = static_cast<uint32_t>(L.code[col]);
   return c;
 }
+
+// Neighbour exchange inside a wave, one level at a time: the wave puts its
+// 64 own values and the tile's 64 halo values of the level into its
+// 128-entry LDS slice, and every lane takes its three neighbours at the slots
+// its code names. LDS operations of one wave complete in order, so a slice is
+// reused level after level without a barrier; the wave barriers only keep the
+// compiler from moving the accesses across each other.
+template <typename T>
+struct Exchange {
+  T* __restrict__ x;   // this wave's 128 entries
+  __device__ __forceinline__ void put(int lane, T own, T halo) {
+    x[lane] = own;
+    x[kTile + lane] = halo;
+    __builtin_amdgcn_wave_barrier();
+  }
+  __device__ __forceinline__ T get(const Column<T>& c, int j) const { return x[(c.code >> (8 * j)) & 0xffu]; }
+  __device__ __forceinline__ void done() { __builtin_amdgcn_wave_barrier(); }
+};
 
 // (A u)_k in flux form from the own-column values um = u_{k-1}, uc = u_k,
 // up = u_{k+1} and the neighbour-column values n0, n1, n2 at level k (every
@@ -116,15 +142,22 @@ __device__ __forceinline__ T apply_row(const Lv<T>& L, const Column<T>& c, const
 template <typename T, int CH>
 struct ChunkLoads {
   T xv[CH + 2], n0[CH], n1[CH], n2[CH];
-  __device__ __forceinline__ void load(const Column<T>& c, const T* __restrict__ u, int k0, int nz) {
+  // own values of levels k0-1 .. k0+CH (clamped), neighbours of k0 .. k0+CH-1
+  // through the wave's exchange slice (all 64 lanes active)
+  __device__ __forceinline__ void load(const Column<T>& c, const T* __restrict__ u, int k0, int nz, Exchange<T> xc,
+                                       int lane) {
+    T hv[CH];
 #pragma unroll
     for (int i = 0; i < CH + 2; ++i) xv[i] = u[c.base + static_cast<size_t>(min(max(k0 - 1 + i, 0), nz - 1)) * kTile];
 #pragma unroll
+    for (int i = 0; i < CH; ++i) hv[i] = u[c.hb + static_cast<size_t>(min(k0 + i, nz - 1)) * kTile];
+#pragma unroll
     for (int i = 0; i < CH; ++i) {
-      const size_t ok = static_cast<size_t>(min(k0 + i, nz - 1)) * kTile;
-      n0[i] = u[c.b0 + ok];
-      n1[i] = u[c.b1 + ok];
-      n2[i] = u[c.b2 + ok];
+      xc.put(lane, xv[i + 1], hv[i]);
+      n0[i] = xc.get(c, 0);
+      n1[i] = xc.get(c, 1);
+      n2[i] = xc.get(c, 2);
+      xc.done();
     }
   }
   // (A u)_{k0+i} for k0 + i < nz
@@ -275,8 +308,9 @@ __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, con
       }
     };
     if constexpr (CH > 0) {
+      __shared__ double xbuf[kStencilWaves][2 * kTile];
       ChunkLoads<double, CH> ld;
-      ld.load(c, x, k0, L.nz);
+      ld.load(c, x, k0, L.nz, Exchange<double>{xbuf[threadIdx.x >> 6]}, lane);
       double bb[MODE == 1 ? CH : 1];
       if (MODE == 1) {
 #pragma unroll
@@ -532,6 +566,8 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // summaries: pivot map (4), elimination map (2), substitution map (2)
   T* __restrict__ sm = reinterpret_cast<T*>(smem);
   auto at = [&](int w, int q) -> T& { return sm[(static_cast<size_t>(w) * 8 + q) * kTile + lane]; };
+  // after the summaries of all the block's waves: the exchange slices
+  Exchange<T> xc{sm + static_cast<size_t>(blockDim.x >> 6) * 8 * kTile + static_cast<size_t>(wave) * 2 * kTile};
   const int tile = xcd_tile(g.b, g.nb);
   const int col = tile * kTile + lane;
   const int kb = (nz + nw - 1) / nw;
@@ -552,10 +588,9 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // value of a clamped load is discarded), so no branch separates them and
   // the wave waits for memory once, not once per level.
   T r[KB], uu[KB];
-  double fd[DOTS ? KB : 1];
   {
     TF fv[KB];
-    T n0[ZERO ? 1 : KB], n1[ZERO ? 1 : KB], n2[ZERO ? 1 : KB];
+    T hv[ZERO ? 1 : KB];
     T below = T(0), above = T(0);
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
@@ -563,9 +598,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
       fv[i] = f[c.base + ok];
       if (!ZERO) {
         uu[i] = u_in[c.base + ok];
-        n0[i] = u_in[c.b0 + ok];
-        n1[i] = u_in[c.b1 + ok];
-        n2[i] = u_in[c.b2 + ok];
+        hv[i] = u_in[c.hb + ok];
       }
     }
     if (!ZERO) {
@@ -578,7 +611,6 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     for (int i = 0; i < KB; ++i) {
       if (i < nb) {
         const int k = k0 + i;
-        if (DOTS) fd[i] = static_cast<double>(fv[i]);
         const T fk = static_cast<T>(fv[i]);
         if (FCOPY) fcopy[c.base + static_cast<size_t>(k) * kTile] = fk;
         if (ZERO) {
@@ -589,7 +621,10 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
           const T um = i == 0 ? below : uu[i > 0 ? i - 1 : 0];
           const T next = i + 1 < KB ? uu[i + 1 < KB ? i + 1 : KB - 1] : above;
           const T up = i + 1 < nb ? next : above;
-          r[i] = fk - row_flux(L, c, k, um, uc, up, n0[i], n1[i], n2[i]);
+          xc.put(lane, uc, hv[i]);
+          const T n0 = xc.get(c, 0), n1 = xc.get(c, 1), n2 = xc.get(c, 2);
+          xc.done();
+          r[i] = fk - row_flux(L, c, k, um, uc, up, n0, n1, n2);
         }
       }
     }
@@ -734,7 +769,9 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
       u_out[o] = zo;
       if (DOTS) {
         acc[0] += static_cast<double>(zo) * q[o];
-        acc[1] += static_cast<double>(zo) * fd[i];
+        // f read again rather than held since the start (registers bound
+        // the tiles in flight; the line is still in cache)
+        acc[1] += static_cast<double>(zo) * static_cast<double>(f[o]);
       }
     }
   }
@@ -764,8 +801,9 @@ __device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk
     if ((lane & 3) == 0 && P < n_coarse) fc[pb + static_cast<size_t>(k) * kTile] = r;
   };
   if constexpr (CH > 0) {
+    __shared__ T xbuf[kStencilWaves][2 * kTile];
     ChunkLoads<T, CH> ld;
-    ld.load(c, u, k0, L.nz);
+    ld.load(c, u, k0, L.nz, Exchange<T>{xbuf[threadIdx.x >> 6]}, lane);
     T fv[CH];
 #pragma unroll
     for (int i = 0; i < CH; ++i) fv[i] = f[c.base + static_cast<size_t>(min(k0 + i, L.nz - 1)) * kTile];
@@ -1254,7 +1292,7 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
   if (!smoother_fits(tn.smoother, tn.scan_levels, L.nz, prec)) return hipErrorInvalidValue;
   if (tn.smoother == kSmScan) {
     const int waves = scan_waves(L.nz, tn.scan_levels);
-    const size_t sl = static_cast<size_t>(waves) * 8 * kTile * sizeof(T);
+    const size_t sl = scan_lds_bytes(waves, static_cast<int>(sizeof(T)));
     scan_levels_variant(tn.scan_levels, [&](auto kbc) {
       constexpr int KB = decltype(kbc)::value;
       smoother_variant<T>(f_double, out_double, zero, fcopy, dots, [&](auto tf, auto to, auto z, auto fcp, auto dt) {

@@ -65,6 +65,8 @@ struct Carver {
 struct DevLevel {
   int n = 0, npad = 0;
   int32_t* nbr = nullptr;
+  int32_t* code = nullptr;             // neighbour location codes (LevelView::code)
+  int32_t* halo = nullptr;             // per-tile out-of-tile neighbour lists
   void* bh[2] = {nullptr, nullptr};   // [0] double, [1] float
   void* arh[2] = {nullptr, nullptr};
   void* ash[2] = {nullptr, nullptr};
@@ -112,6 +114,8 @@ struct tpmg_mg {
     v.npad = d.npad;
     v.nz = nz;
     v.nbr = d.nbr;
+    v.code = d.code;
+    v.halo = d.halo;
     v.beta_h = d.bh[i];
     v.ar_h = d.arh[i];
     v.as_h = d.ash[i];
@@ -129,6 +133,8 @@ struct tpmg_mg {
     v.npad = d.npad;
     v.nz = nz;
     v.nbr = d.nbr;
+    v.code = d.code;
+    v.halo = d.halo;
     v.beta_h = d.bh[0];
     v.ar_h = d.arh[0];
     v.as_h = d.ash[0];
@@ -154,6 +160,8 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
     d.npad = pad64(d.n);
     const size_t np = d.npad;
     d.nbr = static_cast<int32_t*>(cv.take(3 * np * sizeof(int32_t)));
+    d.code = static_cast<int32_t*>(cv.take(np * sizeof(int32_t)));
+    d.halo = static_cast<int32_t*>(cv.take(np * sizeof(int32_t)));
     for (int i = 0; i < 2; ++i) {
       const size_t es = i == 0 ? 8 : 4;
       d.bh[i] = cv.take(np * es);
@@ -189,6 +197,44 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
   m.partials = static_cast<double*>(cv.take(2 * static_cast<size_t>(m.max_partial_blocks) * 8));
   m.scal = static_cast<tpmg::FcgScalars*>(cv.take(sizeof(tpmg::FcgScalars)));
   m.len = fine_len;
+}
+
+// Neighbour location codes and tile halos (see LevelView::code) from the
+// padded [3][npad] neighbour table. A tile's halo lists its distinct
+// out-of-tile neighbour columns in order of first use; false if a tile has
+// more than 64 (the cell ordering keeps a tile a compact patch: a refined
+// icosahedron's tile of 64 cells is the patch of one cell three refinements
+// coarser).
+bool tile_halos(const std::vector<int32_t>& nb, int npad, std::vector<int32_t>& code, std::vector<int32_t>& halo) {
+  code.assign(static_cast<size_t>(npad), 0);
+  halo.assign(static_cast<size_t>(npad), 0);
+  for (int t = 0; t < npad / tpmg::kTile; ++t) {
+    std::vector<int32_t> h;
+    for (int lane = 0; lane < tpmg::kTile; ++lane) {
+      const int col = t * tpmg::kTile + lane;
+      uint32_t packed = 0;
+      for (int j = 0; j < 3; ++j) {
+        const int32_t n = nb[static_cast<size_t>(j) * npad + col];
+        uint32_t cj;
+        if (n / tpmg::kTile == t) {
+          cj = static_cast<uint32_t>(n % tpmg::kTile);
+        } else {
+          auto it = std::find(h.begin(), h.end(), n);
+          if (it == h.end()) {
+            if (h.size() == static_cast<size_t>(tpmg::kTile)) return false;
+            h.push_back(n);
+            it = h.end() - 1;
+          }
+          cj = static_cast<uint32_t>(tpmg::kTile + (it - h.begin()));
+        }
+        packed |= cj << (8 * j);
+      }
+      code[col] = static_cast<int32_t>(packed);
+    }
+    for (int slot = 0; slot < tpmg::kTile; ++slot)
+      halo[t * tpmg::kTile + slot] = slot < static_cast<int>(h.size()) ? h[slot] : t * tpmg::kTile + slot;
+  }
+  return true;
 }
 
 tpmg_status check_params(const tpmg_mg_params* p) {
@@ -583,7 +629,7 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
     L.grid = start;
     L.nseg = static_cast<int>(j - i);
     // every wave of the block, idle or not, publishes its 8 summaries
-    if (o.kind == tpmg::kOpSmooth) L.lds = static_cast<size_t>(L.block / 64) * 8 * tpmg::kTile * static_cast<size_t>(o.prec);
+    if (o.kind == tpmg::kOpSmooth) L.lds = tpmg::scan_lds_bytes(L.block / 64, o.prec);
     seg_offset.push_back(first);
     plan.push_back(L);
     if (reduces) {
@@ -1134,8 +1180,17 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
     std::vector<int32_t> nb(3 * static_cast<size_t>(d.npad));
     for (int j = 0; j < 3; ++j)
       for (int t = 0; t < d.npad; ++t) nb[static_cast<size_t>(j) * d.npad + t] = t < d.n ? C.nbr[3 * static_cast<size_t>(t) + j] : t;
+    std::vector<int32_t> code, halo;
+    if (!tile_halos(nb, d.npad, code, halo)) {
+      (void)hipStreamSynchronize(m->stream);
+      return cleanup_fail(TPMG_ERR_ARG, "a 64-column tile has more than 64 distinct out-of-tile neighbours");
+    }
     keepi.push_back(std::move(nb));
     e = upload(d.nbr, keepi.back(), m->stream);
+    keepi.push_back(std::move(code));
+    if (e == hipSuccess) e = upload(d.code, keepi.back(), m->stream);
+    keepi.push_back(std::move(halo));
+    if (e == hipSuccess) e = upload(d.halo, keepi.back(), m->stream);
     // inert padding columns: beta = 1, no couplings
     keep64.push_back(padded<double>(C.beta_h, d.n, d.npad, 1, 1.0));
     keep32.push_back(padded<float>(C.beta_h, d.n, d.npad, 1, 1.0));
