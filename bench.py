@@ -150,7 +150,8 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
     those solutions (GPU, bf16 matrix cores, Adam, batch 4096), then solve
     t = n_train+1..n_total from four guesses: zero, the previous solution,
     the network (+ one line-relaxation sweep) and the two-step extrapolation
-    2 u_{t-1} - u_{t-2}. Times include producing the guess."""
+    2 u_{t-1} - u_{t-2}; and, for reference, the plain FP64 solve from zero.
+    Times include producing the guess."""
     import numpy as np
     import torch
 
@@ -217,12 +218,22 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
         infer_ms[relax] = e0.elapsed_time(e1) / 20
     flop_inf = 2.0 * P.n * (n_in * h + h * h + h * w.nz)
 
-    res = {k: {"iters": [], "ms": []} for k in ("zero", "previous", "network", "extrapolation")}
+    # the plain FP64 solve (FP64 V-cycle, zero guess) on the same grid and
+    # right-hand sides: the reference the mixed + learned-guess form is to beat
+    P64 = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=False, use_graph=True, autotune=1)
+    res = {k: {"iters": [], "ms": []} for k in ("zero", "previous", "network", "extrapolation", "fp64_zero")}
     for t in range(n_train + 1, n_total + 1):
         f = rhs(t)
         for kind in res:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
+            if kind == "fp64_zero":
+                u = P64.device_vector()
+                torch.cuda.synchronize()
+                st, it, *_ = P64.solve(f, u)
+                res[kind]["ms"].append(1000.0 * (time.perf_counter() - t1))
+                res[kind]["iters"].append(it)
+                continue
             if kind == "zero":
                 u = P.device_vector()
             elif kind == "previous":
@@ -252,7 +263,9 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
     for kind, r in res.items():
         line[kind] = {"mean_iters": float(np.mean(r["iters"])), "max_iters": int(np.max(r["iters"])),
                       "mean_ms_incl_guess": float(np.mean(r["ms"]))}
+    line["network_vs_fp64_zero_speedup"] = line["fp64_zero"]["mean_ms_incl_guess"] / line["network"]["mean_ms_incl_guess"]
     print(json.dumps(line), flush=True)
+    P64.close()
     net.close()
     P.close()
 
