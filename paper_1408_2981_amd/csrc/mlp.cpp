@@ -537,12 +537,35 @@ tpmg_status tpmg_mlp_infer(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, in
   if (g.n > m->max_rows) return fail(TPMG_ERR_ARG, "the grid has more columns than max_rows");
   if (relax != 0 && relax != 1) return fail(TPMG_ERR_ARG, "relax must be 0 or 1");
   if (g.stream != m->stream) return fail(TPMG_ERR_ARG, "the network and mg must share one stream");
-  MLP_HIP(tpmg::launch_mlp_features_bf16(g, d_f, m->colmean, m->mu_x, m->sd_x, m->kp, m->xb, m->stream));
-  if (!relax) {
-    MLP_HIP(forward(*m, g.n, tpmg::kEpiInferTiled, nullptr, d_u0));
-    return TPMG_OK;
+  double* out = relax ? m->guess : d_u0;
+  if (tpmg::mlp_infer_fits(m->h, m->nz, m->kp)) {
+    // one kernel from the right-hand side to the guess (features formed in it)
+    MLP_HIP(tpmg::launch_mlp_col_means(g, d_f, m->colmean, m->stream));
+    tpmg::InferArgs a;
+    a.kp = m->kp;
+    a.n = g.n;
+    a.nz = m->nz;
+    a.f = d_f;
+    a.means = m->colmean;
+    a.nbr = g.nbr;
+    a.npad = g.npad;
+    a.mu_x = m->mu_x;
+    a.sd_x = m->sd_x;
+    a.w1 = m->w1b;
+    a.w2 = m->w2b;
+    a.w3 = m->w3b;
+    a.b1 = m->params + m->ob1();
+    a.b2 = m->params + m->ob2();
+    a.b3 = m->params + m->ob3();
+    a.mu = m->mu_y;
+    a.sd = m->sd_y;
+    a.out = out;
+    MLP_HIP(tpmg::launch_mlp_infer(a, m->stream));
+  } else {
+    MLP_HIP(tpmg::launch_mlp_features_bf16(g, d_f, m->colmean, m->mu_x, m->sd_x, m->kp, m->xb, m->stream));
+    MLP_HIP(forward(*m, g.n, tpmg::kEpiInferTiled, nullptr, out));
   }
-  MLP_HIP(forward(*m, g.n, tpmg::kEpiInferTiled, nullptr, m->guess));
+  if (!relax) return TPMG_OK;
   MLP_HIP(tpmg_relax_finest(mg, d_f, m->guess, d_u0, m->rsd, m->rsc, 1.0, m->stream));
   return TPMG_OK;
 }

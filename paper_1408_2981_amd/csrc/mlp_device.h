@@ -49,6 +49,30 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 
+// Inference in one kernel: the features of launch_mlp_features_bf16 formed
+// from the tiled right-hand side f, the column means (launch_mlp_col_means)
+// and the neighbour table [3][npad], then the three products of the
+// kEpiBiasReluBf16, kEpiBiasReluBf16, kEpiInferTiled GEMMs (same bits):
+// w1 [256][kp], w2 [256][256], w3 [nz][256] bf16, biases and scalings FP32,
+// out the tiled FP64 guess (nz levels; n columns, the tile padding left
+// untouched). Supported: hidden 256, nz a multiple of 32 up to 128, kp a
+// multiple of 8 up to 160 (mlp_infer_fits).
+struct InferArgs {
+  int kp = 0, n = 0, nz = 0;
+  const double* f = nullptr;
+  const double* means = nullptr;
+  const int32_t* nbr = nullptr;
+  int npad = 0;
+  const float *mu_x = nullptr, *sd_x = nullptr;
+  const bf16 *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
+  const float *b1 = nullptr, *b2 = nullptr, *b3 = nullptr, *mu = nullptr, *sd = nullptr;
+  double* out = nullptr;
+};
+bool mlp_infer_fits(int hidden, int nz, int kp);
+// means[T] = mean over the levels of column T of the tiled vector f (FP64).
+hipError_t launch_mlp_col_means(const FineGrid& g, const double* f, double* means, hipStream_t s);
+hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t s);
+
 // x[T][j]: the column's right-hand side (j < nz) and the vertical means of
 // neighbours 0..2 (j = nz + i), from a tiled FP64 vector; means: scratch of
 // n doubles (the column means). The _bf16 form writes the standardised,

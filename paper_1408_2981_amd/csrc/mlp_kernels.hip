@@ -64,6 +64,33 @@ __device__ __forceinline__ void stage(const bf16* __restrict__ src, int ld, int 
   }
 }
 
+// The staging of a K-contiguous operand split in two, so that the next
+// step's loads are in flight while the current step computes: fetch takes
+// this thread's 16-byte chunks of rows [0, ROWS) x k [k0, k0 + 32) into
+// registers (zero outside r < R, k < kend), put stores them as [row][k].
+template <int ROWS>
+struct StageRegs {
+  static constexpr int kPer = (ROWS * kBK / 8 + 255) / 256;
+  uint4 v[kPer];
+  __device__ __forceinline__ void fetch(const bf16* __restrict__ src, int ld, int R, int k0, int kend) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int c = threadIdx.x + 256 * i;
+      const int row = c >> 2, kc = (c & 3) * 8;
+      v[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (c < ROWS * kBK / 8 && row < R && k0 + kc < kend)
+        v[i] = *reinterpret_cast<const uint4*>(src + static_cast<size_t>(row) * ld + k0 + kc);
+    }
+  }
+  __device__ __forceinline__ void put(bf16 (*dst)[kLdsRow]) const {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int c = threadIdx.x + 256 * i;
+      if (c < ROWS * kBK / 8) *reinterpret_cast<uint4*>(&dst[c >> 2][(c & 3) * 8]) = v[i];
+    }
+  }
+};
+
 template <int WM, int WN, bool TR, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
@@ -125,6 +152,158 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           g.out_f64[tiled_index(m, n, g.N)] = static_cast<double>((c + g.bias[n]) * g.sd[n] + g.mu[n]);
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// Inference, the whole network in one kernel: a block of 4 waves takes 64
+// rows (one tile of columns of the solver's grid) from the tiled right-hand
+// side through the features and the three layers, with the activations kept
+// in LDS, so that only the right-hand side is read and only the guess is
+// written. Each layer is the GEMM above at the same
+// operand rounding, K order and epilogue expression, so the result is the
+// bits of the three separate products. Hidden width 256; nz a multiple of 32
+// up to 128 (kp <= 160).
+// ---------------------------------------------------------------------------
+constexpr int kInferRows = 64;
+constexpr int kInferHidden = 256;
+constexpr int kInferKpMax = 160;
+constexpr int kXLd = kInferKpMax + 8;
+constexpr int kHLd = kInferHidden + 8;
+constexpr size_t kInferLds = static_cast<size_t>(kInferRows) * kXLd * 2 + static_cast<size_t>(kInferRows) * kHLd * 2 +
+                             static_cast<size_t>(kInferHidden) * kLdsRow * 2;
+
+template <int NZT>
+__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
+  constexpr int NZ = 32 * NZT;
+  __shared__ __align__(16) unsigned char sm[kInferLds];
+  bf16 (*Xs)[kXLd] = reinterpret_cast<bf16 (*)[kXLd]>(sm);
+  bf16 (*Hs)[kHLd] = reinterpret_cast<bf16 (*)[kHLd]>(sm + static_cast<size_t>(kInferRows) * kXLd * 2);
+  bf16 (*Ws)[kLdsRow] = reinterpret_cast<bf16 (*)[kLdsRow]>(sm + static_cast<size_t>(kInferRows) * kXLd * 2 +
+                                                            static_cast<size_t>(kInferRows) * kHLd * 2);
+  const int m0 = blockIdx.x * kInferRows;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 31, lk = 8 * (lane >> 5);
+
+  {
+    // the features of the block's tile straight from the tiled right-hand
+    // side (one coalesced row per level) and the neighbours' column means,
+    // standardised and rounded as the features kernel does; zero beyond n
+    const int cnt = min(kInferRows, a.n - m0);
+    const size_t base = static_cast<size_t>(blockIdx.x) * kInferRows * NZ;
+    for (int i = threadIdx.x; i < kInferRows * NZ; i += 256) {
+      const int k = i >> 6, c = i & 63;
+      const float val = (static_cast<float>(a.f[base + i]) - a.mu_x[k]) / a.sd_x[k];
+      Xs[c][k] = c < cnt ? static_cast<bf16>(val) : static_cast<bf16>(0.0f);
+    }
+    for (int i = threadIdx.x; i < kInferRows * (a.kp - NZ); i += 256) {
+      const int c = i / (a.kp - NZ), j = i - c * (a.kp - NZ);
+      float val = 0.0f;
+      if (j < 3 && c < cnt) {
+        const float mean = static_cast<float>(a.means[a.nbr[static_cast<size_t>(j) * a.npad + m0 + c]]);
+        val = (mean - a.mu_x[NZ + j]) / a.sd_x[NZ + j];
+      }
+      Xs[c][NZ + j] = static_cast<bf16>(val);
+    }
+  }
+
+  // layers 1 and 2: wave w owns hidden units [64 w, 64 w + 64) of all 64 rows
+  f32x16 acc[2][2];
+  auto hidden_layer = [&](const bf16* __restrict__ w, int K, const float* __restrict__ bias, bool from_x) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    StageRegs<kInferHidden> next;
+    next.fetch(w, K, kInferHidden, 0, K);
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+      next.put(Ws);
+      __syncthreads();
+      if (k0 + kBK < K) next.fetch(w, K, kInferHidden, k0 + kBK, K);
+#pragma unroll
+      for (int ks = 0; ks < kBK; ks += 16) {
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          av[i] = from_x ? *reinterpret_cast<const bf16x8*>(&Xs[32 * i + lr][k0 + ks + lk])
+                         : *reinterpret_cast<const bf16x8*>(&Hs[32 * i + lr][k0 + ks + lk]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const bf16x8*>(&Ws[64 * wave + 32 * j + lr][ks + lk]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    // (every wave is past its last read of Hs: the loop ends with a barrier)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int nn = 64 * wave + 32 * j + lr;
+          Hs[m][nn] = static_cast<bf16>(fmaxf(acc[i][j][r] + bias[nn], 0.0f));
+        }
+    __syncthreads();
+  };
+  hidden_layer(a.w1, a.kp, a.b1, true);
+  hidden_layer(a.w2, kInferHidden, a.b2, false);
+
+  // layer 3: 2 x NZT products of 32 x 32, product t = wave + 4 q on rows
+  // 32 (t % 2), levels 32 (t / 2)
+  constexpr int kOwn = (2 * NZT + 3) / 4;
+  f32x16 acc3[kOwn];
+#pragma unroll
+  for (int q = 0; q < kOwn; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc3[q][r] = 0.0f;
+  StageRegs<NZ> next3;
+  next3.fetch(a.w3, kInferHidden, NZ, 0, kInferHidden);
+  for (int k0 = 0; k0 < kInferHidden; k0 += kBK) {
+    next3.put(Ws);
+    __syncthreads();
+    if (k0 + kBK < kInferHidden) next3.fetch(a.w3, kInferHidden, NZ, k0 + kBK, kInferHidden);
+#pragma unroll
+    for (int ks = 0; ks < kBK; ks += 16) {
+#pragma unroll
+      for (int q = 0; q < kOwn; ++q) {
+        const int t = wave + 4 * q;
+        if (t < 2 * NZT) {
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Hs[32 * (t & 1) + lr][k0 + ks + lk]);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Ws[32 * (t >> 1) + lr][ks + lk]);
+          acc3[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc3[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // de-standardise into [level][row] FP64 staging over the whole LDS, then
+  // one coalesced 64-value row of the tiled guess per level
+  double (*Os)[kInferRows] = reinterpret_cast<double (*)[kInferRows]>(sm);
+#pragma unroll
+  for (int q = 0; q < kOwn; ++q) {
+    const int t = wave + 4 * q;
+    if (t < 2 * NZT) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * (t & 1) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int lev = 32 * (t >> 1) + lr;
+        Os[lev][m] = static_cast<double>((acc3[q][r] + a.b3[lev]) * a.sd[lev] + a.mu[lev]);
+      }
+    }
+  }
+  __syncthreads();
+  double* __restrict__ out = a.out + static_cast<size_t>(blockIdx.x) * kInferRows * NZ;
+  for (int i = threadIdx.x; i < NZ * kInferRows; i += 256) {
+    const int lev = i / kInferRows, m = i - lev * kInferRows;
+    if (m0 + m < a.n) out[i] = Os[lev][m];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -395,6 +574,28 @@ hipError_t gemm_tile(const GemmArgs& g, hipStream_t s) {
 }
 
 }  // namespace
+
+bool mlp_infer_fits(int hidden, int nz, int kp) {
+  return hidden == kInferHidden && nz % 32 == 0 && nz >= 32 && nz <= 128 && kp % 8 == 0 && kp <= kInferKpMax;
+}
+
+hipError_t launch_mlp_col_means(const FineGrid& g, const double* f, double* means, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_means, dim3(g.npad / kTileCols), dim3(256), 0, s, g, f, means);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t s) {
+  if (!mlp_infer_fits(kInferHidden, a.nz, a.kp) || a.n <= 0) return hipErrorInvalidValue;
+  if (!a.f || !a.means || !a.nbr || !a.mu_x || !a.sd_x || a.npad < a.n || a.kp < a.nz + 3) return hipErrorInvalidValue;
+  const unsigned blocks = static_cast<unsigned>((a.n + kInferRows - 1) / kInferRows);
+  switch (a.nz / 32) {
+    case 1: hipLaunchKernelGGL(k_mlp_infer<1>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_mlp_infer<2>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_mlp_infer<3>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_mlp_infer<4>, dim3(blocks), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
   GemmArgs g = g0;

@@ -188,6 +188,49 @@ def test_infer_into_solver_layout():
     assert np.count_nonzero(u1.cpu().numpy()) <= got1.size
 
 
+@pytest.mark.parametrize("name", ["seq_4_32", "seq_4_64", "seq_3_128"])
+def test_one_kernel_inference_equals_layer_by_layer(name):
+    """Hidden width 256 runs the whole inference in one kernel. Its result
+    equals the layer-by-layer products of forward() on the same features:
+    same bf16 operands, same K order, so the same FP32 output, up to the
+    rounding of the final de-standardisation (one fused multiply-add in the
+    kernel, a multiply and an add here): bar 2 FP32 ulps of the larger of
+    the two terms, |y sd| + |mu| (the result may cancel)."""
+    w = synth.workload(name)
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True)
+    h = otpmg.build(w.refinement, w.r_faces(), w.omega2)
+    fine = h.meshes[-1]
+    f = synth.sequence_rhs(w, fine.centre, fine.area, h.vert.vk, 5)
+    net = T.ColumnMLP(w.nz, 256, P.n, stream=P.stream)
+    p = omlp.init_params(w.nz + 3, 256, w.nz, 13)
+    net.set_params(omlp.pack(p).astype(np.float32))
+    fd = P.pack(f)
+    x = net.features(P, fd)
+    yo_raw = np.random.default_rng(14).standard_normal((P.n, w.nz)) * 1e-3
+    xs = x.cpu().numpy().astype(np.float64)
+    s = omlp.fit_scaling(xs, yo_raw)
+    net.set_scaling(s.mu_x, s.sd_x, s.mu_y, s.sd_y)
+    y = net.forward(x).cpu().numpy()                 # layer by layer, standardised output
+    _, _, mu_y, sd_y = net.get_scaling()
+    ref = y * np.asarray(sd_y, np.float32)[None, :] + np.asarray(mu_y, np.float32)[None, :]
+    u0 = P.device_vector()
+    net.infer(P, fd, u0, relax=0)
+    net.synchronize()
+    got = P.unpack(u0)
+    tiled = u0.cpu().numpy()
+    d = np.abs(got - ref.astype(np.float64))
+    mag = (np.abs(y) * np.abs(np.asarray(sd_y, np.float32))[None, :]
+           + np.abs(np.asarray(mu_y, np.float32))[None, :]).astype(np.float32)
+    ulp = np.spacing(mag).astype(np.float64)
+    tol = 2 * ulp
+    print(f"{name}: one-kernel inference vs layer by layer: max diff {d.max():.2e}, "
+          f"max diff in FP32 ulps of the terms {np.max(d / ulp):.2f}")
+    assert np.all(d <= tol)
+    assert np.count_nonzero(tiled) <= got.size       # padding columns untouched
+    net.close()
+    P.close()
+
+
 def test_bad_rows_and_arguments():
     x, y = _data(100, seed=9)
     net, _ = _net(max_rows=256)
