@@ -1438,7 +1438,7 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
     for (int it = 0; it < maxit; ++it) {
       if (launched == it) TPMG_HIP(launch_next());
       const double ratio = prev > 0.0 ? std::min(1.0, rnorm / prev) : 1.0;
-      const bool ahead = it + 1 < maxit && rnorm * (it == 0 ? 1.0 : ratio) > 3.0 * target;
+      const bool ahead = it + 1 < maxit && rnorm * ratio > 3.0 * target;
       if (ahead && launched == it + 1) TPMG_HIP(launch_next());
       tpmg::FcgRecord rec;
       if ((werr = wait_record(mg->ring, it + 1, s, &rec)) != hipSuccess) break;
