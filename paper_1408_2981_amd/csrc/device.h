@@ -65,6 +65,10 @@ struct LevelView {
   const void* beta_v = nullptr;   // [nz]
   const void* as_v = nullptr;     // [nz]
   const void* ar_v = nullptr;     // [nz+1]
+  // tiled [npad * nz]: the margin s_k of every column's Thomas factorisation
+  // (fixed by the operator, factorised once at setup); nullptr: the scan
+  // smoother forms the margins it needs itself
+  const void* margin = nullptr;
   LevelTune tune;
 };
 
@@ -187,6 +191,12 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
                               void* u_fine, hipStream_t s);
 
+// margin[k] = s_k of every column of level L64 (FP64 view): s_0 = e_0,
+// s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k), computed in FP64 and stored in
+// precision prec (tiled like the level's vectors).
+hipError_t launch_margins(const LevelView& L64, int prec, void* margin, hipStream_t s);
+
+// x += alpha p, r -= alpha q (site kFinRR: <r, r>), FP64, padded length len.
 // Skipped once the scalars say done (an iteration queued after convergence
 // leaves x, r and the scalars alone); with ring != nullptr the finalize then
 // publishes the iteration's record.

@@ -43,6 +43,7 @@ struct Lv {
   const T* __restrict__ bv;
   const T* __restrict__ av;
   const T* __restrict__ arv;
+  const T* __restrict__ margin;
 };
 
 template <typename T>
@@ -59,7 +60,8 @@ __host__ __device__ Lv<T> view(const LevelView& L) {
                static_cast<const T*>(L.pw),
                static_cast<const T*>(L.beta_v),
                static_cast<const T*>(L.as_v),
-               static_cast<const T*>(L.ar_v)};
+               static_cast<const T*>(L.ar_v),
+               static_cast<const T*>(L.margin)};
 }
 
 // this block's index and the number of blocks of its problem's launch
@@ -515,23 +517,46 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
   }
 }
 
+// Margins of the margin-form Thomas factorisation, one thread per column:
+// s_0 = e_0, s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k), with
+// e_k = beta_h beta_v,k + (sum of the horizontal couplings) alpha_s,v,k and
+// l_k = alpha_r,h alpha_r,v,k. FP64 throughout.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_margins(Lv<double> L, TO* __restrict__ margin) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= L.npad) return;
+  const Column<double> c = load_column(L, col);
+  const double esum = c.a0 + c.a1 + c.a2;
+  double sk = 0.0;
+  for (int k = 0; k < L.nz; ++k) {
+    const double e = c.bh * L.bv[k] + esum * L.av[k];
+    const double l = c.arh * L.arv[k];
+    sk = k == 0 ? e : e + l * sk / (sk + l);
+    margin[c.base + static_cast<size_t>(k) * kTile] = static_cast<TO>(sk);
+  }
+}
+
 // Line smoother, scan form (nz <= kScanWavesMax * KB): one workgroup per
 // tile of 64 columns, wave w owns the levels [w*kb, (w+1)*kb) (kb <= KB) of
 // every column and keeps them in registers. The column solve of the margin-form
-// Thomas algorithm is evaluated in three rounds of block scans over the waves:
-//  1. pivots: s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) is a Moebius map,
-//     (P, Q) -> ((e_k + l_k) P + e_k l_k Q, P + l_k Q) with s = P / Q; each
-//     wave forms its block's product of 2x2 matrices (positive entries,
-//     rescaled by exact powers of two) and publishes it in LDS; wave 0 runs
-//     the products up the column and hands every block its incoming margin;
+// Thomas algorithm is evaluated in rounds of block scans over the waves:
+//  1. pivots: the margins s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) depend on
+//     the operator only; when the level stores them (factorised at setup) a
+//     wave loads the one entering its block, s_{k0-1}. Otherwise the
+//     recurrence is a Moebius map, (P, Q) -> ((e_k + l_k) P + e_k l_k Q,
+//     P + l_k Q) with s = P / Q: each wave forms its block's product of 2x2
+//     matrices (positive entries, rescaled by exact powers of two) and
+//     publishes it in LDS, and wave 0 runs the products up the column and
+//     hands every block its incoming margin. Each wave then forms its own
+//     pivots with one reciprocal per level;
 //  2. elimination: d_k = (l_k d_{k-1} + r_k) / p_k, an affine map in d;
 //  3. back substitution: x_k = (m_k / p_k) x_{k+1} + d_k, affine in x, its
 //     block maps formed from the block's own d (composing the substitution
 //     with the elimination instead, to save a round, loses the column's
 //     near-null component in FP32 at extreme anisotropy).
-// The chain is kb + 3 n_waves steps instead of 2 nz, only wave 0 runs the
-// across-block chains, and the only workgroup-wide data in LDS are the
-// per-wave summaries.
+// The chain is kb + 2 n_waves steps (3 n_waves without stored margins)
+// instead of 2 nz, only wave 0 runs the across-block chains, and the only
+// workgroup-wide data in LDS are the per-wave summaries.
 
 // binary exponent e with v = m 2^e, 0.5 <= m < 1 (v > 0), and v 2^-e
 __device__ __forceinline__ int exp_of(float v) { return __builtin_amdgcn_frexp_expf(v); }
@@ -588,6 +613,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // value of a clamped load is discarded), so no branch separates them and
   // the wave waits for memory once, not once per level.
   T r[KB], uu[KB];
+  T s_in = T(0);   // margin s_{k0-1} entering the wave's block, when factorised at setup
   {
     TF fv[KB];
     T hv[ZERO ? 1 : KB];
@@ -601,6 +627,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
         hv[i] = u_in[c.hb + ok];
       }
     }
+    if (L.margin != nullptr) s_in = L.margin[c.base + static_cast<size_t>(max(k0 - 1, 0)) * kTile];
     if (!ZERO) {
       const T b = u_in[c.base + static_cast<size_t>(max(k0 - 1, 0)) * kTile];
       const T a = u_in[c.base + static_cast<size_t>(min(k0 + nb, nz - 1)) * kTile];
@@ -630,45 +657,48 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     }
   }
 
-  // ---- round 1, pivot margins: block product of the Moebius matrices
+  // ---- round 1, pivot margins, unless factorised at setup (the operator
+  // fixes them): block product of the Moebius matrices
   // [[e+l, e l'], [1, l']] (l' = l_k, or 1 on level 0 where l_0 = 0, so that
   // (0, 1) -> (e_0, 1)); wave 0 turns the blocks' products into each block's
   // incoming margin s_in = P / Q
-  T p00 = T(1), p01 = T(0), p10 = T(0), p11 = T(1);
+  if (L.margin == nullptr) {
+    T p00 = T(1), p01 = T(0), p10 = T(0), p11 = T(1);
 #pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    if (i < nb) {
-      const T ei = e_of(i), li = l_of(i);
-      const T lp = (k0 + i == 0) ? T(1) : li;
-      const T a = ei + li, b = ei * lp;
-      const T n00 = a * p00 + b * p10, n01 = a * p01 + b * p11;
-      const T n10 = p00 + lp * p10, n11 = p01 + lp * p11;
-      const int ex = exp_of(max(max(n00, n01), max(n10, n11)));
-      p00 = scale2(n00, -ex);
-      p01 = scale2(n01, -ex);
-      p10 = scale2(n10, -ex);
-      p11 = scale2(n11, -ex);
+    for (int i = 0; i < KB; ++i) {
+      if (i < nb) {
+        const T ei = e_of(i), li = l_of(i);
+        const T lp = (k0 + i == 0) ? T(1) : li;
+        const T a = ei + li, b = ei * lp;
+        const T n00 = a * p00 + b * p10, n01 = a * p01 + b * p11;
+        const T n10 = p00 + lp * p10, n11 = p01 + lp * p11;
+        const int ex = exp_of(max(max(n00, n01), max(n10, n11)));
+        p00 = scale2(n00, -ex);
+        p01 = scale2(n01, -ex);
+        p10 = scale2(n10, -ex);
+        p11 = scale2(n11, -ex);
+      }
     }
-  }
-  at(wave, 0) = p00;
-  at(wave, 1) = p01;
-  at(wave, 2) = p10;
-  at(wave, 3) = p11;
-  __syncthreads();
-  if (wave == 0) {
-    T P = T(0), Q = T(1);
-    for (int j = 0; j < nw; ++j) {
-      const T a00 = at(j, 0), a01 = at(j, 1), a10 = at(j, 2), a11 = at(j, 3);
-      at(j, 0) = P;
-      at(j, 1) = Q;
-      const T nP = a00 * P + a01 * Q;
-      const T nQ = a10 * P + a11 * Q;
-      P = nP;
-      Q = nQ;
-      rescale2(P, Q);
+    at(wave, 0) = p00;
+    at(wave, 1) = p01;
+    at(wave, 2) = p10;
+    at(wave, 3) = p11;
+    __syncthreads();
+    if (wave == 0) {
+      T P = T(0), Q = T(1);
+      for (int j = 0; j < nw; ++j) {
+        const T a00 = at(j, 0), a01 = at(j, 1), a10 = at(j, 2), a11 = at(j, 3);
+        at(j, 0) = P;
+        at(j, 1) = Q;
+        const T nP = a00 * P + a01 * Q;
+        const T nQ = a10 * P + a11 * Q;
+        P = nP;
+        Q = nQ;
+        rescale2(P, Q);
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 
   // local pivots p_k = s_k + m_k with s_k = e_k + l_k s_{k-1} / p_{k-1} (one
   // reciprocal per level; p_{k0-1} = s_in + m_{k0-1}, m_{k0-1} = l_{k0}); keep
@@ -678,7 +708,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   {
     T s_prev = T(0), ip_prev = T(0);
     if (wave > 0) {
-      s_prev = at(wave, 0) * rcp_of(at(wave, 1));
+      s_prev = L.margin != nullptr ? s_in : at(wave, 0) * rcp_of(at(wave, 1));
       ip_prev = rcp_of(s_prev + l_of(0));
     }
 #pragma unroll
@@ -1373,6 +1403,15 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, 
   else
     hipLaunchKernelGGL(k_prolong_add<float>, dim3(blocks), dim3(256), 0, s, view<float>(F), view<float>(C), chunk,
                        static_cast<const float*>(e_coarse), static_cast<float*>(u_fine));
+  return hipGetLastError();
+}
+
+hipError_t launch_margins(const LevelView& L64, int prec, void* margin, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>((L64.npad + 255) / 256);
+  if (prec == 8)
+    hipLaunchKernelGGL(k_margins<double>, dim3(blocks), dim3(256), 0, s, view<double>(L64), static_cast<double*>(margin));
+  else
+    hipLaunchKernelGGL(k_margins<float>, dim3(blocks), dim3(256), 0, s, view<double>(L64), static_cast<float*>(margin));
   return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ struct DevLevel {
   void* pw[2] = {nullptr, nullptr};
   void* f = nullptr;                   // right-hand side (coarse levels; precision of the V-cycle)
   void* u[2] = {nullptr, nullptr};     // ping-pong iterates
+  void* margin[2] = {nullptr, nullptr};   // Thomas margins, [0] double, [1] float (tiled)
 };
 
 }  // namespace
@@ -123,6 +124,7 @@ struct tpmg_mg {
     v.beta_v = bv[i];
     v.as_v = asv[i];
     v.ar_v = arv[i];
+    v.margin = d.margin[i];
     if (!tune.empty()) v.tune = tune[l];
     return v;
   }
@@ -142,6 +144,7 @@ struct tpmg_mg {
     v.beta_v = bv[0];
     v.as_v = asv[0];
     v.ar_v = arv[0];
+    v.margin = d.margin[0];
     if (!tune.empty()) v.tune = tune[l];
     return v;
   }
@@ -174,6 +177,10 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
     d.f = finest ? nullptr : cv.take(vec);
     d.u[0] = cv.take(vec);
     d.u[1] = cv.take(vec);
+    // margins in the V-cycle's precision; FP64 ones also on the finest level,
+    // whose FP64 view serves the relaxation after a learned guess
+    d.margin[1] = m.fp32 ? cv.take(np * nz * 4) : nullptr;
+    d.margin[0] = (!m.fp32 || finest) ? cv.take(np * nz * 8) : nullptr;
   }
   for (int i = 0; i < 2; ++i) {
     const size_t es = i == 0 ? 8 : 4;
@@ -1218,6 +1225,12 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
     keep32.push_back(std::vector<float>(vv[i]->begin(), vv[i]->end()));
     e = upload(dst[i][0], keep64.back(), m->stream);
     if (e == hipSuccess) e = upload(dst[i][1], keep32.back(), m->stream);
+  }
+  // the operator's Thomas margins, before the autotuner times the smoothers
+  for (int l = 0; l < m->nlev && e == hipSuccess; ++l) {
+    const tpmg::LevelView v64 = m->view64(l);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      if (m->lv[l].margin[i]) e = tpmg::launch_margins(v64, i == 0 ? 8 : 4, m->lv[l].margin[i], m->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   (void)nz;
