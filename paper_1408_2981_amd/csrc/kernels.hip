@@ -541,36 +541,17 @@ __global__ __launch_bounds__(256) void k_margins(Lv<double> L, TO* __restrict__ 
 // every column and keeps them in registers. The column solve of the margin-form
 // Thomas algorithm is evaluated in rounds of block scans over the waves:
 //  1. pivots: the margins s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k) depend on
-//     the operator only; when the level stores them (factorised at setup) a
-//     wave loads the one entering its block, s_{k0-1}. Otherwise the
-//     recurrence is a Moebius map, (P, Q) -> ((e_k + l_k) P + e_k l_k Q,
-//     P + l_k Q) with s = P / Q: each wave forms its block's product of 2x2
-//     matrices (positive entries, rescaled by exact powers of two) and
-//     publishes it in LDS, and wave 0 runs the products up the column and
-//     hands every block its incoming margin. Each wave then forms its own
-//     pivots with one reciprocal per level;
+//     the operator only and are factorised once per level at setup
+//     (k_margins); a wave loads the one entering its block, s_{k0-1}, and
+//     forms its own pivots with one reciprocal per level;
 //  2. elimination: d_k = (l_k d_{k-1} + r_k) / p_k, an affine map in d;
 //  3. back substitution: x_k = (m_k / p_k) x_{k+1} + d_k, affine in x, its
 //     block maps formed from the block's own d (composing the substitution
 //     with the elimination instead, to save a round, loses the column's
 //     near-null component in FP32 at extreme anisotropy).
-// The chain is kb + 2 n_waves steps (3 n_waves without stored margins)
-// instead of 2 nz, only wave 0 runs the across-block chains, and the only
-// workgroup-wide data in LDS are the per-wave summaries.
-
-// binary exponent e with v = m 2^e, 0.5 <= m < 1 (v > 0), and v 2^-e
-__device__ __forceinline__ int exp_of(float v) { return __builtin_amdgcn_frexp_expf(v); }
-__device__ __forceinline__ int exp_of(double v) { return __builtin_amdgcn_frexp_exp(v); }
-__device__ __forceinline__ float scale2(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
-__device__ __forceinline__ double scale2(double v, int e) { return __builtin_amdgcn_ldexp(v, e); }
-
-template <typename T>
-__device__ __forceinline__ void rescale2(T& a, T& b) {
-  // multiply both entries by the same power of two so the larger is O(1)
-  const int e = exp_of(max(a, b));
-  a = scale2(a, -e);
-  b = scale2(b, -e);
-}
+// The chain is kb + 2 n_waves steps instead of 2 nz, only wave 0 runs the
+// across-block chains, and the only workgroup-wide data in LDS are the
+// per-wave summaries.
 
 template <typename T>
 __device__ __forceinline__ T rcp_of(T v) {
@@ -613,7 +594,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // value of a clamped load is discarded), so no branch separates them and
   // the wave waits for memory once, not once per level.
   T r[KB], uu[KB];
-  T s_in = T(0);   // margin s_{k0-1} entering the wave's block, when factorised at setup
+  T s_in;   // margin s_{k0-1} entering the wave's block (factorised at setup)
   {
     TF fv[KB];
     T hv[ZERO ? 1 : KB];
@@ -627,7 +608,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
         hv[i] = u_in[c.hb + ok];
       }
     }
-    if (L.margin != nullptr) s_in = L.margin[c.base + static_cast<size_t>(max(k0 - 1, 0)) * kTile];
+    s_in = L.margin[c.base + static_cast<size_t>(max(k0 - 1, 0)) * kTile];
     if (!ZERO) {
       const T b = u_in[c.base + static_cast<size_t>(max(k0 - 1, 0)) * kTile];
       const T a = u_in[c.base + static_cast<size_t>(min(k0 + nb, nz - 1)) * kTile];
@@ -657,49 +638,6 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     }
   }
 
-  // ---- round 1, pivot margins, unless factorised at setup (the operator
-  // fixes them): block product of the Moebius matrices
-  // [[e+l, e l'], [1, l']] (l' = l_k, or 1 on level 0 where l_0 = 0, so that
-  // (0, 1) -> (e_0, 1)); wave 0 turns the blocks' products into each block's
-  // incoming margin s_in = P / Q
-  if (L.margin == nullptr) {
-    T p00 = T(1), p01 = T(0), p10 = T(0), p11 = T(1);
-#pragma unroll
-    for (int i = 0; i < KB; ++i) {
-      if (i < nb) {
-        const T ei = e_of(i), li = l_of(i);
-        const T lp = (k0 + i == 0) ? T(1) : li;
-        const T a = ei + li, b = ei * lp;
-        const T n00 = a * p00 + b * p10, n01 = a * p01 + b * p11;
-        const T n10 = p00 + lp * p10, n11 = p01 + lp * p11;
-        const int ex = exp_of(max(max(n00, n01), max(n10, n11)));
-        p00 = scale2(n00, -ex);
-        p01 = scale2(n01, -ex);
-        p10 = scale2(n10, -ex);
-        p11 = scale2(n11, -ex);
-      }
-    }
-    at(wave, 0) = p00;
-    at(wave, 1) = p01;
-    at(wave, 2) = p10;
-    at(wave, 3) = p11;
-    __syncthreads();
-    if (wave == 0) {
-      T P = T(0), Q = T(1);
-      for (int j = 0; j < nw; ++j) {
-        const T a00 = at(j, 0), a01 = at(j, 1), a10 = at(j, 2), a11 = at(j, 3);
-        at(j, 0) = P;
-        at(j, 1) = Q;
-        const T nP = a00 * P + a01 * Q;
-        const T nQ = a10 * P + a11 * Q;
-        P = nP;
-        Q = nQ;
-        rescale2(P, Q);
-      }
-    }
-    __syncthreads();
-  }
-
   // local pivots p_k = s_k + m_k with s_k = e_k + l_k s_{k-1} / p_{k-1} (one
   // reciprocal per level; p_{k0-1} = s_in + m_{k0-1}, m_{k0-1} = l_{k0}); keep
   // the elimination factor l_k / p_k, the substitution factor m_k / p_k and
@@ -708,7 +646,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   {
     T s_prev = T(0), ip_prev = T(0);
     if (wave > 0) {
-      s_prev = L.margin != nullptr ? s_in : at(wave, 0) * rcp_of(at(wave, 1));
+      s_prev = s_in;
       ip_prev = rcp_of(s_prev + l_of(0));
     }
 #pragma unroll
@@ -1321,6 +1259,7 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
   const T om = static_cast<T>(a.omega);
   if (!smoother_fits(tn.smoother, tn.scan_levels, L.nz, prec)) return hipErrorInvalidValue;
   if (tn.smoother == kSmScan) {
+    if (Lg.margin == nullptr) return hipErrorInvalidValue;   // the scan form reads the stored margins
     const int waves = scan_waves(L.nz, tn.scan_levels);
     const size_t sl = scan_lds_bytes(waves, static_cast<int>(sizeof(T)));
     scan_levels_variant(tn.scan_levels, [&](auto kbc) {
