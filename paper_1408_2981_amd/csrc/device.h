@@ -73,7 +73,12 @@ struct LevelView {
 };
 
 // Device scalars of the flexible CG recurrence.
+// Single solves keep the last kDirSlots search directions and their step
+// lengths, and add them to x every kDirSlots iterations and at the end.
+constexpr int kDirSlots = 8;
+
 struct FcgScalars {
+  double alpha_hist[kDirSlots];   // alpha of iteration i at i % kDirSlots (single solves)
   double rz;      // <r, z>
   double pq;      // <p, A p>
   double alpha;
@@ -85,6 +90,7 @@ struct FcgScalars {
   int done;       // converged or broken down: batched launches skip the problem
   int iters;      // completed iterations (maintained on the device)
   int seq;        // records published so far (single solves)
+  int flushed;    // iterations whose alpha p is in x (single solves)
 };
 
 // What a single solve's host loop needs of one FCG iteration, published by
@@ -102,7 +108,8 @@ struct FcgRecord {
 constexpr int kRecords = 4;
 
 // Operations of one FCG iteration, as grouped by the batched executor.
-enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize };
+enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize, kOpPupdateRing,
+              kOpSpmvRing, kOpRupdate, kOpFlush };
 
 // One problem's part of a grouped launch (device memory, sorted by start).
 struct Seg {
@@ -190,6 +197,23 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
 // u_fine += P e_coarse (linear interpolation), in place.
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, const void* e_coarse,
                               void* u_fine, hipStream_t s);
+
+// Single solves with the direction ring (kDirSlots vectors of len at
+// ring): p of iteration k = iters goes to slot k % kDirSlots (skipped once
+// done).
+//   pupdate_ring: p_k = z + beta p_{k-1};
+//   spmv_ring: q = A p_k (site kFinAlpha, which also records alpha_k);
+//   rupdate: r -= alpha q (site kFinRR);
+//   flush: every kDirSlots completed iterations (not once done), x += the
+//     ring's alpha p in iteration order;
+//   flush_final: x += alpha p of the iterations not yet flushed.
+hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, const FcgScalars* sc, size_t len,
+                               hipStream_t s);
+hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, double* q, double* partials,
+                            FcgScalars* sc, hipStream_t s);
+hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
+                          hipStream_t s);
+hipError_t launch_flush(double* x, const double* ring, FcgScalars* sc, size_t len, bool final_flush, hipStream_t s);
 
 // margin[k] = s_k of every column of level L64 (FP64 view): s_0 = e_0,
 // s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k), computed in FP64 and stored in

@@ -219,6 +219,7 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       sc->rtol = rtol;
       sc->iters = 0;
       sc->seq = 0;
+      sc->flushed = 0;
       sc->status = (finite(s0) && finite(s1)) ? 0 : 1;
       sc->done = (sc->status != 0 || sqrt(s0) <= rtol * sqrt(s1)) ? 1 : 0;
       break;
@@ -231,6 +232,7 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       } else {
         sc->alpha = sc->rz / s0;
       }
+      sc->alpha_hist[sc->iters % kDirSlots] = sc->alpha;
       break;
     case kFinRR:
       sc->rr = s0;
@@ -832,7 +834,7 @@ __device__ __forceinline__ void fcg_update_body(double* __restrict__ x, double* 
   double acc[2] = {0.0, 0.0};
   for (size_t i = static_cast<size_t>(g.b) * blockDim.x + threadIdx.x; i < len;
        i += static_cast<size_t>(g.nb) * blockDim.x) {
-    x[i] = x[i] + alpha * p[i];
+    x[i] = __builtin_fma(alpha, p[i], x[i]);
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     acc[0] += ri * ri;
@@ -939,6 +941,74 @@ __global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, doub
                                                     double* __restrict__ partials) {
   if (sc->done) return;
   fcg_update_body(x, r, p, q, sc, len, partials, whole_grid());
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_pupdate_ring(const TZ* __restrict__ z, double* __restrict__ ring,
+                                                      const FcgScalars* __restrict__ sc, size_t len) {
+  if (sc->done) return;
+  const int k = sc->iters;
+  const double beta = sc->beta;
+  const double* __restrict__ pp = ring + static_cast<size_t>((k + kDirSlots - 1) % kDirSlots) * len;
+  double* __restrict__ pn = ring + static_cast<size_t>(k % kDirSlots) * len;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    pn[i] = __builtin_fma(beta, pp[i], static_cast<double>(z[i]));
+}
+
+template <int CH>
+__global__ __launch_bounds__(256) void k_spmv_ring(Lv<double> L, int chunk, const double* __restrict__ ring,
+                                                   size_t len, double* __restrict__ q, double* __restrict__ partials,
+                                                   const FcgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  const double* __restrict__ p = ring + static_cast<size_t>(sc->iters % kDirSlots) * len;
+  spmv_body<0, CH>(L, chunk, p, nullptr, q, partials, whole_grid());
+}
+
+__global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
+                                                 const FcgScalars* __restrict__ sc, size_t len,
+                                                 double* __restrict__ partials) {
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+  }
+  block_sums(acc, partials, blockIdx.x);
+}
+
+// x += alpha_j p_j over iterations [first, first + count), in order, each a
+// fused multiply-add as in the per-iteration update. The periodic form runs
+// when kDirSlots iterations completed since the last flush (and the solve is
+// not done) and records them; the final form adds those not yet added.
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_flush(double* __restrict__ x, const double* __restrict__ ring,
+                                               FcgScalars* __restrict__ sc, size_t len) {
+  const int iters = sc->iters, flushed = sc->flushed;
+  int first, count;
+  if (FINAL) {
+    first = flushed;
+    count = iters - flushed;
+  } else {
+    if (sc->done || iters == 0 || iters % kDirSlots != 0) return;
+    first = iters - kDirSlots;
+    count = kDirSlots;
+  }
+  if (count <= 0) return;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    double xi = x[i];
+    for (int j = 0; j < count; ++j) {
+      const int it = first + j;
+      xi = __builtin_fma(sc->alpha_hist[it % kDirSlots], ring[static_cast<size_t>(it % kDirSlots) * len + i], xi);
+    }
+    x[i] = xi;
+  }
+  // (no block of this kernel reads flushed after its start)
+  if (!FINAL && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = iters;
 }
 
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, const double* __restrict__ q,
@@ -1359,6 +1429,47 @@ hipError_t launch_fcg_update(double* x, double* r, const double* p, const double
   hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
                      ring);
+  return hipGetLastError();
+}
+
+hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, const FcgScalars* sc, size_t len,
+                               hipStream_t s) {
+  if (z_double)
+    hipLaunchKernelGGL(k_pupdate_ring<double>, dim3(pupdate_blocks(len)), dim3(256), 0, s,
+                       static_cast<const double*>(z), ring, sc, len);
+  else
+    hipLaunchKernelGGL(k_pupdate_ring<float>, dim3(pupdate_blocks(len)), dim3(256), 0, s,
+                       static_cast<const float*>(z), ring, sc, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, double* q, double* partials,
+                            FcgScalars* sc, hipStream_t s) {
+  const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
+  const Lv<double> V = view<double>(L);
+  chunk_variant(chunk, [&](auto chc) {
+    constexpr int CH = decltype(chc)::value;
+    hipLaunchKernelGGL((k_spmv_ring<CH>), dim3(blocks), dim3(256), 0, s, V, chunk, ring, len, q, partials, sc);
+  });
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinAlpha), partials,
+                     static_cast<int>(blocks), sc, 0.0, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_rupdate, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, q, sc, len, partials);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
+                     ring);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(double* x, const double* ring, FcgScalars* sc, size_t len, bool final_flush, hipStream_t s) {
+  if (final_flush)
+    hipLaunchKernelGGL(k_flush<true>, dim3(pupdate_blocks(len)), dim3(256), 0, s, x, ring, sc, len);
+  else
+    hipLaunchKernelGGL(k_flush<false>, dim3(pupdate_blocks(len)), dim3(256), 0, s, x, ring, sc, len);
   return hipGetLastError();
 }
 

@@ -92,6 +92,7 @@ struct tpmg_mg {
   void* sd = nullptr;                    // Thomas scratch
   void* sc = nullptr;
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;   // FCG vectors (tiled, FP64)
+  double* dirs = nullptr;                // single solves: the last kDirSlots directions
   double* partials = nullptr;
   tpmg::FcgScalars* scal = nullptr;
   tpmg::FcgScalars* h_scal = nullptr;    // pinned host mirror
@@ -194,6 +195,7 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
   m.sc = cv.take(fine_len * s);
   m.r = static_cast<double*>(cv.take(fine_len * 8));
   m.p = static_cast<double*>(cv.take(fine_len * 8));
+  m.dirs = static_cast<double*>(cv.take(fine_len * 8 * tpmg::kDirSlots));
   m.q = static_cast<double*>(cv.take(fine_len * 8));
   m.z = static_cast<double*>(cv.take(fine_len * 8));
   // reductions: stencil blocks of the finest grid (at most: one level per
@@ -409,7 +411,7 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
 //   x += alpha p, r -= alpha q, rr = <r,r>.
 // With nz beyond the fused smoother's range the dots are a separate op
 // (kind -1, single solves only).
-void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) {
+void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, bool single = true) {
   const bool fused = m.tune.back().smoother == tpmg::kSmScan;
   // z of an FP32 V-cycle is an FP32 value: kept in FP32 when the last sweep
   // also forms the dots (nothing else reads it in FP64)
@@ -426,6 +428,44 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops) 
     d.sc = sc;
     d.len = m.len;
     ops.push_back(d);
+  }
+  if (single) {
+    // single solves keep the directions in a ring and add alpha p to x every
+    // kDirSlots iterations (and after the last), instead of in every update
+    Op pr;
+    pr.kind = tpmg::kOpPupdateRing;
+    pr.f_double = !z_float;
+    pr.in0 = m.z;
+    pr.out0 = m.dirs;
+    pr.sc = sc;
+    pr.len = m.len;
+    ops.push_back(pr);
+    Op sr;
+    sr.kind = tpmg::kOpSpmvRing;
+    sr.L = m.view64(m.nlev - 1);
+    sr.in0 = m.dirs;
+    sr.out0 = m.q;
+    sr.partials = m.partials;
+    sr.sc = sc;
+    sr.len = m.len;
+    ops.push_back(sr);
+    Op ru;
+    ru.kind = tpmg::kOpRupdate;
+    ru.in1 = m.q;
+    ru.out1 = m.r;
+    ru.partials = m.partials;
+    ru.sc = sc;
+    ru.len = m.len;
+    ru.ring = m.ring_dev;
+    ops.push_back(ru);
+    Op fl;
+    fl.kind = tpmg::kOpFlush;
+    fl.in0 = m.dirs;
+    fl.out0 = x;
+    fl.sc = sc;
+    fl.len = m.len;
+    ops.push_back(fl);
+    return;
   }
   Op pu;
   pu.order[0] = 2;
@@ -471,6 +511,17 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
     case tpmg::kOpSmooth:
       return tpmg::launch_smooth(op.L, op.prec, op.in0, op.f_double, op.in1, op.zero, op.out0, op.out_double, op.out1,
                                  op.scratch_d, op.scratch_c, op.omega, s, op.q, op.partials, op.sc);
+    case tpmg::kOpPupdateRing:
+      return tpmg::launch_pupdate_ring(op.in0, op.f_double, static_cast<double*>(op.out0), op.sc, op.len, s);
+    case tpmg::kOpSpmvRing:
+      return tpmg::launch_spmv_ring(op.L, static_cast<const double*>(op.in0), op.len, static_cast<double*>(op.out0),
+                                    op.partials, op.sc, s);
+    case tpmg::kOpRupdate:
+      return tpmg::launch_rupdate(static_cast<double*>(op.out1), static_cast<const double*>(op.in1), op.sc, op.len,
+                                  op.partials, op.ring, s);
+    case tpmg::kOpFlush:
+      return tpmg::launch_flush(static_cast<double*>(op.out0), static_cast<const double*>(op.in0), op.sc, op.len,
+                                false, s);
     case tpmg::kOpRestrict:
       return tpmg::launch_residual_restrict(op.L, op.C, op.prec, op.in0, op.in1, op.out0, s);
     case tpmg::kOpProlong:
@@ -540,7 +591,9 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
   std::vector<Item> items;
   for (size_t p = 0; p < b.probs.size(); ++p) {
     std::vector<Op> ops;
-    fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops);
+    // (batched launches update x and p in place in every iteration; single
+    // solves defer the x update, with the same bits)
+    fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops, false);
     for (const Op& op : ops) items.push_back({op, static_cast<int>(p)});
   }
   // smoother sweeps of one position are grouped by levels per wave (one
@@ -1400,6 +1453,8 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   // r = f - A u, rr, ff; p = q = 0 so that the first iteration takes beta = 0
   TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol));
   TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
+  // the direction before the first iteration, p_{-1} = 0 (slot kDirSlots - 1)
+  TPMG_HIP(tpmg::launch_fill(mg->dirs + (tpmg::kDirSlots - 1) * mg->len, mg->len * 8, s));
   TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
   TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
   TPMG_HIP(hipStreamSynchronize(s));
@@ -1473,6 +1528,10 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
         break;
       }
     }
+    // x += alpha p of the iterations not yet added (after an iteration queued
+    // ahead, which changes neither iters nor the ring's counted slots)
+    hipError_t fe = tpmg::launch_flush(d_u, mg->dirs, mg->scal, mg->len, true, s);
+    if (werr == hipSuccess) werr = fe;
     // drains an iteration queued ahead; reports the first device error
     const hipError_t se = hipStreamSynchronize(s);
     if (werr != hipSuccess || se != hipSuccess)
