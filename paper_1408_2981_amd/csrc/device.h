@@ -109,7 +109,7 @@ constexpr int kRecords = 4;
 
 // Operations of one FCG iteration, as grouped by the batched executor.
 enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize, kOpPupdateRing,
-              kOpSpmvRing, kOpRupdate, kOpFlush };
+              kOpSpmvRing, kOpRupdate };
 
 // One problem's part of a grouped launch (device memory, sorted by start).
 struct Seg {
@@ -199,21 +199,21 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, 
                               void* u_fine, hipStream_t s);
 
 // Single solves with the direction ring (kDirSlots vectors of len at
-// ring): p of iteration k = iters goes to slot k % kDirSlots (skipped once
-// done).
-//   pupdate_ring: p_k = z + beta p_{k-1};
+// ring); iteration k = iters, each launch skipped once done:
+//   pupdate_ring: p_k = z + beta p_{k-1} into slot k % kDirSlots; when k is a
+//     positive multiple of kDirSlots, first x += alpha p of the kDirSlots
+//     iterations before k (in order, the slots about to be reused);
 //   spmv_ring: q = A p_k (site kFinAlpha, which also records alpha_k);
 //   rupdate: r -= alpha q (site kFinRR);
-//   flush: every kDirSlots completed iterations (not once done), x += the
-//     ring's alpha p in iteration order;
-//   flush_final: x += alpha p of the iterations not yet flushed.
-hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, const FcgScalars* sc, size_t len,
+// flush, after the last iteration: x += alpha p of the iterations not yet
+// added.
+hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, double* x, FcgScalars* sc, size_t len,
                                hipStream_t s);
 hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, double* q, double* partials,
                             FcgScalars* sc, hipStream_t s);
 hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
                           hipStream_t s);
-hipError_t launch_flush(double* x, const double* ring, FcgScalars* sc, size_t len, bool final_flush, hipStream_t s);
+hipError_t launch_flush(double* x, const double* ring, const FcgScalars* sc, size_t len, hipStream_t s);
 
 // margin[k] = s_k of every column of level L64 (FP64 view): s_0 = e_0,
 // s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k), computed in FP64 and stored in

@@ -943,17 +943,33 @@ __global__ __launch_bounds__(256) void k_fcg_update(double* __restrict__ x, doub
   fcg_update_body(x, r, p, q, sc, len, partials, whole_grid());
 }
 
+// p_k = z + beta p_{k-1} into slot k % kDirSlots. When the ring is full
+// (k a positive multiple of kDirSlots) x first receives alpha p of the
+// kDirSlots iterations before k, in order, element by element ahead of the
+// slot's overwrite.
 template <typename TZ>
 __global__ __launch_bounds__(256) void k_pupdate_ring(const TZ* __restrict__ z, double* __restrict__ ring,
-                                                      const FcgScalars* __restrict__ sc, size_t len) {
+                                                      double* __restrict__ x, FcgScalars* __restrict__ sc,
+                                                      size_t len) {
   if (sc->done) return;
   const int k = sc->iters;
   const double beta = sc->beta;
+  const bool flush = k > 0 && k % kDirSlots == 0;
   const double* __restrict__ pp = ring + static_cast<size_t>((k + kDirSlots - 1) % kDirSlots) * len;
   double* __restrict__ pn = ring + static_cast<size_t>(k % kDirSlots) * len;
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    if (flush) {
+      double xi = x[i];
+#pragma unroll
+      for (int j = 0; j < kDirSlots; ++j)
+        xi = __builtin_fma(sc->alpha_hist[j], ring[static_cast<size_t>(j) * len + i], xi);
+      x[i] = xi;
+    }
     pn[i] = __builtin_fma(beta, pp[i], static_cast<double>(z[i]));
+  }
+  // (no block of this kernel reads flushed)
+  if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
 }
 
 template <int CH>
@@ -980,23 +996,11 @@ __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const d
   block_sums(acc, partials, blockIdx.x);
 }
 
-// x += alpha_j p_j over iterations [first, first + count), in order, each a
-// fused multiply-add as in the per-iteration update. The periodic form runs
-// when kDirSlots iterations completed since the last flush (and the solve is
-// not done) and records them; the final form adds those not yet added.
-template <bool FINAL>
+// x += alpha_j p_j of the iterations not yet added ([flushed, iters)), in
+// order, each a fused multiply-add as in the per-iteration update.
 __global__ __launch_bounds__(256) void k_flush(double* __restrict__ x, const double* __restrict__ ring,
-                                               FcgScalars* __restrict__ sc, size_t len) {
-  const int iters = sc->iters, flushed = sc->flushed;
-  int first, count;
-  if (FINAL) {
-    first = flushed;
-    count = iters - flushed;
-  } else {
-    if (sc->done || iters == 0 || iters % kDirSlots != 0) return;
-    first = iters - kDirSlots;
-    count = kDirSlots;
-  }
+                                               const FcgScalars* __restrict__ sc, size_t len) {
+  const int first = sc->flushed, count = sc->iters - sc->flushed;
   if (count <= 0) return;
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -1007,8 +1011,6 @@ __global__ __launch_bounds__(256) void k_flush(double* __restrict__ x, const dou
     }
     x[i] = xi;
   }
-  // (no block of this kernel reads flushed after its start)
-  if (!FINAL && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = iters;
 }
 
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ z, const double* __restrict__ q,
@@ -1432,14 +1434,14 @@ hipError_t launch_fcg_update(double* x, double* r, const double* p, const double
   return hipGetLastError();
 }
 
-hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, const FcgScalars* sc, size_t len,
+hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, double* x, FcgScalars* sc, size_t len,
                                hipStream_t s) {
   if (z_double)
     hipLaunchKernelGGL(k_pupdate_ring<double>, dim3(pupdate_blocks(len)), dim3(256), 0, s,
-                       static_cast<const double*>(z), ring, sc, len);
+                       static_cast<const double*>(z), ring, x, sc, len);
   else
     hipLaunchKernelGGL(k_pupdate_ring<float>, dim3(pupdate_blocks(len)), dim3(256), 0, s,
-                       static_cast<const float*>(z), ring, sc, len);
+                       static_cast<const float*>(z), ring, x, sc, len);
   return hipGetLastError();
 }
 
@@ -1465,11 +1467,8 @@ hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len
   return hipGetLastError();
 }
 
-hipError_t launch_flush(double* x, const double* ring, FcgScalars* sc, size_t len, bool final_flush, hipStream_t s) {
-  if (final_flush)
-    hipLaunchKernelGGL(k_flush<true>, dim3(pupdate_blocks(len)), dim3(256), 0, s, x, ring, sc, len);
-  else
-    hipLaunchKernelGGL(k_flush<false>, dim3(pupdate_blocks(len)), dim3(256), 0, s, x, ring, sc, len);
+hipError_t launch_flush(double* x, const double* ring, const FcgScalars* sc, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_flush, dim3(pupdate_blocks(len)), dim3(256), 0, s, x, ring, sc, len);
   return hipGetLastError();
 }
 

@@ -430,13 +430,14 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     ops.push_back(d);
   }
   if (single) {
-    // single solves keep the directions in a ring and add alpha p to x every
-    // kDirSlots iterations (and after the last), instead of in every update
+    // single solves keep the directions in a ring and add alpha p to x when
+    // the ring is full (and after the last iteration), not in every update
     Op pr;
     pr.kind = tpmg::kOpPupdateRing;
     pr.f_double = !z_float;
     pr.in0 = m.z;
     pr.out0 = m.dirs;
+    pr.out1 = x;
     pr.sc = sc;
     pr.len = m.len;
     ops.push_back(pr);
@@ -458,13 +459,6 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     ru.len = m.len;
     ru.ring = m.ring_dev;
     ops.push_back(ru);
-    Op fl;
-    fl.kind = tpmg::kOpFlush;
-    fl.in0 = m.dirs;
-    fl.out0 = x;
-    fl.sc = sc;
-    fl.len = m.len;
-    ops.push_back(fl);
     return;
   }
   Op pu;
@@ -512,16 +506,14 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
       return tpmg::launch_smooth(op.L, op.prec, op.in0, op.f_double, op.in1, op.zero, op.out0, op.out_double, op.out1,
                                  op.scratch_d, op.scratch_c, op.omega, s, op.q, op.partials, op.sc);
     case tpmg::kOpPupdateRing:
-      return tpmg::launch_pupdate_ring(op.in0, op.f_double, static_cast<double*>(op.out0), op.sc, op.len, s);
+      return tpmg::launch_pupdate_ring(op.in0, op.f_double, static_cast<double*>(op.out0),
+                                       static_cast<double*>(op.out1), op.sc, op.len, s);
     case tpmg::kOpSpmvRing:
       return tpmg::launch_spmv_ring(op.L, static_cast<const double*>(op.in0), op.len, static_cast<double*>(op.out0),
                                     op.partials, op.sc, s);
     case tpmg::kOpRupdate:
       return tpmg::launch_rupdate(static_cast<double*>(op.out1), static_cast<const double*>(op.in1), op.sc, op.len,
                                   op.partials, op.ring, s);
-    case tpmg::kOpFlush:
-      return tpmg::launch_flush(static_cast<double*>(op.out0), static_cast<const double*>(op.in0), op.sc, op.len,
-                                false, s);
     case tpmg::kOpRestrict:
       return tpmg::launch_residual_restrict(op.L, op.C, op.prec, op.in0, op.in1, op.out0, s);
     case tpmg::kOpProlong:
@@ -1530,7 +1522,7 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
     }
     // x += alpha p of the iterations not yet added (after an iteration queued
     // ahead, which changes neither iters nor the ring's counted slots)
-    hipError_t fe = tpmg::launch_flush(d_u, mg->dirs, mg->scal, mg->len, true, s);
+    hipError_t fe = tpmg::launch_flush(d_u, mg->dirs, mg->scal, mg->len, s);
     if (werr == hipSuccess) werr = fe;
     // drains an iteration queued ahead; reports the first device error
     const hipError_t se = hipStreamSynchronize(s);
