@@ -109,7 +109,7 @@ constexpr int kRecords = 4;
 
 // Operations of one FCG iteration, as grouped by the batched executor.
 enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize, kOpPupdateRing,
-              kOpSpmvRing, kOpRupdate };
+              kOpSpmvRing, kOpRupdate, kOpSpmvPRing };
 
 // One problem's part of a grouped launch (device memory, sorted by start).
 struct Seg {
@@ -213,6 +213,11 @@ hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, 
                             FcgScalars* sc, hipStream_t s);
 hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
                           hipStream_t s);
+// pupdate_ring and spmv_ring in one launch (the same bits), for the operator
+// chunks that have an instance (spmv_pring_fits).
+bool spmv_pring_fits(const LevelView& L);
+hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, double* ring, size_t len, double* x,
+                             double* q, double* partials, FcgScalars* sc, hipStream_t s, int site = kFinAlpha);
 hipError_t launch_flush(double* x, const double* ring, const FcgScalars* sc, size_t len, hipStream_t s);
 
 // margin[k] = s_k of every column of level L64 (FP64 view): s_0 = e_0,

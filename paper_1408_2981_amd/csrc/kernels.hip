@@ -148,11 +148,17 @@ struct ChunkLoads {
   // through the wave's exchange slice (all 64 lanes active)
   __device__ __forceinline__ void load(const Column<T>& c, const T* __restrict__ u, int k0, int nz, Exchange<T> xc,
                                        int lane) {
+    load_with(c, [&](size_t o) { return u[o]; }, k0, nz, xc, lane);
+  }
+  // the same with the value at offset o given by get(o)
+  template <typename Get>
+  __device__ __forceinline__ void load_with(const Column<T>& c, Get&& get, int k0, int nz, Exchange<T> xc,
+                                            int lane) {
     T hv[CH];
 #pragma unroll
-    for (int i = 0; i < CH + 2; ++i) xv[i] = u[c.base + static_cast<size_t>(min(max(k0 - 1 + i, 0), nz - 1)) * kTile];
+    for (int i = 0; i < CH + 2; ++i) xv[i] = get(c.base + static_cast<size_t>(min(max(k0 - 1 + i, 0), nz - 1)) * kTile);
 #pragma unroll
-    for (int i = 0; i < CH; ++i) hv[i] = u[c.hb + static_cast<size_t>(min(k0 + i, nz - 1)) * kTile];
+    for (int i = 0; i < CH; ++i) hv[i] = get(c.hb + static_cast<size_t>(min(k0 + i, nz - 1)) * kTile);
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
       xc.put(lane, xv[i + 1], hv[i]);
@@ -981,6 +987,54 @@ __global__ __launch_bounds__(256) void k_spmv_ring(Lv<double> L, int chunk, cons
   spmv_body<0, CH>(L, chunk, p, nullptr, q, partials, whole_grid());
 }
 
+// The direction update inside q = A p: p_k = z + beta p_{k-1} is formed on
+// the fly at every point the operator reads (the expression of
+// k_pupdate_ring, so the same bits), stored for the wave's own points, and
+// the ring's flush, when due, runs on the same points first.
+template <int CH, typename TZ>
+__global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __restrict__ z, double* __restrict__ ring,
+                                                    size_t len, double* __restrict__ x, double* __restrict__ q,
+                                                    double* __restrict__ partials, FcgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  const int k = sc->iters;
+  const double beta = sc->beta;
+  const bool flush = k > 0 && k % kDirSlots == 0;
+  const double* __restrict__ pp = ring + static_cast<size_t>((k + kDirSlots - 1) % kDirSlots) * len;
+  double* __restrict__ pn = ring + static_cast<size_t>(k % kDirSlots) * len;
+  const int nchunks = (L.nz + CH - 1) / CH;
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  double acc[2] = {0.0, 0.0};
+  if (item < (L.npad >> 6) * nchunks) {
+    const int tile = item / nchunks, chunk_i = item - tile * nchunks;
+    const int k0 = chunk_i * CH, k1 = min(L.nz, k0 + CH);
+    const Column<double> c = load_column(L, tile * kTile + lane);
+    __shared__ double xbuf[kStencilWaves][2 * kTile];
+    ChunkLoads<double, CH> ld;
+    ld.load_with(c, [&](size_t o) { return __builtin_fma(beta, pp[o], static_cast<double>(z[o])); }, k0, L.nz,
+                 Exchange<double>{xbuf[threadIdx.x >> 6]}, lane);
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (k0 + i < k1) {
+        const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
+        if (flush) {
+          double xi = x[o];
+#pragma unroll
+          for (int j = 0; j < kDirSlots; ++j) xi = __builtin_fma(sc->alpha_hist[j], ring[static_cast<size_t>(j) * len + o], xi);
+          x[o] = xi;
+        }
+        const double uc = ld.xv[i + 1];
+        const double ax = ld.row(L, c, k0, i);
+        pn[o] = uc;
+        q[o] = ax;
+        acc[0] += uc * ax;
+      }
+  }
+  block_sums(acc, partials, blockIdx.x);
+  // (no block of this kernel reads flushed)
+  if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
+}
+
 __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
                                                  const FcgScalars* __restrict__ sc, size_t len,
                                                  double* __restrict__ partials) {
@@ -1456,6 +1510,32 @@ hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, 
   });
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinAlpha), partials,
                      static_cast<int>(blocks), sc, 0.0, nullptr);
+  return hipGetLastError();
+}
+
+bool spmv_pring_fits(const LevelView& L) {
+  const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
+  return chunk == 1 || chunk == 2 || chunk == 4 || chunk == 8 || chunk == 16;
+}
+
+hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, double* ring, size_t len, double* x,
+                             double* q, double* partials, FcgScalars* sc, hipStream_t s, int site) {
+  if (!spmv_pring_fits(L)) return hipErrorInvalidValue;
+  const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
+  const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
+  const Lv<double> V = view<double>(L);
+  chunk_variant(chunk, [&](auto chc) {
+    constexpr int CH = decltype(chc)::value;
+    if constexpr (CH > 0) {
+      if (z_double)
+        hipLaunchKernelGGL((k_spmv_pring<CH, double>), dim3(blocks), dim3(256), 0, s, V, static_cast<const double*>(z),
+                           ring, len, x, q, partials, sc);
+      else
+        hipLaunchKernelGGL((k_spmv_pring<CH, float>), dim3(blocks), dim3(256), 0, s, V, static_cast<const float*>(z),
+                           ring, len, x, q, partials, sc);
+    }
+  });
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, 0.0, nullptr);
   return hipGetLastError();
 }
 

@@ -301,6 +301,7 @@ struct Op {
   void* scratch_d = nullptr;   // fallback smoother only
   void* scratch_c = nullptr;
   tpmg::FcgRecord* ring = nullptr;   // update of a single solve: record ring
+  double* aux = nullptr;             // single solves: the direction ring
 };
 
 bool order_less(const Op& a, const Op& b) {
@@ -429,9 +430,36 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     d.len = m.len;
     ops.push_back(d);
   }
-  if (single) {
+  if (single && tpmg::spmv_pring_fits(m.view64(m.nlev - 1))) {
     // single solves keep the directions in a ring and add alpha p to x when
-    // the ring is full (and after the last iteration), not in every update
+    // the ring is full (and after the last iteration), not in every update;
+    // the direction update runs inside q = A p
+    Op sp;
+    sp.kind = tpmg::kOpSpmvPRing;
+    sp.L = m.view64(m.nlev - 1);
+    sp.f_double = !z_float;
+    sp.in0 = m.z;
+    sp.out0 = m.q;
+    sp.out1 = x;
+    sp.aux = m.dirs;
+    sp.partials = m.partials;
+    sp.sc = sc;
+    sp.len = m.len;
+    ops.push_back(sp);
+    Op ru;
+    ru.kind = tpmg::kOpRupdate;
+    ru.in1 = m.q;
+    ru.out1 = m.r;
+    ru.partials = m.partials;
+    ru.sc = sc;
+    ru.len = m.len;
+    ru.ring = m.ring_dev;
+    ops.push_back(ru);
+    return;
+  }
+  if (single) {
+    // the same with the direction update apart (operator chunks without a
+    // fused instance)
     Op pr;
     pr.kind = tpmg::kOpPupdateRing;
     pr.f_double = !z_float;
@@ -508,6 +536,9 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
     case tpmg::kOpPupdateRing:
       return tpmg::launch_pupdate_ring(op.in0, op.f_double, static_cast<double*>(op.out0),
                                        static_cast<double*>(op.out1), op.sc, op.len, s);
+    case tpmg::kOpSpmvPRing:
+      return tpmg::launch_spmv_pring(op.L, op.in0, op.f_double, op.aux, op.len, static_cast<double*>(op.out1),
+                                     static_cast<double*>(op.out0), op.partials, op.sc, s);
     case tpmg::kOpSpmvRing:
       return tpmg::launch_spmv_ring(op.L, static_cast<const double*>(op.in0), op.len, static_cast<double*>(op.out0),
                                     op.partials, op.sc, s);
@@ -989,9 +1020,15 @@ tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p) {
         });
     }
     if (st == TPMG_OK && l == L)
-      st = tune_chunk("spmv", 8, &t.chunk_spmv, [&](int c) {
+      // timed as single solves run it: the direction update inside the
+      // operator (on the zeroed workspace: iteration 0, no flush), with a
+      // finalize that changes no scalar
+      st = tune_chunk("spmv_p", 8, &t.chunk_spmv, [&](int c) {
         tpmg::LevelView V = m.view64(l);
         V.tune.chunk_spmv = c;
+        if (tpmg::spmv_pring_fits(V))
+          return tpmg::launch_spmv_pring(V, m.z, !m.fp32, m.dirs, m.len, m.r, m.q, m.partials, m.scal, m.stream,
+                                         tpmg::kFinNone);
         hipError_t e = tpmg::launch_spmv64(V, 0, m.p, nullptr, m.q, m.partials, tpmg::kFinNone, m.scal, m.stream);
         if (e != hipSuccess) return e;
         return tpmg::launch_finalize(tpmg::kFinNone, m.partials,
