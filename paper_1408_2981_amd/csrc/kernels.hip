@@ -72,6 +72,14 @@ struct GridPos {
 
 __device__ __forceinline__ GridPos whole_grid() { return GridPos{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)}; }
 
+// Blocks are dealt to the 8 XCDs round-robin; renumber them so that each
+// XCD walks one contiguous range of tiles (or of tile chunks) and neighbour gathers across tile
+// edges hit in that XCD's own L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
 // per-column stencil data held in registers for a whole column sweep
 template <typename T>
 struct Column {
@@ -298,7 +306,8 @@ __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, con
                                           double* __restrict__ partials, GridPos g) {
   const int chunk = CH > 0 ? CH : chunk_rt;
   const int nchunks = (L.nz + chunk - 1) / chunk;
-  const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
+  const int lb = xcd_tile(g.b, g.nb);
+  const int item = __builtin_amdgcn_readfirstlane(lb * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   double acc[2] = {0.0, 0.0};
   if (item < (L.npad >> 6) * nchunks) {
@@ -341,7 +350,7 @@ __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, con
       }
     }
   }
-  block_sums(acc, partials, g.b);
+  block_sums(acc, partials, lb);
 }
 
 // Line smoother: damped block-Jacobi with a Thomas solve per column
@@ -392,14 +401,6 @@ __global__ __launch_bounds__(64) void k_smooth_fallback(Lv<T> L, const TF* __res
     const T uo = ZERO ? omega * x : u_in[o] + omega * x;
     u_out[o] = static_cast<TO>(uo);
   }
-}
-
-// Blocks are dealt to the 8 XCDs round-robin; renumber them so that each
-// XCD walks one contiguous range of tiles and neighbour gathers across tile
-// edges hit in that XCD's own L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-  return x * q + min(x, r) + i;
 }
 
 __device__ __forceinline__ float fast_rcp(float p) { return __builtin_amdgcn_rcpf(p); }
@@ -762,7 +763,7 @@ __device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk
                                                        T* __restrict__ fc, GridPos g) {
   const int chunk = CH > 0 ? CH : chunk_rt;
   const int nchunks = (L.nz + chunk - 1) / chunk;
-  const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(xcd_tile(g.b, g.nb) * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (item >= (L.npad >> 6) * nchunks) return;
   const int tile = item / nchunks, chunk_i = item - tile * nchunks;
@@ -804,7 +805,7 @@ template <typename T>
 __device__ __forceinline__ void prolong_add_body(const Lv<T>& F, const Lv<T>& C, int chunk, const T* __restrict__ e,
                                                  T* __restrict__ u, GridPos g) {
   const int nchunks = (F.nz + chunk - 1) / chunk;
-  const int item = __builtin_amdgcn_readfirstlane(g.b * 4 + (threadIdx.x >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(xcd_tile(g.b, g.nb) * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (item >= (F.npad >> 6) * nchunks) return;
   const int tile = item / nchunks, chunk_i = item - tile * nchunks;
@@ -1002,7 +1003,8 @@ __global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __re
   const double* __restrict__ pp = ring + static_cast<size_t>((k + kDirSlots - 1) % kDirSlots) * len;
   double* __restrict__ pn = ring + static_cast<size_t>(k % kDirSlots) * len;
   const int nchunks = (L.nz + CH - 1) / CH;
-  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  const int item = __builtin_amdgcn_readfirstlane(lb * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   double acc[2] = {0.0, 0.0};
   if (item < (L.npad >> 6) * nchunks) {
@@ -1030,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __re
         acc[0] += uc * ax;
       }
   }
-  block_sums(acc, partials, blockIdx.x);
+  block_sums(acc, partials, lb);
   // (no block of this kernel reads flushed)
   if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
 }
