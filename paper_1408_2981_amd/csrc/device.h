@@ -204,7 +204,8 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, 
 //     positive multiple of kDirSlots, first x += alpha p of the kDirSlots
 //     iterations before k (in order, the slots about to be reused);
 //   spmv_ring: q = A p_k (site kFinAlpha, which also records alpha_k);
-//   rupdate: r -= alpha q (site kFinRR);
+//   rupdate: r -= alpha q (site kFinRR); with r32 non-NULL also r32 = the
+//   FP32 rounding of the new r;
 // flush, after the last iteration: x += alpha p of the iterations not yet
 // added.
 hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, double* x, FcgScalars* sc, size_t len,
@@ -212,7 +213,9 @@ hipError_t launch_pupdate_ring(const void* z, bool z_double, double* ring, doubl
 hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, double* q, double* partials,
                             FcgScalars* sc, hipStream_t s);
 hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
-                          hipStream_t s);
+                          hipStream_t s, float* r32 = nullptr);
+// v32 = the FP32 rounding of v
+hipError_t launch_round_f32(const double* v, float* v32, size_t len, hipStream_t s);
 // pupdate_ring and spmv_ring in one launch (the same bits), for the operator
 // chunks that have an instance (spmv_pring_fits).
 bool spmv_pring_fits(const LevelView& L);

@@ -1037,9 +1037,11 @@ __global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __re
   if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
 }
 
+// r -= alpha q and <r, r>; with r32 also the FP32 rounding of the new r,
+// which the next FP32 V-cycle reads as its finest right-hand side
 __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
                                                  const FcgScalars* __restrict__ sc, size_t len,
-                                                 double* __restrict__ partials) {
+                                                 double* __restrict__ partials, float* __restrict__ r32) {
   if (sc->done) return;
   const double alpha = sc->alpha;
   double acc[2] = {0.0, 0.0};
@@ -1047,9 +1049,16 @@ __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const d
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
+    if (r32) r32[i] = static_cast<float>(ri);
     acc[0] += ri * ri;
   }
   block_sums(acc, partials, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_round_f32(const double* __restrict__ v, float* __restrict__ v32, size_t len) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    v32[i] = static_cast<float>(v[i]);
 }
 
 // x += alpha_j p_j of the iterations not yet added ([flushed, iters)), in
@@ -1542,10 +1551,15 @@ hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, d
 }
 
 hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_rupdate, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, q, sc, len, partials);
+                          hipStream_t s, float* r32) {
+  hipLaunchKernelGGL(k_rupdate, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, q, sc, len, partials, r32);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
                      ring);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_f32(const double* v, float* v32, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_f32, dim3(pupdate_blocks(len)), dim3(256), 0, s, v, v32, len);
   return hipGetLastError();
 }
 

@@ -316,8 +316,10 @@ bool order_less(const Op& a, const Op& b) {
 // mixed mode every level is FP32: the first finest sweep reads the FP64
 // residual and keeps an FP32 copy of it, the last writes FP64 z (and, when
 // q_dots is given, also forms <z, q> and <z, r>, applied at kFinBeta).
+// With r32_ready (mixed single solves) the FP32 rounding of r_in is already
+// in the copy (written by the r update): the first finest sweep reads it.
 void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dots, tpmg::FcgScalars* sc,
-                std::vector<Op>& ops, bool z_float = false) {
+                std::vector<Op>& ops, bool z_float = false, bool r32_ready = false) {
   const int L = m.nlev - 1;
   const int prec = m.fp32 ? 4 : 8;
   std::vector<int> cur(m.nlev, 0);
@@ -361,10 +363,12 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
       const bool finest_first = first && l == L;
       const bool last_of_cycle = (l == 0 && L == 0 && k + 1 == sweeps);
       const bool dots = last_of_cycle && q_dots;
-      const void* f = (finest_first || dots) ? static_cast<const void*>(r_in) : rhs(l);
-      const bool f_double = dots || ((l == L) && (finest_first || !m.fp32));
+      const bool from32 = finest_first && m.fp32 && r32_ready && !dots;
+      const void* f = from32 ? m.fcopy : (finest_first || dots) ? static_cast<const void*>(r_in) : rhs(l);
+      const bool f_double = !from32 && (dots || ((l == L) && (finest_first || !m.fp32)));
       void* out = last_of_cycle ? z_out : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
-      sweep(0, j, 0, k, l, f, f_double, first, out, last_of_cycle && !z_float, finest_first && m.fp32, dots);
+      sweep(0, j, 0, k, l, f, f_double, first, out, last_of_cycle && !z_float, finest_first && m.fp32 && !from32,
+            dots);
       if (!first) cur[l] = 1 - cur[l];
     }
     if (l > 0) {
@@ -417,7 +421,9 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
   // z of an FP32 V-cycle is an FP32 value: kept in FP32 when the last sweep
   // also forms the dots (nothing else reads it in FP64)
   const bool z_float = fused && m.fp32;
-  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops, z_float);
+  // (single solves end each iteration with the r update, which then also
+  // writes the FP32 copy of r; tpmg_solve makes the first one)
+  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops, z_float, single && m.fp32);
   if (!fused) {
     Op d;
     d.order[0] = 2;
@@ -449,6 +455,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     Op ru;
     ru.kind = tpmg::kOpRupdate;
     ru.in1 = m.q;
+    ru.out0 = m.fp32 ? m.fcopy : nullptr;
     ru.out1 = m.r;
     ru.partials = m.partials;
     ru.sc = sc;
@@ -481,6 +488,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     Op ru;
     ru.kind = tpmg::kOpRupdate;
     ru.in1 = m.q;
+    ru.out0 = m.fp32 ? m.fcopy : nullptr;
     ru.out1 = m.r;
     ru.partials = m.partials;
     ru.sc = sc;
@@ -544,7 +552,7 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
                                     op.partials, op.sc, s);
     case tpmg::kOpRupdate:
       return tpmg::launch_rupdate(static_cast<double*>(op.out1), static_cast<const double*>(op.in1), op.sc, op.len,
-                                  op.partials, op.ring, s);
+                                  op.partials, op.ring, s, static_cast<float*>(op.out0));
     case tpmg::kOpRestrict:
       return tpmg::launch_residual_restrict(op.L, op.C, op.prec, op.in0, op.in1, op.out0, s);
     case tpmg::kOpProlong:
@@ -1485,6 +1493,8 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   // the direction before the first iteration, p_{-1} = 0 (slot kDirSlots - 1)
   TPMG_HIP(tpmg::launch_fill(mg->dirs + (tpmg::kDirSlots - 1) * mg->len, mg->len * 8, s));
   TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
+  // the FP32 V-cycle's first right-hand side (later ones come with the r update)
+  if (mg->fp32) TPMG_HIP(tpmg::launch_round_f32(mg->r, static_cast<float*>(mg->fcopy), mg->len, s));
   TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
   TPMG_HIP(hipStreamSynchronize(s));
   const double ff = mg->h_scal->ff;
