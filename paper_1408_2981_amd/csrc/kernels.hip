@@ -906,12 +906,17 @@ __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const d
 }
 
 // Occupancy: an FP32 sweep with up to 8 levels per wave fits two 16-wave
-// workgroups per CU (at most 64 VGPRs, 8 waves per SIMD); otherwise one.
-// FP64 with 16 levels per wave needs more than 128 VGPRs and is limited to
-// 8 waves (nz <= 128).
+// workgroups per CU (at most 64 VGPRs, 8 waves per SIMD); with 16 levels per
+// wave and an FP32 right-hand side, three 8-wave workgroups (at most 80
+// VGPRs, 6 waves per SIMD); otherwise fewer. FP64 with 16 levels per wave
+// needs more than 128 VGPRs and is limited to 8 waves (nz <= 128). wide: an
+// FP64 right-hand side or the fused dots (16 levels per wave: 4 per SIMD).
 template <int KB, typename T>
-constexpr int scan_waves_per_simd(bool dots) {
-  return (sizeof(T) == 4 && KB <= 8 && !dots) ? 8 : (sizeof(T) == 8 && KB == 16) ? 2 : 4;
+constexpr int scan_waves_per_simd(bool wide) {
+  return (sizeof(T) == 4 && KB <= 8)     ? 8
+         : (sizeof(T) == 4 && !wide)    ? 6
+         : (sizeof(T) == 8 && KB == 16) ? 2
+                                        : 4;
 }
 // the batched form also holds its segment's pointers: no FP32 bound beyond 4
 template <int KB, typename T>
@@ -924,7 +929,8 @@ constexpr int scan_max_threads() {
 }
 
 template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd<KB, T>(false))) void k_smooth_scan(
+__global__ __launch_bounds__((scan_max_threads<KB, T>()),
+                             (scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value))) void k_smooth_scan(
     Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in, TO* __restrict__ u_out, T* __restrict__ fcopy,
     T omega, const double* __restrict__ q, double* __restrict__ partials) {
   smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
