@@ -167,9 +167,11 @@ unsigned pupdate_blocks(size_t len);      // blocks of the p-update kernel
 // FCG scalars at `site`.
 
 // mode 0: y = A x (partials <x, y>, e.g. site kFinAlpha). mode 1: y = b - A x
-// (partials <y, y>, <b, b>; site kFinInit). FP64; x and y must not alias.
+// (partials <y, y>, <b, b>; site kFinInit), with y32 non-NULL also its FP32
+// rounding. FP64; x and y must not alias.
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol = 0.0);
+                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol = 0.0,
+                         float* y32 = nullptr);
 // one-block finalisation of nblocks partials at `site` (rtol used at kFinInit)
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s);
 
@@ -214,8 +216,7 @@ hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, 
                             FcgScalars* sc, hipStream_t s);
 hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
                           hipStream_t s, float* r32 = nullptr);
-// v32 = the FP32 rounding of v
-hipError_t launch_round_f32(const double* v, float* v32, size_t len, hipStream_t s);
+
 // pupdate_ring and spmv_ring in one launch (the same bits), for the operator
 // chunks that have an instance (spmv_pring_fits).
 bool spmv_pring_fits(const LevelView& L);

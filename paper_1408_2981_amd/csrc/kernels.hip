@@ -303,7 +303,7 @@ __device__ __forceinline__ void finalize_body(int site, const double* __restrict
 template <int MODE, int CH>
 __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, const double* __restrict__ x,
                                           const double* __restrict__ b, double* __restrict__ y,
-                                          double* __restrict__ partials, GridPos g) {
+                                          double* __restrict__ partials, GridPos g, float* __restrict__ y32 = nullptr) {
   const int chunk = CH > 0 ? CH : chunk_rt;
   const int nchunks = (L.nz + chunk - 1) / chunk;
   const int lb = xcd_tile(g.b, g.nb);
@@ -322,6 +322,7 @@ __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, con
       } else {
         const double rk = bk - ax;
         y[o] = rk;
+        if (y32) y32[o] = static_cast<float>(rk);
         acc[0] += rk * rk;
         acc[1] += bk * bk;
       }
@@ -901,8 +902,8 @@ __global__ __launch_bounds__(256) void k_finalize(int site, const double* __rest
 template <int MODE, int CH>
 __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const double* __restrict__ x,
                                                 const double* __restrict__ b, double* __restrict__ y,
-                                                double* __restrict__ partials) {
-  spmv_body<MODE, CH>(L, chunk, x, b, y, partials, whole_grid());
+                                                double* __restrict__ partials, float* __restrict__ y32) {
+  spmv_body<MODE, CH>(L, chunk, x, b, y, partials, whole_grid(), y32);
 }
 
 // Occupancy: an FP32 sweep with up to 8 levels per wave fits two 16-wave
@@ -1061,11 +1062,6 @@ __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const d
   block_sums(acc, partials, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_round_f32(const double* __restrict__ v, float* __restrict__ v32, size_t len) {
-  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x)
-    v32[i] = static_cast<float>(v[i]);
-}
 
 // x += alpha_j p_j of the iterations not yet added ([flushed, iters)), in
 // order, each a fused multiply-add as in the per-iteration update.
@@ -1301,16 +1297,17 @@ void chunk_variant(int chunk, Fn&& fn) {
 }
 
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol) {
+                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol, float* y32) {
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
   chunk_variant(chunk, [&](auto chc) {
     constexpr int CH = decltype(chc)::value;
     if (mode == 0)
-      hipLaunchKernelGGL((k_spmv64<0, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
+      hipLaunchKernelGGL((k_spmv64<0, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials,
+                         static_cast<float*>(nullptr));
     else
-      hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials);
+      hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials, y32);
   });
   if (site != kFinNone)
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, nullptr);
@@ -1561,11 +1558,6 @@ hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len
   hipLaunchKernelGGL(k_rupdate, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, q, sc, len, partials, r32);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
                      ring);
-  return hipGetLastError();
-}
-
-hipError_t launch_round_f32(const double* v, float* v32, size_t len, hipStream_t s) {
-  hipLaunchKernelGGL(k_round_f32, dim3(pupdate_blocks(len)), dim3(256), 0, s, v, v32, len);
   return hipGetLastError();
 }
 

@@ -1487,14 +1487,14 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = mg->stream;
   const tpmg::LevelView F = mg->view64(mg->nlev - 1);
-  // r = f - A u, rr, ff; p = q = 0 so that the first iteration takes beta = 0
-  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol));
-  TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
-  // the direction before the first iteration, p_{-1} = 0 (slot kDirSlots - 1)
+  // r = f - A u, rr, ff, and for an FP32 V-cycle its first right-hand side,
+  // the FP32 rounding of r (later ones come with the r update); the
+  // direction before the first iteration p_{-1} = 0 (slot kDirSlots - 1) and
+  // q = 0, so that the first iteration takes beta = 0
+  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol,
+                               mg->fp32 ? static_cast<float*>(mg->fcopy) : nullptr));
   TPMG_HIP(tpmg::launch_fill(mg->dirs + (tpmg::kDirSlots - 1) * mg->len, mg->len * 8, s));
   TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
-  // the FP32 V-cycle's first right-hand side (later ones come with the r update)
-  if (mg->fp32) TPMG_HIP(tpmg::launch_round_f32(mg->r, static_cast<float*>(mg->fcopy), mg->len, s));
   TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
   TPMG_HIP(hipStreamSynchronize(s));
   const double ff = mg->h_scal->ff;
