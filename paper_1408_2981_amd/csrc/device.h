@@ -102,8 +102,8 @@ struct FcgRecord {
   int status;
   int done;
   int iters;
-  int seq;        // written last: 0 until the slot holds a record
-  int pad[2];
+  int seq;        // written last: the host sets -1 before a solve
+  double ff;      // ||f||^2 (the record of kFinInit, seq 0)
 };
 constexpr int kRecords = 4;
 
@@ -171,7 +171,7 @@ unsigned pupdate_blocks(size_t len);      // blocks of the p-update kernel
 // rounding. FP64; x and y must not alias.
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
                          double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol = 0.0,
-                         float* y32 = nullptr);
+                         float* y32 = nullptr, FcgRecord* ring = nullptr);
 // one-block finalisation of nblocks partials at `site` (rtol used at kFinInit)
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s);
 

@@ -886,6 +886,18 @@ __global__ __launch_bounds__(256) void k_finalize(int site, const double* __rest
                                                   FcgRecord* __restrict__ ring) {
   const bool iter_site = site == kFinAlpha || site == kFinRR || site == kFinBeta;
   if (!(iter_site && sc->done)) finalize_body(site, partials, nblocks, sc, rtol);
+  if (site == kFinInit && ring != nullptr && threadIdx.x == 0) {
+    // record 0: the initial residual, so that the host can decide while the
+    // first iteration already runs
+    FcgRecord* slot = ring;
+    slot->rr = sc->rr;
+    slot->ff = sc->ff;
+    slot->status = sc->status;
+    slot->done = sc->done;
+    slot->iters = 0;
+    __threadfence_system();
+    slot->seq = 0;
+  }
   if (site == kFinRR && ring != nullptr && threadIdx.x == 0) {
     const int seq = sc->seq + 1;
     sc->seq = seq;
@@ -1297,7 +1309,8 @@ void chunk_variant(int chunk, Fn&& fn) {
 }
 
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
-                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol, float* y32) {
+                         double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol, float* y32,
+                         FcgRecord* ring) {
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
@@ -1310,7 +1323,7 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
       hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials, y32);
   });
   if (site != kFinNone)
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, nullptr);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, ring);
   return hipGetLastError();
 }
 

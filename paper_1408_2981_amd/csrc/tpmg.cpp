@@ -1468,6 +1468,7 @@ hipError_t wait_record(const tpmg::FcgRecord* ring, int seq, hipStream_t s, tpmg
     }
   }
   out->rr = slot->rr;
+  out->ff = slot->ff;
   out->status = slot->status;
   out->done = slot->done;
   out->iters = slot->iters;
@@ -1487,19 +1488,57 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = mg->stream;
   const tpmg::LevelView F = mg->view64(mg->nlev - 1);
-  // r = f - A u, rr, ff, and for an FP32 V-cycle its first right-hand side,
-  // the FP32 rounding of r (later ones come with the r update); the
-  // direction before the first iteration p_{-1} = 0 (slot kDirSlots - 1) and
-  // q = 0, so that the first iteration takes beta = 0
+  // the iteration as a graph, captured once per solution vector (on an idle
+  // stream, before this solve's work is queued)
+  if (maxit > 0 && mg->use_graph && (mg->graph_x != d_u || mg->graph == nullptr)) {
+    TPMG_HIP(hipStreamSynchronize(s));
+    drop_graph(*mg);
+    hipGraph_t g = nullptr;
+    TPMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = fcg_iteration(*mg, d_u);
+    hipError_t ee = hipStreamEndCapture(s, &g);
+    if (ce != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(TPMG_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&mg->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      mg->graph = nullptr;
+      return fail(TPMG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    mg->graph_x = d_u;
+  }
+  // no slot holds a record of this solve yet (the previous solve ended with
+  // its stream drained)
+  for (int i = 0; i < tpmg::kRecords; ++i) mg->ring[i].seq = -1;
+  // r = f - A u, rr, ff (published as record 0), and for an FP32 V-cycle its
+  // first right-hand side, the FP32 rounding of r (later ones come with the r
+  // update); the direction before the first iteration p_{-1} = 0 (slot
+  // kDirSlots - 1) and q = 0, so that the first iteration takes beta = 0
   TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol,
-                               mg->fp32 ? static_cast<float*>(mg->fcopy) : nullptr));
+                               mg->fp32 ? static_cast<float*>(mg->fcopy) : nullptr, mg->ring_dev));
   TPMG_HIP(tpmg::launch_fill(mg->dirs + (tpmg::kDirSlots - 1) * mg->len, mg->len * 8, s));
   TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
-  TPMG_HIP(hipMemcpyAsync(mg->h_scal, mg->scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, s));
-  TPMG_HIP(hipStreamSynchronize(s));
-  const double ff = mg->h_scal->ff;
+  int launched = 0;
+  auto launch_next = [&]() -> hipError_t {
+    ++launched;
+    return mg->use_graph ? hipGraphLaunch(mg->graph, s) : fcg_iteration(*mg, d_u);
+  };
+  // The first iteration is queued before the host reads record 0: when the
+  // initial residual already meets the tolerance (or is not finite) the
+  // device flag is set and the iteration leaves everything as it was.
+  hipError_t werr = hipSuccess;
+  if (maxit > 0) werr = launch_next();
+  tpmg::FcgRecord rec0;
+  if (werr == hipSuccess) werr = wait_record(mg->ring, 0, s, &rec0);
+  if (werr != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    return fail(TPMG_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(werr));
+  }
+  const double ff = rec0.ff;
   const double fnorm = std::sqrt(ff);
-  double rnorm = std::sqrt(mg->h_scal->rr);
+  double rnorm = std::sqrt(rec0.rr);
   int iters = 0;
   auto record = [&](int k, double v) {
     if (info && info->history && k < info->history_cap) info->history[k] = v;
@@ -1511,37 +1550,12 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   } else if (rnorm <= rtol * fnorm) {
     result = TPMG_OK;
   } else {
-    if (mg->use_graph && (mg->graph_x != d_u || mg->graph == nullptr)) {
-      drop_graph(*mg);
-      hipGraph_t g = nullptr;
-      TPMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      hipError_t ce = fcg_iteration(*mg, d_u);
-      hipError_t ee = hipStreamEndCapture(s, &g);
-      if (ce != hipSuccess || ee != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(TPMG_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
-      }
-      hipError_t ie = hipGraphInstantiate(&mg->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ie != hipSuccess) {
-        mg->graph = nullptr;
-        return fail(TPMG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-      }
-      mg->graph_x = d_u;
-    }
     // Iteration it+1 is queued before the host waits for iteration it's
     // record unless the residual norms so far suggest that iteration it may
     // converge: a queued iteration after convergence is left without effect
     // (the update and the scalars skip once done) but costs its time.
-    std::memset(mg->ring, 0, tpmg::kRecords * sizeof(tpmg::FcgRecord));
-    int launched = 0;
-    auto launch_next = [&]() -> hipError_t {
-      ++launched;
-      return mg->use_graph ? hipGraphLaunch(mg->graph, s) : fcg_iteration(*mg, d_u);
-    };
     const double target = rtol * fnorm;
     double prev = rnorm;   // norm before the last known one (ratio estimate)
-    hipError_t werr = hipSuccess;
     for (int it = 0; it < maxit; ++it) {
       if (launched == it) TPMG_HIP(launch_next());
       const double ratio = prev > 0.0 ? std::min(1.0, rnorm / prev) : 1.0;
@@ -1567,15 +1581,15 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
         break;
       }
     }
-    // x += alpha p of the iterations not yet added (after an iteration queued
-    // ahead, which changes neither iters nor the ring's counted slots)
-    hipError_t fe = tpmg::launch_flush(d_u, mg->dirs, mg->scal, mg->len, s);
-    if (werr == hipSuccess) werr = fe;
-    // drains an iteration queued ahead; reports the first device error
-    const hipError_t se = hipStreamSynchronize(s);
-    if (werr != hipSuccess || se != hipSuccess)
-      return fail(TPMG_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(werr != hipSuccess ? werr : se));
   }
+  // x += alpha p of the iterations not yet added (after an iteration queued
+  // ahead, which changes neither iters nor the ring's counted slots)
+  hipError_t fe = tpmg::launch_flush(d_u, mg->dirs, mg->scal, mg->len, s);
+  if (werr == hipSuccess) werr = fe;
+  // drains an iteration queued ahead; reports the first device error
+  const hipError_t se = hipStreamSynchronize(s);
+  if (werr != hipSuccess || se != hipSuccess)
+    return fail(TPMG_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(werr != hipSuccess ? werr : se));
   const auto t1 = std::chrono::steady_clock::now();
   if (info) {
     info->iters = iters;

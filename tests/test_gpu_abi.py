@@ -40,6 +40,27 @@ def test_zero_rhs():
     assert not torch.any(ud)
 
 
+def test_converged_guess_and_maxit_zero_leave_u_unchanged():
+    """The first iteration is queued before the host reads the initial
+    residual: when the guess already meets the tolerance, or maxit is 0, the
+    solve reports 0 iterations and returns the guess bit for bit."""
+    h, P, f = make("ico3_nz13_quad")
+    fd = P.pack(f)
+    ud = P.device_vector()
+    st, iters, *_ = P.solve(fd, ud, rtol=1e-8, maxit=100)
+    assert st == T.TPMG_OK and iters > 0
+    u0 = ud.clone()
+    st, iters, relres, *_ = P.solve(fd, ud, rtol=1e-6, maxit=100)
+    assert st == T.TPMG_OK and iters == 0 and relres <= 1e-6
+    assert torch.equal(ud, u0)
+    st, iters, *_ = P.solve(fd, ud, rtol=1e-14, maxit=0)
+    assert st == T.TPMG_NOT_CONVERGED and iters == 0
+    assert torch.equal(ud, u0)
+    # and a following solve from that guess still converges
+    st, iters, relres, *_ = P.solve(fd, ud, rtol=1e-10, maxit=100)
+    assert st == T.TPMG_OK and iters > 0 and relres <= 1e-10
+
+
 def test_workspace_too_small_and_alias():
     h, P, f = make("ico2_nz8_rand")
     p = T.tpmg_mg_params_default()
