@@ -196,10 +196,13 @@ tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z);
 
 /* Solves A u = f by V-cycle-preconditioned flexible CG, starting from the
  * guess in d_u (tiled FP64), until ||r|| <= rtol ||f|| (2-norms of the
- * cell-integral residual) or maxit iterations. Synchronises the stream once
- * per iteration. Returns TPMG_OK, TPMG_NOT_CONVERGED, or
- * TPMG_ERR_BREAKDOWN (u then holds the last finite iterate). info may be
- * NULL. */
+ * cell-integral residual) or maxit iterations. The host reads each
+ * iteration's residual norm from a record the device writes to pinned
+ * memory, with the next iteration usually queued already; the call returns
+ * after the stream has drained. A guess that already meets the tolerance,
+ * or maxit = 0, returns u unchanged with 0 iterations. Returns TPMG_OK,
+ * TPMG_NOT_CONVERGED, or TPMG_ERR_BREAKDOWN (u then holds the last finite
+ * iterate). info may be NULL. */
 tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
                        tpmg_solve_info* info);
 
