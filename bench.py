@@ -353,6 +353,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
                     help="choose kernels by timed trials at setup (excluded from the timed solves)")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="1: replay each FCG iteration as one HIP graph; 0 (default): launch the iteration's "
+                         "kernels one by one, which on this workload leaves no gap between iterations "
+                         "(a graph launch costs ~8 us at each boundary)")
     ap.add_argument("--report", action="store_true",
                     help="also measure the anisotropy sweep on the refinement-7 grid (one JSON line per ratio)")
     ap.add_argument("--profile-sweep", action="store_true",
@@ -388,7 +392,7 @@ def main():
     f_host = synth.make_rhs(w, geo["centres"], geo["areas"], P64.vk())
     P32 = T.Problem(w.refinement, w.r_faces(), w.omega2)
     for name, P, fp32 in (("fp64", P64, False), ("mixed", P32, True)):
-        P.setup(precond_fp32=fp32, use_graph=True, autotune=args.autotune)
+        P.setup(precond_fp32=fp32, use_graph=bool(args.graph), autotune=args.autotune)
         log(f"{name}: tuning (coarsest first) {P.tuning()}")
         f = P.pack(f_host)
         u = P.device_vector()
@@ -440,6 +444,7 @@ def main():
             "mixed_speedup_vs_fp64": fp64["ms"] / mixed["ms"],
             "fp64_sweep_GBs": fp64["sweep_bytes"] / (fp64["sweep_ms"] / 1000.0) / 1e9,
             "autotune": args.autotune,
+            "graph": args.graph,
             "finest_tuning_mixed": P32.tuning()[-1],
         },
         "roofline": {
