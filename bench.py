@@ -14,6 +14,7 @@ one GPU.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -401,15 +402,22 @@ def main():
             torch.cuda.synchronize()
             P.solve(f, u)
         times, iters, relres = [], None, None
-        for _ in range(args.steps):
-            u.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, it, rr, hist, _ = P.solve(f, u)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            assert st == T.TPMG_OK, (name, st)
-            iters, relres = it, rr
+        # the interpreter's cyclic garbage collector stays off while the solves
+        # are timed (a full collection over torch's objects takes tens of ms)
+        gc.collect()
+        gc.disable()
+        try:
+            for _ in range(args.steps):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it, rr, hist, _ = P.solve(f, u)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                assert st == T.TPMG_OK, (name, st)
+                iters, relres = it, rr
+        finally:
+            gc.enable()
         ms = 1000.0 * sum(times) / len(times)
         avg_sweep_ms, sweep_bytes = T.tpmg_mg_time_sweep(P.mg, args.sweep_reps)
         results[name] = dict(ms=ms, iters=iters, relres=relres, sweep_ms=avg_sweep_ms, sweep_bytes=sweep_bytes,
