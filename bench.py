@@ -119,7 +119,8 @@ def anisotropy_report(steps: int = 3):
         w = synth.workload(f"ico7_nz128_ar{ratio}")
         line = {"workload": w.name, "unknowns": w.unknowns, "thickness_km": w.thickness * synth.R_EARTH_M / 1e3}
         for name, fp32 in (("fp64", False), ("mixed", True)):
-            P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=fp32, use_graph=True)
+            P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=fp32, use_graph=False,
+                                                                      autotune=1)
             geo = P.geometry()
             f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
             u0 = P.pack(synth.uniform_noise(w.n, w.nz, 7))
@@ -378,6 +379,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    # The interpreter's cyclic garbage collector stays off for the run: a full
+    # collection over torch's objects took ~40 ms, inside whichever timed
+    # solve it happened to interrupt.
+    gc.collect()
+    gc.disable()
 
     w = synth.workload(args.workload)
     log(f"workload {w.name}: {w.unknowns} unknowns, refinement {w.refinement}, nz {w.nz}")
@@ -402,22 +408,15 @@ def main():
             torch.cuda.synchronize()
             P.solve(f, u)
         times, iters, relres = [], None, None
-        # the interpreter's cyclic garbage collector stays off while the solves
-        # are timed (a full collection over torch's objects takes tens of ms)
-        gc.collect()
-        gc.disable()
-        try:
-            for _ in range(args.steps):
-                u.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st, it, rr, hist, _ = P.solve(f, u)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-                assert st == T.TPMG_OK, (name, st)
-                iters, relres = it, rr
-        finally:
-            gc.enable()
+        for _ in range(args.steps):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, rr, hist, _ = P.solve(f, u)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            assert st == T.TPMG_OK, (name, st)
+            iters, relres = it, rr
         ms = 1000.0 * sum(times) / len(times)
         avg_sweep_ms, sweep_bytes = T.tpmg_mg_time_sweep(P.mg, args.sweep_reps)
         results[name] = dict(ms=ms, iters=iters, relres=relres, sweep_ms=avg_sweep_ms, sweep_bytes=sweep_bytes,
