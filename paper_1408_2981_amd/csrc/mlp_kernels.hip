@@ -159,27 +159,43 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // rows (one tile of columns of the solver's grid) from the tiled right-hand
 // side through the features and the three layers, with the activations kept
 // in LDS, so that only the right-hand side is read and only the guess is
-// written. Each layer is the GEMM above at the same
-// operand rounding, K order and epilogue expression, so the result is the
-// bits of the three separate products. Hidden width 256; nz a multiple of 32
-// up to 128 (kp <= 160).
+// written. Each wave owns its output units, so it reads its weight
+// fragments straight from memory (the 200 KB of weights stay in L2), a few
+// 16-wide K slices ahead of the matrix cores, without staging or barriers
+// inside a layer. Each layer is the GEMM above at the same operand rounding,
+// K order and epilogue expression, so the result is the bits of the three
+// separate products. Hidden width 256; nz a multiple of 32 up to 128, the
+// padded feature width kp a multiple of 32 with nz + 3 <= kp <= nz + 32.
 // ---------------------------------------------------------------------------
 constexpr int kInferRows = 64;
 constexpr int kInferHidden = 256;
-constexpr int kInferKpMax = 160;
-constexpr int kXLd = kInferKpMax + 8;
+constexpr int kInferAhead = 4;   // K slices of weight fragments in flight per wave
 constexpr int kHLd = kInferHidden + 8;
-constexpr size_t kInferLds = static_cast<size_t>(kInferRows) * kXLd * 2 + static_cast<size_t>(kInferRows) * kHLd * 2 +
-                             static_cast<size_t>(kInferHidden) * kLdsRow * 2;
+template <int NZT>
+constexpr int infer_xld() {
+  return 32 * NZT + 40;
+}
+template <int NZT>
+constexpr size_t infer_lds() {
+  // features + hidden activations; the FP64 output staging reuses them
+  const size_t act = static_cast<size_t>(kInferRows) * infer_xld<NZT>() * 2 + static_cast<size_t>(kInferRows) * kHLd * 2;
+  const size_t out = static_cast<size_t>(32 * NZT) * kInferRows * 8;
+  return act > out ? act : out;
+}
+
+// the B fragment of one 32 x 32 x 16 product: row n of a K-contiguous
+// weight matrix, k .. k + 7 of this lane's half of the slice
+__device__ __forceinline__ bf16x8 weight_fragment(const bf16* __restrict__ w, int ld, int n, int k) {
+  return *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(n) * ld + k);
+}
 
 template <int NZT>
 __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
   constexpr int NZ = 32 * NZT;
-  __shared__ __align__(16) unsigned char sm[kInferLds];
-  bf16 (*Xs)[kXLd] = reinterpret_cast<bf16 (*)[kXLd]>(sm);
-  bf16 (*Hs)[kHLd] = reinterpret_cast<bf16 (*)[kHLd]>(sm + static_cast<size_t>(kInferRows) * kXLd * 2);
-  bf16 (*Ws)[kLdsRow] = reinterpret_cast<bf16 (*)[kLdsRow]>(sm + static_cast<size_t>(kInferRows) * kXLd * 2 +
-                                                            static_cast<size_t>(kInferRows) * kHLd * 2);
+  constexpr int XLd = infer_xld<NZT>();
+  __shared__ __align__(16) unsigned char sm[infer_lds<NZT>()];
+  bf16 (*Xs)[XLd] = reinterpret_cast<bf16 (*)[XLd]>(sm);
+  bf16 (*Hs)[kHLd] = reinterpret_cast<bf16 (*)[kHLd]>(sm + static_cast<size_t>(kInferRows) * XLd * 2);
   const int m0 = blockIdx.x * kInferRows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 31, lk = 8 * (lane >> 5);
@@ -187,58 +203,81 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
   {
     // the features of the block's tile straight from the tiled right-hand
     // side (one coalesced row per level) and the neighbours' column means,
-    // standardised and rounded as the features kernel does; zero beyond n
+    // standardised and rounded as the features kernel does; zero beyond n.
+    // Every load of the tile is issued before the first is used.
     const int cnt = min(kInferRows, a.n - m0);
     const size_t base = static_cast<size_t>(blockIdx.x) * kInferRows * NZ;
-    for (int i = threadIdx.x; i < kInferRows * NZ; i += 256) {
+    constexpr int kPer = kInferRows * NZ / 256;
+    double fv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) fv[q] = a.f[base + threadIdx.x + 256 * q];
+    double mean = 0.0;
+    const int jm = threadIdx.x >> 6, cm = threadIdx.x & 63;
+    if (jm < 3 && cm < cnt) mean = a.means[a.nbr[static_cast<size_t>(jm) * a.npad + m0 + cm]];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + 256 * q;
       const int k = i >> 6, c = i & 63;
-      const float val = (static_cast<float>(a.f[base + i]) - a.mu_x[k]) / a.sd_x[k];
+      const float val = (static_cast<float>(fv[q]) - a.mu_x[k]) / a.sd_x[k];
       Xs[c][k] = c < cnt ? static_cast<bf16>(val) : static_cast<bf16>(0.0f);
     }
-    for (int i = threadIdx.x; i < kInferRows * (a.kp - NZ); i += 256) {
-      const int c = i / (a.kp - NZ), j = i - c * (a.kp - NZ);
+    if (jm < 3) {
       float val = 0.0f;
-      if (j < 3 && c < cnt) {
-        const float mean = static_cast<float>(a.means[a.nbr[static_cast<size_t>(j) * a.npad + m0 + c]]);
-        val = (mean - a.mu_x[NZ + j]) / a.sd_x[NZ + j];
-      }
-      Xs[c][NZ + j] = static_cast<bf16>(val);
+      if (cm < cnt) val = (static_cast<float>(mean) - a.mu_x[NZ + jm]) / a.sd_x[NZ + jm];
+      Xs[cm][NZ + jm] = static_cast<bf16>(val);
+    }
+    // padding features
+    const int pad = a.kp - NZ - 3;
+    for (int i = threadIdx.x; i < kInferRows * pad; i += 256) {
+      const int c = i / pad, j = 3 + (i - c * pad);
+      Xs[c][NZ + j] = static_cast<bf16>(0.0f);
     }
   }
+  __syncthreads();
 
-  // layers 1 and 2: wave w owns hidden units [64 w, 64 w + 64) of all 64 rows
+  // layers 1 and 2: wave w owns hidden units [64 w, 64 w + 64) of all 64
+  // rows; its fragments of slice s are rows 64 w + 32 j + lr, k 16 s + lk
   f32x16 acc[2][2];
-  auto hidden_layer = [&](const bf16* __restrict__ w, int K, const float* __restrict__ bias, bool from_x) {
+  auto hidden_layer = [&](const bf16* __restrict__ w, int K, bool from_x) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    StageRegs<kInferHidden> next;
-    next.fetch(w, K, kInferHidden, 0, K);
-    for (int k0 = 0; k0 < K; k0 += kBK) {
-      next.put(Ws);
-      __syncthreads();
-      if (k0 + kBK < K) next.fetch(w, K, kInferHidden, k0 + kBK, K);
+    const int ns = K / 16;
+    bf16x8 bq[kInferAhead][2];
 #pragma unroll
-      for (int ks = 0; ks < kBK; ks += 16) {
-        bf16x8 av[2], bv[2];
+    for (int d = 0; d < kInferAhead; ++d)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-          av[i] = from_x ? *reinterpret_cast<const bf16x8*>(&Xs[32 * i + lr][k0 + ks + lk])
-                         : *reinterpret_cast<const bf16x8*>(&Hs[32 * i + lr][k0 + ks + lk]);
+      for (int j = 0; j < 2; ++j)
+        if (d < ns) bq[d][j] = weight_fragment(w, K, 64 * wave + 32 * j + lr, 16 * d + lk);
+    for (int s0 = 0; s0 < ns; s0 += kInferAhead) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const bf16x8*>(&Ws[64 * wave + 32 * j + lr][ks + lk]);
+      for (int d = 0; d < kInferAhead; ++d) {
+        const int sl = s0 + d;
+        if (sl < ns) {
+          const int k = 16 * sl + lk;
+          bf16x8 av[2], bv[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < 2; ++i)
+            av[i] = from_x ? *reinterpret_cast<const bf16x8*>(&Xs[32 * i + lr][k])
+                           : *reinterpret_cast<const bf16x8*>(&Hs[32 * i + lr][k]);
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 2; ++j) {
+            bv[j] = bq[d][j];
+            if (sl + kInferAhead < ns) bq[d][j] = weight_fragment(w, K, 64 * wave + 32 * j + lr, k + 16 * kInferAhead);
+          }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
       }
-      __syncthreads();
     }
-    // (every wave is past its last read of Hs: the loop ends with a barrier)
+  };
+  auto hidden_out = [&](const float* __restrict__ bias) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -249,39 +288,49 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
           const int nn = 64 * wave + 32 * j + lr;
           Hs[m][nn] = static_cast<bf16>(fmaxf(acc[i][j][r] + bias[nn], 0.0f));
         }
-    __syncthreads();
   };
-  hidden_layer(a.w1, a.kp, a.b1, true);
-  hidden_layer(a.w2, kInferHidden, a.b2, false);
+  hidden_layer(a.w1, a.kp, true);
+  hidden_out(a.b1);   // (layer 1 reads Xs only)
+  __syncthreads();
+  hidden_layer(a.w2, kInferHidden, false);
+  __syncthreads();   // every wave is past its last read of Hs
+  hidden_out(a.b2);
+  __syncthreads();
 
   // layer 3: 2 x NZT products of 32 x 32, product t = wave + 4 q on rows
-  // 32 (t % 2), levels 32 (t / 2)
+  // 32 (t % 2), levels 32 (t / 2); fragments rows 32 (t / 2) + lr of w3
   constexpr int kOwn = (2 * NZT + 3) / 4;
+  constexpr int ns3 = kInferHidden / 16;
   f32x16 acc3[kOwn];
+  bf16x8 bq3[kInferAhead][kOwn];
 #pragma unroll
-  for (int q = 0; q < kOwn; ++q)
+  for (int q = 0; q < kOwn; ++q) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc3[q][r] = 0.0f;
-  StageRegs<NZ> next3;
-  next3.fetch(a.w3, kInferHidden, NZ, 0, kInferHidden);
-  for (int k0 = 0; k0 < kInferHidden; k0 += kBK) {
-    next3.put(Ws);
-    __syncthreads();
-    if (k0 + kBK < kInferHidden) next3.fetch(a.w3, kInferHidden, NZ, k0 + kBK, kInferHidden);
+    const int t = wave + 4 * q;
 #pragma unroll
-    for (int ks = 0; ks < kBK; ks += 16) {
+    for (int d = 0; d < kInferAhead; ++d)
+      if (t < 2 * NZT) bq3[d][q] = weight_fragment(a.w3, kInferHidden, 32 * (t >> 1) + lr, 16 * d + lk);
+  }
+  for (int s0 = 0; s0 < ns3; s0 += kInferAhead) {
+#pragma unroll
+    for (int d = 0; d < kInferAhead; ++d) {
+      const int sl = s0 + d;
+      const int k = 16 * sl + lk;
 #pragma unroll
       for (int q = 0; q < kOwn; ++q) {
         const int t = wave + 4 * q;
         if (t < 2 * NZT) {
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Hs[32 * (t & 1) + lr][k0 + ks + lk]);
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Ws[32 * (t >> 1) + lr][ks + lk]);
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Hs[32 * (t & 1) + lr][k]);
+          const bf16x8 bv = bq3[d][q];
+          if (sl + kInferAhead < ns3)
+            bq3[d][q] = weight_fragment(a.w3, kInferHidden, 32 * (t >> 1) + lr, k + 16 * kInferAhead);
           acc3[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc3[q], 0, 0, 0);
         }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();   // every wave is past its last read of Hs (the staging below overlays it)
 
   // de-standardise into [level][row] FP64 staging over the whole LDS, then
   // one coalesced 64-value row of the tiled guess per level
@@ -576,7 +625,8 @@ hipError_t gemm_tile(const GemmArgs& g, hipStream_t s) {
 }  // namespace
 
 bool mlp_infer_fits(int hidden, int nz, int kp) {
-  return hidden == kInferHidden && nz % 32 == 0 && nz >= 32 && nz <= 128 && kp % 8 == 0 && kp <= kInferKpMax;
+  return hidden == kInferHidden && nz % 32 == 0 && nz >= 32 && nz <= 128 && kp % 32 == 0 && kp >= nz + 3 &&
+         kp <= nz + 32;
 }
 
 hipError_t launch_mlp_col_means(const FineGrid& g, const double* f, double* means, hipStream_t s) {
