@@ -8,7 +8,7 @@ levels, H = 10 km, unit profiles, right-hand side = manufactured field plus
 (FP64 CG, FP32 V-cycle); the FP64 solve is timed on the same grid and
 reported alongside. Inputs are resident in HBM before timing starts.
 
-Prints one JSON line. `--gpus N` with N > 1 is refused: this build runs on
+Prints one JSON line. `--gpus N` with N > 1 is refused: the solver runs on
 one GPU.
 """
 from __future__ import annotations
@@ -367,7 +367,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is not part of this build", file=sys.stderr)
+              "the multi-GPU decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

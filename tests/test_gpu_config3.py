@@ -3,7 +3,7 @@ levels (41,943,040 unknowns), at both ends of the anisotropy sweep
 (H = 1e-1 and 1e-3 x the horizontal spacing), in the configuration bench.py times
 (graph replay, autotuned kernels). The oracle cannot run the full solve
 here in seconds, so the checks are what holds at any size, with the
-oracle's own FP64 operator as the judge: the operator against the oracle's
+oracle's own FP64 operator as the reference: the operator against the oracle's
 on a random field, and both solves' true residual f - A u, evaluated by the
 oracle, below the stopping tolerance."""
 import numpy as np
