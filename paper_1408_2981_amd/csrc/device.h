@@ -134,6 +134,8 @@ struct BatchLaunch {
   int kind;         // OpKind
   int prec;         // 8 or 4 (V-cycle precision)
   int scan_levels;  // smoother: levels per wave (the same for every segment of the launch)
+  int chunk;        // residual + restriction, operator: the levels-per-wave instance of every
+                    // segment (1, 2, 4, 8, 16), or 0 for the per-segment runtime chunk
   bool f_double, out_double, zero, fcopy, dots;   // smoother variant
   double omega;
   unsigned grid, block;

@@ -1169,13 +1169,15 @@ __global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd_b
                                                      sg->partials, g);
 }
 
-template <typename T>
+// (CH > 0: every segment's chunk is CH, the instance the single launches
+// use for that chunk, so a batch forms the same bits)
+template <typename T, int CH>
 __global__ __launch_bounds__(256) void kb_residual_restrict(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  residual_restrict_body<T, 0>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
-                            static_cast<const T*>(sg->in1), static_cast<T*>(sg->out0), g);
+  residual_restrict_body<T, CH>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
+                             static_cast<const T*>(sg->in1), static_cast<T*>(sg->out0), g);
 }
 
 template <typename T>
@@ -1187,12 +1189,13 @@ __global__ __launch_bounds__(256) void kb_prolong_add(const Seg* __restrict__ se
                       static_cast<T*>(sg->out0), g);
 }
 
+template <int CH>
 __global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
   const Seg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  spmv_body<0, 0>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
-               static_cast<double*>(sg->out0), sg->partials, g);
+  spmv_body<0, CH>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
+                   static_cast<double*>(sg->out0), sg->partials, g);
 }
 
 template <typename TZ>
@@ -1643,10 +1646,13 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
       if (b.prec == 8) return batched_smooth_t<double>(b, s);
       return batched_smooth_t<float>(b, s);
     case kOpRestrict:
-      if (b.prec == 8)
-        hipLaunchKernelGGL(kb_residual_restrict<double>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
-      else
-        hipLaunchKernelGGL(kb_residual_restrict<float>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      chunk_variant(b.chunk, [&](auto chc) {
+        constexpr int CH = decltype(chc)::value;
+        if (b.prec == 8)
+          hipLaunchKernelGGL((kb_residual_restrict<double, CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+        else
+          hipLaunchKernelGGL((kb_residual_restrict<float, CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      });
       break;
     case kOpProlong:
       if (b.prec == 8)
@@ -1655,7 +1661,10 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
         hipLaunchKernelGGL(kb_prolong_add<float>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       break;
     case kOpSpmv:
-      hipLaunchKernelGGL(kb_spmv64, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      chunk_variant(b.chunk, [&](auto chc) {
+        constexpr int CH = decltype(chc)::value;
+        hipLaunchKernelGGL((kb_spmv64<CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      });
       break;
     case kOpPupdate:
       if (b.f_double)

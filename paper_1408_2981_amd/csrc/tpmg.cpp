@@ -630,10 +630,19 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
   // smoother sweeps of one position are grouped by levels per wave (one
   // kernel instance per launch)
   auto kb_of = [](const Op& o) { return o.kind == tpmg::kOpSmooth ? o.L.tune.scan_levels : 0; };
+  // residual + restriction and the operator: problems whose chunk has an
+  // instance of its own launch it apart from the rest (runtime chunk, 0)
+  auto ch_of = [](const Op& o) {
+    if (o.kind != tpmg::kOpRestrict && o.kind != tpmg::kOpSpmv) return 0;
+    const int c = tpmg::effective_chunk(o.kind == tpmg::kOpRestrict ? o.L.tune.chunk_rr : o.L.tune.chunk_spmv,
+                                        o.L.npad, o.L.nz);
+    return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) ? c : 0;
+  };
   auto group_less = [&](const Op& a, const Op& c) {
     if (order_less(a, c)) return true;
     if (order_less(c, a)) return false;
-    return kb_of(a) < kb_of(c);
+    if (kb_of(a) != kb_of(c)) return kb_of(a) < kb_of(c);
+    return ch_of(a) < ch_of(c);
   };
   std::stable_sort(items.begin(), items.end(),
                    [&](const Item& a, const Item& c) { return group_less(a.op, c.op); });
@@ -649,6 +658,7 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
     L.kind = o.kind;
     L.prec = o.prec;
     L.scan_levels = kb_of(o);
+    L.chunk = ch_of(o);
     L.f_double = o.f_double;
     L.out_double = o.out_double;
     L.zero = o.zero;
