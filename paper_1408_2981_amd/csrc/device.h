@@ -127,6 +127,7 @@ struct Seg {
   double* partials;
   FcgScalars* sc;
   size_t len;       // BLAS-1 vector length
+  double* aux;      // direction update inside the operator: the direction ring
 };
 
 // A grouped launch over the segments of several problems.

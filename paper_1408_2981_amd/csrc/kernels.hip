@@ -1012,17 +1012,17 @@ __global__ __launch_bounds__(256) void k_spmv_ring(Lv<double> L, int chunk, cons
 // k_pupdate_ring, so the same bits), stored for the wave's own points, and
 // the ring's flush, when due, runs on the same points first.
 template <int CH, typename TZ>
-__global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __restrict__ z, double* __restrict__ ring,
-                                                    size_t len, double* __restrict__ x, double* __restrict__ q,
-                                                    double* __restrict__ partials, FcgScalars* __restrict__ sc) {
-  if (sc->done) return;
+__device__ __forceinline__ void spmv_pring_body(const Lv<double>& L, const TZ* __restrict__ z,
+                                                double* __restrict__ ring, size_t len, double* __restrict__ x,
+                                                double* __restrict__ q, double* __restrict__ partials,
+                                                FcgScalars* __restrict__ sc, GridPos g) {
   const int k = sc->iters;
   const double beta = sc->beta;
   const bool flush = k > 0 && k % kDirSlots == 0;
   const double* __restrict__ pp = ring + static_cast<size_t>((k + kDirSlots - 1) % kDirSlots) * len;
   double* __restrict__ pn = ring + static_cast<size_t>(k % kDirSlots) * len;
   const int nchunks = (L.nz + CH - 1) / CH;
-  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  const int lb = xcd_tile(g.b, g.nb);
   const int item = __builtin_amdgcn_readfirstlane(lb * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   double acc[2] = {0.0, 0.0};
@@ -1053,25 +1053,39 @@ __global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __re
   }
   block_sums(acc, partials, lb);
   // (no block of this kernel reads flushed)
-  if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
+  if (flush && g.b == 0 && threadIdx.x == 0) sc->flushed = k;
+}
+
+template <int CH, typename TZ>
+__global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __restrict__ z, double* __restrict__ ring,
+                                                    size_t len, double* __restrict__ x, double* __restrict__ q,
+                                                    double* __restrict__ partials, FcgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  spmv_pring_body<CH, TZ>(L, z, ring, len, x, q, partials, sc, whole_grid());
 }
 
 // r -= alpha q and <r, r>; with r32 also the FP32 rounding of the new r,
 // which the next FP32 V-cycle reads as its finest right-hand side
-__global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
-                                                 const FcgScalars* __restrict__ sc, size_t len,
-                                                 double* __restrict__ partials, float* __restrict__ r32) {
-  if (sc->done) return;
+__device__ __forceinline__ void rupdate_body(double* __restrict__ r, const double* __restrict__ q,
+                                             const FcgScalars* __restrict__ sc, size_t len,
+                                             double* __restrict__ partials, float* __restrict__ r32, GridPos g) {
   const double alpha = sc->alpha;
   double acc[2] = {0.0, 0.0};
-  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+  for (size_t i = static_cast<size_t>(g.b) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(g.nb) * blockDim.x) {
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     if (r32) r32[i] = static_cast<float>(ri);
     acc[0] += ri * ri;
   }
-  block_sums(acc, partials, blockIdx.x);
+  block_sums(acc, partials, g.b);
+}
+
+__global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
+                                                 const FcgScalars* __restrict__ sc, size_t len,
+                                                 double* __restrict__ partials, float* __restrict__ r32) {
+  if (sc->done) return;
+  rupdate_body(r, q, sc, len, partials, r32, whole_grid());
 }
 
 
@@ -1212,6 +1226,23 @@ __global__ __launch_bounds__(256) void kb_fcg_update(const Seg* __restrict__ seg
   if (!sg) return;
   fcg_update_body(static_cast<double*>(sg->out0), static_cast<double*>(sg->out1), static_cast<const double*>(sg->in0),
                   static_cast<const double*>(sg->in1), sg->sc, sg->len, sg->partials, g);
+}
+
+template <int CH, typename TZ>
+__global__ __launch_bounds__(256) void kb_spmv_pring(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  spmv_pring_body<CH, TZ>(view<double>(sg->L), static_cast<const TZ*>(sg->in0), sg->aux, sg->len,
+                          static_cast<double*>(sg->out1), static_cast<double*>(sg->out0), sg->partials, sg->sc, g);
+}
+
+__global__ __launch_bounds__(256) void kb_rupdate(const Seg* __restrict__ segs, int nseg) {
+  GridPos g;
+  const Seg* sg = find_segment(segs, nseg, g);
+  if (!sg) return;
+  rupdate_body(static_cast<double*>(sg->out1), static_cast<const double*>(sg->in1), sg->sc, sg->len, sg->partials,
+               static_cast<float*>(sg->out0), g);
 }
 
 // one block per problem
@@ -1665,6 +1696,22 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
         constexpr int CH = decltype(chc)::value;
         hipLaunchKernelGGL((kb_spmv64<CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       });
+      break;
+    case kOpSpmvPRing:
+      // (the plan only forms it for chunks with an instance)
+      if (b.chunk == 0) return hipErrorInvalidValue;
+      chunk_variant(b.chunk, [&](auto chc) {
+        constexpr int CH = decltype(chc)::value;
+        if constexpr (CH > 0) {
+          if (b.f_double)
+            hipLaunchKernelGGL((kb_spmv_pring<CH, double>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+          else
+            hipLaunchKernelGGL((kb_spmv_pring<CH, float>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+        }
+      });
+      break;
+    case kOpRupdate:
+      hipLaunchKernelGGL(kb_rupdate, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       break;
     case kOpPupdate:
       if (b.f_double)

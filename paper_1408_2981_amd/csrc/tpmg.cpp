@@ -416,14 +416,18 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
 //   x += alpha p, r -= alpha q, rr = <r,r>.
 // With nz beyond the fused smoother's range the dots are a separate op
 // (kind -1, single solves only).
-void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, bool single = true) {
+// batch_ring: a batch whose problems all have the fused operator instance
+// runs the single solves' direction-ring form too.
+void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, bool single = true,
+             bool batch_ring = false) {
   const bool fused = m.tune.back().smoother == tpmg::kSmScan;
   // z of an FP32 V-cycle is an FP32 value: kept in FP32 when the last sweep
   // also forms the dots (nothing else reads it in FP64)
   const bool z_float = fused && m.fp32;
-  // (single solves end each iteration with the r update, which then also
-  // writes the FP32 copy of r; tpmg_solve makes the first one)
-  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops, z_float, single && m.fp32);
+  const bool pring = single ? tpmg::spmv_pring_fits(m.view64(m.nlev - 1)) : batch_ring;
+  // (the ring form ends each iteration with the r update, which then also
+  // writes the FP32 copy of r; the solve's start makes the first one)
+  vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops, z_float, (single || pring) && m.fp32);
   if (!fused) {
     Op d;
     d.order[0] = 2;
@@ -436,11 +440,14 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     d.len = m.len;
     ops.push_back(d);
   }
-  if (single && tpmg::spmv_pring_fits(m.view64(m.nlev - 1))) {
-    // single solves keep the directions in a ring and add alpha p to x when
-    // the ring is full (and after the last iteration), not in every update;
-    // the direction update runs inside q = A p
+  if (pring) {
+    // the directions stay in a ring and alpha p is added to x when the ring
+    // is full (and after the last iteration), not in every update; the
+    // direction update runs inside q = A p
     Op sp;
+    sp.order[0] = 2;
+    sp.order[1] = 1;
+    sp.site = tpmg::kFinAlpha;
     sp.kind = tpmg::kOpSpmvPRing;
     sp.L = m.view64(m.nlev - 1);
     sp.f_double = !z_float;
@@ -453,6 +460,9 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     sp.len = m.len;
     ops.push_back(sp);
     Op ru;
+    ru.order[0] = 2;
+    ru.order[1] = 2;
+    ru.site = tpmg::kFinRR;
     ru.kind = tpmg::kOpRupdate;
     ru.in1 = m.q;
     ru.out0 = m.fp32 ? m.fcopy : nullptr;
@@ -460,7 +470,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     ru.partials = m.partials;
     ru.sc = sc;
     ru.len = m.len;
-    ru.ring = m.ring_dev;
+    ru.ring = single ? m.ring_dev : nullptr;
     ops.push_back(ru);
     return;
   }
@@ -614,17 +624,25 @@ namespace {
 // one grouped launch per position, followed by a grouped finalize where the
 // operation reduces. Returns the number of segments; with upload == false it
 // only counts them.
+// whether every problem of the batch has the fused operator instance
+bool batch_ring(const tpmg_batch& b) {
+  for (const tpmg_mg* m : b.probs)
+    if (!tpmg::spmv_pring_fits(m->view64(m->nlev - 1))) return false;
+  return true;
+}
+
 hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* nsegs_out) {
   struct Item {
     Op op;
     int prob;
   };
   std::vector<Item> items;
+  const bool ring = batch_ring(b);
   for (size_t p = 0; p < b.probs.size(); ++p) {
     std::vector<Op> ops;
-    // (batched launches update x and p in place in every iteration; single
-    // solves defer the x update, with the same bits)
-    fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops, false);
+    // (with the direction ring, as single solves; otherwise x and p are
+    // updated in place in every iteration, with the same bits)
+    fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops, false, ring);
     for (const Op& op : ops) items.push_back({op, static_cast<int>(p)});
   }
   // smoother sweeps of one position are grouped by levels per wave (one
@@ -633,7 +651,7 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
   // residual + restriction and the operator: problems whose chunk has an
   // instance of its own launch it apart from the rest (runtime chunk, 0)
   auto ch_of = [](const Op& o) {
-    if (o.kind != tpmg::kOpRestrict && o.kind != tpmg::kOpSpmv) return 0;
+    if (o.kind != tpmg::kOpRestrict && o.kind != tpmg::kOpSpmv && o.kind != tpmg::kOpSpmvPRing) return 0;
     const int c = tpmg::effective_chunk(o.kind == tpmg::kOpRestrict ? o.L.tune.chunk_rr : o.L.tune.chunk_spmv,
                                         o.L.npad, o.L.nz);
     return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) ? c : 0;
@@ -689,6 +707,7 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
       g.partials = a.partials;
       g.sc = a.sc;
       g.len = a.len;
+      g.aux = a.aux;
       int nb = 0;
       switch (a.kind) {
         case tpmg::kOpSmooth: {
@@ -700,7 +719,8 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
         }
         case tpmg::kOpRestrict:
         case tpmg::kOpProlong:
-        case tpmg::kOpSpmv: {
+        case tpmg::kOpSpmv:
+        case tpmg::kOpSpmvPRing: {
           const int tuned = a.kind == tpmg::kOpRestrict  ? a.L.tune.chunk_rr
                             : a.kind == tpmg::kOpProlong ? a.L.tune.chunk_pr
                                                          : a.L.tune.chunk_spmv;
@@ -712,6 +732,7 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
           nb = static_cast<int>(tpmg::pupdate_blocks(a.len));
           break;
         case tpmg::kOpUpdate:
+        case tpmg::kOpRupdate:
           nb = tpmg::kRedBlocks;
           break;
         default:
@@ -1719,12 +1740,17 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = b->stream;
   // per problem: r = f - A u, rr, ff (kFinInit also marks already-converged
-  // problems done); p = q = 0
+  // problems done); the previous direction (p, or slot kDirSlots - 1 of the
+  // ring, and the FP32 copy of r for an FP32 V-cycle) and q = 0
+  const bool ring = batch_ring(*b);
   for (int p = 0; p < n; ++p) {
     tpmg_mg& m = *b->probs[p];
     TPMG_HIP(tpmg::launch_spmv64(m.view64(m.nlev - 1), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit,
-                                  b->scal + p, s, rtol));
-    TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
+                                  b->scal + p, s, rtol, ring && m.fp32 ? static_cast<float*>(m.fcopy) : nullptr));
+    if (ring)
+      TPMG_HIP(tpmg::launch_fill(m.dirs + (tpmg::kDirSlots - 1) * m.len, m.len * 8, s));
+    else
+      TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
     TPMG_HIP(tpmg::launch_fill(m.q, m.len * 8, s));
   }
   const bool rebuild = b->plan_u.size() != static_cast<size_t>(n) || !std::equal(b->plan_u.begin(), b->plan_u.end(), d_u);
@@ -1777,6 +1803,12 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
       if (infos && infos[p].history && c.status == 0 && c.iters < infos[p].history_cap && c.iters == it + 1)
         infos[p].history[c.iters] = fnorm[p] > 0 ? std::sqrt(c.rr) / fnorm[p] : 0.0;
     }
+  }
+  if (ring) {
+    // x += alpha p of each problem's iterations not yet added
+    for (int p = 0; p < n; ++p)
+      TPMG_HIP(tpmg::launch_flush(d_u[p], b->probs[p]->dirs, b->scal + p, b->probs[p]->len, s));
+    TPMG_HIP(hipStreamSynchronize(s));
   }
   const auto t1 = std::chrono::steady_clock::now();
   tpmg_status worst = TPMG_OK;
