@@ -383,6 +383,7 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
       op.in0 = rhs(l);
       op.in1 = m.lv[l].u[cur[l]];
       op.out0 = m.lv[l - 1].f;
+      op.sc = sc;   // (a batch skips a finished problem's operations)
       ops.push_back(op);
     }
   }
@@ -397,6 +398,7 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
     op.C = m.view(l - 1);
     op.in0 = m.lv[l - 1].u[cur[l - 1]];
     op.out0 = m.lv[l].u[cur[l]];
+    op.sc = sc;
     ops.push_back(op);
     for (int k = 0; k < m.nu_post; ++k) {
       const bool last = l == L && k + 1 == m.nu_post;
@@ -610,7 +612,8 @@ struct tpmg_batch {
   std::vector<tpmg_mg*> probs;
   hipStream_t stream = nullptr;
   tpmg::FcgScalars* scal = nullptr;     // device, one per problem
-  tpmg::FcgScalars* h_scal = nullptr;   // pinned host mirror
+  tpmg::FcgScalars* h_scal = nullptr;   // pinned host mirrors: the initial scalars, then two per iteration in turn
+  hipEvent_t ev[2] = {nullptr, nullptr};   // each iteration's copy of the scalars has arrived
   tpmg::Seg* segs = nullptr;            // device segment tables
   size_t max_segs = 0;
   std::vector<tpmg::BatchLaunch> plan;
@@ -1717,11 +1720,12 @@ tpmg_status tpmg_batch_create(tpmg_mg* const* problems, int n, void* d_workspace
   b->scal = static_cast<tpmg::FcgScalars*>(cv.take(static_cast<size_t>(n) * sizeof(tpmg::FcgScalars)));
   b->max_segs = (need - 256 - (static_cast<size_t>(n) * sizeof(tpmg::FcgScalars) + 255) / 256 * 256) / sizeof(tpmg::Seg);
   b->segs = static_cast<tpmg::Seg*>(cv.take(b->max_segs * sizeof(tpmg::Seg)));
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_scal), static_cast<size_t>(n) * sizeof(tpmg::FcgScalars),
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_scal), 3 * static_cast<size_t>(n) * sizeof(tpmg::FcgScalars),
                                hipHostMallocDefault);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
-    delete b;
-    return fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    tpmg_batch_destroy(b);
+    return fail(TPMG_ERR_DEVICE, std::string("batch host buffers: ") + hipGetErrorString(e));
   }
   *out = b;
   return TPMG_OK;
@@ -1779,41 +1783,71 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
     b->plan_u.assign(d_u, d_u + n);
   }
   const size_t sbytes = static_cast<size_t>(n) * sizeof(tpmg::FcgScalars);
-  auto read_scalars = [&]() -> hipError_t {
-    hipError_t e = hipMemcpyAsync(b->h_scal, b->scal, sbytes, hipMemcpyDeviceToHost, s);
-    return e == hipSuccess ? hipStreamSynchronize(s) : e;
-  };
-  TPMG_HIP(read_scalars());
-  std::vector<double> fnorm(n);
+  TPMG_HIP(hipMemcpyAsync(b->h_scal, b->scal, sbytes, hipMemcpyDeviceToHost, s));
+  TPMG_HIP(hipStreamSynchronize(s));
+  const tpmg::FcgScalars* cur = b->h_scal;   // the latest scalars the host has
+  std::vector<double> fnorm(n), rn(n), prev(n);
   for (int p = 0; p < n; ++p) {
-    fnorm[p] = std::sqrt(b->h_scal[p].ff);
+    fnorm[p] = std::sqrt(cur[p].ff);
+    rn[p] = prev[p] = std::sqrt(cur[p].rr);
     if (infos && infos[p].history && infos[p].history_cap > 0)
-      infos[p].history[0] = fnorm[p] > 0 ? std::sqrt(b->h_scal[p].rr) / fnorm[p] : 0.0;
+      infos[p].history[0] = fnorm[p] > 0 ? rn[p] / fnorm[p] : 0.0;
   }
   auto all_done = [&]() {
     for (int p = 0; p < n; ++p)
-      if (!b->h_scal[p].done) return false;
+      if (!cur[p].done) return false;
     return true;
   };
+  // Iteration it+1 is queued before the host waits for iteration it's
+  // scalars unless every unfinished problem may converge in it; a queued
+  // iteration after all have converged does nothing (every operation of a
+  // finished problem is skipped on the device) and costs only its launches.
+  int launched = 0;
+  auto launch_next = [&]() -> hipError_t {
+    const int slot = launched % 2;
+    hipError_t e = hipGraphLaunch(b->graph, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->h_scal + static_cast<size_t>(1 + slot) * n, b->scal, sbytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[slot], s);
+    ++launched;
+    return e;
+  };
+  hipError_t werr = hipSuccess;
   for (int it = 0; it < maxit && !all_done(); ++it) {
-    TPMG_HIP(hipGraphLaunch(b->graph, s));
-    TPMG_HIP(read_scalars());
+    if (launched == it && (werr = launch_next()) != hipSuccess) break;
+    bool ahead = false;
     for (int p = 0; p < n; ++p) {
-      const tpmg::FcgScalars& c = b->h_scal[p];
-      if (infos && infos[p].history && c.status == 0 && c.iters < infos[p].history_cap && c.iters == it + 1)
-        infos[p].history[c.iters] = fnorm[p] > 0 ? std::sqrt(c.rr) / fnorm[p] : 0.0;
+      if (cur[p].done) continue;
+      const double ratio = prev[p] > 0.0 ? std::min(1.0, rn[p] / prev[p]) : 1.0;
+      if (rn[p] * ratio > 3.0 * rtol * fnorm[p]) ahead = true;
+    }
+    if (ahead && it + 1 < maxit && launched == it + 1 && (werr = launch_next()) != hipSuccess) break;
+    if ((werr = hipEventSynchronize(b->ev[it % 2])) != hipSuccess) break;
+    cur = b->h_scal + static_cast<size_t>(1 + it % 2) * n;
+    for (int p = 0; p < n; ++p) {
+      const tpmg::FcgScalars& c = cur[p];
+      if (c.status == 0 && c.iters == it + 1) {
+        prev[p] = rn[p];
+        rn[p] = std::sqrt(c.rr);
+        if (infos && infos[p].history && c.iters < infos[p].history_cap)
+          infos[p].history[c.iters] = fnorm[p] > 0 ? rn[p] / fnorm[p] : 0.0;
+      }
     }
   }
-  if (ring) {
-    // x += alpha p of each problem's iterations not yet added
+  if (werr != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    return fail(TPMG_ERR_DEVICE, std::string("batch solve: ") + hipGetErrorString(werr));
+  }
+  // x += alpha p of each problem's iterations not yet added (after an
+  // iteration queued ahead, which changes neither); drains the stream
+  if (ring)
     for (int p = 0; p < n; ++p)
       TPMG_HIP(tpmg::launch_flush(d_u[p], b->probs[p]->dirs, b->scal + p, b->probs[p]->len, s));
-    TPMG_HIP(hipStreamSynchronize(s));
-  }
+  TPMG_HIP(hipStreamSynchronize(s));
   const auto t1 = std::chrono::steady_clock::now();
   tpmg_status worst = TPMG_OK;
   for (int p = 0; p < n; ++p) {
-    const tpmg::FcgScalars& c = b->h_scal[p];
+    const tpmg::FcgScalars& c = cur[p];
     tpmg_status st = c.status ? TPMG_ERR_BREAKDOWN : (c.done ? TPMG_OK : TPMG_NOT_CONVERGED);
     if (infos) {
       infos[p].iters = c.iters;
@@ -1831,6 +1865,8 @@ void tpmg_batch_destroy(tpmg_batch* b) {
   if (!b) return;
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
+  for (hipEvent_t ev : b->ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 
