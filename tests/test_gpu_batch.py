@@ -66,6 +66,43 @@ def test_batch_equals_single_solves(fp32):
     T.tpmg_batch_destroy(batch)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_batch_converged_and_capped_problems(fp32):
+    """A problem converged from the start stays untouched (0 iterations), and
+    with maxit below convergence every problem stops after exactly maxit
+    iterations, NOT_CONVERGED, with the solution, residual norm and history of
+    its own single solve capped the same way (bit for bit): the iteration
+    the host queues ahead changes nothing."""
+    stream = torch.cuda.Stream()
+    probs = _setup(fp32, stream)[:3]
+    fs = [P.pack(f) for P, f, _ in probs]
+    fs[1] = probs[1][0].pack(np.zeros_like(probs[1][1]))
+    mgs = [P.mg for P, _, _ in probs]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, ws.data_ptr() + off, nbytes)
+    for maxit in (200, 3):
+        singles = []
+        for (P, _, _), fd in zip(probs, fs):
+            u = P.device_vector()
+            st, iters, relres, hist, _ = P.solve(fd, u, rtol=1e-8, maxit=maxit)
+            singles.append((st, iters, relres, hist, P.unpack(u)))
+        us = [P.device_vector() for P, _, _ in probs]
+        st, per, _ = T.tpmg_batch_solve(batch, fs, us, 1e-8, maxit)
+        assert st == (T.TPMG_OK if maxit == 200 else T.TPMG_NOT_CONVERGED)
+        for (P, _, _), u, (iters, relres, hist), (st_s, it_s, rr_s, hist_s, u_s) in zip(probs, us, per, singles):
+            assert iters == it_s
+            assert relres == rr_s
+            assert np.array_equal(hist, hist_s[: iters + 1])
+            assert np.array_equal(P.unpack(u), u_s)
+        assert per[1][0] == 0 and not torch.any(us[1])
+        if maxit == 3:
+            assert per[0][0] == 3 and per[2][0] == 3
+    T.tpmg_batch_destroy(batch)
+
+
 def test_batch_rejects_mixed_parameters():
     stream = torch.cuda.Stream()
     a = _setup(False, stream)[:1]
