@@ -359,6 +359,8 @@ def main():
                     help="1: replay each FCG iteration as one HIP graph; 0 (default): launch the iteration's "
                          "kernels one by one, which on this workload leaves no gap between iterations "
                          "(a graph launch costs ~8 us at each boundary)")
+    ap.add_argument("--batch", action="store_true",
+                    help="only the batched-solve report (16 problems of uneven size, batched and one by one)")
     ap.add_argument("--report", action="store_true",
                     help="also measure the anisotropy sweep on the refinement-7 grid (one JSON line per ratio)")
     ap.add_argument("--profile-sweep", action="store_true",
@@ -392,6 +394,9 @@ def main():
         return
     if args.sequence:
         sequence_report(epochs=args.epochs)
+        return
+    if args.batch:
+        batch_report()
         return
     results = {}
     P64 = T.Problem(w.refinement, w.r_faces(), w.omega2)
