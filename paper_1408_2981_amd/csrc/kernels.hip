@@ -259,7 +259,8 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       }
       break;
     case kFinBeta:
-      sc->beta = -s0 / sc->pq;
+      // (the first direction is z itself: no previous q enters)
+      sc->beta = sc->iters == 0 ? 0.0 : -s0 / sc->pq;
       sc->rz = s1;
       break;
     default:
@@ -992,7 +993,8 @@ __global__ __launch_bounds__(256) void k_pupdate_ring(const TZ* __restrict__ z, 
         xi = __builtin_fma(sc->alpha_hist[j], ring[static_cast<size_t>(j) * len + i], xi);
       x[i] = xi;
     }
-    pn[i] = __builtin_fma(beta, pp[i], static_cast<double>(z[i]));
+    // (the first direction is z itself; the ring's previous slot is not read)
+    pn[i] = k == 0 ? static_cast<double>(z[i]) : __builtin_fma(beta, pp[i], static_cast<double>(z[i]));
   }
   // (no block of this kernel reads flushed)
   if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
@@ -1032,8 +1034,13 @@ __device__ __forceinline__ void spmv_pring_body(const Lv<double>& L, const TZ* _
     const Column<double> c = load_column(L, tile * kTile + lane);
     __shared__ double xbuf[kStencilWaves][2 * kTile];
     ChunkLoads<double, CH> ld;
-    ld.load_with(c, [&](size_t o) { return __builtin_fma(beta, pp[o], static_cast<double>(z[o])); }, k0, L.nz,
-                 Exchange<double>{xbuf[threadIdx.x >> 6]}, lane);
+    // (the first direction is z itself; the ring's previous slot is not read)
+    if (k == 0)
+      ld.load_with(c, [&](size_t o) { return static_cast<double>(z[o]); }, k0, L.nz,
+                   Exchange<double>{xbuf[threadIdx.x >> 6]}, lane);
+    else
+      ld.load_with(c, [&](size_t o) { return __builtin_fma(beta, pp[o], static_cast<double>(z[o])); }, k0, L.nz,
+                   Exchange<double>{xbuf[threadIdx.x >> 6]}, lane);
 #pragma unroll
     for (int i = 0; i < CH; ++i)
       if (k0 + i < k1) {

@@ -1548,12 +1548,10 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   for (int i = 0; i < tpmg::kRecords; ++i) mg->ring[i].seq = -1;
   // r = f - A u, rr, ff (published as record 0), and for an FP32 V-cycle its
   // first right-hand side, the FP32 rounding of r (later ones come with the r
-  // update); the direction before the first iteration p_{-1} = 0 (slot
-  // kDirSlots - 1) and q = 0, so that the first iteration takes beta = 0
+  // update). The first iteration takes beta = 0 and p = z, reading neither
+  // q nor the ring's previous slot.
   TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol,
                                mg->fp32 ? static_cast<float*>(mg->fcopy) : nullptr, mg->ring_dev));
-  TPMG_HIP(tpmg::launch_fill(mg->dirs + (tpmg::kDirSlots - 1) * mg->len, mg->len * 8, s));
-  TPMG_HIP(tpmg::launch_fill(mg->q, mg->len * 8, s));
   int launched = 0;
   auto launch_next = [&]() -> hipError_t {
     ++launched;
@@ -1744,18 +1742,15 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = b->stream;
   // per problem: r = f - A u, rr, ff (kFinInit also marks already-converged
-  // problems done); the previous direction (p, or slot kDirSlots - 1 of the
-  // ring, and the FP32 copy of r for an FP32 V-cycle) and q = 0
+  // problems done), with the ring form the FP32 copy of r for an FP32
+  // V-cycle; the first iteration takes beta = 0 (p = 0 for the in-place
+  // form, whose update reads it)
   const bool ring = batch_ring(*b);
   for (int p = 0; p < n; ++p) {
     tpmg_mg& m = *b->probs[p];
     TPMG_HIP(tpmg::launch_spmv64(m.view64(m.nlev - 1), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit,
                                   b->scal + p, s, rtol, ring && m.fp32 ? static_cast<float*>(m.fcopy) : nullptr));
-    if (ring)
-      TPMG_HIP(tpmg::launch_fill(m.dirs + (tpmg::kDirSlots - 1) * m.len, m.len * 8, s));
-    else
-      TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
-    TPMG_HIP(tpmg::launch_fill(m.q, m.len * 8, s));
+    if (!ring) TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
   }
   const bool rebuild = b->plan_u.size() != static_cast<size_t>(n) || !std::equal(b->plan_u.begin(), b->plan_u.end(), d_u);
   if (rebuild || b->graph == nullptr) {
