@@ -228,7 +228,9 @@ tpmg_status tpmg_batch_create(tpmg_mg* const* problems, int n, void* d_workspace
  * (tiled FP64, as tpmg_solve). infos (optional) holds n entries. Returns
  * TPMG_OK when all converged, TPMG_NOT_CONVERGED if one reached maxit,
  * TPMG_ERR_BREAKDOWN if one broke down (its u holds its last finite
- * iterate). Synchronises the stream once per iteration. */
+ * iterate). The host waits for each iteration's scalars (an event after
+ * their copy) with the next iteration usually queued already; the call
+ * returns after the stream has drained. */
 tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* const* d_u, double rtol, int maxit,
                              tpmg_solve_info* infos);
 void tpmg_batch_destroy(tpmg_batch* b);
