@@ -6,7 +6,7 @@
  * with A u = f, where A is the cell-centred finite-volume discretisation of
  *     L u = -omega^2 div(alpha grad u) + beta u
  * on the shell S x [1, 1+H] (lengths in Earth radii), without the vertical
- * advection term (Section 3.3.1: this operator is symmetric positive
+ * advection term (Section 3.2.1: this operator is symmetric positive
  * definite). The horizontal grid is an icosahedral grid refined
  * `refinement` times; each horizontal cell T carries a column of nz cells
  * between radial faces r_0 = 1 < ... < r_nz = 1 + H (Section 4.1). Profiles
@@ -235,7 +235,7 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
                              tpmg_solve_info* infos);
 void tpmg_batch_destroy(tpmg_batch* b);
 
-/* Asymptotic V-cycle convergence factor (Section 6.1: the rate of the
+/* Asymptotic V-cycle convergence factor (Section 5.2: the rate of the
  * V-cycle in the Richardson iteration): runs u <- u + M(f - A u) with f = 0
  * from the start vector in d_u (tiled FP64, overwritten by the last
  * iterate), records ||r_i|| = ||A u_i|| for i = 0..cycles in norms

@@ -1,7 +1,7 @@
 """Finite-volume operator of the pressure-correction equation (oracle).
 
 The operator is L u = -omega^2 div(alpha grad u) + beta u on the shell
-S x [1, 1+H] without the advection term (Section 3.3.1), discretised with
+S x [1, 1+H] without the advection term (Section 3.2.1), discretised with
 cell-centred finite volumes (Appendix A). For cell E = (T, k):
 
   (A u)_{T,k} = beta^_{T,k} u_{T,k}

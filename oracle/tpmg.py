@@ -10,7 +10,7 @@ for the prolongation, 4 - 7 levels).
 
 Readings (where the paper is silent or its implementation and theory differ):
   * smoother: damped block-Jacobi with omega_J = 2/3 (the theory's weighted
-    block-Jacobi, Section 3.3.1) rather than sequential block-SOR, so the
+    block-Jacobi, Section 3.2.1) rather than sequential block-SOR, so the
     sweep is order independent;
   * Thomas algorithm tracked through the diagonal-dominance margin
     s_k = p_k - m_k (p_k the pivot), so every addition is of positive terms;
@@ -21,14 +21,14 @@ Readings (where the paper is silent or its implementation and theory differ):
   * outer solver: flexible CG with one-term orthogonalisation,
     alpha = <r,z>/<p,q>, beta = -<z',q>/<p,q>, stopping when
     ||r||_2 <= rtol ||f||_2 (the operator is SPD without advection,
-    Section 3.3.1);
+    Section 3.2.1);
   * V-cycle rate: Richardson u <- u + M(f - A u) with f = 0, 12 cycles from
     seeded U[-1,1], rate (||r_12|| / ||r_4||)^(1/8).
 
 Pins (tests/test_oracle_tpmg.py): Thomas vs dense LU; the smoother vs dense
 block inverses; conservation of the restriction; exactness of the
 prolongation on constants and O(h^2) on linear fields; the tensor-decoupling
-of the V-cycle spectrum (Section 3.3.1, eq. EigenvalueEquation); a V-cycle
+of the V-cycle spectrum (Section 3.2.1, eq. EigenvalueEquation); a V-cycle
 rate bounded in h and anisotropy; FCG == textbook CG (scipy) for M = I,
 one step for M = A^-1, == PCG (scipy) for a symmetric M; the solve ==
 scipy.sparse.linalg.spsolve.

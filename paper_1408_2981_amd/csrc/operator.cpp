@@ -1,7 +1,7 @@
 // Factorised tensor-stencil coefficients and grid-transfer weights.
 //
 // Paper, Appendix A (eq. hatFunctionsFac) with the vertical advection term
-// dropped (Section 3.3.1):
+// dropped (Section 3.2.1):
 //   beta^S_T     = |T| beta^S_T               beta^r_k   = v_k beta^r_k
 //   alphaS^S_TT' = omega^2 g_TT' alpha_S^S    alphaS^r_k = (r_{k+1}-r_k) alpha_S^r_k
 //   alphar^S_T   = omega^2 |T| alpha_r^S_T    alphar^r_k = sigma_k 2 r_k^2/(r_{k+1}-r_{k-1}) alpha_r^r_k
@@ -10,7 +10,7 @@
 // profile factor on an edge is the mean of its two cells; on coarse grids
 // the horizontal factors are area-weighted means of the four children and
 // the stencil is rediscretised on the coarse geometry (the matrix-free
-// counterpart of the Galerkin coarse operator of Section 3.3.1).
+// counterpart of the Galerkin coarse operator of Section 3.2.1).
 //
 // Prolongation (Section 5, "linear interpolation"): a fine cell c with
 // parent P takes e_P + G . delta_c, where G is the least-squares gradient

@@ -74,7 +74,7 @@ def vertical_faces(nz: int, thickness: float, grading: str = "uniform") -> np.nd
 
 @dataclass
 class Profiles:
-    """Factorised profile samples (Section 3.2 / Appendix A.1).
+    """Factorised profile samples (eq. alphaxrfac in Section 3, Appendix A).
 
     Vertical factors: alpha_r_v at the nz+1 radial faces, alpha_s_v and beta_v
     at the nz layer midpoints. Horizontal factors: one value per finest-grid
@@ -98,7 +98,7 @@ def profiles_random(nz: int, n_fine: int, seed: int, tie_beta_to_alpha_r: bool =
     """Seeded positive factorised profiles, every factor drawn from U[0.5, 2].
 
     With tie_beta_to_alpha_r the horizontal factor of beta equals that of
-    alpha_r (the assumption beta^S = alpha_r^S of Section 3.3.1).
+    alpha_r (the assumption beta^S = alpha_r^S of Section 3.2.1).
     """
     rng = np.random.default_rng(seed)
     ar_v = rng.uniform(0.5, 2.0, nz + 1)

@@ -92,5 +92,5 @@ def test_full_size_solve_mixed(setup):
           f"relres {relres:.2e}; vs oracle FP64 solution: sampled max rel diff {err:.2e}, norm rel diff {nrm:.2e}")
     assert st == T.TPMG_OK and relres <= 1e-8
     assert abs(iters - g["mixed"]["iters"]) <= 1
-    assert err <= 1e-5 and nrm <= 1e-6
+    assert err <= 1e-6 and nrm <= 1e-6
     P.close()

@@ -123,3 +123,30 @@ def test_solve_equals_direct():
     ud = tpmg.direct_solve(h.finest, f)
     assert res.status == "converged"
     assert np.linalg.norm(res.x - ud) <= 1e-9 * np.linalg.norm(ud)
+
+
+def test_coarse_coefficients_conserve_children():
+    """Coarse grids (rediscretised with the horizontal profile factors of the
+    four children combined): the children of a coarse cell tile it exactly
+    (Section 4.1: each coarse triangle is four fine ones), so the coarse mass
+    and vertical-coupling coefficients, which are cell integrals |T| x
+    profile, must equal the sums of their four children's. An unweighted
+    mean of the children's factors fails this on the icosahedral grid, whose
+    children differ in area."""
+    nz = 4
+    prof = synth.profiles_random(nz, 1280, seed=21, tie_beta_to_alpha_r=False)
+    h = _hier(3, nz, "quadratic", prof, levels=4)
+    for lvl in range(1, len(h.ops)):
+        fine, coarse = h.ops[lvl], h.ops[lvl - 1]
+        for name in ("beta", "alpha_r"):
+            child_sum = getattr(fine, name).reshape(coarse.n, 4, -1).sum(axis=1)
+            parent = getattr(coarse, name)
+            assert np.allclose(parent, child_sum, rtol=1e-13, atol=0.0), (lvl, name)
+    # the children really differ in area, so the weighting matters
+    a = h.meshes[-1].area.reshape(-1, 4)
+    assert np.max(np.abs(a - a.mean(axis=1, keepdims=True))) > 1e-3 * a.mean()
+    # and an unweighted mean is caught
+    ar_h = prof.alpha_r_h.reshape(-1, 4)
+    plain = ar_h.mean(axis=1) * h.meshes[-2].area
+    weighted = (ar_h * h.meshes[-1].area.reshape(-1, 4)).sum(axis=1)
+    assert not np.allclose(plain, weighted, rtol=1e-6)

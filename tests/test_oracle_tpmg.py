@@ -161,7 +161,7 @@ def _vcycle_matrix(h):
 
 
 def test_tensor_decoupling_of_vcycle_spectrum():
-    """Section 3.3.1: with factorising profiles and beta^S = alpha_r^S the
+    """Section 3.2.1: with factorising profiles and beta^S = alpha_r^S the
     3-D V-cycle error operator is similar to the direct sum over the radial
     eigenpairs (omega^2 A^r + B^r) e = lambda M^r e of 2-D V-cycles for
     omega^2 A^S + lambda M^S with point smoothing. Traces of its powers and
@@ -272,3 +272,73 @@ def test_mixed_precision_converges():
     x32 = tpmg.solve(h, f, rtol=1e-8, precision="fp32")
     assert x32.status == "converged"
     assert np.linalg.norm(x32.x - x64.x) <= 1e-6 * np.linalg.norm(x64.x)
+
+
+def _dense_vcycle(h, level):
+    """The V-cycle of Algorithm 1 as a dense matrix B (z = B f), composed from
+    explicit matrices and not from tpmg.vcycle. With W = omega D^-1 (D the
+    block diagonal of the column matrices A_T, eq. BlockJacobi) one sweep is
+    u <- S u + W f with S = I - W A, so nu sweeps from zero give
+    G_nu = sum_{i<nu} S^i W. On the coarsest level B = G_nu_coarse; above it,
+    pre-smoothing from zero, restriction R (sum over the four children) of
+    the residual, the coarse V-cycle B_c from zero, prolongation P from the
+    interpolation weights, then post-smoothing:
+        B = S^nu_post (G_nu_pre + P B_c R (I - A G_nu_pre)) + G_nu_post."""
+    op = h.ops[level]
+    n, nz = op.n, op.nz
+    N = n * nz
+    a = opm.to_sparse(op).toarray()
+    d = np.zeros_like(a)
+    for t in range(n):
+        sl = slice(t * nz, (t + 1) * nz)
+        d[sl, sl] = a[sl, sl]
+    W = h.omega * np.linalg.inv(d)
+    S = np.eye(N) - W @ a
+
+    def G(nu):
+        out, Si = np.zeros((N, N)), np.eye(N)
+        for _ in range(nu):
+            out += Si @ W
+            Si = S @ Si
+        return out
+
+    if level == 0:
+        return G(h.nu_coarse)
+    cop = h.ops[level - 1]
+    nc = cop.n
+    R = np.zeros((nc * nz, N))
+    P = np.zeros((N, nc * nz))
+    w = h.weights[level]
+    for c in range(n):
+        p = c // 4
+        for k in range(nz):
+            R[p * nz + k, c * nz + k] = 1.0
+            P[c * nz + k, p * nz + k] += 1.0 - w[c].sum()
+            for j in range(3):
+                P[c * nz + k, cop.nbr[p, j] * nz + k] += w[c, j]
+    bc = _dense_vcycle(h, level - 1)
+    gpre = G(h.nu_pre)
+    return np.linalg.matrix_power(S, h.nu_post) @ (gpre + P @ bc @ R @ (np.eye(N) - a @ gpre)) + G(h.nu_post)
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_vcycle_schedule_dense_identity(levels):
+    """Algorithm 1 with nu_pre = nu_post = 2 and one coarsest sweep from zero
+    (Section 5), checked column by column against the composition of dense
+    operators: a dropped or extra sweep, a non-zero coarse guess or a
+    transposed transfer changes the matrix. A thick shell keeps the column
+    matrices well conditioned, so the dense inverses are accurate to a few
+    ulps."""
+    nz, ref = 3, 2
+    prof = synth.profiles_random(nz, synth.n_cells(ref), seed=31, tie_beta_to_alpha_r=False)
+    h = tpmg.build(ref, synth.vertical_faces(nz, 0.3, "uniform"), synth.omega_for(ref) ** 2, profiles=prof,
+                   n_levels=levels)
+    op = h.finest
+    n = op.n * op.nz
+    want = _dense_vcycle(h, len(h.ops) - 1)
+    got = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        got[:, i] = tpmg.vcycle(h, e.reshape(op.n, op.nz)).ravel()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
