@@ -32,31 +32,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(scan_levels: int):
-    """HBM bytes per finest-sweep dispatch from the committed counter summary,
-    or None when kernels.hip has changed since the counters were taken or the
-    timed sweep uses another levels-per-wave instance than the one counted."""
+def measured_traffic(path: str, key: str, instance: str):
+    """HBM bytes per dispatch of one kernel from a committed counter summary
+    under profiles/ (lines "traffic_<key>_bytes_per_dispatch: B"), or None
+    when kernels.hip has changed since the counters were taken or the timed
+    kernel is another instance than the one counted."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "smoother_ico6_nz128_counters.md")
     src = os.path.join(ROOT, "paper_1408_2981_amd", "csrc", "kernels.hip")
     try:
-        vals = dict(l.strip().split(": ", 1) for l in open(path)
-                    if l.strip().startswith(("traffic_", "kernels_hip_", "scan_levels")))
+        vals = dict(l.strip().split(": ", 1) for l in open(os.path.join(ROOT, "profiles", path))
+                    if l.strip().startswith(("traffic_", "kernels_hip_", "instance_")))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if vals.get("kernels_hip_sha256") != digest or vals.get("scan_levels") != str(scan_levels):
+    if vals.get("kernels_hip_sha256") != digest or vals.get(f"instance_{key}") != instance:
         return None
-    return float(vals["traffic_bytes_per_dispatch"])
+    v = vals.get(f"traffic_{key}_bytes_per_dispatch")
+    return float(v) if v is not None else None
 
 
-def cpu_baseline(w, iters_fp64: int, sample_iters: int = 3) -> dict:
+def cpu_baseline(w, iters_fp64: int, sample_iters: int = 2) -> dict:
     """The CPU oracle (NumPy, FP64, one thread) on a bounded sample of the same
-    workload: its FCG solve is run for `sample_iters` iterations (initial
-    residual included) and timed, and the time is scaled to the iteration
-    count the full solve needs (the GPU FP64 count, which the parity tests pin
-    to the oracle's own)."""
+    workload. Its FCG solve stopped by maxit = m runs the initial residual and
+    V-cycle and m iterations of (q = A p, update, V-cycle): m + 1 operator
+    applications and V-cycles. A converged solve of k iterations runs k
+    V-cycles and k + 1 operator applications, so the sample's time is scaled
+    by k / (m + 1) (k = the GPU FP64 count, which the parity tests pin to the
+    oracle's own), leaving out one operator application. Also timed whole,
+    on the 20,480-unknown workload: the oracle's FCG solve and a sparse
+    direct solve of the assembled matrix (scipy spsolve)."""
     from threadpoolctl import threadpool_limits
 
     import synth
@@ -69,40 +74,104 @@ def cpu_baseline(w, iters_fp64: int, sample_iters: int = 3) -> dict:
         t0 = time.perf_counter()
         res = otpmg.solve(h, f, rtol=1e-8, maxit=sample_iters)
         t1 = time.perf_counter()
-    done = max(res.iters, 1)
-    t_solve = (t1 - t0) * iters_fp64 / done
+        del h, f
+        w1 = synth.workload("ico3_nz16")
+        h1 = otpmg.build(w1.refinement, w1.r_faces(), w1.omega2)
+        f1 = synth.make_rhs(w1, h1.meshes[-1].centre, h1.meshes[-1].area, h1.vert.vk)
+        t2 = time.perf_counter()
+        s1 = otpmg.solve(h1, f1, rtol=1e-8)
+        t3 = time.perf_counter()
+        otpmg.direct_solve(h1.finest, f1)
+        t4 = time.perf_counter()
+    units = res.iters + 1 if res.status == "maxit" else res.iters
+    t_solve = (t1 - t0) * iters_fp64 / max(units, 1)
     return {
         "value": w.unknowns / t_solve,
         "unit": "unknowns/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"oracle FP64 FCG on {w.name}, first {done} iterations timed ({t1 - t0:.1f} s), "
-                  f"scaled to the {iters_fp64} iterations of the full solve",
+        "sample": f"oracle FP64 FCG on {w.name} stopped after {res.iters} iterations ({units} V-cycles and "
+                  f"operator applications, {t1 - t0:.1f} s), scaled to the {iters_fp64} V-cycles of the full solve",
+        "ico3_nz16_fcg_unknowns_per_s": w1.unknowns / (t3 - t2),
+        "ico3_nz16_fcg_iters": s1.iters,
+        "ico3_nz16_spsolve_unknowns_per_s": w1.unknowns / (t4 - t3),
     }
 
 
-def profile_sweep(w, reps: int):
-    """Counter run: `reps` finest-grid FP32 sweeps, then one copy of 512 MiB
-    (a plain copy kernel of known size, to calibrate FETCH_SIZE and
-    WRITE_SIZE)."""
+def roofline_workload(steps: int, reps: int) -> dict:
+    """The HBM-bound workload (icosahedral refinement 7 x 128 quadratic levels,
+    41,943,040 unknowns, H = 0.1 x the horizontal spacing, seeded uniform
+    right-hand side; at refinement 6 the FP32 fields fit the 256 MB
+    last-level cache): mixed and FP64 solve times, and the two dominant
+    kernels of the mixed solve timed alone with HIP events on the solver's
+    stream (`reps` back-to-back launches each): the finest FP32 line-smoother
+    sweep and q = A p with the direction update."""
+    import numpy as np
     import torch
 
     import paper_1408_2981_amd as T
     import synth
 
+    w = synth.workload("ico7_nz128_ar0.1")
+    out = {"workload": f"{w.name}: icosahedral refinement 7 x nz 128 quadratic, H = 0.1 h_7, {w.unknowns} unknowns, "
+                       f"uniform RHS, rtol 1e-8"}
+    for name, fp32 in (("fp64", False), ("mixed", True)):
+        P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=fp32, use_graph=False, autotune=1)
+        geo = P.geometry()
+        f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
+        u = P.device_vector()
+        P.solve(f, u)
+        times = []
+        for _ in range(steps):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, rr, _, _ = P.solve(f, u)
+            times.append(time.perf_counter() - t0)
+            assert st == T.TPMG_OK, (name, st)
+        ms = 1000.0 * float(np.median(times))
+        r = {"ms_per_solve": ms, "iters": it, "unknowns_per_s": w.unknowns / (ms / 1000.0)}
+        if fp32:
+            fine = P.tuning()[-1]
+            sw_ms, sw_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_SWEEP, reps)
+            op_ms, op_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_OPERATOR_PRING, reps)
+            r.update(sweep_us=sw_ms * 1000.0, sweep_bytes=sw_b, operator_us=op_ms * 1000.0, operator_bytes=op_b,
+                     sweep_instance=f"scan{fine['scan_levels']}", operator_instance=f"chunk{fine['chunk_spmv']}")
+        out[name] = r
+        P.close()
+        del P, f, u
+        torch.cuda.empty_cache()
+    return out
+
+
+def profile_kernels(reps: int):
+    """Counter run on the HBM-bound workload (refinement 7 x 128 levels,
+    mixed): one solve, then `reps` finest-grid FP32 sweeps, `reps` launches of
+    q = A p with the direction update, then one copy of 1 GiB (a plain copy
+    kernel of known size, larger than the last-level cache, to calibrate
+    FETCH_SIZE and WRITE_SIZE)."""
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    w = synth.workload("ico7_nz128_ar0.1")
     P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=False, autotune=1)
     geo = P.geometry()
     f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
     u = P.device_vector()
-    st, it, rr, _, _ = P.solve(f, u)            # leaves realistic data in the sweep buffers
-    ms, nbytes = T.tpmg_mg_time_sweep(P.mg, reps)
-    src = torch.ones(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    st, it, rr, _, _ = P.solve(f, u)            # leaves realistic data in the buffers
+    sw_ms, sw_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_SWEEP, reps)
+    op_ms, op_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_OPERATOR_PRING, reps)
+    src = torch.ones(1024 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"sweep_avg_us": ms * 1000.0, "sweep_model_bytes": nbytes, "sweep_dispatches": reps,
-                      "copy_bytes": 512 * 1024 * 1024, "solve_iters": it}), flush=True)
+    fine = P.tuning()[-1]
+    print(json.dumps({"workload": w.name, "sweep_avg_us": sw_ms * 1000.0, "sweep_model_bytes": sw_b,
+                      "operator_avg_us": op_ms * 1000.0, "operator_model_bytes": op_b, "dispatches_each": reps + 1,
+                      "copy_bytes": 1024 * 1024 * 1024, "solve_iters": it, "tuning": fine}), flush=True)
 
 
 def anisotropy_report(steps: int = 3):
@@ -363,9 +432,11 @@ def main():
                     help="only the batched-solve report (16 problems of uneven size, batched and one by one)")
     ap.add_argument("--report", action="store_true",
                     help="also measure the anisotropy sweep on the refinement-7 grid (one JSON line per ratio)")
-    ap.add_argument("--profile-sweep", action="store_true",
-                    help="only the finest-grid sweep timing loop (mixed) and a 512 MiB calibration copy, "
-                         "for hardware-counter runs")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only the kernel timing loops on the refinement-7 grid (finest FP32 sweep and the operator "
+                         "with the direction update) and a 1 GiB calibration copy, for hardware-counter runs")
+    ap.add_argument("--no-roofline-workload", action="store_true",
+                    help="skip the refinement-7 solves and kernel timings that the roofline is taken on")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -389,8 +460,8 @@ def main():
 
     w = synth.workload(args.workload)
     log(f"workload {w.name}: {w.unknowns} unknowns, refinement {w.refinement}, nz {w.nz}")
-    if args.profile_sweep:
-        profile_sweep(w, args.sweep_reps)
+    if args.profile_kernels:
+        profile_kernels(args.sweep_reps)
         return
     if args.sequence:
         sequence_report(epochs=args.epochs)
@@ -424,13 +495,23 @@ def main():
             iters, relres = it, rr
         ms = 1000.0 * sum(times) / len(times)
         avg_sweep_ms, sweep_bytes = T.tpmg_mg_time_sweep(P.mg, args.sweep_reps)
+        # one more solve, untimed, with the per-phase device timers on (kernels
+        # launched one by one with HIP events between the phases)
+        u.zero_()
+        torch.cuda.synchronize()
+        d = T.tpmg_solve_details(P.mg, f, u, 1e-8, 100, phase_timers=True)
         results[name] = dict(ms=ms, iters=iters, relres=relres, sweep_ms=avg_sweep_ms, sweep_bytes=sweep_bytes,
-                             value=w.unknowns / (ms / 1000.0))
+                             value=w.unknowns / (ms / 1000.0), model_bytes=d["model_bytes"],
+                             phases_ms={k: d[f"t_{k}_ms"] for k in ("vcycle", "spmv", "blas")})
         log(f"{name}: {ms:.3f} ms/solve, {iters} iterations, relres {relres:.2e}, "
-            f"finest sweep {avg_sweep_ms * 1000:.1f} us ({sweep_bytes / avg_sweep_ms / 1e6:.0f} GB/s model)")
+            f"finest sweep {avg_sweep_ms * 1000:.1f} us ({sweep_bytes / avg_sweep_ms / 1e6:.0f} GB/s model), "
+            f"phases {results[name]['phases_ms']}, model bytes {d['model_bytes'] / 1e9:.2f} GB")
 
     mixed, fp64 = results["mixed"], results["fp64"]
-    achieved = mixed["sweep_bytes"] / (mixed["sweep_ms"] / 1000.0) / 1e9
+    tuning32 = P32.tuning()[-1]
+    for P in (P64, P32):
+        P.close()
+    torch.cuda.empty_cache()
     out = {
         "metric": METRIC,
         "value": mixed["value"],
@@ -450,35 +531,62 @@ def main():
             "precond": "fp32 V-cycle in fp64 FCG",
             "iters": mixed["iters"],
             "relres": mixed["relres"],
+            "model_GBs": mixed["model_bytes"] / (mixed["ms"] / 1000.0) / 1e9,
+            "phases_ms": mixed["phases_ms"],
             "fp64_unknowns_per_s": fp64["value"],
             "fp64_ms_per_solve": fp64["ms"],
             "fp64_iters": fp64["iters"],
+            "fp64_model_GBs": fp64["model_bytes"] / (fp64["ms"] / 1000.0) / 1e9,
+            "fp64_phases_ms": fp64["phases_ms"],
             "mixed_speedup_vs_fp64": fp64["ms"] / mixed["ms"],
-            "fp64_sweep_GBs": fp64["sweep_bytes"] / (fp64["sweep_ms"] / 1000.0) / 1e9,
+            "cache_resident_sweep_GBs": {
+                "note": "finest sweep of this workload; its FP32 fields fit the 256 MB last-level cache",
+                "mixed": mixed["sweep_bytes"] / (mixed["sweep_ms"] / 1000.0) / 1e9,
+                "fp64": fp64["sweep_bytes"] / (fp64["sweep_ms"] / 1000.0) / 1e9},
             "autotune": args.autotune,
             "graph": args.graph,
-            "finest_tuning_mixed": P32.tuning()[-1],
+            "finest_tuning_mixed": tuning32,
         },
-        "roofline": {
-            "kernel": "finest-grid line-smoother sweep (FP32, mixed solve)",
+    }
+    if not args.no_roofline_workload:
+        log("refinement-7 workload: solves and kernel timings ...")
+        rw = roofline_workload(steps=3, reps=args.sweep_reps)
+        m3 = rw["mixed"]
+        out["config"]["roofline_workload"] = {
+            "workload": rw["workload"],
+            "mixed_unknowns_per_s": m3["unknowns_per_s"], "mixed_ms_per_solve": m3["ms_per_solve"],
+            "mixed_iters": m3["iters"],
+            "fp64_unknowns_per_s": rw["fp64"]["unknowns_per_s"], "fp64_ms_per_solve": rw["fp64"]["ms_per_solve"],
+            "fp64_iters": rw["fp64"]["iters"]}
+        achieved = m3["sweep_bytes"] / (m3["sweep_us"] / 1e6) / 1e9
+        out["roofline"] = {
+            "kernel": "finest-grid line-smoother sweep (FP32, mixed solve), refinement 7 x 128 levels",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(P32.tuning()[-1]["scan_levels"]) if args.workload == "ico6_nz128" else None,
-            "avg_launch_us": mixed["sweep_ms"] * 1000.0,
-            "bytes_per_launch": mixed["sweep_bytes"],
-        },
-    }
+            "traffic": measured_traffic("kernels_ico7_nz128_counters.md", "sweep", m3["sweep_instance"]),
+            "avg_launch_us": m3["sweep_us"],
+            "bytes_per_launch": m3["sweep_bytes"],
+        }
+        achieved_op = m3["operator_bytes"] / (m3["operator_us"] / 1e6) / 1e9
+        out["roofline_operator"] = {
+            "kernel": "q = A p with the direction update (FP64), refinement 7 x 128 levels",
+            "bound": "hbm",
+            "achieved": achieved_op,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_op / HBM_PEAK_GBS,
+            "traffic": measured_traffic("kernels_ico7_nz128_counters.md", "operator", m3["operator_instance"]),
+            "avg_launch_us": m3["operator_us"],
+            "bytes_per_launch": m3["operator_bytes"],
+        }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(w, fp64["iters"])
     print(json.dumps(out), flush=True)
     if args.report:
-        for P in (P64, P32):
-            P.close()
-        torch.cuda.empty_cache()
         batch_report()
         sequence_report()
         anisotropy_report()

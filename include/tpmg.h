@@ -87,14 +87,30 @@ typedef struct {
   int reserved[1];
 } tpmg_mg_params;
 
-/* Result of a solve. history (optional, caller-owned, history_cap entries)
- * receives ||r_k|| / ||f|| for k = 0 .. iters. */
+/* Result of a solve. Inputs: history (optional, caller-owned, history_cap
+ * entries) receives ||r_k|| / ||f|| for k = 0 .. iters; phase_timers = 1
+ * times the phases of every iteration with HIP events on the solve's stream
+ * (the iteration's kernels are then launched one by one, never as a graph);
+ * div_tol (0 = 1e3) stops the solve with TPMG_ERR_BREAKDOWN once
+ * ||r_k|| > div_tol ||r_0||. Outputs: the rest. */
 typedef struct {
   int iters;
   double relres;       /* ||r|| / ||f|| of the recursively updated residual */
   double* history;
   int history_cap;
   double t_total_ms;   /* wall time of tpmg_solve, first kernel to return   */
+  int phase_timers;    /* in: 1 = fill t_vcycle_ms, t_spmv_ms, t_blas_ms    */
+  double div_tol;      /* in: divergence bound on ||r_k|| / ||r_0||; 0 = 1e3 */
+  double t_vcycle_ms;  /* device time in the V-cycles (smoother sweeps,
+                          transfers, the dots formed by the last sweep)     */
+  double t_spmv_ms;    /* device time in q = A p (with the direction update
+                          formed inside it) and the initial residual        */
+  double t_blas_ms;    /* device time in the other vector updates and
+                          reductions (r -= alpha q, x += alpha p)           */
+  double model_bytes;  /* algorithmic HBM bytes the solve moved: every
+                          field read or written once per kernel that touches
+                          it (the per-kernel figures of the kernel table),
+                          summed over the kernels the solve ran             */
 } tpmg_solve_info;
 
 /* Fills p with the defaults above. */
@@ -225,7 +241,10 @@ tpmg_status tpmg_batch_workspace_size(tpmg_mg* const* problems, int n, size_t* b
 tpmg_status tpmg_batch_create(tpmg_mg* const* problems, int n, void* d_workspace, size_t bytes, tpmg_batch** out);
 
 /* Solves problem p from the guess in d_u[p] with right-hand side d_f[p]
- * (tiled FP64, as tpmg_solve). infos (optional) holds n entries. Returns
+ * (tiled FP64, as tpmg_solve). infos (optional) holds n entries; of their
+ * inputs only history and history_cap are read (no phase timers; the
+ * divergence bound is 1e3), and each receives its problem's iters, relres,
+ * model_bytes and the batch's t_total_ms. Returns
  * TPMG_OK when all converged, TPMG_NOT_CONVERGED if one reached maxit,
  * TPMG_ERR_BREAKDOWN if one broke down (its u holds its last finite
  * iterate). The host waits for each iteration's scalars (an event after
@@ -252,6 +271,24 @@ tpmg_status tpmg_richardson_rate(tpmg_mg* mg, double* d_u, int cycles, int skip,
  * of one sweep (read u and f, write u: 3 values per unknown of the
  * finest grid, counting padding columns). Synchronises the stream. */
 tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* model_bytes);
+
+/* Diagnostics: times `reps` back-to-back launches (after one untimed launch)
+ * of one finest-grid kernel of the solve, alone (no finalize kernel), between
+ * two HIP events on the setup stream, on workspace buffers (overwritten):
+ *   0  the line-smoother sweep, as tpmg_mg_time_sweep (3 s B per unknown,
+ *      s the V-cycle precision's bytes);
+ *   1  q = A p with the direction update p = z + beta p_prev formed inside
+ *      it, as in an iteration of tpmg_solve (z in the V-cycle's output
+ *      precision, p_prev, p and q FP64: 4 or 8 + 24 B per unknown);
+ *   2  q = A p (FP64, 16 B per unknown);
+ *   3  residual + restriction from the finest grid (2.25 s B per unknown);
+ *   4  prolongation + correction into the finest grid (2.25 s B).
+ * The counts are per unknown of the padded finest grid. avg_ms: mean
+ * duration per launch; model_bytes: the algorithmic HBM bytes of one launch.
+ * Kernel 1 overwrites the solver's scalars (the next solve resets them).
+ * Synchronises the stream. Errors: TPMG_ERR_ARG (kernel 1 without a fused
+ * operator instance, 3 and 4 on a single level). */
+tpmg_status tpmg_mg_time_kernel(tpmg_mg* mg, int kernel, int reps, double* avg_ms, double* model_bytes);
 
 /* ------------------------------------------------------ launch tuning -- */
 

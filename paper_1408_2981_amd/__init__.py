@@ -41,7 +41,7 @@ EXPORTED = [
     "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
     "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
     "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
-    "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
+    "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_time_kernel", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
     "tpmg_tune_save", "tpmg_tune_clear", "tpmg_tune_entries", "tpmg_grid_destroy", "tpmg_op_destroy",
     "tpmg_mlp_param_count", "tpmg_mlp_workspace_size", "tpmg_mlp_create", "tpmg_mlp_set_params", "tpmg_mlp_get_params",
     "tpmg_mlp_set_scaling", "tpmg_mlp_get_scaling", "tpmg_mlp_fit_scaling", "tpmg_mlp_features", "tpmg_mlp_targets",
@@ -75,7 +75,9 @@ SMOOTHER_GLOBAL = 3
 class SolveInfo(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int), ("relres", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
-        ("history_cap", ctypes.c_int), ("t_total_ms", ctypes.c_double),
+        ("history_cap", ctypes.c_int), ("t_total_ms", ctypes.c_double), ("phase_timers", ctypes.c_int),
+        ("div_tol", ctypes.c_double), ("t_vcycle_ms", ctypes.c_double), ("t_spmv_ms", ctypes.c_double),
+        ("t_blas_ms", ctypes.c_double), ("model_bytes", ctypes.c_double),
     ]
 
 
@@ -111,6 +113,7 @@ _sig = {
     "tpmg_batch_destroy": (None, [_vp]),
     "tpmg_richardson_rate": (_ip, [_vp, _vp, _ip, _ip, _dp, _dp]),
     "tpmg_mg_time_sweep": (_ip, [_vp, _ip, _dp, _dp]),
+    "tpmg_mg_time_kernel": (_ip, [_vp, _ip, _ip, _dp, _dp]),
     "tpmg_mg_tuning": (_ip, [_vp, _ip] + [ctypes.POINTER(_ip)] * 5),
     "tpmg_mg_autotune_stats": (_ip, [_vp, ctypes.POINTER(_ip), _dp]),
     "tpmg_tune_load": (_ip, [ctypes.c_char_p]),
@@ -288,13 +291,27 @@ def tpmg_vcycle(mg: int, d_r, d_z):
 
 def tpmg_solve(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 256):
     """Returns (status, iters, relres, history, t_total_ms)."""
+    info = tpmg_solve_details(mg, d_f, d_u, rtol, maxit, history_cap)
+    return info["status"], info["iters"], info["relres"], info["history"], info["t_total_ms"]
+
+
+def tpmg_solve_details(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 256, phase_timers: bool = False,
+                    div_tol: float = 0.0) -> dict:
+    """tpmg_solve with every field of tpmg_solve_info returned in a dict
+    (status, iters, relres, history, t_total_ms, t_vcycle_ms, t_spmv_ms,
+    t_blas_ms, model_bytes) and the message of a breakdown."""
     hist = np.zeros(history_cap)
     info = SolveInfo()
     info.history = hist.ctypes.data_as(_dp)
     info.history_cap = history_cap
+    info.phase_timers = int(phase_timers)
+    info.div_tol = float(div_tol)
     s = _lib.tpmg_solve(mg, _dev(d_f), _dev(d_u), float(rtol), int(maxit), ctypes.byref(info))
     _check(s, ok=(TPMG_OK, TPMG_NOT_CONVERGED, TPMG_ERR_BREAKDOWN))
-    return s, info.iters, info.relres, hist[: info.iters + 1].copy(), info.t_total_ms
+    return dict(status=s, iters=info.iters, relres=info.relres, history=hist[: info.iters + 1].copy(),
+                t_total_ms=info.t_total_ms, t_vcycle_ms=info.t_vcycle_ms, t_spmv_ms=info.t_spmv_ms,
+                t_blas_ms=info.t_blas_ms, model_bytes=info.model_bytes,
+                message=tpmg_last_error() if s == TPMG_ERR_BREAKDOWN else "")
 
 
 def _ptrs(handles):
@@ -344,6 +361,18 @@ def tpmg_mg_time_sweep(mg: int, reps: int):
     ms = ctypes.c_double()
     b = ctypes.c_double()
     _check(_lib.tpmg_mg_time_sweep(mg, reps, ctypes.byref(ms), ctypes.byref(b)))
+    return ms.value, b.value
+
+
+# kernels of tpmg_mg_time_kernel
+KERNEL_SWEEP, KERNEL_OPERATOR_PRING, KERNEL_OPERATOR, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
+
+
+def tpmg_mg_time_kernel(mg: int, kernel: int, reps: int):
+    """Returns (avg_ms, model_bytes) of one launch of a finest-grid kernel."""
+    ms = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(_lib.tpmg_mg_time_kernel(mg, kernel, reps, ctypes.byref(ms), ctypes.byref(b)))
     return ms.value, b.value
 
 

@@ -86,7 +86,9 @@ struct FcgScalars {
   double rr;      // <r, r>
   double ff;      // <f, f>
   double rtol;    // stopping tolerance (set at kFinInit)
-  int status;     // 0 ok, 1 breakdown
+  double rr0;     // <r_0, r_0> (set at kFinInit)
+  double div2;    // divergence bound on <r, r> / <r_0, r_0> (set at kFinInit)
+  int status;     // 0 ok, 1 breakdown, 2 divergence
   int done;       // converged or broken down: batched launches skip the problem
   int iters;      // completed iterations (maintained on the device)
   int seq;        // records published so far (single solves)
@@ -106,6 +108,8 @@ struct FcgRecord {
   double ff;      // ||f||^2 (the record of kFinInit, seq 0)
 };
 constexpr int kRecords = 4;
+// A solve stops as diverged once ||r_k|| > 1e3 ||r_0|| unless told otherwise.
+constexpr double kDefaultDiv2 = 1e6;
 
 // Operations of one FCG iteration, as grouped by the batched executor.
 enum OpKind { kOpSmooth = 0, kOpRestrict, kOpProlong, kOpSpmv, kOpPupdate, kOpUpdate, kOpFinalize, kOpPupdateRing,
@@ -172,9 +176,10 @@ unsigned pupdate_blocks(size_t len);      // blocks of the p-update kernel
 // mode 0: y = A x (partials <x, y>, e.g. site kFinAlpha). mode 1: y = b - A x
 // (partials <y, y>, <b, b>; site kFinInit), with y32 non-NULL also its FP32
 // rounding. FP64; x and y must not alias.
+// div2 (kFinInit): the squared divergence bound, see FcgScalars::div2.
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
                          double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol = 0.0,
-                         float* y32 = nullptr, FcgRecord* ring = nullptr);
+                         float* y32 = nullptr, FcgRecord* ring = nullptr, double div2 = kDefaultDiv2);
 // one-block finalisation of nblocks partials at `site` (rtol used at kFinInit)
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s);
 
@@ -223,6 +228,7 @@ hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len
 // pupdate_ring and spmv_ring in one launch (the same bits), for the operator
 // chunks that have an instance (spmv_pring_fits).
 bool spmv_pring_fits(const LevelView& L);
+// (site kFinNone: the operator kernel alone, no finalize; for timing)
 hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, double* ring, size_t len, double* x,
                              double* q, double* partials, FcgScalars* sc, hipStream_t s, int site = kFinAlpha);
 hipError_t launch_flush(double* x, const double* ring, const FcgScalars* sc, size_t len, hipStream_t s);

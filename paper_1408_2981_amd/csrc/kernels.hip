@@ -221,11 +221,14 @@ __device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
 // (s0, s1) of all blocks' partials. done/iters serve batched solves, which
 // test convergence on the device (||r|| <= rtol ||f||, as the host does for a
 // single solve).
-__device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restrict__ sc, double rtol) {
+__device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restrict__ sc, double rtol,
+                            double div2) {
   switch (site) {
     case kFinInit:
       sc->rr = s0;
       sc->ff = s1;
+      sc->rr0 = s0;
+      sc->div2 = div2;
       sc->pq = 1.0;
       sc->rz = 0.0;
       sc->alpha = 0.0;
@@ -256,6 +259,9 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
         sc->done = 1;
       } else if (sqrt(s0) <= sc->rtol * sqrt(sc->ff)) {
         sc->done = 1;
+      } else if (s0 > sc->div2 * sc->rr0) {
+        sc->status = 2;   // diverged: the iterate is finite and kept
+        sc->done = 1;
       }
       break;
     case kFinBeta:
@@ -274,7 +280,7 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
 // all blocks' partials visible (a device-scope fence per block would write
 // back the whole L2).
 __device__ __forceinline__ void finalize_body(int site, const double* __restrict__ partials, int nblocks,
-                                              FcgScalars* __restrict__ sc, double rtol) {
+                                              FcgScalars* __restrict__ sc, double rtol, double div2 = kDefaultDiv2) {
   double v[2] = {0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     v[0] += partials[2 * b];
@@ -291,7 +297,7 @@ __device__ __forceinline__ void finalize_body(int site, const double* __restrict
   __syncthreads();
   if (threadIdx.x == 0)
     fcg_scalars(site, (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]),
-                (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]), sc, rtol);
+                (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]), sc, rtol, div2);
 }
 
 // ---------------------------------------------------------------------------
@@ -884,9 +890,9 @@ __device__ __forceinline__ void pupdate_body(const TZ* __restrict__ z, double* _
 // iteration's record to the host ring when one is given.
 __global__ __launch_bounds__(256) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
                                                   FcgScalars* __restrict__ sc, double rtol,
-                                                  FcgRecord* __restrict__ ring) {
+                                                  FcgRecord* __restrict__ ring, double div2) {
   const bool iter_site = site == kFinAlpha || site == kFinRR || site == kFinBeta;
-  if (!(iter_site && sc->done)) finalize_body(site, partials, nblocks, sc, rtol);
+  if (!(iter_site && sc->done)) finalize_body(site, partials, nblocks, sc, rtol, div2);
   if (site == kFinInit && ring != nullptr && threadIdx.x == 0) {
     // record 0: the initial residual, so that the host can decide while the
     // first iteration already runs
@@ -1331,7 +1337,7 @@ LevelTune default_tune(int nz, int prec) {
 unsigned pupdate_blocks(size_t len) { return grid_for(len, 2048); }
 
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, nblocks, sc, rtol, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, nblocks, sc, rtol, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1351,7 +1357,7 @@ void chunk_variant(int chunk, Fn&& fn) {
 
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
                          double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol, float* y32,
-                         FcgRecord* ring) {
+                         FcgRecord* ring, double div2) {
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
@@ -1364,7 +1370,8 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
       hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials, y32);
   });
   if (site != kFinNone)
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, ring);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, ring,
+                       div2);
   return hipGetLastError();
 }
 
@@ -1468,7 +1475,7 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
     });
     if (dots)
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), a.partials,
-                         static_cast<int>(ntiles), a.scal, 0.0, nullptr);
+                         static_cast<int>(ntiles), a.scal, 0.0, nullptr, kDefaultDiv2);
     return hipGetLastError();
   }
   if (dots) return hipErrorInvalidValue;   // only the scan kernel forms the dots
@@ -1552,7 +1559,7 @@ hipError_t launch_fcg_update(double* x, double* r, const double* p, const double
                              double* partials, FcgRecord* ring, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
-                     ring);
+                     ring, kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1577,7 +1584,7 @@ hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, 
     hipLaunchKernelGGL((k_spmv_ring<CH>), dim3(blocks), dim3(256), 0, s, V, chunk, ring, len, q, partials, sc);
   });
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinAlpha), partials,
-                     static_cast<int>(blocks), sc, 0.0, nullptr);
+                     static_cast<int>(blocks), sc, 0.0, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1603,7 +1610,9 @@ hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, d
                            ring, len, x, q, partials, sc);
     }
   });
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, 0.0, nullptr);
+  if (site != kFinNone)
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, 0.0, nullptr,
+                       kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1611,7 +1620,7 @@ hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len
                           hipStream_t s, float* r32) {
   hipLaunchKernelGGL(k_rupdate, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, q, sc, len, partials, r32);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
-                     ring);
+                     ring, kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1623,7 +1632,7 @@ hipError_t launch_flush(double* x, const double* ring, const FcgScalars* sc, siz
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, z, q, r, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
 

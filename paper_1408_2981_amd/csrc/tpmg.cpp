@@ -100,6 +100,8 @@ struct tpmg_mg {
   tpmg::FcgRecord* ring_dev = nullptr;   // the same memory as the device addresses it
   size_t len = 0;                        // padded finest vector length
   int max_partial_blocks = 0;
+  // events of the per-phase timers (created on first use, reused)
+  std::vector<hipEvent_t> tev;
   // graph of one FCG iteration for the solution vector graph_x
   hipGraphExec_t graph = nullptr;
   double* graph_x = nullptr;
@@ -584,6 +586,80 @@ hipError_t exec_op(const Op& op, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
+}
+
+// Phase of an operation for the per-phase timers of a solve: 0 V-cycle,
+// 1 operator, 2 other vector updates and reductions.
+int op_phase(const Op& op) {
+  switch (op.kind) {
+    case tpmg::kOpSmooth:
+    case tpmg::kOpRestrict:
+    case tpmg::kOpProlong:
+      return 0;
+    case tpmg::kOpSpmv:
+    case tpmg::kOpSpmvRing:
+    case tpmg::kOpSpmvPRing:
+      return 1;
+    default:
+      return 2;
+  }
+}
+
+// Algorithmic HBM bytes of one operation: every field it reads or writes
+// counted once (per-column coefficients, halo rows and the scalars are
+// O(1/nz) per unknown and left out). it: the iteration the operation belongs
+// to (the first takes p = z; every kDirSlots-th direction update also adds
+// the ring's kDirSlots directions to x).
+double op_model_bytes(const Op& op, int it) {
+  const double s = op.prec;
+  const double n = static_cast<double>(op.L.npad) * op.L.nz;
+  const double len = static_cast<double>(op.len);
+  const double zb = op.f_double ? 8.0 : 4.0;
+  const bool flush = it > 0 && it % tpmg::kDirSlots == 0;
+  const double ring_x = flush ? 8.0 * (tpmg::kDirSlots + 2) : 0.0;
+  switch (op.kind) {
+    case tpmg::kOpSmooth: {
+      double b = (op.zero ? 0.0 : s) + (op.f_double ? 8.0 : s) + (op.out_double ? 8.0 : s);
+      if (op.fcopy) b += 4.0;
+      if (op.dots) b += 8.0;   // q (the residual is the right-hand side)
+      return b * n;
+    }
+    case tpmg::kOpRestrict:
+    case tpmg::kOpProlong:
+      return (2.0 * s + s / 4.0) * n;
+    case tpmg::kOpSpmvPRing:
+      return (zb + (it > 0 ? 8.0 : 0.0) + 16.0 + ring_x) * len;
+    case tpmg::kOpPupdateRing:
+      return (zb + (it > 0 ? 8.0 : 0.0) + 8.0 + ring_x) * len;
+    case tpmg::kOpSpmvRing:
+      return 16.0 * len;
+    case tpmg::kOpRupdate:
+      return (24.0 + (op.out0 ? 4.0 : 0.0)) * len;
+    case tpmg::kOpPupdate:
+      return (zb + 16.0) * len;
+    case tpmg::kOpSpmv:
+      return 16.0 * n;
+    case tpmg::kOpUpdate:
+      return 48.0 * len;
+    case -1:
+      return 24.0 * len;
+    default:
+      return 0.0;
+  }
+}
+
+// Model bytes of a solve of `iters` iterations: the initial residual
+// (reads u and f, writes r and, for an FP32 V-cycle, its FP32 copy), the
+// iterations, and the final x update of a single solve's direction ring.
+double solve_model_bytes(const std::vector<Op>& ops, int iters, size_t len, bool fp32, bool ring) {
+  double b = (24.0 + (fp32 ? 4.0 : 0.0)) * static_cast<double>(len);
+  for (int it = 0; it < iters; ++it)
+    for (const Op& op : ops) b += op_model_bytes(op, it);
+  if (ring && iters > 0) {
+    const int flushed = (iters - 1) / tpmg::kDirSlots * tpmg::kDirSlots;
+    b += 8.0 * (2 + iters - flushed) * static_cast<double>(len);
+  }
+  return b;
 }
 
 hipError_t vcycle(tpmg_mg& m, const double* r_in, double* z_out) {
@@ -1519,12 +1595,20 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   if (d_f == d_u) return fail(TPMG_ERR_ARG, "f and u must not alias");
   if (!(rtol >= 0.0) || maxit < 0) return fail(TPMG_ERR_ARG, "rtol must be >= 0 and maxit >= 0");
   if (info && info->history_cap > 0 && !info->history) return fail(TPMG_ERR_ARG, "history_cap > 0 with NULL history");
+  if (info && !(info->div_tol >= 0.0)) return fail(TPMG_ERR_ARG, "div_tol must be >= 0");
+  const bool timers = info && info->phase_timers != 0;
+  const double div2 = info && info->div_tol > 0.0 ? info->div_tol * info->div_tol : tpmg::kDefaultDiv2;
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = mg->stream;
   const tpmg::LevelView F = mg->view64(mg->nlev - 1);
+  // one FCG iteration as a list of operations (also the basis of the byte
+  // count and of the per-phase timers)
+  std::vector<Op> iter_ops;
+  fcg_ops(*mg, d_u, mg->scal, iter_ops);
+  const bool graph = mg->use_graph && !timers;
   // the iteration as a graph, captured once per solution vector (on an idle
   // stream, before this solve's work is queued)
-  if (maxit > 0 && mg->use_graph && (mg->graph_x != d_u || mg->graph == nullptr)) {
+  if (maxit > 0 && graph && (mg->graph_x != d_u || mg->graph == nullptr)) {
     TPMG_HIP(hipStreamSynchronize(s));
     drop_graph(*mg);
     hipGraph_t g = nullptr;
@@ -1543,6 +1627,33 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
     }
     mg->graph_x = d_u;
   }
+  // per-phase timers: an event where a phase starts (its phase) and where a
+  // timed stretch ends (-1); the gaps between iterations are not counted
+  std::vector<std::pair<hipEvent_t, int>> marks;
+  auto mark = [&](int phase) -> hipError_t {
+    if (marks.size() == mg->tev.size()) {
+      hipEvent_t ev = nullptr;
+      const hipError_t ce = hipEventCreate(&ev);
+      if (ce != hipSuccess) return ce;
+      mg->tev.push_back(ev);
+    }
+    const hipEvent_t ev = mg->tev[marks.size()];
+    marks.emplace_back(ev, phase);
+    return hipEventRecord(ev, s);
+  };
+  auto run_ops = [&](const std::vector<Op>& ops) -> hipError_t {
+    int cur = -1;
+    for (const Op& op : ops) {
+      if (timers && op_phase(op) != cur) {
+        cur = op_phase(op);
+        const hipError_t me = mark(cur);
+        if (me != hipSuccess) return me;
+      }
+      const hipError_t e = exec_op(op, s);
+      if (e != hipSuccess) return e;
+    }
+    return timers ? mark(-1) : hipSuccess;
+  };
   // no slot holds a record of this solve yet (the previous solve ended with
   // its stream drained)
   for (int i = 0; i < tpmg::kRecords; ++i) mg->ring[i].seq = -1;
@@ -1550,12 +1661,14 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   // first right-hand side, the FP32 rounding of r (later ones come with the r
   // update). The first iteration takes beta = 0 and p = z, reading neither
   // q nor the ring's previous slot.
+  if (timers) TPMG_HIP(mark(1));
   TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, mg->r, mg->partials, tpmg::kFinInit, mg->scal, s, rtol,
-                               mg->fp32 ? static_cast<float*>(mg->fcopy) : nullptr, mg->ring_dev));
+                               mg->fp32 ? static_cast<float*>(mg->fcopy) : nullptr, mg->ring_dev, div2));
+  if (timers) TPMG_HIP(mark(-1));
   int launched = 0;
   auto launch_next = [&]() -> hipError_t {
     ++launched;
-    return mg->use_graph ? hipGraphLaunch(mg->graph, s) : fcg_iteration(*mg, d_u);
+    return graph ? hipGraphLaunch(mg->graph, s) : run_ops(iter_ops);
   };
   // The first iteration is queued before the host reads record 0: when the
   // initial residual already meets the tolerance (or is not finite) the
@@ -1572,6 +1685,7 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   const double fnorm = std::sqrt(ff);
   double rnorm = std::sqrt(rec0.rr);
   int iters = 0;
+  bool diverged = false;
   auto record = [&](int k, double v) {
     if (info && info->history && k < info->history_cap) info->history[k] = v;
   };
@@ -1596,6 +1710,14 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
       tpmg::FcgRecord rec;
       if ((werr = wait_record(mg->ring, it + 1, s, &rec)) != hipSuccess) break;
       iters = it + 1;
+      if (rec.status == 2) {
+        // ||r|| > div_tol ||r_0||: the iterate is finite and kept
+        rnorm = std::sqrt(rec.rr);
+        record(iters, fnorm > 0 ? rnorm / fnorm : 0.0);
+        diverged = true;
+        result = TPMG_ERR_BREAKDOWN;
+        break;
+      }
       if (rec.status != 0) {
         iters = it;
         result = TPMG_ERR_BREAKDOWN;
@@ -1616,8 +1738,10 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   }
   // x += alpha p of the iterations not yet added (after an iteration queued
   // ahead, which changes neither iters nor the ring's counted slots)
+  if (timers && werr == hipSuccess) werr = mark(2);
   hipError_t fe = tpmg::launch_flush(d_u, mg->dirs, mg->scal, mg->len, s);
   if (werr == hipSuccess) werr = fe;
+  if (timers && werr == hipSuccess) werr = mark(-1);
   // drains an iteration queued ahead; reports the first device error
   const hipError_t se = hipStreamSynchronize(s);
   if (werr != hipSuccess || se != hipSuccess)
@@ -1627,7 +1751,18 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
     info->iters = iters;
     info->relres = fnorm > 0 ? rnorm / fnorm : 0.0;
     info->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    info->t_vcycle_ms = info->t_spmv_ms = info->t_blas_ms = 0.0;
+    double* tp[3] = {&info->t_vcycle_ms, &info->t_spmv_ms, &info->t_blas_ms};
+    for (size_t i = 0; i + 1 < marks.size(); ++i) {
+      if (marks[i].second < 0) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, marks[i].first, marks[i + 1].first) == hipSuccess) *tp[marks[i].second] += ms;
+    }
+    // the device ran the iterations it counted (one queued after the last
+    // returned at once)
+    info->model_bytes = solve_model_bytes(iter_ops, iters, mg->len, mg->fp32, true);
   }
+  if (diverged) return fail(TPMG_ERR_BREAKDOWN, "divergence: ||r|| exceeded div_tol ||r_0||");
   if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite value or <p, A p> <= 0");
   return result;
 }
@@ -1684,6 +1819,73 @@ tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* mo
   if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("time sweep: ") + hipGetErrorString(e));
   *avg_ms = static_cast<double>(ms) / reps;
   if (model_bytes) *model_bytes = 3.0 * (mg->fp32 ? 4.0 : 8.0) * static_cast<double>(mg->len);
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mg_time_kernel(tpmg_mg* mg, int kernel, int reps, double* avg_ms, double* model_bytes) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (reps < 1 || !avg_ms) return fail(TPMG_ERR_ARG, "reps must be >= 1 and avg_ms non-NULL");
+  if (kernel < 0 || kernel > 4) return fail(TPMG_ERR_ARG, "kernel must be 0 .. 4");
+  if (kernel >= 3 && mg->nlev < 2) return fail(TPMG_ERR_ARG, "the transfer kernels need two levels");
+  const int L = mg->nlev - 1;
+  const int prec = mg->fp32 ? 4 : 8;
+  const tpmg::LevelView V = mg->view(L);
+  const tpmg::LevelView F = mg->view64(L);
+  hipStream_t s = mg->stream;
+  const bool z_float = mg->tune.back().smoother == tpmg::kSmScan && mg->fp32;
+  if (kernel == 1 && !tpmg::spmv_pring_fits(F))
+    return fail(TPMG_ERR_ARG, "the operator chunk of this grid has no direction-update instance");
+  if (kernel == 1) {
+    // scalars of an iteration in the middle of a solve (not done, iteration 1:
+    // p_1 = z + beta p_0, no x update); the next solve's start resets them
+    std::memset(mg->h_scal, 0, sizeof(tpmg::FcgScalars));
+    mg->h_scal->iters = 1;
+    mg->h_scal->beta = 0.5;
+    TPMG_HIP(hipMemcpyAsync(mg->scal, mg->h_scal, sizeof(tpmg::FcgScalars), hipMemcpyHostToDevice, s));
+  }
+  const void* f = mg->fp32 ? static_cast<const void*>(mg->fcopy) : static_cast<const void*>(mg->r);
+  const int Lc = L > 0 ? L - 1 : 0;
+  auto launch = [&](int i) -> hipError_t {
+    switch (kernel) {
+      case 0:
+        return tpmg::launch_smooth(V, prec, f, false, mg->lv[L].u[i & 1], false, mg->lv[L].u[1 - (i & 1)], false,
+                                   nullptr, mg->sd, mg->sc, mg->omega, s);
+      case 1:
+        return tpmg::launch_spmv_pring(F, mg->z, !z_float, mg->dirs, mg->len, mg->p, mg->q, mg->partials, mg->scal, s,
+                                       tpmg::kFinNone);
+      case 2:
+        return tpmg::launch_spmv64(F, 0, mg->p, nullptr, mg->q, mg->partials, tpmg::kFinNone, mg->scal, s);
+      case 3:
+        return tpmg::launch_residual_restrict(V, mg->view(Lc), prec, f, mg->lv[L].u[0], mg->lv[Lc].f, s);
+      default:
+        return tpmg::launch_prolong_add(V, mg->view(Lc), prec, mg->lv[Lc].u[0], mg->lv[L].u[0], s);
+    }
+  };
+  hipEvent_t e0, e1;
+  TPMG_HIP(hipEventCreate(&e0));
+  TPMG_HIP(hipEventCreate(&e1));
+  hipError_t e = launch(0);   // one untimed launch
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch(i + 1);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("time kernel: ") + hipGetErrorString(e));
+  *avg_ms = static_cast<double>(ms) / reps;
+  if (model_bytes) {
+    const double n = static_cast<double>(mg->len);
+    const double s_b = prec;
+    switch (kernel) {
+      case 0: *model_bytes = 3.0 * s_b * n; break;
+      case 1: *model_bytes = ((z_float ? 4.0 : 8.0) + 24.0) * n; break;
+      case 2: *model_bytes = 16.0 * n; break;
+      default: *model_bytes = (2.0 * s_b + s_b / 4.0) * n; break;
+    }
+  }
   return TPMG_OK;
 }
 
@@ -1848,6 +2050,10 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
       infos[p].iters = c.iters;
       infos[p].relres = fnorm[p] > 0 ? std::sqrt(c.rr) / fnorm[p] : 0.0;
       infos[p].t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      infos[p].t_vcycle_ms = infos[p].t_spmv_ms = infos[p].t_blas_ms = 0.0;
+      std::vector<Op> ops;
+      fcg_ops(*b->probs[p], d_u[p], b->scal + p, ops, false, ring);
+      infos[p].model_bytes = solve_model_bytes(ops, c.iters, b->probs[p]->len, b->probs[p]->fp32, ring);
     }
     if (st == TPMG_ERR_BREAKDOWN) worst = st;
     else if (st == TPMG_NOT_CONVERGED && worst == TPMG_OK) worst = st;
@@ -1870,6 +2076,7 @@ void tpmg_op_destroy(tpmg_op* op) { delete op; }
 void tpmg_mg_destroy(tpmg_mg* mg) {
   if (!mg) return;
   drop_graph(*mg);
+  for (hipEvent_t ev : mg->tev) (void)hipEventDestroy(ev);
   if (mg->h_scal) (void)hipHostFree(mg->h_scal);
   if (mg->ring) (void)hipHostFree(mg->ring);
   delete mg;

@@ -1,11 +1,21 @@
 """The largest workload: icosahedral refinement 7 x 128 quadratically graded
 levels (41,943,040 unknowns), at both ends of the anisotropy sweep
 (H = 1e-1 and 1e-3 x the horizontal spacing), in the configuration bench.py times
-(graph replay, autotuned kernels). The oracle cannot run the full solve
-here in seconds, so the checks are what holds at any size, with the
-oracle's own FP64 operator as the reference: the operator against the oracle's
-on a random field, and both solves' true residual f - A u, evaluated by the
-oracle, below the stopping tolerance."""
+(graph replay, autotuned kernels). Two kinds of checks:
+
+  * against the oracle's results for these workloads, stored in
+    tests/golden/ico7_nz128_ar{0.1,0.001}_oracle.json by
+    tests/golden/make_full_size.py (it calls only oracle/ and synth/):
+    identical FP64 iteration counts and residual histories, sampled FP64
+    solution and V-cycle values, the FP64 and FP32 V-cycle convergence
+    factors (Section 5.2), the mixed solve's iteration count;
+  * what holds at any size with the oracle's own FP64 operator as the
+    reference: the operator against the oracle's on a random field, and
+    both solves' true residual f - A u, evaluated by the oracle, below the
+    stopping tolerance."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -20,6 +30,9 @@ import synth  # noqa: E402
 from oracle import operator as opm, tpmg as otpmg  # noqa: E402
 
 
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
 @pytest.fixture(scope="module", params=["0.1", "0.001"])
 def config3(request):
     w = synth.workload(f"ico7_nz128_ar{request.param}")
@@ -27,6 +40,77 @@ def config3(request):
     fine = h.meshes[-1]
     f = synth.make_rhs(w, fine.centre, fine.area, h.vert.vk)
     return w, h, f
+
+
+def _gold(w):
+    return json.load(open(os.path.join(GOLD, f"{w.name}_oracle.json")))
+
+
+def _samples(P, tiled, g):
+    u = P.unpack(tiled)
+    return u[np.array(g["sample_cells"]), np.array(g["sample_levels"])], u
+
+
+def test_config3_fp64_against_oracle(config3):
+    """FP64 solve: the oracle's iteration count and residual history (1e-6
+    relative), sampled solution and one V-cycle of the right-hand side
+    within 1e-10 of the oracle's (relative to the largest sample)."""
+    w, h, f = config3
+    g = _gold(w)
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=False, use_graph=True, autotune=1)
+    fd = P.pack(f)
+    z = P.device_vector()
+    P.vcycle(fd, z)
+    P.synchronize()
+    zs, zf = _samples(P, z, g)
+    zref = np.array(g["vcycle_samples"])
+    zerr = np.max(np.abs(zs - zref)) / np.max(np.abs(zref))
+    u = P.device_vector()
+    st, iters, relres, hist, ms = P.solve(fd, u, rtol=1e-8, maxit=100)
+    xs, xf = _samples(P, u, g)
+    xref = np.array(g["fp64"]["x_samples"])
+    xerr = np.max(np.abs(xs - xref)) / np.max(np.abs(xref))
+    print(f"config 3 {w.name} FP64: {iters} iterations (oracle {g['fp64']['iters']}), sampled solution rel diff "
+          f"{xerr:.2e}, V-cycle {zerr:.2e}, norms {abs(np.linalg.norm(xf) / g['fp64']['x_norm'] - 1):.2e} / "
+          f"{abs(np.linalg.norm(zf) / g['vcycle_norm'] - 1):.2e}")
+    assert st == T.TPMG_OK and iters == g["fp64"]["iters"]
+    assert np.allclose(hist, g["fp64"]["history"], rtol=1e-6, atol=0)
+    assert zerr <= 1e-10 and xerr <= 1e-10
+    P.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_config3_vcycle_rate_against_oracle(config3, fp32):
+    """V-cycle convergence factor in the Richardson iteration (f = 0, seed 7,
+    12 cycles, rate over the last 8): FP64 within 1e-8 relative of the
+    oracle's; FP32 against the oracle's own FP32 V-cycle within the bar of
+    the mixed-rate reading (absolute 0.05: two FP32 roundings of the same
+    cycle differ by a perturbation of relative size ~1e-6 per cycle, which
+    moves a factor by far less; 0.05 leaves room for the slow components
+    on which FP32 V-cycles differ most)."""
+    w, h, f = config3
+    g = _gold(w)
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=fp32, use_graph=False, autotune=1)
+    u0 = P.pack(synth.uniform_noise(w.n, w.nz, g["rate_seed"]))
+    rate, _ = T.tpmg_richardson_rate(P.mg, u0, *g["rate_cycles"])
+    ref = g["mixed" if fp32 else "fp64"]["vcycle_rate"]
+    print(f"config 3 {w.name} {'FP32' if fp32 else 'FP64'} V-cycle rate: GPU {rate:.6f}, oracle {ref:.6f}")
+    if fp32:
+        assert rate < 1.0 and abs(rate - ref) <= 0.05
+    else:
+        assert abs(rate - ref) <= 1e-8 * ref
+    P.close()
+
+
+def test_config3_mixed_iterations_against_oracle(config3):
+    w, h, f = config3
+    g = _gold(w)
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True, autotune=1)
+    u = P.device_vector()
+    st, iters, relres, hist, ms = P.solve(P.pack(f), u, rtol=1e-8, maxit=100)
+    print(f"config 3 {w.name} mixed: {iters} iterations (oracle FP32 V-cycle {g['mixed']['iters']})")
+    assert st == T.TPMG_OK and abs(iters - g["mixed"]["iters"]) <= 1
+    P.close()
 
 
 def _residual_and_floor(h, f, u):

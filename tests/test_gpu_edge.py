@@ -1,0 +1,92 @@
+"""Degenerate shapes of the method, against the oracle (FP64: solution and
+V-cycle within 1e-10, identical iteration counts; operator within 1e-12):
+
+  * nz = 1: one layer, no radial faces inside the column (sigma_0 =
+    sigma_nz = 0), so the operator has no vertical coupling and the line
+    smoother is point block-Jacobi on a 2-D problem (the j = 1 case of the
+    tensor decoupling, Section 3.2.1);
+  * one multigrid level: the V-cycle is the coarse solve alone, one damped
+    sweep from zero (Algorithm 1 on the coarsest grid);
+  * refinement 0: the 20 cells of the icosahedron in one padded tile of 64
+    columns, one level.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1408_2981_amd as T  # noqa: E402
+import synth  # noqa: E402
+from oracle import operator as opm, tpmg as otpmg  # noqa: E402
+
+CASES = {
+    # name: (refinement, nz, n_levels, seed, random profiles, refinement whose
+    # spacing sets omega: the grid itself, or for the one-level case a grid
+    # three refinements finer, so that this grid is the mass-dominated
+    # coarsest level of a four-level hierarchy, Section 4.2)
+    "nz1_ref3": (3, 1, 0, 21, True, 3),
+    "nz1_ref4_unit": (4, 1, 0, 22, False, 4),
+    "one_level_ref3_nz16": (3, 16, 1, 23, True, 6),
+    "ref0_nz8": (0, 8, 0, 24, True, 1),
+    "ref0_nz1": (0, 1, 0, 25, False, 1),
+}
+
+
+def _make(case, **setup):
+    ref, nz, nlev, seed, rand, ref_omega = CASES[case]
+    r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+    om2 = synth.omega_for(ref_omega) ** 2
+    prof = synth.profiles_random(nz, synth.n_cells(ref), seed=seed + 100) if rand else None
+    h = otpmg.build(ref, r, om2, profiles=prof, n_levels=nlev)
+    P = T.Problem(ref, r, om2, profiles=prof, n_levels=nlev).setup(**setup)
+    fine = h.meshes[-1]
+    f = synth.cell_integral(synth.uniform_noise(fine.n, nz, seed), fine.area, h.vert.vk)
+    return h, P, f
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_edge_operator_vcycle_solve(case):
+    h, P, f = _make(case)
+    assert P.n_levels == len(h.ops)
+    x = np.random.default_rng(5).standard_normal(f.shape)
+    y = P.device_vector()
+    P.spmv(P.pack(x), y)
+    P.synchronize()
+    ref_ax = opm.apply(h.finest, x)
+    assert np.max(np.abs(P.unpack(y) - ref_ax)) <= 1e-12 * np.max(np.abs(ref_ax))
+    z = P.device_vector()
+    P.vcycle(P.pack(f), z)
+    P.synchronize()
+    zv = otpmg.vcycle(h, f)
+    assert _rel(P.unpack(z), zv) <= 1e-10
+    ref = otpmg.solve(h, f, rtol=1e-8, maxit=200)
+    u = P.device_vector()
+    st, iters, relres, hist, _ = P.solve(P.pack(f), u, rtol=1e-8, maxit=200)
+    err = _rel(P.unpack(u), ref.x)
+    print(f"{case}: {iters} iterations (oracle {ref.iters}), solution rel diff {err:.2e}")
+    assert st == T.TPMG_OK and iters == ref.iters
+    assert np.allclose(hist, ref.history, rtol=1e-6, atol=0)
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["nz1_ref3", "one_level_ref3_nz16", "ref0_nz8"])
+def test_edge_mixed_solve(case):
+    """The mixed path on the same shapes: converges to the stopping
+    tolerance, and its solution stays within the FP32 bar of the oracle's
+    tight FP64 solve once solved to rtol 1e-11."""
+    h, P, f = _make(case, precond_fp32=True)
+    tight = otpmg.solve(h, f, rtol=1e-13, maxit=400)
+    u = P.device_vector()
+    st, iters, relres, hist, _ = P.solve(P.pack(f), u, rtol=1e-11, maxit=400)
+    err = _rel(P.unpack(u), tight.x)
+    print(f"{case} mixed: {iters} iterations, relres {relres:.2e}, error vs tight FP64 solve {err:.2e}")
+    assert st == T.TPMG_OK and relres <= 1e-11
+    assert err <= 1e-6

@@ -316,3 +316,49 @@ def test_learned_guess_saves_iterations():
     print(f"t=41..50: initial residual / |f|: network {np.mean(q_raw):.2e}, with relaxation {np.mean(q_rel):.2e}")
     print(f"iterations: zero guess {zero_it}, network {raw_it}, network + relaxation {mlp_it}")
     assert all(b < a for a, b in zip(zero_it, mlp_it))
+
+
+def test_features_and_inference_at_sequence_shape():
+    """The learned guess at the sequence workload's own shape (icosahedral
+    refinement 6 x 64 quadratic levels, 81,920 columns, hidden width 256,
+    the one-kernel inference): features of every column against the
+    oracle's (1e-6 relative), and the network's output on 2,048 seeded
+    sample columns against the oracle's forward pass on the same columns
+    (bars of the module header)."""
+    w = synth.workload("ico6_nz64_seq")
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True)
+    h = otpmg.build(w.refinement, w.r_faces(), w.omega2)
+    fine = h.meshes[-1]
+    f = synth.sequence_rhs(w, fine.centre, fine.area, h.vert.vk, 160)
+    net = T.ColumnMLP(w.nz, 256, P.n, stream=P.stream)
+    p = omlp.init_params(w.nz + 3, 256, w.nz, 17)
+    rng = np.random.default_rng(18)
+    for k in ("b1", "b2", "b3"):
+        p[k] = omlp.fp32(rng.standard_normal(p[k].shape) * 0.05)
+    net.set_params(omlp.pack(p).astype(np.float32))
+    fd = P.pack(f)
+    x = net.features(P, fd)
+    net.synchronize()
+    xo = omlp.features(f, fine.nbr)
+    xg = x.cpu().numpy()
+    assert xg.shape == xo.shape == (fine.n, w.nz + 3)
+    assert np.all(np.abs(xg - xo) <= 1e-6 * np.abs(xo) + 1e-30)
+    yo_raw = np.random.default_rng(19).standard_normal((P.n, w.nz)) * 1e-3
+    s = omlp.fit_scaling(xo, yo_raw)
+    net.set_scaling(s.mu_x, s.sd_x, s.mu_y, s.sd_y)
+    s32 = _oracle_scaling(net)
+    u0 = P.device_vector()
+    net.infer(P, fd, u0, relax=0)
+    net.synchronize()
+    got = P.unpack(u0)
+    cols = np.sort(np.random.default_rng(20).choice(fine.n, 2048, replace=False))
+    yo, _ = omlp.forward(p, omlp.standardise_x(s32, xo[cols]), act_bf16=True)
+    ref = yo * s32.sd_y + s32.mu_y
+    scale = np.sqrt(np.mean((ref - s32.mu_y) ** 2))
+    d = got[cols] - ref
+    print(f"sequence shape: features max rel diff {np.max(np.abs(xg - xo) / (np.abs(xo) + 1e-300)):.2e}; "
+          f"inference rms diff {np.sqrt(np.mean(d ** 2)) / scale:.2e}, max {np.max(np.abs(d)) / np.max(np.abs(ref - s32.mu_y)):.2e}")
+    assert np.sqrt(np.mean(d ** 2)) <= 1e-3 * scale
+    assert np.max(np.abs(d)) <= 1e-2 * np.max(np.abs(ref - s32.mu_y))
+    net.close()
+    P.close()
