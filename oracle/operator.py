@@ -115,6 +115,44 @@ def restrict_cell_factor(fine_values: np.ndarray, fine_area: np.ndarray) -> np.n
     return w / fine_area.reshape(-1, 4).sum(axis=1)
 
 
+@dataclass
+class FullProfiles:
+    """Point samples of profiles that need not factorise (Section 4.2: the
+    non-factorising case; Appendix A, eq. hatFunctionsNonFac), one value per
+    cell and level of a grid, cell-major:
+      alpha_r [n, nz+1] at the radial faces (r_k, centre of T),
+      alpha_s [n, nz]   at the layer midpoints (r_{k+1/2}, centre of T),
+      beta    [n, nz]   at the layer midpoints (r_{k+1/2}, centre of T)."""
+
+    alpha_r: np.ndarray
+    alpha_s: np.ndarray
+    beta: np.ndarray
+
+
+def restrict_cell_profile(fine_values: np.ndarray, fine_area: np.ndarray) -> np.ndarray:
+    """Area-weighted mean of the four children 4P..4P+3 of every column
+    entry of a per-cell profile [n, m] (the coarse-grid reading of the
+    factorised case, applied level by level)."""
+    n, m = fine_values.shape
+    w = (fine_values * fine_area[:, None]).reshape(n // 4, 4, m).sum(axis=1)
+    return w / fine_area.reshape(-1, 4).sum(axis=1)[:, None]
+
+
+def assemble_full(mesh: Mesh, vert: Vertical, omega2: float, alpha_r: np.ndarray, alpha_s: np.ndarray,
+                  beta: np.ndarray) -> LevelOperator:
+    """Coefficients of eq. hatFunctionsNonFac from point samples of profiles
+    that need not factorise (FullProfiles layout on this mesh). As in the
+    factorised case, the horizontal profile on an edge is the mean of its two
+    cells' values (here level by level)."""
+    n, nz = mesh.n, vert.nz
+    assert alpha_r.shape == (n, nz + 1) and alpha_s.shape == (n, nz) and beta.shape == (n, nz)
+    edge = 0.5 * (alpha_s[:, None, :] + alpha_s[mesh.nbr])                    # [n, 3, nz]
+    beta_hat = mesh.area[:, None] * vert.vk[None, :] * beta
+    alpha_s_hat = omega2 * vert.dr[None, None, :] * mesh.g[:, :, None] * edge
+    alpha_r_hat = omega2 * vert.face_factor[None, :] * mesh.area[:, None] * alpha_r
+    return LevelOperator(mesh.nbr, beta_hat, alpha_s_hat, alpha_r_hat)
+
+
 def apply(op: LevelOperator, u: np.ndarray) -> np.ndarray:
     """y = A u in flux form; u is [n, nz] (cell-major)."""
     y = op.beta * u

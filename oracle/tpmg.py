@@ -167,14 +167,25 @@ class Hierarchy:
                          self.meshes, self.vert, self.nu_pre, self.nu_post, self.nu_coarse, self.omega, dtype)
 
 
+FULL_TERMS = ("alpha_r", "alpha_s", "beta")
+
+
 def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0,
-          meshes: list | None = None, vert: opmod.Vertical | None = None) -> Hierarchy:
+          meshes: list | None = None, vert: opmod.Vertical | None = None,
+          full: opmod.FullProfiles | None = None, full_terms=FULL_TERMS) -> Hierarchy:
     """Meshes, coefficients and transfer weights for TPMG on refinement `refinement`.
 
     profiles: object with alpha_r_v, alpha_s_v, beta_v and optional per-cell
     finest-grid alpha_r_h, alpha_s_h, beta_h (None = 1). vert replaces the
     radial factors derived from r_faces (used to pose the 2-D problems of the
     tensor decoupling).
+
+    full: profiles that need not factorise, sampled on the finest grid
+    (Section 4.2). The coefficients named in full_terms are then taken from
+    them on every level (coarse grids: area-weighted means of the four
+    children, level by level), the others from the factorised `profiles`:
+    all three terms give the operator of TPMG^(full), alpha_r alone that of
+    TPMG^(partial) (Section 5.3), none (full = None) that of TPMG^(x).
     """
     if n_levels <= 0:
         n_levels = min(6, refinement + 1)
@@ -198,10 +209,26 @@ def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int 
     for ref in range(refinement, levels[0], -1):
         fine_area = meshes[ref].area
         per_level[ref - 1] = [opmod.restrict_cell_factor(x, fine_area) for x in per_level[ref]]
+    full_level = {}
+    if full is not None and full_terms:
+        full_level[refinement] = {k: np.asarray(getattr(full, k), dtype=np.float64) for k in full_terms}
+        for ref in range(refinement, levels[0], -1):
+            full_level[ref - 1] = {k: opmod.restrict_cell_profile(v, meshes[ref].area)
+                                   for k, v in full_level[ref].items()}
     ops, weights, used = [], [None], []
     for ref in levels:
         ar, as_, b = per_level[ref]
-        ops.append(opmod.assemble(meshes[ref], vert, omega2, ar_v, as_v, b_v, ar, as_, b))
+        op = opmod.assemble(meshes[ref], vert, omega2, ar_v, as_v, b_v, ar, as_, b)
+        if ref in full_level:
+            fl = full_level[ref]
+            n = meshes[ref].n
+            # the factorised samples of the other terms, as [n, *] arrays
+            fac = {"alpha_r": ar[:, None] * np.asarray(ar_v)[None, :], "alpha_s": as_[:, None] * np.asarray(as_v)[None, :],
+                   "beta": b[:, None] * np.asarray(b_v)[None, :]}
+            fac.update(fl)
+            assert fac["alpha_r"].shape == (n, nz + 1)
+            op = opmod.assemble_full(meshes[ref], vert, omega2, fac["alpha_r"], fac["alpha_s"], fac["beta"])
+        ops.append(op)
         used.append(meshes[ref])
     for i in range(1, len(levels)):
         weights.append(prolongation_weights(used[i - 1], used[i]))
@@ -292,15 +319,20 @@ def fcg(apply_a, precond, f: np.ndarray, x0: np.ndarray | None = None, rtol: flo
     return SolveResult(x, maxit, "maxit", hist)
 
 
-def solve(h: Hierarchy, f: np.ndarray, x0=None, rtol=1e-8, maxit=100, precision="fp64") -> SolveResult:
-    """TPMG-preconditioned FCG on the finest level of h."""
-    op = h.finest
+def solve(h: Hierarchy, f: np.ndarray, x0=None, rtol=1e-8, maxit=100, precision="fp64",
+          outer: opmod.LevelOperator | None = None) -> SolveResult:
+    """TPMG-preconditioned FCG on the finest level of h. outer: the operator
+    of the equation when it differs from the one the V-cycle is built on
+    (TPMG^(x) or TPMG^(partial) for non-factorising profiles, Section 3.2.2)."""
+    op = h.finest if outer is None else outer
     return fcg(lambda v: opmod.apply(op, v), make_preconditioner(h, precision), f, x0, rtol, maxit)
 
 
-def richardson_rate(h: Hierarchy, seed: int = 7, cycles: int = 12, skip: int = 4, precision="fp64") -> float:
-    """Asymptotic V-cycle factor of u <- u + M(f - A u) with f = 0."""
-    op = h.finest
+def richardson_rate(h: Hierarchy, seed: int = 7, cycles: int = 12, skip: int = 4, precision="fp64",
+                    outer: opmod.LevelOperator | None = None) -> float:
+    """Asymptotic V-cycle factor of u <- u + M(f - A u) with f = 0 (A: the
+    finest operator of h, or `outer`, Section 3.2.2)."""
+    op = h.finest if outer is None else outer
     m = make_preconditioner(h, precision)
     u = np.random.default_rng(seed).uniform(-1.0, 1.0, size=(op.n, op.nz))
     norms = []

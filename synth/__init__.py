@@ -111,6 +111,110 @@ def profiles_random(nz: int, n_fine: int, seed: int, tie_beta_to_alpha_r: bool =
 
 
 # ---------------------------------------------------------------------------
+# balanced zonal flow (Section 5.2): profiles that do not factorise
+# ---------------------------------------------------------------------------
+
+# physical constants of the balanced-flow profiles (SI units); g, c_p and R_d
+# are not printed in the paper and take their usual values
+GRAVITY = 9.81
+C_P = 1005.0
+R_DRY = 287.0
+T_0 = 273.0
+P_0 = 1.0e4
+OMEGA_EARTH = 2.0 * np.pi / (24.0 * 3600.0)
+JET_U0, JET_LAT, JET_SIGMA = 100.0, np.pi / 4.0, 0.1
+
+
+def buoyancy_reference() -> float:
+    """N* = g / sqrt(c_p T_0), the buoyancy frequency at which the balanced
+    flow's profiles factorise exactly (0.01873 1/s)."""
+    return GRAVITY / np.sqrt(C_P * T_0)
+
+
+def jet_function(lat: np.ndarray) -> np.ndarray:
+    """F(lat) with dF/dlat = 2 R Omega u(lat) sin(lat) + u(lat)^2 tan(lat),
+    F(0) = 0, for the two-jet zonal wind u(lat) = u0 cos(lat)/cos(lat_M)
+    exp(-(cos(lat) - cos(lat_M))^2 / (2 sigma^2)); integrated on a fine grid
+    (composite Simpson, 20,001 points on [0, pi/2]) and interpolated. F is
+    even in lat."""
+    grid = np.linspace(0.0, np.pi / 2, 20001)
+    c, sn = np.cos(grid), np.sin(grid)
+    u = JET_U0 * c / np.cos(JET_LAT) * np.exp(-((c - np.cos(JET_LAT)) ** 2) / (2 * JET_SIGMA ** 2))
+    # u^2 tan = u * (u / cos) * sin, finite at the pole (u ~ cos)
+    u_over_c = JET_U0 / np.cos(JET_LAT) * np.exp(-((c - np.cos(JET_LAT)) ** 2) / (2 * JET_SIGMA ** 2))
+    dF = 2.0 * R_EARTH_M * OMEGA_EARTH * u * sn + u * u_over_c * sn
+    h = grid[1] - grid[0]
+    F = np.zeros_like(grid)
+    # Simpson on pairs of intervals, trapezoid for the odd point in between
+    F[2::2] = np.cumsum(h / 3.0 * (dF[0:-2:2] + 4 * dF[1:-1:2] + dF[2::2]))
+    F[1::2] = F[0:-1:2] + 0.5 * h * (dF[0:-1:2] + dF[1::2])
+    return np.interp(np.abs(lat), grid, F)
+
+
+@dataclass
+class BalancedFlow:
+    """Profiles of the balanced zonal flow with constant buoyancy frequency N
+    (Section 5.2, eqs. BalancedFlow, JetFunction, VelocityField) and their
+    approximate factorisation pi ~ pi^r(r) pi^S(lat) (eq. FacApproxBalancedFlow),
+    sampled at the points the discretisation uses (Appendix A): alpha_r at the
+    radial faces (r_k, centre), alpha_S and beta at the layer midpoints
+    (r_{k+1/2}, centre). Background fields are scaled by T_0 and p_0/(R_d T_0):
+    theta = 1/(E_h E_v), rho = pi^gamma E_h E_v, with E_h = exp(-N^2 F/g^2),
+    E_v = exp(-N^2 R (r-1)/g), pi = (eps + E_h E_v)/(1 + eps),
+    eps = (N/N*)^2 - 1; profiles (eq. profiles) alpha_S = rho theta,
+    alpha_r = r^2 Lambda rho theta, beta = gamma rho/pi, xi_r = Lambda rho d_r theta
+    (d_r in the radial unit, Earth radii), Lambda = 1/(1 + dt^2 N^2) with
+    dt = omega R / c_h, c_h = sqrt(c_p T_0), gamma = (1 - kappa)/kappa,
+    kappa = R_d/c_p."""
+
+    alpha_r: np.ndarray        # [n, nz+1]
+    alpha_s: np.ndarray        # [n, nz]
+    beta: np.ndarray           # [n, nz]
+    xi_r: np.ndarray           # [n, nz+1] (vertical advection, at the faces)
+    factorised: Profiles       # the approximate factorisation's factors
+    eps: float
+    lam: float
+
+
+def balanced_flow(eps: float, centres: np.ndarray, r_faces: np.ndarray, omega: float) -> BalancedFlow:
+    r = np.asarray(r_faces, dtype=np.float64)
+    rm = 0.5 * (r[:-1] + r[1:])
+    lat, _ = _latlon(centres)
+    n_star = buoyancy_reference()
+    nb = n_star * np.sqrt(1.0 + eps)
+    kappa = R_DRY / C_P
+    gam = (1.0 - kappa) / kappa
+    dt = omega * R_EARTH_M / np.sqrt(C_P * T_0)
+    lam = 1.0 / (1.0 + (dt * nb) ** 2)
+    e_h = np.exp(-(nb ** 2) / GRAVITY ** 2 * jet_function(lat))          # [n]
+
+    def fields(rr):
+        e_v = np.exp(-(nb ** 2) * R_EARTH_M / GRAVITY * (rr - 1.0))      # [m]
+        eh, ev = e_h[:, None], e_v[None, :]
+        pi = (eps + eh * ev) / (1.0 + eps)
+        rho = pi ** gam * eh * ev
+        theta = 1.0 / (eh * ev)
+        # d_r theta = theta N^2 R / g (E_v' / E_v = -N^2 R / g)
+        dtheta = theta * (nb ** 2) * R_EARTH_M / GRAVITY
+        return pi, rho, theta, dtheta, e_v
+
+    pi_m, rho_m, th_m, _, ev_m = fields(rm)
+    pi_f, rho_f, th_f, dth_f, ev_f = fields(r)
+    alpha_s = rho_m * th_m
+    beta = gam * rho_m / pi_m
+    alpha_r = (r ** 2)[None, :] * lam * rho_f * th_f
+    xi_r = lam * rho_f * dth_f
+    # factorisation: pi^x = pi^r(r) pi^S(lat), pi^r = (eps + E_v)/(1 + eps),
+    # pi^S = E_h; the profiles of pi^x split into radial and horizontal factors
+    pr_m = (eps + ev_m) / (1.0 + eps)
+    pr_f = (eps + ev_f) / (1.0 + eps)
+    fac = Profiles(alpha_r_v=r ** 2 * lam * pr_f ** gam, alpha_s_v=pr_m ** gam,
+                   beta_v=gam * pr_m ** (gam - 1.0) * ev_m,
+                   alpha_r_h=e_h ** gam, alpha_s_h=e_h ** gam, beta_h=e_h ** gam)
+    return BalancedFlow(alpha_r, alpha_s, beta, xi_r, fac, eps, lam)
+
+
+# ---------------------------------------------------------------------------
 # right-hand sides
 # ---------------------------------------------------------------------------
 
