@@ -110,3 +110,61 @@ def test_batch_rejects_mixed_parameters():
     with pytest.raises(T.TpmgError) as e:
         T.tpmg_batch_workspace_size([a[0][0].mg, b[0][0].mg])
     assert e.value.status == T.TPMG_ERR_ARG
+
+
+def test_batch16_at_its_own_shape():
+    """The sixteen-problem batch at its own shape (refinements 4, 5, 6 x nz
+    32, 64, 128, quadratic grading, seeded uniform right-hand sides,
+    35,061,760 unknowns, mixed precision, autotuned scan smoothers, as the
+    batch report runs it): bitwise equal to the sixteen single solves, and
+    for one problem of each (refinement, nz) pair the oracle's results
+    stored in tests/golden/batch16_oracle.json by
+    tests/golden/make_batch16.py: iteration count within one of the
+    oracle's mixed solve, sampled solution within the mixed bar of the
+    oracle's FP64 solution (1e-6 of the largest sample, or ten times the
+    oracle's own mixed-vs-FP64 distance where that is larger)."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch16_oracle.json")))
+    stream = torch.cuda.Stream()
+    ws = synth.batch_list()
+    probs, fs = [], []
+    for w in ws:
+        P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True, stream=stream,
+                                                                 smoother=T.SMOOTHER_SCAN, autotune=1)
+        geo = P.geometry()
+        fs.append(P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk())))
+        probs.append(P)
+    singles = []
+    for P, fd in zip(probs, fs):
+        u = P.device_vector()
+        st, iters, *_ = P.solve(fd, u, rtol=1e-8, maxit=100)
+        assert st == T.TPMG_OK
+        singles.append((iters, u))
+    mgs = [P.mg for P in probs]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    wsp = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, wsp.data_ptr() + (-wsp.data_ptr()) % 256, nbytes)
+    us = [P.device_vector() for P in probs]
+    st, per, ms = T.tpmg_batch_solve(batch, fs, us, 1e-8, 100)
+    assert st == T.TPMG_OK
+    for i, ((it_b, _, _), (it_s, u_s), u_b) in enumerate(zip(per, singles, us)):
+        assert it_b == it_s, i
+        assert torch.equal(u_b, u_s), i
+    for pg in g["problems"]:
+        i = pg["index"]
+        P = probs[i]
+        assert (P.refinement, P.nz) == (pg["refinement"], pg["nz"])
+        x = P.unpack(us[i])[np.array(pg["sample_cells"]), np.array(pg["sample_levels"])]
+        ref = np.array(pg["fp64_x_samples"])
+        err = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
+        bar = max(1e-6, 10 * pg["mixed_vs_fp64"])
+        print(f"batch problem {i} (refinement {P.refinement}, nz {P.nz}): {per[i][0]} iterations (oracle mixed "
+              f"{pg['mixed_iters']}), sampled solution vs oracle FP64 {err:.2e} (bar {bar:.1e})")
+        assert abs(per[i][0] - pg["mixed_iters"]) <= 1
+        assert err <= bar
+    T.tpmg_batch_destroy(batch)
+    for P in probs:
+        P.close()
