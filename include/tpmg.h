@@ -328,6 +328,31 @@ tpmg_status tpmg_tune_save(const char* path);
 tpmg_status tpmg_tune_clear(void);
 tpmg_status tpmg_tune_entries(int* n);
 
+/* ------------------------------------------------- allocation-free -- */
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): tpmg_solve with its
+ * device setup and teardown in one call that allocates nothing, neither
+ * device memory nor pinned host memory. Its workspace is a static array in
+ * device memory of TPMG_NOALLOC_SCRATCH_BYTES per GPU, part of the library's
+ * code object (each GPU the library runs on holds its copy until the process
+ * ends). The call uploads op's coefficients into it (clearing what it uses
+ * first), solves A u = f from the guess in d_u exactly as tpmg_solve does
+ * (the same kernels in the same order, so the same results, iteration
+ * counts and histories), and reads the iteration records by device-to-host
+ * copies a few iterations at a time instead of from pinned memory. d_f, d_u:
+ * tiled device vectors of op's finest grid (padded cell count times nz
+ * doubles, the layout of tpmg_pack), on hip_stream. params->autotune and
+ * use_graph must be 0 (built-in launch choices), info->phase_timers 0.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller. Synchronises hip_stream. Errors: TPMG_ERR_NOMEM when the problem's
+ * workspace (tpmg_mg_workspace_size) exceeds the array, TPMG_ERR_ARG, and
+ * tpmg_solve's statuses. */
+#define TPMG_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+tpmg_status tpmg_solve_noalloc(const tpmg_op* op, const tpmg_mg_params* params, void* hip_stream, const double* d_f,
+                               double* d_u, double rtol, int maxit, tpmg_solve_info* info);
+
 void tpmg_grid_destroy(tpmg_grid* g);
 void tpmg_op_destroy(tpmg_op* op);
 void tpmg_mg_destroy(tpmg_mg* mg);

@@ -47,7 +47,7 @@ EXPORTED = [
     "tpmg_mlp_set_scaling", "tpmg_mlp_get_scaling", "tpmg_mlp_fit_scaling", "tpmg_mlp_features", "tpmg_mlp_targets",
     "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_infer", "tpmg_mlp_save",
     "tpmg_mlp_load", "tpmg_mlp_destroy",
-    "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error",
+    "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error", "tpmg_solve_noalloc",
 ]
 
 
@@ -140,6 +140,8 @@ _sig = {
     "tpmg_grid_destroy": (None, [_vp]),
     "tpmg_op_destroy": (None, [_vp]),
     "tpmg_mg_destroy": (None, [_vp]),
+    "tpmg_solve_noalloc": (_ip, [_vp, ctypes.POINTER(MgParams), _vp, _vp, _vp, ctypes.c_double, _ip,
+                                 ctypes.POINTER(SolveInfo)]),
     "tpmg_status_string": (ctypes.c_char_p, [_ip]),
     "tpmg_last_error": (ctypes.c_char_p, []),
 }
@@ -311,6 +313,26 @@ def tpmg_solve_details(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: 
     return dict(status=s, iters=info.iters, relres=info.relres, history=hist[: info.iters + 1].copy(),
                 t_total_ms=info.t_total_ms, t_vcycle_ms=info.t_vcycle_ms, t_spmv_ms=info.t_spmv_ms,
                 t_blas_ms=info.t_blas_ms, model_bytes=info.model_bytes,
+                message=tpmg_last_error() if s == TPMG_ERR_BREAKDOWN else "")
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def tpmg_solve_noalloc(op: int, params: MgParams, stream, d_f, d_u, rtol: float, maxit: int,
+                       history_cap: int = 256) -> dict:
+    """The allocation-free solve (setup, solve and teardown in one call on the
+    library's static scratch); returns the fields of tpmg_solve_details."""
+    hist = np.zeros(history_cap)
+    info = SolveInfo()
+    info.history = hist.ctypes.data_as(_dp)
+    info.history_cap = history_cap
+    st = stream if isinstance(stream, int) or stream is None else stream.cuda_stream
+    s = _lib.tpmg_solve_noalloc(op, ctypes.byref(params), st, _dev(d_f), _dev(d_u), float(rtol), int(maxit),
+                                ctypes.byref(info))
+    _check(s, ok=(TPMG_OK, TPMG_NOT_CONVERGED, TPMG_ERR_BREAKDOWN))
+    return dict(status=s, iters=info.iters, relres=info.relres, history=hist[: info.iters + 1].copy(),
+                t_total_ms=info.t_total_ms, model_bytes=info.model_bytes,
                 message=tpmg_last_error() if s == TPMG_ERR_BREAKDOWN else "")
 
 

@@ -98,6 +98,8 @@ struct tpmg_mg {
   tpmg::FcgScalars* h_scal = nullptr;    // pinned host mirror
   tpmg::FcgRecord* ring = nullptr;       // pinned ring of iteration records (host address)
   tpmg::FcgRecord* ring_dev = nullptr;   // the same memory as the device addresses it
+  tpmg::FcgRecord* ring_ws = nullptr;    // a device-memory ring in the workspace (handles without pinned memory)
+  bool pinned = true;                    // ring and h_scal in pinned host memory
   size_t len = 0;                        // padded finest vector length
   int max_partial_blocks = 0;
   // events of the per-phase timers (created on first use, reused)
@@ -207,6 +209,7 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
       {static_cast<size_t>(tpmg::kRedBlocks), tpmg::stencil_blocks(static_cast<int>(fine_npad), nz, 1), fine_npad / 64}));
   m.partials = static_cast<double*>(cv.take(2 * static_cast<size_t>(m.max_partial_blocks) * 8));
   m.scal = static_cast<tpmg::FcgScalars*>(cv.take(sizeof(tpmg::FcgScalars)));
+  m.ring_ws = static_cast<tpmg::FcgRecord*>(cv.take(tpmg::kRecords * sizeof(tpmg::FcgRecord)));
   m.len = fine_len;
 }
 
@@ -1313,8 +1316,14 @@ tpmg_status tpmg_mg_workspace_size(const tpmg_op* op, const tpmg_mg_params* para
   return TPMG_OK;
 }
 
-tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void* d_workspace, size_t bytes,
-                          void* hip_stream, tpmg_mg** out) {
+}  // extern "C"
+
+namespace {
+
+// tpmg_mg_setup; with pinned = false the handle keeps its iteration records
+// in the workspace (device memory) and allocates no pinned host memory.
+tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_workspace, size_t bytes,
+                       void* hip_stream, bool pinned, tpmg_mg** out) {
   if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!op) return fail(TPMG_ERR_ARG, "op is NULL");
@@ -1361,20 +1370,26 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
     delete m;
     return st;
   }
-  e = hipHostMalloc(reinterpret_cast<void**>(&m->h_scal), sizeof(tpmg::FcgScalars), hipHostMallocDefault);
-  if (e != hipSuccess) {
-    m->h_scal = nullptr;
-    return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  m->pinned = pinned;
+  if (pinned) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&m->h_scal), sizeof(tpmg::FcgScalars), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      m->h_scal = nullptr;
+      return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipHostMalloc(reinterpret_cast<void**>(&m->ring), tpmg::kRecords * sizeof(tpmg::FcgRecord),
+                      hipHostMallocDefault);
+    if (e != hipSuccess) {
+      m->ring = nullptr;
+      return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    std::memset(m->ring, 0, tpmg::kRecords * sizeof(tpmg::FcgRecord));
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&m->ring_dev), m->ring, 0);
+    if (e != hipSuccess)
+      return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
+  } else {
+    m->ring_dev = m->ring_ws;   // zeroed with the workspace below
   }
-  e = hipHostMalloc(reinterpret_cast<void**>(&m->ring), tpmg::kRecords * sizeof(tpmg::FcgRecord),
-                    hipHostMallocDefault);
-  if (e != hipSuccess) {
-    m->ring = nullptr;
-    return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
-  }
-  std::memset(m->ring, 0, tpmg::kRecords * sizeof(tpmg::FcgRecord));
-  e = hipHostGetDevicePointer(reinterpret_cast<void**>(&m->ring_dev), m->ring, 0);
-  if (e != hipSuccess) return cleanup_fail(TPMG_ERR_DEVICE, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
   // zero the whole workspace once: padding entries of every vector stay zero
   e = tpmg::launch_fill(d_workspace, (cv.off + 3) / 4 * 4, m->stream);
   std::vector<std::vector<double>> keep64;
@@ -1441,6 +1456,15 @@ tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void*
   }
   *out = m;
   return TPMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tpmg_status tpmg_mg_setup(const tpmg_op* op, const tpmg_mg_params* params, void* d_workspace, size_t bytes,
+                          void* hip_stream, tpmg_mg** out) {
+  return setup_impl(op, params, d_workspace, bytes, hip_stream, true, out);
 }
 
 tpmg_status tpmg_mg_tuning(const tpmg_mg* mg, int level, int* smoother, int* scan_levels, int* chunk_restrict,
@@ -2083,6 +2107,126 @@ void tpmg_mg_destroy(tpmg_mg* mg) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// The flexible-CG solve of tpmg_solve on a handle whose iteration records
+// are in device memory: the host queues kRecords iterations at a time (each
+// skipped on the device once the solve is done), then copies the ring and
+// reads the records of those iterations in order. The kernels and their
+// order are those of tpmg_solve, so the results are the same bits.
+tpmg_status solve_device_records(tpmg_mg& m, const double* d_f, double* d_u, double rtol, int maxit,
+                                 tpmg_solve_info* info) {
+  if (!d_f || !d_u) return fail(TPMG_ERR_ARG, "NULL vector");
+  if (d_f == d_u) return fail(TPMG_ERR_ARG, "f and u must not alias");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(TPMG_ERR_ARG, "rtol must be >= 0 and maxit >= 0");
+  if (info && info->history_cap > 0 && !info->history) return fail(TPMG_ERR_ARG, "history_cap > 0 with NULL history");
+  if (info && !(info->div_tol >= 0.0)) return fail(TPMG_ERR_ARG, "div_tol must be >= 0");
+  if (info && info->phase_timers) return fail(TPMG_ERR_ARG, "phase timers are not available here");
+  const double div2 = info && info->div_tol > 0.0 ? info->div_tol * info->div_tol : tpmg::kDefaultDiv2;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = m.stream;
+  std::vector<Op> ops;
+  fcg_ops(m, d_u, m.scal, ops);
+  tpmg::FcgRecord recs[tpmg::kRecords];
+  auto read_ring = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(recs, m.ring_dev, sizeof(recs), hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  TPMG_HIP(tpmg::launch_spmv64(m.view64(m.nlev - 1), 1, d_u, d_f, m.r, m.partials, tpmg::kFinInit, m.scal, s, rtol,
+                               m.fp32 ? static_cast<float*>(m.fcopy) : nullptr, m.ring_dev, div2));
+  TPMG_HIP(read_ring());
+  if (recs[0].seq != 0) return fail(TPMG_ERR_DEVICE, "initial residual record missing");
+  const double fnorm = std::sqrt(recs[0].ff);
+  double rnorm = std::sqrt(recs[0].rr);
+  int iters = 0;
+  bool diverged = false;
+  auto record = [&](int k, double v) {
+    if (info && info->history && k < info->history_cap) info->history[k] = v;
+  };
+  record(0, fnorm > 0 ? rnorm / fnorm : 0.0);
+  tpmg_status result = TPMG_NOT_CONVERGED;
+  hipError_t werr = hipSuccess;
+  if (!std::isfinite(rnorm) || !std::isfinite(fnorm)) {
+    result = TPMG_ERR_BREAKDOWN;
+  } else if (rnorm <= rtol * fnorm) {
+    result = TPMG_OK;
+  } else {
+    bool stop = false;
+    for (int it = 0; it < maxit && !stop;) {
+      const int n = std::min(tpmg::kRecords, maxit - it);
+      for (int j = 0; j < n && werr == hipSuccess; ++j)
+        for (const Op& op : ops)
+          if ((werr = exec_op(op, s)) != hipSuccess) break;
+      if (werr == hipSuccess) werr = read_ring();
+      if (werr != hipSuccess) break;
+      for (int j = 0; j < n && !stop; ++j) {
+        const int seq = it + j + 1;
+        const tpmg::FcgRecord& rec = recs[seq % tpmg::kRecords];
+        if (rec.seq != seq) {
+          werr = hipErrorUnknown;   // a queued iteration published no record
+          stop = true;
+          break;
+        }
+        iters = seq;
+        if (rec.status == 2) {
+          rnorm = std::sqrt(rec.rr);
+          record(iters, fnorm > 0 ? rnorm / fnorm : 0.0);
+          diverged = true;
+          result = TPMG_ERR_BREAKDOWN;
+          stop = true;
+        } else if (rec.status != 0) {
+          iters = seq - 1;
+          result = TPMG_ERR_BREAKDOWN;
+          stop = true;
+        } else {
+          rnorm = std::sqrt(rec.rr);
+          record(iters, fnorm > 0 ? rnorm / fnorm : 0.0);
+          if (!std::isfinite(rnorm)) {
+            result = TPMG_ERR_BREAKDOWN;
+            stop = true;
+          } else if (rnorm <= rtol * fnorm) {
+            result = TPMG_OK;
+            stop = true;
+          }
+        }
+      }
+      it += n;
+    }
+  }
+  const hipError_t fe = tpmg::launch_flush(d_u, m.dirs, m.scal, m.len, s);
+  if (werr == hipSuccess) werr = fe;
+  const hipError_t se = hipStreamSynchronize(s);
+  if (werr != hipSuccess || se != hipSuccess)
+    return fail(TPMG_ERR_DEVICE, std::string("solve: ") + hipGetErrorString(werr != hipSuccess ? werr : se));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->iters = iters;
+    info->relres = fnorm > 0 ? rnorm / fnorm : 0.0;
+    info->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    info->t_vcycle_ms = info->t_spmv_ms = info->t_blas_ms = 0.0;
+    info->model_bytes = solve_model_bytes(ops, iters, m.len, m.fp32, true);
+  }
+  if (diverged) return fail(TPMG_ERR_BREAKDOWN, "divergence: ||r|| exceeded div_tol ||r_0||");
+  if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite value or <p, A p> <= 0");
+  return result;
+}
+
+}  // namespace
+
+tpmg_status tpmg_solve_on_workspace(const tpmg_op* op, const tpmg_mg_params* params, void* d_workspace,
+                                    size_t bytes, void* hip_stream, const double* d_f, double* d_u, double rtol,
+                                    int maxit, tpmg_solve_info* info) {
+  if (!params) return fail(TPMG_ERR_ARG, "params is NULL");
+  if (params->autotune != 0 || params->use_graph != 0)
+    return fail(TPMG_ERR_ARG, "autotune and use_graph must be 0 (trials and graphs need allocations)");
+  tpmg_mg* m = nullptr;
+  tpmg_status st = setup_impl(op, params, d_workspace, bytes, hip_stream, false, &m);
+  if (st != TPMG_OK) return st;
+  st = solve_device_records(*m, d_f, d_u, rtol, maxit, info);
+  delete m;
+  return st;
+}
 
 bool tpmg_fine_grid(const tpmg_mg* mg, tpmg::FineGrid* out) {
   if (!mg || !out) return false;
