@@ -341,6 +341,65 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
     P.close()
 
 
+def profiles_report(refinement: int = 5, nz: int = 128, eps_list=(0.0, 0.25, 0.5, 0.75, 1.0, 1.23), steps: int = 3):
+    """Balanced zonal flow (Section 5.2; profiles from constant buoyancy
+    frequency N, eps = (N/N*)^2 - 1, approximate factorisation of the Exner
+    pressure) on icosahedral refinement `refinement` x nz quadratically
+    graded levels (refinement 5 x 128: the paper's 2.6 million unknowns),
+    seeded uniform right-hand side: for each eps, precision and V-cycle
+    kind (TPMG^(full), TPMG^(x), TPMG^(partial); the Krylov method always
+    uses the full operator) the FCG iterations to 1e-8, the V-cycle's
+    Richardson factor, the median solve time, time per iteration and the
+    V-cycle's device time per iteration (phase timers)."""
+    import numpy as np
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+    om = synth.omega_for(refinement)
+    base = T.Problem(refinement, r, om * om)
+    geo = base.geometry()
+    vk = base.vk()
+    base.close()
+    n = synth.n_cells(refinement)
+    f_host = synth.cell_integral(synth.uniform_noise(n, nz, 60), geo["areas"], vk)
+    u0_host = synth.uniform_noise(n, nz, 7)
+    modes = (("full", T.PRECOND_FULL), ("factorised", T.PRECOND_FACTORISED), ("partial", T.PRECOND_PARTIAL))
+    for eps in eps_list:
+        bf = synth.balanced_flow(eps, geo["centres"], r, om)
+        line = {"workload": f"balanced flow eps {eps}: icosahedral refinement {refinement} x nz {nz} quadratic, "
+                            f"{n * nz} unknowns, uniform RHS, rtol 1e-8", "eps": eps, "lambda": bf.lam}
+        for prec, fp32 in (("fp64", False), ("mixed", True)):
+            for name, code in modes:
+                P = T.Problem(refinement, r, om * om, profiles=bf.factorised, full=bf).setup(
+                    precond_fp32=fp32, use_graph=False, autotune=1, precond_profiles=code)
+                f = P.pack(f_host)
+                rate, _ = T.tpmg_richardson_rate(P.mg, P.pack(u0_host), 12, 4)
+                u = P.device_vector()
+                P.solve(f, u)
+                times = []
+                for _ in range(steps):
+                    u.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st, it, rr, _, _ = P.solve(f, u, maxit=200)
+                    times.append(time.perf_counter() - t0)
+                ms = 1000.0 * float(np.median(times))
+                u.zero_()
+                torch.cuda.synchronize()
+                d = T.tpmg_solve_details(P.mg, f, u, 1e-8, 200, phase_timers=True)
+                line[f"{prec}_{name}"] = {
+                    "status": int(st), "iters": it, "richardson_factor": rate, "ms_per_solve": ms,
+                    "ms_per_iter": ms / max(it, 1), "vcycle_ms_per_iter": d["t_vcycle_ms"] / max(d["iters"], 1),
+                    "model_GB_per_solve": d["model_bytes"] / 1e9}
+                P.close()
+                del P, f, u
+                torch.cuda.empty_cache()
+        print(json.dumps(line), flush=True)
+
+
 def batch_report(steps: int = 3):
     """Sixteen solves of uneven size (refinement 4/5/6 x nz 32/64/128,
     quadratic grading, seeded uniform right-hand sides, mixed precision):
@@ -428,6 +487,8 @@ def main():
                     help="1: replay each FCG iteration as one HIP graph; 0 (default): launch the iteration's "
                          "kernels one by one, which on this workload leaves no gap between iterations "
                          "(a graph launch costs ~8 us at each boundary)")
+    ap.add_argument("--profiles", action="store_true",
+                    help="only the balanced-flow report: TPMG with full, factorised and partial profiles over eps")
     ap.add_argument("--batch", action="store_true",
                     help="only the batched-solve report (16 problems of uneven size, batched and one by one)")
     ap.add_argument("--report", action="store_true",
@@ -468,6 +529,9 @@ def main():
         return
     if args.batch:
         batch_report()
+        return
+    if args.profiles:
+        profiles_report()
         return
     results = {}
     P64 = T.Problem(w.refinement, w.r_faces(), w.omega2)

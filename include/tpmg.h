@@ -84,7 +84,16 @@ typedef struct {
   int scan_levels;     /* levels per wave of the scan smoother: 4, 8, 16   */
   int stencil_chunk;   /* levels per wave of the transfer kernels and the
                           operator: 1 .. 256                              */
-  int reserved[1];
+  int precond_profiles; /* for an operator with profiles that do not
+                          factorise (tpmg_op_set_full_profiles), the
+                          operator the V-cycle is built on (Section 4.2,
+                          Section 5.3): 0 = the full profiles
+                          (TPMG^(full)); 1 = the factorised profiles given
+                          to tpmg_op_create, the approximate factorisation
+                          (TPMG^(x)); 2 = the full alpha_r with the
+                          factorised alpha_S and beta (TPMG^(partial)).
+                          The Krylov method always uses the full operator.
+                          1 and 2 need full profiles.                     */
 } tpmg_mg_params;
 
 /* Result of a solve. Inputs: history (optional, caller-owned, history_cap
@@ -157,6 +166,30 @@ tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk);
 tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
                            const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
                            const double* alpha_s_h, const double* beta_h, tpmg_op** out);
+
+/* Profiles that do not factorise (Section 4.2: the general case of
+ * Appendix A, eq. hatFunctionsNonFac, with the vertical advection dropped):
+ * point samples on the finest grid of g (the grid op was created on),
+ * cell-major: alpha_r [n][nz+1] at the radial faces (r_k, centre of T),
+ * alpha_s and beta [n][nz] at the layer midpoints (r_{k+1/2}, centre of T);
+ * all positive (alpha_r at the top and bottom faces is not used). The
+ * coefficients per (T, k) are formed on every level (coarse grids:
+ * area-weighted means of the four children's samples, level by level; on an
+ * edge the mean of its two cells, as in the factorised case). The operator
+ * of the equation then uses them (tpmg_spmv, the Krylov method of
+ * tpmg_solve); the factorised profiles given to tpmg_op_create stay as the
+ * approximate factorisation a V-cycle may be built on
+ * (tpmg_mg_params.precond_profiles). Host arrays, copied. Such operators run
+ * the scan smoother at 8 or 16 levels per wave and no batched solves.
+ * Errors: TPMG_ERR_ARG. */
+tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const double* alpha_r, const double* alpha_s,
+                                      const double* beta);
+
+/* The coefficients per (T, k) of level (0 = coarsest) of an operator with
+ * full profiles, cell-major: beta^_{T,k} [n][nz], alphaS^_{TT'_j,k}
+ * [n][3][nz] (coupling to neighbour j), alphar^_{T,k} [n][nz+1] (radial
+ * face k). Any output may be NULL. TPMG_ERR_STATE without full profiles. */
+tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta, double* alpha_s, double* alpha_r);
 
 /* Number of multigrid levels of op, and the cell count of level (0 =
  * coarsest). */
@@ -283,7 +316,10 @@ tpmg_status tpmg_mg_time_sweep(tpmg_mg* mg, int reps, double* avg_ms, double* mo
  *   2  q = A p (FP64, 16 B per unknown);
  *   3  residual + restriction from the finest grid (2.25 s B per unknown);
  *   4  prolongation + correction into the finest grid (2.25 s B).
- * The counts are per unknown of the padded finest grid. avg_ms: mean
+ * With coefficients per (T, k) (tpmg_op_set_full_profiles) the stencil
+ * kernels also read 5 values per unknown (beta^, three alphaS^, one radial
+ * face; 1 for the partial form): 0, 3 + 5 s (or + s) and the operators
+ * + 40 B. The counts are per unknown of the padded finest grid. avg_ms: mean
  * duration per launch; model_bytes: the algorithmic HBM bytes of one launch.
  * Kernel 1 overwrites the solver's scalars (the next solve resets them).
  * Synchronises the stream. Errors: TPMG_ERR_ARG (kernel 1 without a fused

@@ -38,7 +38,7 @@ TPMG_ERR_STATE = -5
 
 EXPORTED = [
     "tpmg_mg_params_default", "tpmg_grid_icosahedral", "tpmg_grid_level_size", "tpmg_grid_geometry",
-    "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
+    "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_set_full_profiles", "tpmg_op_coefficients_full", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
     "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
     "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
     "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_time_kernel", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
@@ -62,7 +62,7 @@ class MgParams(ctypes.Structure):
         ("n_levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
         ("nu_coarse", ctypes.c_int), ("omega_relax", ctypes.c_double), ("precond_fp32", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int), ("smoother", ctypes.c_int),
-        ("scan_levels", ctypes.c_int), ("stencil_chunk", ctypes.c_int), ("reserved", ctypes.c_int * 1),
+        ("scan_levels", ctypes.c_int), ("stencil_chunk", ctypes.c_int), ("precond_profiles", ctypes.c_int),
     ]
 
 
@@ -94,6 +94,8 @@ _sig = {
     "tpmg_grid_geometry": (_ip, [_vp, _ip, _dp, _dp, _i32p, _dp, _dp]),
     "tpmg_grid_vertical": (_ip, [_vp, _dp]),
     "tpmg_op_create": (_ip, [_vp, _ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.POINTER(_vp)]),
+    "tpmg_op_set_full_profiles": (_ip, [_vp, _vp, _dp, _dp, _dp]),
+    "tpmg_op_coefficients_full": (_ip, [_vp, _ip, _dp, _dp, _dp]),
     "tpmg_op_levels": (_ip, [_vp, ctypes.POINTER(_ip)]),
     "tpmg_op_level_size": (_ip, [_vp, _ip, ctypes.POINTER(_ip)]),
     "tpmg_op_coefficients": (_ip, [_vp, _ip, _dp, _dp, _dp, _dp, _dp, _dp]),
@@ -216,6 +218,22 @@ def tpmg_op_create(grid: int, n_levels: int, omega2: float, alpha_r_v, alpha_s_v
     h = _vp()
     _check(_lib.tpmg_op_create(grid, n_levels, float(omega2), *[_dptr(a) for a in arrs], ctypes.byref(h)))
     return h.value
+
+
+def tpmg_op_set_full_profiles(op: int, grid: int, alpha_r, alpha_s, beta) -> None:
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (alpha_r, alpha_s, beta)]
+    _check(_lib.tpmg_op_set_full_profiles(op, grid, *[_dptr(a) for a in arrs]))
+
+
+def tpmg_op_coefficients_full(op: int, level: int, nz: int) -> dict:
+    n = tpmg_op_level_size(op, level)
+    out = dict(beta=np.zeros((n, nz)), alpha_s=np.zeros((n, 3, nz)), alpha_r=np.zeros((n, nz + 1)))
+    _check(_lib.tpmg_op_coefficients_full(op, level, _dptr(out["beta"]), _dptr(out["alpha_s"]), _dptr(out["alpha_r"])))
+    return out
+
+
+# tpmg_mg_params.precond_profiles: the V-cycle of an operator with full profiles
+PRECOND_FULL, PRECOND_FACTORISED, PRECOND_PARTIAL = 0, 1, 2
 
 
 def tpmg_op_levels(op: int) -> int:

@@ -69,6 +69,17 @@ struct LevelView {
   // (fixed by the operator, factorised once at setup); nullptr: the scan
   // smoother forms the margins it needs itself
   const void* margin = nullptr;
+  // profiles that do not factorise (Section 4.2): pm = 0 factorised (the
+  // column scalars and vertical vectors above); 1 radial couplings per (T, k)
+  // from far, the rest factorised (TPMG^(partial)); 2 every coefficient per
+  // (T, k): fb (beta^, tiled like a vector), fas (alphaS^, three such planes,
+  // one per neighbour j), far (alphar^ at the nz + 1 radial faces, tiled with
+  // nz + 1 rows per tile). pm > 0 runs the scan smoother with 8 or 16 levels
+  // per wave only, and no batched kernels.
+  int pm = 0;
+  const void* fb = nullptr;
+  const void* far = nullptr;
+  const void* fas = nullptr;
   LevelTune tune;
 };
 

@@ -48,6 +48,11 @@ struct LevelCoeffs {
   std::vector<double> ar_h;     // n
   std::vector<double> as_h;     // 3n
   std::vector<double> pw;       // 3n prolongation weights from the next coarser level (empty on level 0)
+  // profiles that do not factorise (Operator::full; Appendix A, eq.
+  // hatFunctionsNonFac): the coefficients per (T, k), cell-major
+  std::vector<double> fb;       // n (nz):        beta^_{T,k}
+  std::vector<double> far;      // n (nz + 1):    alphar^_{T,k} on radial face k
+  std::vector<double> fas;      // n (3) (nz):    alphaS^_{TT'_j,k}
 };
 
 struct Operator {
@@ -58,11 +63,19 @@ struct Operator {
   std::vector<double> as_v;     // nz
   std::vector<double> ar_v;     // nz+1
   std::vector<LevelCoeffs> levels;  // 0 = coarsest
+  bool full = false;            // the levels also hold coefficients of profiles that do not factorise
 };
 
 // Assembles the operator on the n_levels finest grids of g.
 void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, const double* alpha_r_v,
                     const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
                     const double* alpha_s_h, const double* beta_h);
+
+// Adds the coefficients of profiles that do not factorise, point samples on
+// the finest grid (cell-major: alpha_r [n][nz+1] at the radial faces,
+// alpha_s and beta [n][nz] at the layer midpoints), to every level of op
+// (coarse grids: area-weighted means of the four children, level by level;
+// on an edge the mean of its two cells). Throws std::runtime_error.
+void build_full(Operator& op, const Grid& g, const double* alpha_r, const double* alpha_s, const double* beta);
 
 }  // namespace tpmg

@@ -44,6 +44,12 @@ struct Lv {
   const T* __restrict__ av;
   const T* __restrict__ arv;
   const T* __restrict__ margin;
+  // profiles that do not factorise (LevelView::pm > 0): per-(T, k)
+  // coefficients, tiled like the vectors (fas: three planes, one per
+  // neighbour; far: nz + 1 rows per tile, the radial faces)
+  const T* __restrict__ fb;
+  const T* __restrict__ far;
+  const T* __restrict__ fas;
 };
 
 template <typename T>
@@ -61,7 +67,10 @@ __host__ __device__ Lv<T> view(const LevelView& L) {
                static_cast<const T*>(L.beta_v),
                static_cast<const T*>(L.as_v),
                static_cast<const T*>(L.ar_v),
-               static_cast<const T*>(L.margin)};
+               static_cast<const T*>(L.margin),
+               static_cast<const T*>(L.fb),
+               static_cast<const T*>(L.far),
+               static_cast<const T*>(L.fas)};
 }
 
 // this block's index and the number of blocks of its problem's launch
@@ -86,6 +95,7 @@ struct Column {
   T bh, arh, a0, a1, a2;
   size_t base, b0, b1, b2;   // tile offsets of the column and its neighbours
   size_t hb;                 // tile offset of the column's halo slot
+  size_t abase;              // offset of the column in the (nz + 1)-row face arrays (full profiles)
   uint32_t code;             // where the wave finds each neighbour (see LevelView)
 };
 
@@ -102,6 +112,7 @@ __device__ __forceinline__ Column<T> load_column(const Lv<T>& L, int col) {
   c.b1 = tile_base(L.nbr[L.npad + col], L.nz);
   c.b2 = tile_base(L.nbr[2 * L.npad + col], L.nz);
   c.hb = tile_base(L.halo[col], L.nz);
+  c.abase = tile_base(col, L.nz + 1);
   c.code = static_cast<uint32_t>(L.code[col]);
   return c;
 }
@@ -132,18 +143,58 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 
 // The fused multiply-adds are written out, so the rounding of a row does not
 // depend on how a kernel's instance happens to be compiled.
-template <typename T>
+//
+// PM, the profile mode of the level (Section 4.2): 0 factorised (column
+// scalars times vertical vectors, eq. TridiagonalFactorising); 1 the radial
+// couplings per (T, k) and the rest factorised (the operator of
+// TPMG^(partial)); 2 every coefficient per (T, k) (eq.
+// TridiagonalNonFactorising).
+template <int PM = 0, typename T>
 __device__ __forceinline__ T row_flux(const Lv<T>& L, const Column<T>& c, int k, T um, T uc, T up, T n0, T n1, T n2) {
-  const T h = fma_t(c.a2, uc - n2, fma_t(c.a1, uc - n1, c.a0 * (uc - n0)));
-  const T v = fma_t(L.arv[k], uc - um, L.arv[k + 1] * (uc - up));
-  return fma_t(c.arh, v, fma_t(L.av[k], h, (c.bh * L.bv[k]) * uc));
+  if constexpr (PM == 0) {
+    const T h = fma_t(c.a2, uc - n2, fma_t(c.a1, uc - n1, c.a0 * (uc - n0)));
+    const T v = fma_t(L.arv[k], uc - um, L.arv[k + 1] * (uc - up));
+    return fma_t(c.arh, v, fma_t(L.av[k], h, (c.bh * L.bv[k]) * uc));
+  } else {
+    const size_t oa = c.abase + static_cast<size_t>(k) * kTile;
+    const T v = fma_t(L.far[oa], uc - um, L.far[oa + kTile] * (uc - up));
+    if constexpr (PM == 1) {
+      const T h = fma_t(c.a2, uc - n2, fma_t(c.a1, uc - n1, c.a0 * (uc - n0)));
+      return v + fma_t(L.av[k], h, (c.bh * L.bv[k]) * uc);
+    } else {
+      const size_t o = c.base + static_cast<size_t>(k) * kTile;
+      const size_t pl = static_cast<size_t>(L.npad) * L.nz;
+      const T h = fma_t(L.fas[2 * pl + o], uc - n2, fma_t(L.fas[pl + o], uc - n1, L.fas[o] * (uc - n0)));
+      return v + fma_t(L.fb[o], uc, h);
+    }
+  }
 }
 
-template <typename T>
+// Column excess e_k (mass plus horizontal couplings) and radial coupling
+// through face k of a column, in the level's profile mode.
+template <int PM, typename T>
+__device__ __forceinline__ T coef_excess(const Lv<T>& L, const Column<T>& c, T esum, int k) {
+  if constexpr (PM == 2) {
+    const size_t o = c.base + static_cast<size_t>(k) * kTile;
+    const size_t pl = static_cast<size_t>(L.npad) * L.nz;
+    return L.fb[o] + ((L.fas[o] + L.fas[pl + o]) + L.fas[2 * pl + o]);
+  } else {
+    return c.bh * L.bv[k] + esum * L.av[k];
+  }
+}
+template <int PM, typename T>
+__device__ __forceinline__ T coef_face(const Lv<T>& L, const Column<T>& c, int k) {
+  if constexpr (PM >= 1)
+    return L.far[c.abase + static_cast<size_t>(k) * kTile];
+  else
+    return c.arh * L.arv[k];
+}
+
+template <int PM = 0, typename T>
 __device__ __forceinline__ T apply_row(const Lv<T>& L, const Column<T>& c, const T* __restrict__ u, int k, T um,
                                        T uc, T up) {
   const size_t o = static_cast<size_t>(k) * kTile;
-  return row_flux(L, c, k, um, uc, up, u[c.b0 + o], u[c.b1 + o], u[c.b2 + o]);
+  return row_flux<PM>(L, c, k, um, uc, up, u[c.b0 + o], u[c.b1 + o], u[c.b2 + o]);
 }
 
 // Values of a column at levels k0-1 .. k0+CH and of its neighbours at
@@ -177,11 +228,12 @@ struct ChunkLoads {
     }
   }
   // (A u)_{k0+i} for k0 + i < nz
+  template <int PM = 0>
   __device__ __forceinline__ T row(const Lv<T>& L, const Column<T>& c, int k0, int i) const {
     const int k = k0 + i;
     const T um = k > 0 ? xv[i] : T(0);
     const T up = k + 1 < L.nz ? xv[i + 2] : T(0);
-    return row_flux(L, c, k, um, xv[i + 1], up, n0[i], n1[i], n2[i]);
+    return row_flux<PM>(L, c, k, um, xv[i + 1], up, n0[i], n1[i], n2[i]);
   }
 };
 
@@ -307,7 +359,7 @@ __device__ __forceinline__ void finalize_body(int site, const double* __restrict
 
 // MODE 0: y = A x, partials <x, y>. MODE 1: y = b - A x, partials <y, y>,
 // <b, b>.
-template <int MODE, int CH>
+template <int MODE, int CH, int PM = 0>
 __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, const double* __restrict__ x,
                                           const double* __restrict__ b, double* __restrict__ y,
                                           double* __restrict__ partials, GridPos g, float* __restrict__ y32 = nullptr) {
@@ -345,14 +397,15 @@ __device__ __forceinline__ void spmv_body(const Lv<double>& L, int chunk_rt, con
       }
 #pragma unroll
       for (int i = 0; i < CH; ++i)
-        if (k0 + i < k1) emit(k0 + i, ld.xv[i + 1], ld.row(L, c, k0, i), MODE == 1 ? bb[MODE == 1 ? i : 0] : 0.0);
+        if (k0 + i < k1)
+          emit(k0 + i, ld.xv[i + 1], ld.template row<PM>(L, c, k0, i), MODE == 1 ? bb[MODE == 1 ? i : 0] : 0.0);
     } else {
       double um = k0 > 0 ? x[c.base + static_cast<size_t>(k0 - 1) * kTile] : 0.0;
       double uc = x[c.base + static_cast<size_t>(k0) * kTile];
       for (int k = k0; k < k1; ++k) {
         const size_t o = c.base + static_cast<size_t>(k) * kTile;
         const double up = k + 1 < L.nz ? x[o + kTile] : 0.0;
-        emit(k, uc, apply_row(L, c, x, k, um, uc, up), MODE == 1 ? b[o] : 0.0);
+        emit(k, uc, apply_row<PM>(L, c, x, k, um, uc, up), MODE == 1 ? b[o] : 0.0);
         um = uc;
         uc = up;
       }
@@ -538,7 +591,7 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
 // s_0 = e_0, s_k = e_k + l_k s_{k-1} / (s_{k-1} + l_k), with
 // e_k = beta_h beta_v,k + (sum of the horizontal couplings) alpha_s,v,k and
 // l_k = alpha_r,h alpha_r,v,k. FP64 throughout.
-template <typename TO>
+template <typename TO, int PM>
 __global__ __launch_bounds__(256) void k_margins(Lv<double> L, TO* __restrict__ margin) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= L.npad) return;
@@ -546,8 +599,8 @@ __global__ __launch_bounds__(256) void k_margins(Lv<double> L, TO* __restrict__ 
   const double esum = c.a0 + c.a1 + c.a2;
   double sk = 0.0;
   for (int k = 0; k < L.nz; ++k) {
-    const double e = c.bh * L.bv[k] + esum * L.av[k];
-    const double l = c.arh * L.arv[k];
+    const double e = coef_excess<PM>(L, c, esum, k);
+    const double l = coef_face<PM>(L, c, k);
     sk = k == 0 ? e : e + l * sk / (sk + l);
     margin[c.base + static_cast<size_t>(k) * kTile] = static_cast<TO>(sk);
   }
@@ -575,7 +628,7 @@ __device__ __forceinline__ T rcp_of(T v) {
   return fast_rcp(v);
 }
 
-template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS, int PM = 0>
 __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __restrict__ f, const T* __restrict__ u_in,
                                                  TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
                                                  const double* __restrict__ q, double* __restrict__ partials,
@@ -602,9 +655,9 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // column coefficients of level k0 + i, rebuilt from the per-column scalars
   // and the wave-uniform vertical vectors whenever needed (cheaper than
   // holding them: registers decide how many tiles a CU keeps in flight)
-  auto e_of = [&](int i) -> T { return c.bh * L.bv[k0 + i] + esum * L.av[k0 + i]; };
-  auto l_of = [&](int i) -> T { return c.arh * L.arv[k0 + i]; };
-  auto m_of = [&](int i) -> T { return c.arh * L.arv[k0 + i + 1]; };
+  auto e_of = [&](int i) -> T { return coef_excess<PM>(L, c, esum, k0 + i); };
+  auto l_of = [&](int i) -> T { return coef_face<PM>(L, c, k0 + i); };
+  auto m_of = [&](int i) -> T { return coef_face<PM>(L, c, k0 + i + 1); };
 
   // ---- residual of the wave's levels, in registers. All loads are issued
   // before any is used: their level indices are clamped into the column (the
@@ -649,7 +702,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
           xc.put(lane, uc, hv[i]);
           const T n0 = xc.get(c, 0), n1 = xc.get(c, 1), n2 = xc.get(c, 2);
           xc.done();
-          r[i] = fk - row_flux(L, c, k, um, uc, up, n0, n1, n2);
+          r[i] = fk - row_flux<PM>(L, c, k, um, uc, up, n0, n1, n2);
         }
       }
     }
@@ -765,7 +818,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
 
 // residual on the fine level, summed over the four children of each coarse
 // cell (Algorithm 1 residual + restriction by summation, Section 5)
-template <typename T, int CH>
+template <typename T, int CH, int PM = 0>
 __device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk_rt, int n_coarse,
                                                        const T* __restrict__ f, const T* __restrict__ u,
                                                        T* __restrict__ fc, GridPos g) {
@@ -794,14 +847,14 @@ __device__ __forceinline__ void residual_restrict_body(const Lv<T>& L, int chunk
     for (int i = 0; i < CH; ++i) fv[i] = f[c.base + static_cast<size_t>(min(k0 + i, L.nz - 1)) * kTile];
 #pragma unroll
     for (int i = 0; i < CH; ++i)
-      if (k0 + i < k1) emit(k0 + i, fv[i] - ld.row(L, c, k0, i));
+      if (k0 + i < k1) emit(k0 + i, fv[i] - ld.template row<PM>(L, c, k0, i));
   } else {
     T um = k0 > 0 ? u[c.base + static_cast<size_t>(k0 - 1) * kTile] : T(0);
     T uc = u[c.base + static_cast<size_t>(k0) * kTile];
     for (int k = k0; k < k1; ++k) {
       const size_t o = c.base + static_cast<size_t>(k) * kTile;
       const T up = k + 1 < L.nz ? u[o + kTile] : T(0);
-      emit(k, f[o] - apply_row(L, c, u, k, um, uc, up));
+      emit(k, f[o] - apply_row<PM>(L, c, u, k, um, uc, up));
       um = uc;
       uc = up;
     }
@@ -918,11 +971,11 @@ __global__ __launch_bounds__(256) void k_finalize(int site, const double* __rest
   }
 }
 
-template <int MODE, int CH>
+template <int MODE, int CH, int PM>
 __global__ __launch_bounds__(256) void k_spmv64(Lv<double> L, int chunk, const double* __restrict__ x,
                                                 const double* __restrict__ b, double* __restrict__ y,
                                                 double* __restrict__ partials, float* __restrict__ y32) {
-  spmv_body<MODE, CH>(L, chunk, x, b, y, partials, whole_grid(), y32);
+  spmv_body<MODE, CH, PM>(L, chunk, x, b, y, partials, whole_grid(), y32);
 }
 
 // Occupancy: an FP32 sweep with up to 8 levels per wave fits two 16-wave
@@ -948,18 +1001,21 @@ constexpr int scan_max_threads() {
   return 64 * ((sizeof(T) == 8 && KB == 16) ? 8 : kScanWavesMax);
 }
 
-template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+// (profiles that do not factorise load their coefficients per level: the
+// occupancy bound of the batched form)
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS, int PM>
 __global__ __launch_bounds__((scan_max_threads<KB, T>()),
-                             (scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value))) void k_smooth_scan(
+                             (PM == 0 ? scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value)
+                                      : scan_waves_per_simd_batched<KB, T>())) void k_smooth_scan(
     Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in, TO* __restrict__ u_out, T* __restrict__ fcopy,
     T omega, const double* __restrict__ q, double* __restrict__ partials) {
-  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
+  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS, PM>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
 }
 
-template <typename T, int CH>
+template <typename T, int CH, int PM>
 __global__ __launch_bounds__(256) void k_residual_restrict(Lv<T> L, int chunk, int n_coarse, const T* __restrict__ f,
                                                            const T* __restrict__ u, T* __restrict__ fc) {
-  residual_restrict_body<T, CH>(L, chunk, n_coarse, f, u, fc, whole_grid());
+  residual_restrict_body<T, CH, PM>(L, chunk, n_coarse, f, u, fc, whole_grid());
 }
 
 template <typename T>
@@ -1006,20 +1062,20 @@ __global__ __launch_bounds__(256) void k_pupdate_ring(const TZ* __restrict__ z, 
   if (flush && blockIdx.x == 0 && threadIdx.x == 0) sc->flushed = k;
 }
 
-template <int CH>
+template <int CH, int PM>
 __global__ __launch_bounds__(256) void k_spmv_ring(Lv<double> L, int chunk, const double* __restrict__ ring,
                                                    size_t len, double* __restrict__ q, double* __restrict__ partials,
                                                    const FcgScalars* __restrict__ sc) {
   if (sc->done) return;
   const double* __restrict__ p = ring + static_cast<size_t>(sc->iters % kDirSlots) * len;
-  spmv_body<0, CH>(L, chunk, p, nullptr, q, partials, whole_grid());
+  spmv_body<0, CH, PM>(L, chunk, p, nullptr, q, partials, whole_grid());
 }
 
 // The direction update inside q = A p: p_k = z + beta p_{k-1} is formed on
 // the fly at every point the operator reads (the expression of
 // k_pupdate_ring, so the same bits), stored for the wave's own points, and
 // the ring's flush, when due, runs on the same points first.
-template <int CH, typename TZ>
+template <int CH, typename TZ, int PM = 0>
 __device__ __forceinline__ void spmv_pring_body(const Lv<double>& L, const TZ* __restrict__ z,
                                                 double* __restrict__ ring, size_t len, double* __restrict__ x,
                                                 double* __restrict__ q, double* __restrict__ partials,
@@ -1058,7 +1114,7 @@ __device__ __forceinline__ void spmv_pring_body(const Lv<double>& L, const TZ* _
           x[o] = xi;
         }
         const double uc = ld.xv[i + 1];
-        const double ax = ld.row(L, c, k0, i);
+        const double ax = ld.template row<PM>(L, c, k0, i);
         pn[o] = uc;
         q[o] = ax;
         acc[0] += uc * ax;
@@ -1069,12 +1125,12 @@ __device__ __forceinline__ void spmv_pring_body(const Lv<double>& L, const TZ* _
   if (flush && g.b == 0 && threadIdx.x == 0) sc->flushed = k;
 }
 
-template <int CH, typename TZ>
+template <int CH, typename TZ, int PM>
 __global__ __launch_bounds__(256) void k_spmv_pring(Lv<double> L, const TZ* __restrict__ z, double* __restrict__ ring,
                                                     size_t len, double* __restrict__ x, double* __restrict__ q,
                                                     double* __restrict__ partials, FcgScalars* __restrict__ sc) {
   if (sc->done) return;
-  spmv_pring_body<CH, TZ>(L, z, ring, len, x, q, partials, sc, whole_grid());
+  spmv_pring_body<CH, TZ, PM>(L, z, ring, len, x, q, partials, sc, whole_grid());
 }
 
 // r -= alpha q and <r, r>; with r32 also the FP32 rounding of the new r,
@@ -1355,19 +1411,33 @@ void chunk_variant(int chunk, Fn&& fn) {
   }
 }
 
+// Calls fn(std::integral_constant<int, PM>) for the profile mode of a level
+// (0 factorised, 1 radial couplings per (T, k), 2 all coefficients per (T, k)).
+template <typename Fn>
+void profile_variant(int pm, Fn&& fn) {
+  switch (pm) {
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    default: fn(std::integral_constant<int, 0>{}); break;
+  }
+}
+
 hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const double* b, double* y,
                          double* partials, int site, FcgScalars* sc, hipStream_t s, double rtol, float* y32,
                          FcgRecord* ring, double div2) {
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
-  chunk_variant(chunk, [&](auto chc) {
-    constexpr int CH = decltype(chc)::value;
-    if (mode == 0)
-      hipLaunchKernelGGL((k_spmv64<0, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials,
-                         static_cast<float*>(nullptr));
-    else
-      hipLaunchKernelGGL((k_spmv64<1, CH>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials, y32);
+  profile_variant(L.pm, [&](auto pmc) {
+    constexpr int PM = decltype(pmc)::value;
+    chunk_variant(chunk, [&](auto chc) {
+      constexpr int CH = decltype(chc)::value;
+      if (mode == 0)
+        hipLaunchKernelGGL((k_spmv64<0, CH, PM>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials,
+                           static_cast<float*>(nullptr));
+      else
+        hipLaunchKernelGGL((k_spmv64<1, CH, PM>), dim3(blocks), dim3(256), 0, s, V, chunk, x, b, y, partials, y32);
+    });
   });
   if (site != kFinNone)
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, ring,
@@ -1463,14 +1533,20 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
     if (Lg.margin == nullptr) return hipErrorInvalidValue;   // the scan form reads the stored margins
     const int waves = scan_waves(L.nz, tn.scan_levels);
     const size_t sl = scan_lds_bytes(waves, static_cast<int>(sizeof(T)));
+    if (Lg.pm != 0 && tn.scan_levels == 4) return hipErrorInvalidValue;   // (no instance)
     scan_levels_variant(tn.scan_levels, [&](auto kbc) {
       constexpr int KB = decltype(kbc)::value;
-      smoother_variant<T>(f_double, out_double, zero, fcopy, dots, [&](auto tf, auto to, auto z, auto fcp, auto dt) {
-        using TF = typename decltype(tf)::type;
-        using TO = typename decltype(to)::type;
-        hipLaunchKernelGGL((k_smooth_scan<KB, T, TF, TO, decltype(z)::value, decltype(fcp)::value, decltype(dt)::value>),
-                           dim3(ntiles), dim3(64 * waves), sl, s, L, static_cast<const TF*>(a.f), ui,
-                           static_cast<TO*>(a.u_out), fc, om, a.q, a.partials);
+      profile_variant(Lg.pm, [&](auto pmc) {
+        constexpr int PM = decltype(pmc)::value;
+        if constexpr (PM == 0 || KB != 4)
+          smoother_variant<T>(f_double, out_double, zero, fcopy, dots, [&](auto tf, auto to, auto z, auto fcp, auto dt) {
+            using TF = typename decltype(tf)::type;
+            using TO = typename decltype(to)::type;
+            hipLaunchKernelGGL((k_smooth_scan<KB, T, TF, TO, decltype(z)::value, decltype(fcp)::value,
+                                              decltype(dt)::value, PM>),
+                               dim3(ntiles), dim3(64 * waves), sl, s, L, static_cast<const TF*>(a.f), ui,
+                               static_cast<TO*>(a.u_out), fc, om, a.q, a.partials);
+          });
       });
     });
     if (dots)
@@ -1479,6 +1555,7 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
     return hipGetLastError();
   }
   if (dots) return hipErrorInvalidValue;   // only the scan kernel forms the dots
+  if (Lg.pm != 0) return hipErrorInvalidValue;   // profiles that do not factorise: the scan kernel only
   if (tn.smoother == kSmLds) {
     const size_t lds = lds_smoother_bytes(L.nz, prec);
     const unsigned waves = static_cast<unsigned>(std::min(16, std::max(1, (L.nz + kBatch - 1) / kBatch)));
@@ -1521,14 +1598,19 @@ hipError_t launch_residual_restrict(const LevelView& L, const LevelView& C, int 
                                     const void* u, void* f_coarse, hipStream_t s) {
   const int chunk = effective_chunk(L.tune.chunk_rr, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
-  chunk_variant(chunk, [&](auto chc) {
-    constexpr int CH = decltype(chc)::value;
-    if (prec == 8)
-      hipLaunchKernelGGL((k_residual_restrict<double, CH>), dim3(blocks), dim3(256), 0, s, view<double>(L), chunk, C.n,
-                         static_cast<const double*>(f), static_cast<const double*>(u), static_cast<double*>(f_coarse));
-    else
-      hipLaunchKernelGGL((k_residual_restrict<float, CH>), dim3(blocks), dim3(256), 0, s, view<float>(L), chunk, C.n,
-                         static_cast<const float*>(f), static_cast<const float*>(u), static_cast<float*>(f_coarse));
+  profile_variant(L.pm, [&](auto pmc) {
+    constexpr int PM = decltype(pmc)::value;
+    chunk_variant(chunk, [&](auto chc) {
+      constexpr int CH = decltype(chc)::value;
+      if (prec == 8)
+        hipLaunchKernelGGL((k_residual_restrict<double, CH, PM>), dim3(blocks), dim3(256), 0, s, view<double>(L), chunk,
+                           C.n, static_cast<const double*>(f), static_cast<const double*>(u),
+                           static_cast<double*>(f_coarse));
+      else
+        hipLaunchKernelGGL((k_residual_restrict<float, CH, PM>), dim3(blocks), dim3(256), 0, s, view<float>(L), chunk,
+                           C.n, static_cast<const float*>(f), static_cast<const float*>(u),
+                           static_cast<float*>(f_coarse));
+    });
   });
   return hipGetLastError();
 }
@@ -1548,10 +1630,15 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, int prec, 
 
 hipError_t launch_margins(const LevelView& L64, int prec, void* margin, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((L64.npad + 255) / 256);
-  if (prec == 8)
-    hipLaunchKernelGGL(k_margins<double>, dim3(blocks), dim3(256), 0, s, view<double>(L64), static_cast<double*>(margin));
-  else
-    hipLaunchKernelGGL(k_margins<float>, dim3(blocks), dim3(256), 0, s, view<double>(L64), static_cast<float*>(margin));
+  profile_variant(L64.pm, [&](auto pmc) {
+    constexpr int PM = decltype(pmc)::value;
+    if (prec == 8)
+      hipLaunchKernelGGL((k_margins<double, PM>), dim3(blocks), dim3(256), 0, s, view<double>(L64),
+                         static_cast<double*>(margin));
+    else
+      hipLaunchKernelGGL((k_margins<float, PM>), dim3(blocks), dim3(256), 0, s, view<double>(L64),
+                         static_cast<float*>(margin));
+  });
   return hipGetLastError();
 }
 
@@ -1579,9 +1666,12 @@ hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, 
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
-  chunk_variant(chunk, [&](auto chc) {
-    constexpr int CH = decltype(chc)::value;
-    hipLaunchKernelGGL((k_spmv_ring<CH>), dim3(blocks), dim3(256), 0, s, V, chunk, ring, len, q, partials, sc);
+  profile_variant(L.pm, [&](auto pmc) {
+    constexpr int PM = decltype(pmc)::value;
+    chunk_variant(chunk, [&](auto chc) {
+      constexpr int CH = decltype(chc)::value;
+      hipLaunchKernelGGL((k_spmv_ring<CH, PM>), dim3(blocks), dim3(256), 0, s, V, chunk, ring, len, q, partials, sc);
+    });
   });
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinAlpha), partials,
                      static_cast<int>(blocks), sc, 0.0, nullptr, kDefaultDiv2);
@@ -1599,16 +1689,19 @@ hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, d
   const int chunk = effective_chunk(L.tune.chunk_spmv, L.npad, L.nz);
   const unsigned blocks = static_cast<unsigned>(stencil_blocks(L.npad, L.nz, chunk));
   const Lv<double> V = view<double>(L);
-  chunk_variant(chunk, [&](auto chc) {
-    constexpr int CH = decltype(chc)::value;
-    if constexpr (CH > 0) {
-      if (z_double)
-        hipLaunchKernelGGL((k_spmv_pring<CH, double>), dim3(blocks), dim3(256), 0, s, V, static_cast<const double*>(z),
-                           ring, len, x, q, partials, sc);
-      else
-        hipLaunchKernelGGL((k_spmv_pring<CH, float>), dim3(blocks), dim3(256), 0, s, V, static_cast<const float*>(z),
-                           ring, len, x, q, partials, sc);
-    }
+  profile_variant(L.pm, [&](auto pmc) {
+    constexpr int PM = decltype(pmc)::value;
+    chunk_variant(chunk, [&](auto chc) {
+      constexpr int CH = decltype(chc)::value;
+      if constexpr (CH > 0) {
+        if (z_double)
+          hipLaunchKernelGGL((k_spmv_pring<CH, double, PM>), dim3(blocks), dim3(256), 0, s, V,
+                             static_cast<const double*>(z), ring, len, x, q, partials, sc);
+        else
+          hipLaunchKernelGGL((k_spmv_pring<CH, float, PM>), dim3(blocks), dim3(256), 0, s, V,
+                             static_cast<const float*>(z), ring, len, x, q, partials, sc);
+      }
+    });
   });
   if (site != kFinNone)
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, 0.0, nullptr,

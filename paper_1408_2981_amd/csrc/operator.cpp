@@ -151,4 +151,65 @@ void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, co
   }
 }
 
+void build_full(Operator& op, const Grid& g, const double* alpha_r, const double* alpha_s, const double* beta) {
+  const int nz = op.nz;
+  if (g.nz != nz || g.refinement != op.refinement) throw std::runtime_error("grid and operator differ");
+  const int fine_ref = g.refinement;
+  const int nl = static_cast<int>(op.levels.size());
+  const int coarse_ref = fine_ref - nl + 1;
+  // per-level profiles [n][m], finest first; coarse = area-weighted means
+  struct Prof {
+    std::vector<double> ar, as, b;
+  };
+  std::vector<Prof> pf(fine_ref + 1);
+  const size_t nf = g.levels[fine_ref].n;
+  pf[fine_ref].ar.assign(alpha_r, alpha_r + nf * (nz + 1));
+  pf[fine_ref].as.assign(alpha_s, alpha_s + nf * nz);
+  pf[fine_ref].b.assign(beta, beta + nf * nz);
+  for (int r = fine_ref; r > coarse_ref; --r) {
+    const MeshLevel& F = g.levels[r];
+    const int nc = g.levels[r - 1].n;
+    auto restrict_rows = [&](const std::vector<double>& src, std::vector<double>& dst, int m) {
+      dst.assign(static_cast<size_t>(nc) * m, 0.0);
+      for (int P = 0; P < nc; ++P) {
+        double den = 0.0;
+        for (int i = 0; i < 4; ++i) den += F.area[4 * P + i];
+        for (int k = 0; k < m; ++k) {
+          double num = 0.0;
+          for (int i = 0; i < 4; ++i) num += src[static_cast<size_t>(4 * P + i) * m + k] * F.area[4 * P + i];
+          dst[static_cast<size_t>(P) * m + k] = num / den;
+        }
+      }
+    };
+    restrict_rows(pf[r].ar, pf[r - 1].ar, nz + 1);
+    restrict_rows(pf[r].as, pf[r - 1].as, nz);
+    restrict_rows(pf[r].b, pf[r - 1].b, nz);
+  }
+  const double omega2 = op.omega2;
+  std::vector<double> face(nz + 1, 0.0);
+  for (int k = 1; k < nz; ++k) face[k] = 2.0 * g.r[k] * g.r[k] / (g.r[k + 1] - g.r[k - 1]);
+  for (int l = 0; l < nl; ++l) {
+    const int r = coarse_ref + l;
+    const MeshLevel& M = g.levels[r];
+    LevelCoeffs& C = op.levels[l];
+    const Prof& P = pf[r];
+    const size_t n = M.n;
+    C.fb.resize(n * nz);
+    C.far.resize(n * (nz + 1));
+    C.fas.resize(3 * n * nz);
+    for (size_t t = 0; t < n; ++t) {
+      for (int k = 0; k < nz; ++k) C.fb[t * nz + k] = M.area[t] * g.vk[k] * P.b[t * nz + k];
+      for (int k = 0; k <= nz; ++k)
+        C.far[t * (nz + 1) + k] = omega2 * face[k] * M.area[t] * P.ar[t * (nz + 1) + k];
+      for (int j = 0; j < 3; ++j) {
+        const size_t o = M.nbr[3 * t + j];
+        for (int k = 0; k < nz; ++k)
+          C.fas[(3 * t + j) * nz + k] = omega2 * (g.r[k + 1] - g.r[k]) * M.g[3 * t + j] *
+                                        (0.5 * (P.as[t * nz + k] + P.as[o * nz + k]));
+      }
+    }
+  }
+  op.full = true;
+}
+
 }  // namespace tpmg

@@ -74,6 +74,12 @@ struct DevLevel {
   void* f = nullptr;                   // right-hand side (coarse levels; precision of the V-cycle)
   void* u[2] = {nullptr, nullptr};     // ping-pong iterates
   void* margin[2] = {nullptr, nullptr};   // Thomas margins, [0] double, [1] float (tiled)
+  // coefficients of profiles that do not factorise ([0] double, [1] float):
+  // beta^ and the three alphaS^ planes tiled like a vector, alphar^ with
+  // nz + 1 rows per tile
+  void* fb[2] = {nullptr, nullptr};
+  void* far[2] = {nullptr, nullptr};
+  void* fas[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -83,6 +89,10 @@ struct tpmg_mg {
   int nu_pre = 2, nu_post = 2, nu_coarse = 1;
   double omega = 2.0 / 3.0;
   bool fp32 = false, use_graph = false;
+  // profile mode of the V-cycle's levels (tpmg::LevelView::pm) and whether
+  // the operator of the equation has profiles that do not factorise
+  int pm = 0;
+  bool full_outer = false;
   hipStream_t stream = nullptr;
   std::vector<DevLevel> lv;
   void* bv[2] = {nullptr, nullptr};
@@ -130,7 +140,19 @@ struct tpmg_mg {
     v.as_v = asv[i];
     v.ar_v = arv[i];
     v.margin = d.margin[i];
+    v.pm = pm;
+    v.fb = d.fb[i];
+    v.far = d.far[i];
+    v.fas = d.fas[i];
     if (!tune.empty()) v.tune = tune[l];
+    return v;
+  }
+  // the finest grid's FP64 operator of the equation itself (the outer
+  // Krylov method's), every coefficient per (T, k) when the profiles do not
+  // factorise
+  tpmg::LevelView view_outer() const {
+    tpmg::LevelView v = view64(nlev - 1);
+    v.pm = full_outer ? 2 : 0;
     return v;
   }
   tpmg::LevelView view64(int l) const {
@@ -150,6 +172,10 @@ struct tpmg_mg {
     v.as_v = asv[0];
     v.ar_v = arv[0];
     v.margin = d.margin[0];
+    v.pm = pm;
+    v.fb = d.fb[0];
+    v.far = d.far[0];
+    v.fas = d.fas[0];
     if (!tune.empty()) v.tune = tune[l];
     return v;
   }
@@ -186,6 +212,13 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
     // whose FP64 view serves the relaxation after a learned guess
     d.margin[1] = m.fp32 ? cv.take(np * nz * 4) : nullptr;
     d.margin[0] = (!m.fp32 || finest) ? cv.take(np * nz * 8) : nullptr;
+    if (op.full)
+      for (int i = 0; i < (m.fp32 ? 2 : 1); ++i) {
+        const size_t es = i == 0 ? 8 : 4;
+        d.fb[i] = cv.take(np * nz * es);
+        d.far[i] = cv.take(np * (nz + 1) * es);
+        d.fas[i] = cv.take(3 * np * nz * es);
+      }
   }
   for (int i = 0; i < 2; ++i) {
     const size_t es = i == 0 ? 8 : 4;
@@ -264,6 +297,8 @@ tpmg_status check_params(const tpmg_mg_params* p) {
   if (p->scan_levels != 0 && p->smoother > 1)
     return fail(TPMG_ERR_ARG, "scan_levels applies to the scan smoother only");
   if (p->stencil_chunk < 0 || p->stencil_chunk > 256) return fail(TPMG_ERR_ARG, "stencil_chunk must be in 0..256");
+  if (p->precond_profiles < 0 || p->precond_profiles > 2)
+    return fail(TPMG_ERR_ARG, "precond_profiles must be 0, 1 or 2");
   return TPMG_OK;
 }
 
@@ -273,6 +308,20 @@ std::vector<T> padded(const std::vector<double>& src, int n, int npad, int comps
   std::vector<T> out(static_cast<size_t>(npad) * comps, static_cast<T>(fill));
   for (int c = 0; c < comps; ++c)
     for (int t = 0; t < n; ++t) out[static_cast<size_t>(c) * npad + t] = static_cast<T>(src[static_cast<size_t>(t) * comps + c]);
+  return out;
+}
+
+// cell-major [n][comps][rows] -> comps tiled planes (value (T, k) of plane
+// c at c npad rows + (T / 64) 64 rows + k 64 + T % 64); padding columns fill
+template <typename T>
+std::vector<T> tiled(const std::vector<double>& cm, int n, int npad, int comps, int rows, double fill) {
+  std::vector<T> out(static_cast<size_t>(comps) * npad * rows, static_cast<T>(fill));
+  for (int c = 0; c < comps; ++c)
+    for (int t = 0; t < n; ++t)
+      for (int k = 0; k < rows; ++k)
+        out[static_cast<size_t>(c) * npad * rows + static_cast<size_t>(t / tpmg::kTile) * tpmg::kTile * rows +
+            static_cast<size_t>(k) * tpmg::kTile + t % tpmg::kTile] =
+            static_cast<T>(cm[(static_cast<size_t>(t) * comps + c) * rows + k]);
   return out;
 }
 
@@ -431,7 +480,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
   // z of an FP32 V-cycle is an FP32 value: kept in FP32 when the last sweep
   // also forms the dots (nothing else reads it in FP64)
   const bool z_float = fused && m.fp32;
-  const bool pring = single ? tpmg::spmv_pring_fits(m.view64(m.nlev - 1)) : batch_ring;
+  const bool pring = single ? tpmg::spmv_pring_fits(m.view_outer()) : batch_ring;
   // (the ring form ends each iteration with the r update, which then also
   // writes the FP32 copy of r; the solve's start makes the first one)
   vcycle_ops(m, m.r, m.z, fused ? m.q : nullptr, sc, ops, z_float, (single || pring) && m.fp32);
@@ -456,7 +505,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     sp.order[1] = 1;
     sp.site = tpmg::kFinAlpha;
     sp.kind = tpmg::kOpSpmvPRing;
-    sp.L = m.view64(m.nlev - 1);
+    sp.L = m.view_outer();
     sp.f_double = !z_float;
     sp.in0 = m.z;
     sp.out0 = m.q;
@@ -495,7 +544,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
     ops.push_back(pr);
     Op sr;
     sr.kind = tpmg::kOpSpmvRing;
-    sr.L = m.view64(m.nlev - 1);
+    sr.L = m.view_outer();
     sr.in0 = m.dirs;
     sr.out0 = m.q;
     sr.partials = m.partials;
@@ -528,7 +577,7 @@ void fcg_ops(tpmg_mg& m, double* x, tpmg::FcgScalars* sc, std::vector<Op>& ops, 
   sp.order[0] = 2;
   sp.order[1] = 2;
   sp.kind = tpmg::kOpSpmv;
-  sp.L = m.view64(m.nlev - 1);
+  sp.L = m.view_outer();
   sp.in0 = m.p;
   sp.out0 = m.q;
   sp.partials = m.partials;
@@ -619,29 +668,34 @@ double op_model_bytes(const Op& op, int it) {
   const double len = static_cast<double>(op.len);
   const double zb = op.f_double ? 8.0 : 4.0;
   const bool flush = it > 0 && it % tpmg::kDirSlots == 0;
+  // coefficients per (T, k) of profiles that do not factorise, read by every
+  // stencil kernel: beta^, three alphaS^ and one new radial face per unknown
+  // (all of them), or the radial face alone (the partial form)
+  const double coef = op.L.pm == 2 ? 5.0 : op.L.pm == 1 ? 1.0 : 0.0;
   const double ring_x = flush ? 8.0 * (tpmg::kDirSlots + 2) : 0.0;
   switch (op.kind) {
     case tpmg::kOpSmooth: {
       double b = (op.zero ? 0.0 : s) + (op.f_double ? 8.0 : s) + (op.out_double ? 8.0 : s);
       if (op.fcopy) b += 4.0;
       if (op.dots) b += 8.0;   // q (the residual is the right-hand side)
-      return b * n;
+      return (b + coef * s) * n;
     }
     case tpmg::kOpRestrict:
+      return (2.0 * s + s / 4.0 + coef * s) * n;
     case tpmg::kOpProlong:
       return (2.0 * s + s / 4.0) * n;
     case tpmg::kOpSpmvPRing:
-      return (zb + (it > 0 ? 8.0 : 0.0) + 16.0 + ring_x) * len;
+      return (zb + (it > 0 ? 8.0 : 0.0) + 16.0 + ring_x + coef * 8.0) * len;
     case tpmg::kOpPupdateRing:
       return (zb + (it > 0 ? 8.0 : 0.0) + 8.0 + ring_x) * len;
     case tpmg::kOpSpmvRing:
-      return 16.0 * len;
+      return (16.0 + coef * 8.0) * len;
     case tpmg::kOpRupdate:
       return (24.0 + (op.out0 ? 4.0 : 0.0)) * len;
     case tpmg::kOpPupdate:
       return (zb + 16.0) * len;
     case tpmg::kOpSpmv:
-      return 16.0 * n;
+      return (16.0 + coef * 8.0) * n;
     case tpmg::kOpUpdate:
       return 48.0 * len;
     case -1:
@@ -654,8 +708,8 @@ double op_model_bytes(const Op& op, int it) {
 // Model bytes of a solve of `iters` iterations: the initial residual
 // (reads u and f, writes r and, for an FP32 V-cycle, its FP32 copy), the
 // iterations, and the final x update of a single solve's direction ring.
-double solve_model_bytes(const std::vector<Op>& ops, int iters, size_t len, bool fp32, bool ring) {
-  double b = (24.0 + (fp32 ? 4.0 : 0.0)) * static_cast<double>(len);
+double solve_model_bytes(const std::vector<Op>& ops, int iters, size_t len, bool fp32, bool ring, bool full = false) {
+  double b = (24.0 + (fp32 ? 4.0 : 0.0) + (full ? 40.0 : 0.0)) * static_cast<double>(len);
   for (int it = 0; it < iters; ++it)
     for (const Op& op : ops) b += op_model_bytes(op, it);
   if (ring && iters > 0) {
@@ -865,6 +919,7 @@ tpmg_status check_batch(tpmg_mg* const* problems, int n) {
     const tpmg_mg* m = problems[i];
     if (!m) return fail(TPMG_ERR_ARG, "NULL problem");
     if (m->nlev < 2) return fail(TPMG_ERR_ARG, "batched problems need at least 2 multigrid levels");
+    if (m->full_outer) return fail(TPMG_ERR_ARG, "batched problems need factorising profiles");
     for (const tpmg::LevelTune& t : m->tune)
       if (t.smoother != tpmg::kSmScan)
         return fail(TPMG_ERR_ARG, "batched problems need the scan smoother on every level (params.smoother = 1)");
@@ -1037,6 +1092,14 @@ tpmg_status choose_tuning(tpmg_mg& m, const tpmg_mg_params& p, bool trials) {
       t.scan_levels = p.scan_levels;
     }
     if (p.stencil_chunk != 0) t.chunk_rr = t.chunk_pr = t.chunk_spmv = p.stencil_chunk;
+    if (m.pm != 0) {
+      // coefficients per (T, k): the scan smoother at 8 or 16 levels per wave
+      if (p.smoother > 1 || p.scan_levels == 4)
+        return fail(TPMG_ERR_ARG, "profiles that do not factorise run the scan smoother at 8 or 16 levels per wave");
+      t.smoother = tpmg::kSmScan;
+      if (t.scan_levels == 4) t.scan_levels = 8;
+      if (!tpmg::smoother_fits(tpmg::kSmScan, t.scan_levels, m.nz, prec)) t.scan_levels = 16;
+    }
     if (!tpmg::smoother_fits(t.smoother, t.scan_levels, m.nz, prec))
       return fail(TPMG_ERR_ARG, "the requested line smoother cannot run nz = " + std::to_string(m.nz) +
                                     " (scan form: nz <= 16 * scan_levels; LDS form: two [nz][64] arrays in LDS)");
@@ -1079,8 +1142,11 @@ tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p) {
     tpmg::LevelTune& t = m.tune[l];
     const int npad = m.lv[l].npad;
     const void* f = l < L ? m.lv[l].f : (m.fp32 ? static_cast<const void*>(m.fcopy) : static_cast<const void*>(m.r));
+    // (the profile mode changes what the kernels load: its own cache entries)
+    const std::string pm_tag = m.pm == 0 ? "" : (m.pm == 1 ? "_partial" : "_full");
     if (tune_smoother || tune_scan_levels) {
-      const std::string key = tune_key(dev, tune_smoother ? "smooth" : "smooth_scan", prec, npad, m.nz);
+      const std::string key =
+          tune_key(dev, (std::string(tune_smoother ? "smooth" : "smooth_scan") + pm_tag).c_str(), prec, npad, m.nz);
       std::array<int, 2> v{};
       if (lookup(key, &v) && tpmg::smoother_fits(v[0], v[1], m.nz, prec)) {
         t.smoother = v[0];
@@ -1088,9 +1154,10 @@ tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p) {
       } else {
         std::vector<std::array<int, 2>> cands{{t.smoother, t.scan_levels}};
         for (int kb : {4, 8, 16})
-          if (tpmg::smoother_fits(tpmg::kSmScan, kb, m.nz, prec) && !(t.smoother == tpmg::kSmScan && t.scan_levels == kb))
+          if (tpmg::smoother_fits(tpmg::kSmScan, kb, m.nz, prec) && !(t.smoother == tpmg::kSmScan && t.scan_levels == kb) &&
+              !(m.pm != 0 && kb == 4))
             cands.push_back({tpmg::kSmScan, kb});
-        if (tune_smoother)
+        if (tune_smoother && m.pm == 0)
           for (int kind : {tpmg::kSmLds, tpmg::kSmGlobal})
             if (tpmg::smoother_fits(kind, 8, m.nz, prec) && t.smoother != kind) cands.push_back({kind, 8});
         size_t best = 0;
@@ -1112,7 +1179,9 @@ tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p) {
     const std::vector<int> cc = chunk_cands(npad);
     auto tune_chunk = [&](const char* kernel, int kprec, int* field,
                           const std::function<hipError_t(int)>& launch) -> tpmg_status {
-      const std::string key = tune_key(dev, kernel, kprec, npad, m.nz);
+      const bool outer = std::string(kernel) == "spmv_p";
+      const std::string tag = outer ? (m.full_outer ? "_full" : "") : pm_tag;
+      const std::string key = tune_key(dev, (std::string(kernel) + tag).c_str(), kprec, npad, m.nz);
       std::array<int, 2> v{};
       if (lookup(key, &v) && v[0] >= 1 && v[0] <= 256) {
         *field = v[0];
@@ -1145,7 +1214,7 @@ tpmg_status autotune(tpmg_mg& m, const tpmg_mg_params& p) {
       // operator (on the zeroed workspace: iteration 0, no flush), with a
       // finalize that changes no scalar
       st = tune_chunk("spmv_p", 8, &t.chunk_spmv, [&](int c) {
-        tpmg::LevelView V = m.view64(l);
+        tpmg::LevelView V = m.view_outer();
         V.tune.chunk_spmv = c;
         if (tpmg::spmv_pring_fits(V))
           return tpmg::launch_spmv_pring(V, m.z, !m.fp32, m.dirs, m.len, m.r, m.q, m.partials, m.scal, m.stream,
@@ -1269,6 +1338,42 @@ tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, cons
   return TPMG_OK;
 }
 
+tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const double* alpha_r, const double* alpha_s,
+                                      const double* beta) {
+  if (!op || !g || !alpha_r || !alpha_s || !beta) return fail(TPMG_ERR_ARG, "NULL argument");
+  const int ref = g->g.refinement, nz = g->g.nz;
+  if (ref != op->op.refinement || nz != op->op.nz) return fail(TPMG_ERR_ARG, "op was not created on this grid");
+  const size_t n = g->g.levels[ref].n;
+  auto positive = [](const double* v, size_t count, size_t stride, size_t skip_lo, size_t skip_hi) {
+    for (size_t i = 0; i < count; ++i) {
+      const size_t k = i % stride;
+      if (k < skip_lo || k + skip_hi >= stride) continue;
+      if (!(v[i] > 0.0) || !std::isfinite(v[i])) return false;
+    }
+    return true;
+  };
+  if (!positive(alpha_r, n * (nz + 1), nz + 1, 1, 1) || !positive(alpha_s, n * nz, nz, 0, 0) ||
+      !positive(beta, n * nz, nz, 0, 0))
+    return fail(TPMG_ERR_ARG, "full profiles must be positive and finite");
+  try {
+    tpmg::build_full(op->op, g->g, alpha_r, alpha_s, beta);
+  } catch (const std::exception& ex) {
+    return fail(TPMG_ERR_ARG, ex.what());
+  }
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta, double* alpha_s, double* alpha_r) {
+  if (!op) return fail(TPMG_ERR_ARG, "op is NULL");
+  if (level < 0 || level >= static_cast<int>(op->op.levels.size())) return fail(TPMG_ERR_ARG, "level out of range");
+  if (!op->op.full) return fail(TPMG_ERR_STATE, "the operator has no full profiles");
+  const tpmg::LevelCoeffs& C = op->op.levels[level];
+  if (beta) std::copy(C.fb.begin(), C.fb.end(), beta);
+  if (alpha_s) std::copy(C.fas.begin(), C.fas.end(), alpha_s);
+  if (alpha_r) std::copy(C.far.begin(), C.far.end(), alpha_r);
+  return TPMG_OK;
+}
+
 tpmg_status tpmg_op_levels(const tpmg_op* op, int* n_levels) {
   if (!op || !n_levels) return fail(TPMG_ERR_ARG, "NULL argument");
   *n_levels = static_cast<int>(op->op.levels.size());
@@ -1347,6 +1452,12 @@ tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_
   m->nu_coarse = params->nu_coarse;
   m->omega = params->omega_relax;
   m->fp32 = params->precond_fp32 != 0;
+  m->full_outer = op->op.full;
+  if (params->precond_profiles != 0 && !op->op.full) {
+    delete m;
+    return fail(TPMG_ERR_ARG, "precond_profiles 1 and 2 need an operator with full profiles (tpmg_op_set_full_profiles)");
+  }
+  m->pm = !op->op.full ? 0 : params->precond_profiles == 0 ? 2 : params->precond_profiles == 1 ? 0 : 1;
   m->stream = static_cast<hipStream_t>(hip_stream);
   m->use_graph = params->use_graph != 0 && m->stream != nullptr;
   Carver cv(d_workspace);
@@ -1431,6 +1542,21 @@ tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_
       keep32.push_back(padded<float>(C.pw, d.n, d.npad, 3, 0.0));
       if (e == hipSuccess) e = upload(d.pw[0], keep64.back(), m->stream);
       if (e == hipSuccess) e = upload(d.pw[1], keep32.back(), m->stream);
+    }
+    if (op->op.full) {
+      // (padding columns: unit mass, no couplings)
+      const std::vector<double>* src[3] = {&C.fb, &C.far, &C.fas};
+      void* const* dst[3] = {d.fb, d.far, d.fas};
+      const int comps[3] = {1, 1, 3}, rows[3] = {nz, nz + 1, nz};
+      const double fill[3] = {1.0, 0.0, 0.0};
+      for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+        keep64.push_back(tiled<double>(*src[a], d.n, d.npad, comps[a], rows[a], fill[a]));
+        e = upload(dst[a][0], keep64.back(), m->stream);
+        if (e == hipSuccess && dst[a][1]) {
+          keep32.push_back(tiled<float>(*src[a], d.n, d.npad, comps[a], rows[a], fill[a]));
+          e = upload(dst[a][1], keep32.back(), m->stream);
+        }
+      }
     }
   }
   const std::vector<double>* vv[3] = {&op->op.beta_v, &op->op.as_v, &op->op.ar_v};
@@ -1570,7 +1696,7 @@ tpmg_status tpmg_spmv(tpmg_mg* mg, const double* d_x, double* d_y) {
   if (st != TPMG_OK) return st;
   if (!d_x || !d_y) return fail(TPMG_ERR_ARG, "NULL vector");
   if (d_x == d_y) return fail(TPMG_ERR_ARG, "x and y must not alias");
-  TPMG_HIP(tpmg::launch_spmv64(mg->view64(mg->nlev - 1), 0, d_x, nullptr, d_y, mg->partials, tpmg::kFinNone, mg->scal,
+  TPMG_HIP(tpmg::launch_spmv64(mg->view_outer(), 0, d_x, nullptr, d_y, mg->partials, tpmg::kFinNone, mg->scal,
                                 mg->stream));
   return TPMG_OK;
 }
@@ -1624,7 +1750,7 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   const double div2 = info && info->div_tol > 0.0 ? info->div_tol * info->div_tol : tpmg::kDefaultDiv2;
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = mg->stream;
-  const tpmg::LevelView F = mg->view64(mg->nlev - 1);
+  const tpmg::LevelView F = mg->view_outer();
   // one FCG iteration as a list of operations (also the basis of the byte
   // count and of the per-phase timers)
   std::vector<Op> iter_ops;
@@ -1784,7 +1910,7 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
     }
     // the device ran the iterations it counted (one queued after the last
     // returned at once)
-    info->model_bytes = solve_model_bytes(iter_ops, iters, mg->len, mg->fp32, true);
+    info->model_bytes = solve_model_bytes(iter_ops, iters, mg->len, mg->fp32, true, mg->full_outer);
   }
   if (diverged) return fail(TPMG_ERR_BREAKDOWN, "divergence: ||r|| exceeded div_tol ||r_0||");
   if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite value or <p, A p> <= 0");
@@ -1797,7 +1923,7 @@ tpmg_status tpmg_richardson_rate(tpmg_mg* mg, double* d_u, int cycles, int skip,
   if (!d_u || !rate) return fail(TPMG_ERR_ARG, "NULL argument");
   if (skip < 0 || cycles <= skip) return fail(TPMG_ERR_ARG, "need 0 <= skip < cycles");
   hipStream_t s = mg->stream;
-  const tpmg::LevelView F = mg->view64(mg->nlev - 1);
+  const tpmg::LevelView F = mg->view_outer();
   // p holds the zero right-hand side, r the residual -A u, z the correction
   TPMG_HIP(tpmg::launch_fill(mg->p, mg->len * 8, s));
   std::vector<double> nrm(cycles + 1);
@@ -1855,7 +1981,7 @@ tpmg_status tpmg_mg_time_kernel(tpmg_mg* mg, int kernel, int reps, double* avg_m
   const int L = mg->nlev - 1;
   const int prec = mg->fp32 ? 4 : 8;
   const tpmg::LevelView V = mg->view(L);
-  const tpmg::LevelView F = mg->view64(L);
+  const tpmg::LevelView F = mg->view_outer();
   hipStream_t s = mg->stream;
   const bool z_float = mg->tune.back().smoother == tpmg::kSmScan && mg->fp32;
   if (kernel == 1 && !tpmg::spmv_pring_fits(F))
@@ -1903,10 +2029,14 @@ tpmg_status tpmg_mg_time_kernel(tpmg_mg* mg, int kernel, int reps, double* avg_m
   if (model_bytes) {
     const double n = static_cast<double>(mg->len);
     const double s_b = prec;
+    // (coefficients per (T, k): five values per unknown, or the radial one)
+    const double cv = mg->pm == 2 ? 5.0 : mg->pm == 1 ? 1.0 : 0.0;
+    const double co = mg->full_outer ? 40.0 : 0.0;
     switch (kernel) {
-      case 0: *model_bytes = 3.0 * s_b * n; break;
-      case 1: *model_bytes = ((z_float ? 4.0 : 8.0) + 24.0) * n; break;
-      case 2: *model_bytes = 16.0 * n; break;
+      case 0: *model_bytes = (3.0 + cv) * s_b * n; break;
+      case 1: *model_bytes = ((z_float ? 4.0 : 8.0) + 24.0 + co) * n; break;
+      case 2: *model_bytes = (16.0 + co) * n; break;
+      case 3: *model_bytes = (2.0 * s_b + s_b / 4.0 + cv * s_b) * n; break;
       default: *model_bytes = (2.0 * s_b + s_b / 4.0) * n; break;
     }
   }
@@ -2133,7 +2263,7 @@ tpmg_status solve_device_records(tpmg_mg& m, const double* d_f, double* d_u, dou
     hipError_t e = hipMemcpyAsync(recs, m.ring_dev, sizeof(recs), hipMemcpyDeviceToHost, s);
     return e == hipSuccess ? hipStreamSynchronize(s) : e;
   };
-  TPMG_HIP(tpmg::launch_spmv64(m.view64(m.nlev - 1), 1, d_u, d_f, m.r, m.partials, tpmg::kFinInit, m.scal, s, rtol,
+  TPMG_HIP(tpmg::launch_spmv64(m.view_outer(), 1, d_u, d_f, m.r, m.partials, tpmg::kFinInit, m.scal, s, rtol,
                                m.fp32 ? static_cast<float*>(m.fcopy) : nullptr, m.ring_dev, div2));
   TPMG_HIP(read_ring());
   if (recs[0].seq != 0) return fail(TPMG_ERR_DEVICE, "initial residual record missing");
@@ -2205,7 +2335,7 @@ tpmg_status solve_device_records(tpmg_mg& m, const double* d_f, double* d_u, dou
     info->relres = fnorm > 0 ? rnorm / fnorm : 0.0;
     info->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     info->t_vcycle_ms = info->t_spmv_ms = info->t_blas_ms = 0.0;
-    info->model_bytes = solve_model_bytes(ops, iters, m.len, m.fp32, true);
+    info->model_bytes = solve_model_bytes(ops, iters, m.len, m.fp32, true, m.full_outer);
   }
   if (diverged) return fail(TPMG_ERR_BREAKDOWN, "divergence: ||r|| exceeded div_tol ||r_0||");
   if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite value or <p, A p> <= 0");

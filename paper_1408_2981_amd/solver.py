@@ -11,14 +11,18 @@ from . import (
     tpmg_grid_icosahedral, tpmg_grid_geometry, tpmg_grid_vertical, tpmg_op_create, tpmg_op_levels,
     tpmg_mg_params_default, tpmg_mg_workspace_size, tpmg_mg_setup, tpmg_mg_vector_length, tpmg_pack,
     tpmg_unpack, tpmg_spmv, tpmg_vcycle, tpmg_solve, tpmg_grid_destroy, tpmg_op_destroy, tpmg_mg_destroy,
-    tpmg_mg_tuning,
+    tpmg_mg_tuning, tpmg_op_set_full_profiles,
 )
 
 
 class Problem:
     """Grid + operator on the host; call setup() to place it on the GPU."""
 
-    def __init__(self, refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0):
+    def __init__(self, refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0, full=None):
+        """profiles: factorised profile factors (None: unit profiles). full:
+        an object with alpha_r [n, nz+1], alpha_s, beta [n, nz], samples of
+        profiles that do not factorise on the finest grid; the factorised
+        profiles then serve as their approximate factorisation."""
         r_faces = np.asarray(r_faces, dtype=np.float64)
         self.refinement = refinement
         self.nz = len(r_faces) - 1
@@ -30,6 +34,8 @@ class Problem:
             ar_v, as_v, b_v = profiles.alpha_r_v, profiles.alpha_s_v, profiles.beta_v
             h = (profiles.alpha_r_h, profiles.alpha_s_h, profiles.beta_h)
         self.op = tpmg_op_create(self.grid, n_levels, omega2, ar_v, as_v, b_v, *h)
+        if full is not None:
+            tpmg_op_set_full_profiles(self.op, self.grid, full.alpha_r, full.alpha_s, full.beta)
         self.n_levels = tpmg_op_levels(self.op)
         self.mg = None
         self.workspace = None

@@ -148,3 +148,47 @@ def test_tune_cache_file_roundtrip(tmp_path):
     T.tpmg_tune_save(str(tmp_path / "again.json"))
     assert (tmp_path / "again.json").read_text() == text
     T.tpmg_tune_clear()
+
+
+@pytest.mark.parametrize("ref,nz,seed", [(3, 7, 4), (0, 3, 5)])
+def test_full_profile_coefficients_match_oracle(ref, nz, seed):
+    """Profiles that do not factorise (Section 4.2, Appendix A eq.
+    hatFunctionsNonFac): the library's coefficients per (T, k) on every
+    level equal the oracle's (coarse grids from area-weighted means of the
+    children's samples), and the precond_profiles modes are checked."""
+    from oracle import operator as opm
+
+    r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+    om2 = synth.omega_for(max(ref, 1)) ** 2
+    n = synth.n_cells(ref)
+    rng = np.random.default_rng(seed)
+    full = opm.FullProfiles(rng.uniform(0.5, 2.0, (n, nz + 1)), rng.uniform(0.5, 2.0, (n, nz)),
+                            rng.uniform(0.5, 2.0, (n, nz)))
+    prof = synth.profiles_random(nz, n, seed=seed + 10)
+    P = T.Problem(ref, r, om2, profiles=prof, full=full)
+    h = otpmg.build(ref, r, om2, profiles=prof, full=full)
+    assert P.n_levels == len(h.ops)
+    for lvl in range(P.n_levels):
+        c = T.tpmg_op_coefficients_full(P.op, lvl, nz)
+        o = h.ops[lvl]
+        assert np.allclose(c["beta"], o.beta, rtol=1e-13, atol=0)
+        assert np.allclose(c["alpha_s"], o.alpha_s, rtol=1e-12, atol=0)
+        assert np.allclose(c["alpha_r"], o.alpha_r, rtol=1e-13, atol=0)
+        assert np.all(c["alpha_r"][:, 0] == 0) and np.all(c["alpha_r"][:, -1] == 0)
+    # a factorised-only operator has no full coefficients and refuses the
+    # preconditioner modes that need them
+    Q = T.Problem(ref, r, om2, profiles=prof)
+    with pytest.raises(T.TpmgError) as e:
+        T.tpmg_op_coefficients_full(Q.op, 0, nz)
+    assert e.value.status == T.TPMG_ERR_STATE
+    p = T.tpmg_mg_params_default()
+    p.precond_profiles = 3
+    with pytest.raises(T.TpmgError):
+        T.tpmg_mg_workspace_size(P.op, p)
+    bad = full.beta.copy()
+    bad[0, 0] = -1.0
+    with pytest.raises(T.TpmgError) as e:
+        T.tpmg_op_set_full_profiles(Q.op, Q.grid, full.alpha_r, full.alpha_s, bad)
+    assert e.value.status == T.TPMG_ERR_ARG
+    P.close()
+    Q.close()
