@@ -84,6 +84,37 @@ def smooth(op: opmod.LevelOperator, f: np.ndarray, u: np.ndarray, omega: float) 
     return u + omega * thomas_margin(l, m, e, r)
 
 
+def greedy_colouring(nbr: np.ndarray) -> np.ndarray:
+    """Colours of the cells such that neighbours differ: cells in index
+    order, each taking the smallest colour none of its already coloured
+    neighbours has (at most 4 colours on a graph of degree 3)."""
+    n = len(nbr)
+    col = np.full(n, -1, dtype=np.int64)
+    for t in range(n):
+        used = {int(col[j]) for j in nbr[t] if col[j] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        col[t] = c
+    return col
+
+
+def smooth_sor(op: opmod.LevelOperator, f: np.ndarray, u: np.ndarray, omega: float, colours: np.ndarray,
+               reverse: bool = False) -> np.ndarray:
+    """One multicolour block-SOR sweep (eq. BlockJacobi with the cells of one
+    colour relaxed at a time, each colour seeing the updates of the colours
+    before it): for c in colour order, u_T += omega A_T^-1 (f - A u)_T for
+    every cell T of colour c. reverse: colours in descending order."""
+    l, m, e = opmod.column_bands(op)
+    order = range(int(colours.max()) + 1)
+    for c in (reversed(order) if reverse else order):
+        sel = colours == c
+        r = f - opmod.apply(op, u)
+        u = u.copy()
+        u[sel] += omega * thomas_margin(l[sel], m[sel], e[sel], r[sel])
+    return u
+
+
 # ---------------------------------------------------------------------------
 # grid transfers
 # ---------------------------------------------------------------------------
@@ -157,6 +188,7 @@ class Hierarchy:
     nu_coarse: int = 1
     omega: float = 2.0 / 3.0
     dtype: type = np.float64
+    colours: list | None = None   # multicolour block-SOR: colours per level (None: block-Jacobi)
 
     @property
     def finest(self) -> opmod.LevelOperator:
@@ -164,7 +196,15 @@ class Hierarchy:
 
     def astype(self, dtype) -> "Hierarchy":
         return Hierarchy([o.astype(dtype) for o in self.ops], [None if w is None else w.astype(dtype) for w in self.weights],
-                         self.meshes, self.vert, self.nu_pre, self.nu_post, self.nu_coarse, self.omega, dtype)
+                         self.meshes, self.vert, self.nu_pre, self.nu_post, self.nu_coarse, self.omega, dtype,
+                         self.colours)
+
+    def with_sor(self, omega: float = 1.0) -> "Hierarchy":
+        """The same hierarchy with the multicolour block-SOR smoother (the
+        paper's implementation, Section 5: block-SOR with relaxation factor
+        1, here in colour order), colours from greedy_colouring."""
+        return Hierarchy(self.ops, self.weights, self.meshes, self.vert, self.nu_pre, self.nu_post, self.nu_coarse,
+                         omega, self.dtype, [greedy_colouring(o.nbr) for o in self.ops])
 
 
 FULL_TERMS = ("alpha_r", "alpha_s", "beta")
@@ -241,18 +281,25 @@ def vcycle(h: Hierarchy, f: np.ndarray, level: int | None = None) -> np.ndarray:
         level = len(h.ops) - 1
     op = h.ops[level]
     u = np.zeros_like(f)
+
+    def sweep(u, post=False):
+        if h.colours is None:
+            return smooth(op, f, u, h.omega)
+        # colours ascending before the coarse-grid correction, descending after
+        return smooth_sor(op, f, u, h.omega, h.colours[level], reverse=post)
+
     if level == 0:
         for _ in range(h.nu_coarse):
-            u = smooth(op, f, u, h.omega)
+            u = sweep(u)
         return u
     for _ in range(h.nu_pre):
-        u = smooth(op, f, u, h.omega)
+        u = sweep(u)
     r = f - opmod.apply(op, u)
     fc = restrict(r)
     uc = vcycle(h, fc, level - 1)
     u = u + prolong(uc, h.ops[level - 1].nbr, h.weights[level])
     for _ in range(h.nu_post):
-        u = smooth(op, f, u, h.omega)
+        u = sweep(u, post=True)
     return u
 
 
