@@ -49,6 +49,11 @@ class Vertical:
     vk: np.ndarray           # [nz]  (r_{k+1}^3 - r_k^3)/3
     dr: np.ndarray           # [nz]  r_{k+1} - r_k
     face_factor: np.ndarray  # [nz+1] sigma_k 2 r_k^2 / (r_{k+1} - r_{k-1})
+    # vertical advection of cell k through its lower and upper face
+    # (Appendix A): sigma_k r_k^2 (r_{k+1}-r_k)/(r_{k+1}-r_{k-1}) and
+    # sigma_{k+1} r_{k+1}^2 (r_{k+1}-r_k)/(r_{k+2}-r_k), [nz] each
+    adv_lo_factor: np.ndarray | None = None
+    adv_up_factor: np.ndarray | None = None
 
     @property
     def nz(self) -> int:
@@ -64,7 +69,14 @@ def vertical(r: np.ndarray) -> Vertical:
     ff = np.zeros(nz + 1)
     for k in range(1, nz):
         ff[k] = 2.0 * r[k] * r[k] / (r[k + 1] - r[k - 1])
-    return Vertical(r, vk, dr, ff)
+    lo = np.zeros(nz)
+    up = np.zeros(nz)
+    for k in range(nz):
+        if k > 0:
+            lo[k] = r[k] * r[k] * (r[k + 1] - r[k]) / (r[k + 1] - r[k - 1])
+        if k + 1 < nz:
+            up[k] = r[k + 1] * r[k + 1] * (r[k + 1] - r[k]) / (r[k + 2] - r[k])
+    return Vertical(r, vk, dr, ff, lo, up)
 
 
 @dataclass
@@ -75,6 +87,10 @@ class LevelOperator:
     beta: np.ndarray      # beta^_{T,k}
     alpha_s: np.ndarray   # alphaS^_{T,j,k}, coupling to nbr[T, j]
     alpha_r: np.ndarray   # alphar^_{T,k} on radial face k (0 and nz are zero)
+    # vertical advection (None: absent): omega^2 times the coefficients of
+    # the cell's lower and upper face, [n, nz]
+    adv_lo: np.ndarray | None = None
+    adv_up: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -85,7 +101,9 @@ class LevelOperator:
         return self.beta.shape[1]
 
     def astype(self, dtype) -> "LevelOperator":
-        return LevelOperator(self.nbr, self.beta.astype(dtype), self.alpha_s.astype(dtype), self.alpha_r.astype(dtype))
+        cast = (lambda a: None if a is None else a.astype(dtype))
+        return LevelOperator(self.nbr, self.beta.astype(dtype), self.alpha_s.astype(dtype), self.alpha_r.astype(dtype),
+                             cast(self.adv_lo), cast(self.adv_up))
 
 
 def assemble(mesh: Mesh, vert: Vertical, omega2: float, alpha_r_v, alpha_s_v, beta_v,
@@ -122,11 +140,13 @@ class FullProfiles:
     cell and level of a grid, cell-major:
       alpha_r [n, nz+1] at the radial faces (r_k, centre of T),
       alpha_s [n, nz]   at the layer midpoints (r_{k+1/2}, centre of T),
-      beta    [n, nz]   at the layer midpoints (r_{k+1/2}, centre of T)."""
+      beta    [n, nz]   at the layer midpoints (r_{k+1/2}, centre of T),
+      xi_r    [n, nz+1] at the radial faces, or None (no vertical advection)."""
 
     alpha_r: np.ndarray
     alpha_s: np.ndarray
     beta: np.ndarray
+    xi_r: np.ndarray | None = None
 
 
 def restrict_cell_profile(fine_values: np.ndarray, fine_area: np.ndarray) -> np.ndarray:
@@ -139,18 +159,32 @@ def restrict_cell_profile(fine_values: np.ndarray, fine_area: np.ndarray) -> np.
 
 
 def assemble_full(mesh: Mesh, vert: Vertical, omega2: float, alpha_r: np.ndarray, alpha_s: np.ndarray,
-                  beta: np.ndarray) -> LevelOperator:
+                  beta: np.ndarray, xi_r: np.ndarray | None = None) -> LevelOperator:
     """Coefficients of eq. hatFunctionsNonFac from point samples of profiles
     that need not factorise (FullProfiles layout on this mesh). As in the
     factorised case, the horizontal profile on an edge is the mean of its two
-    cells' values (here level by level)."""
+    cells' values (here level by level).
+
+    Vertical advection (xi_r given, Appendix A "Vertical advection"): the
+    cell integral of xi_r d_r u over cell k is taken as the appendix writes
+    it, |T| (r_{k+1}-r_k) times the mean of the two face terms
+    r_f^2 xi_{T,f} (u across face f) / (centre distance across f), f = k,
+    k+1; the operator term is -omega^2 times it:
+      -omega^2 adv_k = adv_up_k (u_k - u_{k+1}) - adv_lo_k (u_k - u_{k-1}),
+      adv_lo_k = omega^2 sigma_k |T| r_k^2 (r_{k+1}-r_k)/(r_{k+1}-r_{k-1}) xi_{T,k},
+      adv_up_k = omega^2 sigma_{k+1} |T| r_{k+1}^2 (r_{k+1}-r_k)/(r_{k+2}-r_k) xi_{T,k+1}."""
     n, nz = mesh.n, vert.nz
     assert alpha_r.shape == (n, nz + 1) and alpha_s.shape == (n, nz) and beta.shape == (n, nz)
     edge = 0.5 * (alpha_s[:, None, :] + alpha_s[mesh.nbr])                    # [n, 3, nz]
     beta_hat = mesh.area[:, None] * vert.vk[None, :] * beta
     alpha_s_hat = omega2 * vert.dr[None, None, :] * mesh.g[:, :, None] * edge
     alpha_r_hat = omega2 * vert.face_factor[None, :] * mesh.area[:, None] * alpha_r
-    return LevelOperator(mesh.nbr, beta_hat, alpha_s_hat, alpha_r_hat)
+    adv_lo = adv_up = None
+    if xi_r is not None:
+        assert xi_r.shape == (n, nz + 1)
+        adv_lo = omega2 * mesh.area[:, None] * vert.adv_lo_factor[None, :] * xi_r[:, :-1]
+        adv_up = omega2 * mesh.area[:, None] * vert.adv_up_factor[None, :] * xi_r[:, 1:]
+    return LevelOperator(mesh.nbr, beta_hat, alpha_s_hat, alpha_r_hat, adv_lo, adv_up)
 
 
 def apply(op: LevelOperator, u: np.ndarray) -> np.ndarray:
@@ -161,6 +195,10 @@ def apply(op: LevelOperator, u: np.ndarray) -> np.ndarray:
     flux = op.alpha_r[:, 1:-1] * (u[:, :-1] - u[:, 1:])   # face k = 1..nz-1
     y[:, :-1] += flux
     y[:, 1:] -= flux
+    if op.adv_lo is not None:
+        d = u[:, :-1] - u[:, 1:]                           # u_k - u_{k+1} across face k+1
+        y[:, :-1] += op.adv_up[:, :-1] * d
+        y[:, 1:] += op.adv_lo[:, 1:] * d                   # -adv_lo (u_k - u_{k-1})
     return y
 
 
@@ -173,6 +211,10 @@ def column_bands(op: LevelOperator):
     """
     l = op.alpha_r[:, :-1]
     m = op.alpha_r[:, 1:]
+    if op.adv_lo is not None:
+        # vertical advection: the couplings differ below and above
+        l = l - op.adv_lo
+        m = m + op.adv_up
     e = op.beta + op.alpha_s.sum(axis=1)
     return l, m, e
 
@@ -182,11 +224,12 @@ def to_sparse(op: LevelOperator) -> sp.csr_matrix:
     n, nz = op.n, op.nz
     idx = np.arange(n * nz).reshape(n, nz)
     rows, cols, vals = [], [], []
-    diag = op.beta + op.alpha_s.sum(axis=1) + op.alpha_r[:, :-1] + op.alpha_r[:, 1:]
+    l, m, e = column_bands(op)
+    diag = e + l + m
     rows.append(idx.ravel()); cols.append(idx.ravel()); vals.append(diag.ravel())
     for j in range(3):
         rows.append(idx.ravel()); cols.append(idx[op.nbr[:, j], :].ravel()); vals.append(-op.alpha_s[:, j, :].ravel())
-    rows.append(idx[:, 1:].ravel()); cols.append(idx[:, :-1].ravel()); vals.append(-op.alpha_r[:, 1:-1].ravel())
-    rows.append(idx[:, :-1].ravel()); cols.append(idx[:, 1:].ravel()); vals.append(-op.alpha_r[:, 1:-1].ravel())
+    rows.append(idx[:, 1:].ravel()); cols.append(idx[:, :-1].ravel()); vals.append(-l[:, 1:].ravel())
+    rows.append(idx[:, :-1].ravel()); cols.append(idx[:, 1:].ravel()); vals.append(-m[:, :-1].ravel())
     a = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n * nz, n * nz))
     return a.tocsr()

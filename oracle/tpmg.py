@@ -208,6 +208,8 @@ class Hierarchy:
 
 
 FULL_TERMS = ("alpha_r", "alpha_s", "beta")
+# the full operator with vertical advection (FullProfiles.xi_r given)
+FULL_TERMS_ADV = FULL_TERMS + ("xi_r",)
 
 
 def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0,
@@ -251,6 +253,8 @@ def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int 
         per_level[ref - 1] = [opmod.restrict_cell_factor(x, fine_area) for x in per_level[ref]]
     full_level = {}
     if full is not None and full_terms:
+        if "xi_r" in full_terms and getattr(full, "xi_r", None) is None:
+            full_terms = tuple(k for k in full_terms if k != "xi_r")
         full_level[refinement] = {k: np.asarray(getattr(full, k), dtype=np.float64) for k in full_terms}
         for ref in range(refinement, levels[0], -1):
             full_level[ref - 1] = {k: opmod.restrict_cell_profile(v, meshes[ref].area)
@@ -267,7 +271,8 @@ def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int 
                    "beta": b[:, None] * np.asarray(b_v)[None, :]}
             fac.update(fl)
             assert fac["alpha_r"].shape == (n, nz + 1)
-            op = opmod.assemble_full(meshes[ref], vert, omega2, fac["alpha_r"], fac["alpha_s"], fac["beta"])
+            op = opmod.assemble_full(meshes[ref], vert, omega2, fac["alpha_r"], fac["alpha_s"], fac["beta"],
+                                     fl.get("xi_r"))
         ops.append(op)
         used.append(meshes[ref])
     for i in range(1, len(levels)):
@@ -366,13 +371,84 @@ def fcg(apply_a, precond, f: np.ndarray, x0: np.ndarray | None = None, rtol: flo
     return SolveResult(x, maxit, "maxit", hist)
 
 
+def richardson(apply_a, precond, f: np.ndarray, x0: np.ndarray | None = None, rtol: float = 1e-8,
+               maxit: int = 100) -> SolveResult:
+    """Preconditioned Richardson iteration (Section 3.2.2, Section 5.2):
+    x_{k+1} = x_k + M (f - A x_k), stopping when ||f - A x_k|| <= rtol ||f||
+    (k corrections applied)."""
+    x = np.zeros_like(f) if x0 is None else x0.astype(np.float64).copy()
+    fnorm = math.sqrt(float(np.sum(f * f)))
+    hist = []
+    for it in range(maxit + 1):
+        r = f - apply_a(x)
+        rnorm = math.sqrt(float(np.sum(r * r)))
+        hist.append(rnorm / fnorm if fnorm > 0 else 0.0)
+        if not math.isfinite(rnorm):
+            return SolveResult(x, it, "breakdown", hist)
+        if rnorm <= rtol * fnorm:
+            return SolveResult(x, it, "converged", hist)
+        if it == maxit:
+            break
+        x = x + precond(r)
+    return SolveResult(x, maxit, "maxit", hist)
+
+
+def bicgstab(apply_a, precond, f: np.ndarray, x0: np.ndarray | None = None, rtol: float = 1e-8,
+             maxit: int = 100) -> SolveResult:
+    """Right-preconditioned BiCGStab (van der Vorst; the paper's second outer
+    solver, Section 5.2: two operator applications and two preconditioner
+    applications per iteration). r0 = f - A x0, shadow residual r^ = r0;
+    per iteration: rho = <r^, r>, beta = (rho / rho_prev)(alpha / w),
+    p = r + beta (p - w v), y = M p, v = A y, alpha = rho / <r^, v>,
+    s = r - alpha v, z = M s, t = A z, w = <t, s> / <t, t>,
+    x += alpha y + w z, r = s - w t; stop when ||r|| <= rtol ||f||
+    (tested once per iteration)."""
+    x = np.zeros_like(f) if x0 is None else x0.astype(np.float64).copy()
+    fnorm = math.sqrt(float(np.sum(f * f)))
+    r = f - apply_a(x)
+    rnorm = math.sqrt(float(np.sum(r * r)))
+    hist = [rnorm / fnorm if fnorm > 0 else 0.0]
+    if rnorm <= rtol * fnorm:
+        return SolveResult(x, 0, "converged", hist)
+    rh = r.copy()
+    rho_prev = alpha = w = 1.0
+    p = np.zeros_like(f)
+    v = np.zeros_like(f)
+    for it in range(maxit):
+        rho = float(np.sum(rh * r))
+        if rho == 0.0 or not math.isfinite(rho):
+            return SolveResult(x, it, "breakdown", hist)
+        beta = (rho / rho_prev) * (alpha / w)
+        p = r + beta * (p - w * v)
+        y = precond(p)
+        v = apply_a(y)
+        alpha = rho / float(np.sum(rh * v))
+        s = r - alpha * v
+        z = precond(s)
+        t = apply_a(z)
+        tt = float(np.sum(t * t))
+        w = float(np.sum(t * s)) / tt if tt > 0 else 0.0
+        x = x + alpha * y + w * z
+        r = s - w * t
+        rnorm = math.sqrt(float(np.sum(r * r)))
+        hist.append(rnorm / fnorm)
+        if not math.isfinite(rnorm) or w == 0.0:
+            return SolveResult(x, it + 1, "breakdown", hist)
+        if rnorm <= rtol * fnorm:
+            return SolveResult(x, it + 1, "converged", hist)
+        rho_prev = rho
+    return SolveResult(x, maxit, "maxit", hist)
+
+
 def solve(h: Hierarchy, f: np.ndarray, x0=None, rtol=1e-8, maxit=100, precision="fp64",
-          outer: opmod.LevelOperator | None = None) -> SolveResult:
-    """TPMG-preconditioned FCG on the finest level of h. outer: the operator
-    of the equation when it differs from the one the V-cycle is built on
-    (TPMG^(x) or TPMG^(partial) for non-factorising profiles, Section 3.2.2)."""
+          outer: opmod.LevelOperator | None = None, method: str = "fcg") -> SolveResult:
+    """TPMG-preconditioned FCG (or "bicgstab", "richardson") on the finest
+    level of h. outer: the operator of the equation when it differs from the
+    one the V-cycle is built on (TPMG^(x) or TPMG^(partial) for
+    non-factorising profiles, Section 3.2.2)."""
     op = h.finest if outer is None else outer
-    return fcg(lambda v: opmod.apply(op, v), make_preconditioner(h, precision), f, x0, rtol, maxit)
+    solver = {"fcg": fcg, "bicgstab": bicgstab, "richardson": richardson}[method]
+    return solver(lambda v: opmod.apply(op, v), make_preconditioner(h, precision), f, x0, rtol, maxit)
 
 
 def richardson_rate(h: Hierarchy, seed: int = 7, cycles: int = 12, skip: int = 4, precision="fp64",
