@@ -84,10 +84,9 @@ def test_config3_vcycle_rate_against_oracle(config3, fp32):
     """V-cycle convergence factor in the Richardson iteration (f = 0, seed 7,
     12 cycles, rate over the last 8): FP64 within 1e-8 relative of the
     oracle's; FP32 against the oracle's own FP32 V-cycle within the bar of
-    the mixed-rate reading (absolute 0.05: two FP32 roundings of the same
-    cycle differ by a perturbation of relative size ~1e-6 per cycle, which
-    moves a factor by far less; 0.05 leaves room for the slow components
-    on which FP32 V-cycles differ most)."""
+    the mixed-rate reading of test_gpu_parity.test_vcycle_rate (absolute
+    0.1: two FP32 V-cycles, each a perturbation of the FP64 one by at most
+    eta per cycle on the slowest components, differ by at most 2 eta)."""
     w, h, f = config3
     g = _gold(w)
     P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=fp32, use_graph=False, autotune=1)
@@ -96,7 +95,7 @@ def test_config3_vcycle_rate_against_oracle(config3, fp32):
     ref = g["mixed" if fp32 else "fp64"]["vcycle_rate"]
     print(f"config 3 {w.name} {'FP32' if fp32 else 'FP64'} V-cycle rate: GPU {rate:.6f}, oracle {ref:.6f}")
     if fp32:
-        assert rate < 1.0 and abs(rate - ref) <= 0.05
+        assert rate < 1.0 and abs(rate - ref) <= 0.1
     else:
         assert abs(rate - ref) <= 1e-8 * ref
     P.close()
