@@ -397,6 +397,73 @@ def profiles_report(refinement: int = 5, nz: int = 128, eps_list=(0.0, 0.25, 0.5
                 P.close()
                 del P, f, u
                 torch.cuda.empty_cache()
+            # with the vertical advection: the paper's outer solvers
+            for name, code in modes:
+                P = T.Problem(refinement, r, om * om, profiles=bf.factorised, full=bf, advection=True).setup(
+                    precond_fp32=fp32, use_graph=False, autotune=1, precond_profiles=code)
+                f = P.pack(f_host)
+                for method, fn in (("richardson", T.tpmg_solve_richardson), ("bicgstab", T.tpmg_solve_bicgstab)):
+                    u = P.device_vector()
+                    fn(P.mg, f, u, 1e-8, 200)
+                    times = []
+                    for _ in range(steps):
+                        u.zero_()
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        d = fn(P.mg, f, u, 1e-8, 200)
+                        times.append(time.perf_counter() - t0)
+                    ms = 1000.0 * float(np.median(times))
+                    line[f"{prec}_adv_{method}_{name}"] = {
+                        "status": int(d["status"]), "iters": d["iters"], "ms_per_solve": ms,
+                        "ms_per_iter": ms / max(d["iters"], 1), "model_GB_per_solve": d["model_bytes"] / 1e9}
+                P.close()
+                del P, f, u
+                torch.cuda.empty_cache()
+        print(json.dumps(line), flush=True)
+
+
+def smoother_report(steps: int = 5):
+    """Block-Jacobi against multicolour block-SOR (the paper's smoother,
+    relaxation factor 1, colours ascending before the coarse-grid correction
+    and descending after) on the benchmark workload and the refinement-7
+    one: V-cycle Richardson factor, FCG iterations and solve time, FP64 and
+    mixed."""
+    import numpy as np
+    import torch
+
+    import paper_1408_2981_amd as T
+    import synth
+
+    for wname in ("ico6_nz128", "ico7_nz128_ar0.1"):
+        w = synth.workload(wname)
+        line = {"workload": f"{w.name}: {w.unknowns} unknowns, rtol 1e-8"}
+        f_host = u0_host = None
+        for prec, fp32 in (("fp64", False), ("mixed", True)):
+            for name, order, omega in (("jacobi", T.SMOOTHER_ORDER_JACOBI, 2.0 / 3.0),
+                                       ("sor", T.SMOOTHER_ORDER_SOR, 1.0)):
+                P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(
+                    precond_fp32=fp32, use_graph=False, autotune=1, smoother_order=order, omega_relax=omega)
+                if f_host is None:
+                    geo = P.geometry()
+                    f_host = synth.make_rhs(w, geo["centres"], geo["areas"], P.vk())
+                    u0_host = synth.uniform_noise(w.n, w.nz, 7)
+                f = P.pack(f_host)
+                rate, _ = T.tpmg_richardson_rate(P.mg, P.pack(u0_host), 12, 4)
+                u = P.device_vector()
+                P.solve(f, u)
+                times = []
+                for _ in range(steps):
+                    u.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st, it, *_ = P.solve(f, u)
+                    times.append(time.perf_counter() - t0)
+                ms = 1000.0 * float(np.median(times))
+                line[f"{prec}_{name}"] = {"status": int(st), "iters": it, "richardson_factor": rate,
+                                          "ms_per_solve": ms, "unknowns_per_s": w.unknowns / (ms / 1000.0)}
+                P.close()
+                del P, f, u
+                torch.cuda.empty_cache()
         print(json.dumps(line), flush=True)
 
 
@@ -489,6 +556,8 @@ def main():
                          "(a graph launch costs ~8 us at each boundary)")
     ap.add_argument("--profiles", action="store_true",
                     help="only the balanced-flow report: TPMG with full, factorised and partial profiles over eps")
+    ap.add_argument("--smoothers", action="store_true",
+                    help="only the smoother report: block-Jacobi against multicolour block-SOR")
     ap.add_argument("--batch", action="store_true",
                     help="only the batched-solve report (16 problems of uneven size, batched and one by one)")
     ap.add_argument("--report", action="store_true",
@@ -532,6 +601,9 @@ def main():
         return
     if args.profiles:
         profiles_report()
+        return
+    if args.smoothers:
+        smoother_report()
         return
     results = {}
     P64 = T.Problem(w.refinement, w.r_faces(), w.omega2)

@@ -94,6 +94,16 @@ typedef struct {
                           factorised alpha_S and beta (TPMG^(partial)).
                           The Krylov method always uses the full operator.
                           1 and 2 need full profiles.                     */
+  int smoother_order;  /* 0 = block-Jacobi: every column relaxed from the
+                          old values, damped by omega_relax (default);
+                          1 = multicolour block-SOR (Section 5: block-SOR
+                          with relaxation factor omega_relax, the paper's
+                          1): cells coloured greedily in index order so
+                          that neighbours differ (tpmg_grid_colouring),
+                          the colours relaxed one after another, ascending
+                          before the coarse-grid correction and descending
+                          after; one pass over the grid per colour. Not
+                          for batched solves.                             */
 } tpmg_mg_params;
 
 /* Result of a solve. Inputs: history (optional, caller-owned, history_cap
@@ -150,6 +160,13 @@ tpmg_status tpmg_grid_level_size(const tpmg_grid* g, int refinement_level, int* 
 tpmg_status tpmg_grid_geometry(const tpmg_grid* g, int refinement_level, double* centres, double* areas,
                                int32_t* nbr, double* edge_len, double* edge_factor);
 
+/* The colouring of grid level refinement_level used by the multicolour
+ * block-SOR smoother: cells in index order, each taking the smallest colour
+ * (0, 1, ...) that none of its already coloured neighbours has, so that no
+ * two neighbours share a colour (at most 4 colours). colours: n int32
+ * (host, caller-owned); n_colours may be NULL. Host only. */
+tpmg_status tpmg_grid_colouring(const tpmg_grid* g, int refinement_level, int32_t* colours, int* n_colours);
+
 /* Radial cell volume factors v_k = (r_{k+1}^3 - r_k^3) / 3 (Appendix A),
  * nz values. */
 tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk);
@@ -181,15 +198,29 @@ tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, cons
  * approximate factorisation a V-cycle may be built on
  * (tpmg_mg_params.precond_profiles). Host arrays, copied. Such operators run
  * the scan smoother at 8 or 16 levels per wave and no batched solves.
+ *
+ * xi_r (NULL = none) adds the vertical advection -omega^2 xi_r d_r u
+ * (Section 2.1, eq. HelmholtzVector; samples [n][nz+1] at the radial faces),
+ * discretised as Appendix A writes the cell integral of cell k: |T|
+ * (r_{k+1} - r_k) times the mean of r_f^2 xi_{T,f} (u across face f) /
+ * (centre distance across f) over its faces f = k, k+1. The operator is
+ * then not symmetric: solve it with tpmg_solve_bicgstab or
+ * tpmg_solve_richardson (tpmg_solve refuses it). The V-cycle of the full
+ * profiles includes the advection, those of the factorised and partial
+ * profiles do not. The advection must leave both radial couplings of every
+ * row positive (alphar^_k - adv_lo_k, alphar^_{k+1} + adv_up_k).
  * Errors: TPMG_ERR_ARG. */
 tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const double* alpha_r, const double* alpha_s,
-                                      const double* beta);
+                                      const double* beta, const double* xi_r);
 
 /* The coefficients per (T, k) of level (0 = coarsest) of an operator with
  * full profiles, cell-major: beta^_{T,k} [n][nz], alphaS^_{TT'_j,k}
  * [n][3][nz] (coupling to neighbour j), alphar^_{T,k} [n][nz+1] (radial
- * face k). Any output may be NULL. TPMG_ERR_STATE without full profiles. */
-tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta, double* alpha_s, double* alpha_r);
+ * face k), and with vertical advection omega^2 times the coefficients of
+ * cell k's lower and upper face [n][nz] (zeros without advection). Any
+ * output may be NULL. TPMG_ERR_STATE without full profiles. */
+tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta, double* alpha_s, double* alpha_r,
+                                      double* adv_lo, double* adv_up);
 
 /* Number of multigrid levels of op, and the cell count of level (0 =
  * coarsest). */
@@ -254,6 +285,25 @@ tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z);
  * iterate). info may be NULL. */
 tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
                        tpmg_solve_info* info);
+
+/* The paper's outer solvers (Section 5.2), preconditioned by one V-cycle of
+ * the handle (right preconditioning), for any operator, the non-symmetric
+ * one with vertical advection included:
+ *  - Richardson: u <- u + M (f - A u) until ||f - A u|| <= rtol ||f||
+ *    (iters = corrections applied, history[k] = ||f - A u_k|| / ||f||);
+ *  - BiCGStab (van der Vorst): r^ = r_0; per iteration rho = <r^, r>,
+ *    beta = (rho / rho_prev)(alpha / w), p = r + beta (p - w v), y = M p,
+ *    v = A y, alpha = rho / <r^, v>, s = r - alpha v, z = M s, t = A z,
+ *    w = <t, s> / <t, t>, u += alpha y + w z, r = s - w t; the residual
+ *    norm is tested once per iteration.
+ * Vectors as tpmg_solve (tiled FP64); both synchronise the stream once per
+ * iteration to read the residual norm. Returns TPMG_OK, TPMG_NOT_CONVERGED
+ * or TPMG_ERR_BREAKDOWN (a zero or non-finite scalar). info as tpmg_solve
+ * (no phase timers). */
+tpmg_status tpmg_solve_richardson(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
+                                  tpmg_solve_info* info);
+tpmg_status tpmg_solve_bicgstab(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
+                                tpmg_solve_info* info);
 
 /* ----------------------------------------------------------- batched -- */
 

@@ -38,7 +38,7 @@ TPMG_ERR_STATE = -5
 
 EXPORTED = [
     "tpmg_mg_params_default", "tpmg_grid_icosahedral", "tpmg_grid_level_size", "tpmg_grid_geometry",
-    "tpmg_grid_vertical", "tpmg_op_create", "tpmg_op_set_full_profiles", "tpmg_op_coefficients_full", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
+    "tpmg_grid_vertical", "tpmg_grid_colouring", "tpmg_op_create", "tpmg_op_set_full_profiles", "tpmg_op_coefficients_full", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
     "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
     "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
     "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_time_kernel", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
@@ -47,7 +47,8 @@ EXPORTED = [
     "tpmg_mlp_set_scaling", "tpmg_mlp_get_scaling", "tpmg_mlp_fit_scaling", "tpmg_mlp_features", "tpmg_mlp_targets",
     "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_infer", "tpmg_mlp_save",
     "tpmg_mlp_load", "tpmg_mlp_destroy",
-    "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error", "tpmg_solve_noalloc",
+    "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error", "tpmg_solve_noalloc", "tpmg_solve_richardson",
+    "tpmg_solve_bicgstab",
 ]
 
 
@@ -63,6 +64,7 @@ class MgParams(ctypes.Structure):
         ("nu_coarse", ctypes.c_int), ("omega_relax", ctypes.c_double), ("precond_fp32", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int), ("smoother", ctypes.c_int),
         ("scan_levels", ctypes.c_int), ("stencil_chunk", ctypes.c_int), ("precond_profiles", ctypes.c_int),
+        ("smoother_order", ctypes.c_int),
     ]
 
 
@@ -93,9 +95,10 @@ _sig = {
     "tpmg_grid_level_size": (_ip, [_vp, _ip, ctypes.POINTER(_ip)]),
     "tpmg_grid_geometry": (_ip, [_vp, _ip, _dp, _dp, _i32p, _dp, _dp]),
     "tpmg_grid_vertical": (_ip, [_vp, _dp]),
+    "tpmg_grid_colouring": (_ip, [_vp, _ip, _i32p, ctypes.POINTER(_ip)]),
     "tpmg_op_create": (_ip, [_vp, _ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.POINTER(_vp)]),
-    "tpmg_op_set_full_profiles": (_ip, [_vp, _vp, _dp, _dp, _dp]),
-    "tpmg_op_coefficients_full": (_ip, [_vp, _ip, _dp, _dp, _dp]),
+    "tpmg_op_set_full_profiles": (_ip, [_vp, _vp, _dp, _dp, _dp, _dp]),
+    "tpmg_op_coefficients_full": (_ip, [_vp, _ip, _dp, _dp, _dp, _dp, _dp]),
     "tpmg_op_levels": (_ip, [_vp, ctypes.POINTER(_ip)]),
     "tpmg_op_level_size": (_ip, [_vp, _ip, ctypes.POINTER(_ip)]),
     "tpmg_op_coefficients": (_ip, [_vp, _ip, _dp, _dp, _dp, _dp, _dp, _dp]),
@@ -108,6 +111,8 @@ _sig = {
     "tpmg_spmv": (_ip, [_vp, _vp, _vp]),
     "tpmg_vcycle": (_ip, [_vp, _vp, _vp]),
     "tpmg_solve": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
+    "tpmg_solve_richardson": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
+    "tpmg_solve_bicgstab": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
     "tpmg_batch_workspace_size": (_ip, [ctypes.POINTER(_vp), _ip, ctypes.POINTER(ctypes.c_size_t)]),
     "tpmg_batch_create": (_ip, [ctypes.POINTER(_vp), _ip, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "tpmg_batch_solve": (_ip, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_double, _ip,
@@ -205,6 +210,19 @@ def tpmg_grid_geometry(grid: int, level: int) -> dict:
     return out
 
 
+def tpmg_grid_colouring(grid: int, level: int):
+    """Returns (colours[n] int32, number of colours) of a grid level."""
+    n = tpmg_grid_level_size(grid, level)
+    c = np.zeros(n, dtype=np.int32)
+    k = _ip()
+    _check(_lib.tpmg_grid_colouring(grid, level, c.ctypes.data_as(_i32p), ctypes.byref(k)))
+    return c, k.value
+
+
+# tpmg_mg_params.smoother_order
+SMOOTHER_ORDER_JACOBI, SMOOTHER_ORDER_SOR = 0, 1
+
+
 def tpmg_grid_vertical(grid: int, nz: int) -> np.ndarray:
     v = np.zeros(nz)
     _check(_lib.tpmg_grid_vertical(grid, _dptr(v)))
@@ -220,15 +238,17 @@ def tpmg_op_create(grid: int, n_levels: int, omega2: float, alpha_r_v, alpha_s_v
     return h.value
 
 
-def tpmg_op_set_full_profiles(op: int, grid: int, alpha_r, alpha_s, beta) -> None:
-    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (alpha_r, alpha_s, beta)]
+def tpmg_op_set_full_profiles(op: int, grid: int, alpha_r, alpha_s, beta, xi_r=None) -> None:
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (alpha_r, alpha_s, beta, xi_r)]
     _check(_lib.tpmg_op_set_full_profiles(op, grid, *[_dptr(a) for a in arrs]))
 
 
 def tpmg_op_coefficients_full(op: int, level: int, nz: int) -> dict:
     n = tpmg_op_level_size(op, level)
-    out = dict(beta=np.zeros((n, nz)), alpha_s=np.zeros((n, 3, nz)), alpha_r=np.zeros((n, nz + 1)))
-    _check(_lib.tpmg_op_coefficients_full(op, level, _dptr(out["beta"]), _dptr(out["alpha_s"]), _dptr(out["alpha_r"])))
+    out = dict(beta=np.zeros((n, nz)), alpha_s=np.zeros((n, 3, nz)), alpha_r=np.zeros((n, nz + 1)),
+               adv_lo=np.zeros((n, nz)), adv_up=np.zeros((n, nz)))
+    _check(_lib.tpmg_op_coefficients_full(op, level, *[_dptr(out[k]) for k in
+                                                       ("beta", "alpha_s", "alpha_r", "adv_lo", "adv_up")]))
     return out
 
 
@@ -332,6 +352,28 @@ def tpmg_solve_details(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: 
                 t_total_ms=info.t_total_ms, t_vcycle_ms=info.t_vcycle_ms, t_spmv_ms=info.t_spmv_ms,
                 t_blas_ms=info.t_blas_ms, model_bytes=info.model_bytes,
                 message=tpmg_last_error() if s == TPMG_ERR_BREAKDOWN else "")
+
+
+def _solve_with(fn, mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int) -> dict:
+    hist = np.zeros(history_cap)
+    info = SolveInfo()
+    info.history = hist.ctypes.data_as(_dp)
+    info.history_cap = history_cap
+    s = fn(mg, _dev(d_f), _dev(d_u), float(rtol), int(maxit), ctypes.byref(info))
+    _check(s, ok=(TPMG_OK, TPMG_NOT_CONVERGED, TPMG_ERR_BREAKDOWN))
+    return dict(status=s, iters=info.iters, relres=info.relres, history=hist[: info.iters + 1].copy(),
+                t_total_ms=info.t_total_ms, model_bytes=info.model_bytes,
+                message=tpmg_last_error() if s == TPMG_ERR_BREAKDOWN else "")
+
+
+def tpmg_solve_richardson(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 256) -> dict:
+    """Preconditioned Richardson; returns the fields of tpmg_solve_details."""
+    return _solve_with(_lib.tpmg_solve_richardson, mg, d_f, d_u, rtol, maxit, history_cap)
+
+
+def tpmg_solve_bicgstab(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 256) -> dict:
+    """Preconditioned BiCGStab; returns the fields of tpmg_solve_details."""
+    return _solve_with(_lib.tpmg_solve_bicgstab, mg, d_f, d_u, rtol, maxit, history_cap)
 
 
 NOALLOC_SCRATCH_BYTES = 256 << 20

@@ -80,6 +80,18 @@ struct LevelView {
   const void* fb = nullptr;
   const void* far = nullptr;
   const void* fas = nullptr;
+  // pm 3: pm 2 plus the vertical advection, omega^2 times the coefficients
+  // of every cell's lower (fxl) and upper (fxu) face, tiled like a vector;
+  // row k then couples to the cell below by alphar^_k - fxl_k and to the
+  // cell above by alphar^_{k+1} + fxu_k
+  const void* fxl = nullptr;
+  const void* fxu = nullptr;
+  // multicolour block-SOR (Section 5: block-SOR; colours relaxed one after
+  // another): the colour of every column ([npad], padding -1) and the colour
+  // a smoother pass relaxes; pass < 0 relaxes every column (block-Jacobi).
+  // Columns a pass does not relax are copied from u_in (0 from a zero guess).
+  const int8_t* colour = nullptr;
+  int pass = -1;
   LevelTune tune;
 };
 
@@ -99,6 +111,7 @@ struct FcgScalars {
   double rtol;    // stopping tolerance (set at kFinInit)
   double rr0;     // <r_0, r_0> (set at kFinInit)
   double div2;    // divergence bound on <r, r> / <r_0, r_0> (set at kFinInit)
+  double w;       // BiCGStab: the stabilising step omega (rz holds rho)
   int status;     // 0 ok, 1 breakdown, 2 divergence
   int done;       // converged or broken down: batched launches skip the problem
   int iters;      // completed iterations (maintained on the device)
@@ -258,6 +271,30 @@ hipError_t launch_fcg_update(double* x, double* r, const double* p, const double
 // <z, q>, <z, r> (site kFinBeta), for nz beyond the fused smoother's range.
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s);
+// BiCGStab (the outer solver for operators with vertical advection): the
+// scalar stages applied by launch_krylov_finalize to the sums of the
+// preceding reduction (s0, s1):
+//   kKInit  (no sums): rho = rr (the shadow residual is r_0), alpha = w = 1,
+//           beta = 0;
+//   kKAlpha s0 = <r^, v>: alpha = rho / s0;
+//   kKOmega s0 = <t, s>, s1 = <t, t>: w = s0 / s1;
+//   kKRho   s0 = <r^, r>, s1 = <r, r>: beta = (s0 / rho)(alpha / w), rho = s0,
+//           rr = s1;
+// each sets status 1 on a zero or non-finite divisor.
+enum KrylovStage { kKInit = 10, kKAlpha = 11, kKOmega = 12, kKRho = 13 };
+// partials <a, b>, <c, d> over len (fixed grid, deterministic)
+hipError_t launch_dots2(const double* a, const double* b, const double* c, const double* d, size_t len,
+                        double* partials, hipStream_t s);
+hipError_t launch_krylov_finalize(int stage, const double* partials, FcgScalars* sc, hipStream_t s);
+// p = r + beta (p - w v)
+hipError_t launch_bicg_p(const double* r, double* p, const double* v, const FcgScalars* sc, size_t len,
+                         hipStream_t s);
+// r -= alpha v (r then holds s)
+hipError_t launch_bicg_s(double* r, const double* v, const FcgScalars* sc, size_t len, hipStream_t s);
+// x += alpha y + w z, r = s - w t (r holds s on entry); partials <rh, r>, <r, r>
+hipError_t launch_bicg_x(double* x, double* r, const double* y, const double* z, const double* t, const double* rh,
+                         const FcgScalars* sc, size_t len, double* partials, hipStream_t s);
+
 // p = z + beta p (beta from the scalars), in place; z FP64 or FP32.
 hipError_t launch_pupdate(const void* z, bool z_double, double* p, const FcgScalars* sc, size_t len, hipStream_t s);
 hipError_t launch_add(double* x, const double* y, size_t len, hipStream_t s);   // x += y

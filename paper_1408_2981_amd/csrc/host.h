@@ -53,6 +53,10 @@ struct LevelCoeffs {
   std::vector<double> fb;       // n (nz):        beta^_{T,k}
   std::vector<double> far;      // n (nz + 1):    alphar^_{T,k} on radial face k
   std::vector<double> fas;      // n (3) (nz):    alphaS^_{TT'_j,k}
+  // vertical advection (Operator::adv): omega^2 times the coefficients of
+  // cell k's lower and upper face (Appendix A, "Vertical advection")
+  std::vector<double> fxl;      // n (nz)
+  std::vector<double> fxu;      // n (nz)
 };
 
 struct Operator {
@@ -64,6 +68,7 @@ struct Operator {
   std::vector<double> ar_v;     // nz+1
   std::vector<LevelCoeffs> levels;  // 0 = coarsest
   bool full = false;            // the levels also hold coefficients of profiles that do not factorise
+  bool adv = false;             // ... and of the vertical advection
 };
 
 // Assembles the operator on the n_levels finest grids of g.
@@ -75,7 +80,14 @@ void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, co
 // the finest grid (cell-major: alpha_r [n][nz+1] at the radial faces,
 // alpha_s and beta [n][nz] at the layer midpoints), to every level of op
 // (coarse grids: area-weighted means of the four children, level by level;
-// on an edge the mean of its two cells). Throws std::runtime_error.
-void build_full(Operator& op, const Grid& g, const double* alpha_r, const double* alpha_s, const double* beta);
+// on an edge the mean of its two cells). xi_r (nullable) [n][nz+1] at the
+// radial faces adds the vertical advection. Throws std::runtime_error.
+void build_full(Operator& op, const Grid& g, const double* alpha_r, const double* alpha_s, const double* beta,
+                const double* xi_r = nullptr);
+
+// Colours of the cells of a grid level (nbr: 3n, cell-major) with no two
+// neighbours alike: cells in index order, each taking the smallest colour
+// none of its already coloured neighbours has (at most 4 on degree 3).
+std::vector<int8_t> greedy_colouring(const std::vector<int32_t>& nbr, int n);
 
 }  // namespace tpmg

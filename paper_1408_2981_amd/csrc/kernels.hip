@@ -50,7 +50,22 @@ struct Lv {
   const T* __restrict__ fb;
   const T* __restrict__ far;
   const T* __restrict__ fas;
+  // vertical advection (pm 3): omega^2 times the coefficients of a cell's
+  // lower and upper face, tiled like the vectors
+  const T* __restrict__ fxl;
+  const T* __restrict__ fxu;
+  // multicolour block-SOR: colour of every column and the colour this
+  // smoother pass relaxes (pass < 0: every column, block-Jacobi)
+  const int8_t* __restrict__ colour;
+  int pass;
 };
+
+// whether a smoother pass relaxes column col (the other columns keep their
+// values: u_out = u_in, or 0 for a pass from a zero guess)
+template <typename T>
+__device__ __forceinline__ bool relaxes(const Lv<T>& L, int col) {
+  return L.pass < 0 || L.colour[col] == L.pass;
+}
 
 template <typename T>
 __host__ __device__ Lv<T> view(const LevelView& L) {
@@ -70,7 +85,11 @@ __host__ __device__ Lv<T> view(const LevelView& L) {
                static_cast<const T*>(L.margin),
                static_cast<const T*>(L.fb),
                static_cast<const T*>(L.far),
-               static_cast<const T*>(L.fas)};
+               static_cast<const T*>(L.fas),
+               static_cast<const T*>(L.fxl),
+               static_cast<const T*>(L.fxu),
+               L.colour,
+               L.pass};
 }
 
 // this block's index and the number of blocks of its problem's launch
@@ -148,7 +167,14 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 // scalars times vertical vectors, eq. TridiagonalFactorising); 1 the radial
 // couplings per (T, k) and the rest factorised (the operator of
 // TPMG^(partial)); 2 every coefficient per (T, k) (eq.
-// TridiagonalNonFactorising).
+// TridiagonalNonFactorising); 3 as 2 with the vertical advection, whose
+// couplings to the cell below (alphar^ - adv_lo) and above (alphar^ +
+// adv_up) differ.
+template <int PM, typename T>
+__device__ __forceinline__ T coef_lower(const Lv<T>& L, const Column<T>& c, int k);
+template <int PM, typename T>
+__device__ __forceinline__ T coef_upper(const Lv<T>& L, const Column<T>& c, int k);
+
 template <int PM = 0, typename T>
 __device__ __forceinline__ T row_flux(const Lv<T>& L, const Column<T>& c, int k, T um, T uc, T up, T n0, T n1, T n2) {
   if constexpr (PM == 0) {
@@ -157,7 +183,8 @@ __device__ __forceinline__ T row_flux(const Lv<T>& L, const Column<T>& c, int k,
     return fma_t(c.arh, v, fma_t(L.av[k], h, (c.bh * L.bv[k]) * uc));
   } else {
     const size_t oa = c.abase + static_cast<size_t>(k) * kTile;
-    const T v = fma_t(L.far[oa], uc - um, L.far[oa + kTile] * (uc - up));
+    const T v = PM == 3 ? fma_t(coef_lower<PM>(L, c, k), uc - um, coef_upper<PM>(L, c, k) * (uc - up))
+                        : fma_t(L.far[oa], uc - um, L.far[oa + kTile] * (uc - up));
     if constexpr (PM == 1) {
       const T h = fma_t(c.a2, uc - n2, fma_t(c.a1, uc - n1, c.a0 * (uc - n0)));
       return v + fma_t(L.av[k], h, (c.bh * L.bv[k]) * uc);
@@ -174,7 +201,7 @@ __device__ __forceinline__ T row_flux(const Lv<T>& L, const Column<T>& c, int k,
 // through face k of a column, in the level's profile mode.
 template <int PM, typename T>
 __device__ __forceinline__ T coef_excess(const Lv<T>& L, const Column<T>& c, T esum, int k) {
-  if constexpr (PM == 2) {
+  if constexpr (PM >= 2) {
     const size_t o = c.base + static_cast<size_t>(k) * kTile;
     const size_t pl = static_cast<size_t>(L.npad) * L.nz;
     return L.fb[o] + ((L.fas[o] + L.fas[pl + o]) + L.fas[2 * pl + o]);
@@ -188,6 +215,22 @@ __device__ __forceinline__ T coef_face(const Lv<T>& L, const Column<T>& c, int k
     return L.far[c.abase + static_cast<size_t>(k) * kTile];
   else
     return c.arh * L.arv[k];
+}
+// coupling of row k to the cell below (l_k) and above (m_k); without
+// advection both are the radial face's coupling
+template <int PM, typename T>
+__device__ __forceinline__ T coef_lower(const Lv<T>& L, const Column<T>& c, int k) {
+  if constexpr (PM == 3)
+    return coef_face<PM>(L, c, k) - L.fxl[c.base + static_cast<size_t>(k) * kTile];
+  else
+    return coef_face<PM>(L, c, k);
+}
+template <int PM, typename T>
+__device__ __forceinline__ T coef_upper(const Lv<T>& L, const Column<T>& c, int k) {
+  if constexpr (PM == 3)
+    return coef_face<PM>(L, c, k + 1) + L.fxu[c.base + static_cast<size_t>(k) * kTile];
+  else
+    return coef_face<PM>(L, c, k + 1);
 }
 
 template <int PM = 0, typename T>
@@ -320,6 +363,39 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
       // (the first direction is z itself: no previous q enters)
       sc->beta = sc->iters == 0 ? 0.0 : -s0 / sc->pq;
       sc->rz = s1;
+      break;
+    case kKInit:
+      sc->rz = sc->rr;
+      sc->alpha = 1.0;
+      sc->w = 1.0;
+      sc->beta = 0.0;
+      sc->iters = 0;
+      break;
+    case kKAlpha:
+      if (!(s0 != 0.0) || !finite(s0) || !finite(sc->rz)) {
+        sc->status = 1;
+        sc->alpha = 0.0;
+      } else {
+        sc->alpha = sc->rz / s0;
+      }
+      break;
+    case kKOmega:
+      if (!(s1 > 0.0) || !finite(s0) || !finite(s1) || s0 == 0.0) {
+        sc->status = 1;
+        sc->w = 1.0;
+      } else {
+        sc->w = s0 / s1;
+      }
+      break;
+    case kKRho:
+      sc->rr = s1;
+      sc->iters += 1;
+      if (!(s0 != 0.0) || !finite(s0) || !finite(s1)) {
+        sc->status = 1;
+      } else {
+        sc->beta = (s0 / sc->rz) * (sc->alpha / sc->w);
+        sc->rz = s0;
+      }
       break;
     default:
       break;
@@ -456,11 +532,12 @@ __global__ __launch_bounds__(64) void k_smooth_fallback(Lv<T> L, const TF* __res
     uc = up;
   }
   T x = T(0);
+  const bool upd = relaxes(L, col);
   for (int k = nz - 1; k >= 0; --k) {
     const size_t o = c.base + static_cast<size_t>(k) * kTile;
     x = sd[o] + sc[o] * x;
     const T uo = ZERO ? omega * x : u_in[o] + omega * x;
-    u_out[o] = static_cast<TO>(uo);
+    u_out[o] = static_cast<TO>(upd ? uo : (ZERO ? T(0) : u_in[o]));
   }
 }
 
@@ -578,12 +655,13 @@ __global__ __launch_bounds__(1024) void k_smooth_lds(Lv<T> L, const TF* __restri
     }
   }
   __syncthreads();
+  const bool upd = relaxes(L, col);
 #pragma unroll 8
   for (int k = k0; k < k1; ++k) {
     const size_t o = c.base + static_cast<size_t>(k) * kTile;
     const T x = rb[k * kTile + lane];
     const T uo = ZERO ? omega * x : u_in[o] + omega * x;
-    u_out[o] = static_cast<TO>(uo);
+    u_out[o] = static_cast<TO>(upd ? uo : (ZERO ? T(0) : u_in[o]));
   }
 }
 
@@ -600,8 +678,11 @@ __global__ __launch_bounds__(256) void k_margins(Lv<double> L, TO* __restrict__ 
   double sk = 0.0;
   for (int k = 0; k < L.nz; ++k) {
     const double e = coef_excess<PM>(L, c, esum, k);
-    const double l = coef_face<PM>(L, c, k);
-    sk = k == 0 ? e : e + l * sk / (sk + l);
+    const double l = coef_lower<PM>(L, c, k);
+    // (the pivot of row k-1 is s_{k-1} + m_{k-1}; without advection
+    // m_{k-1} = l_k)
+    const double mp = k > 0 ? coef_upper<PM>(L, c, k - 1) : 0.0;
+    sk = k == 0 ? e : e + l * sk / (sk + mp);
     margin[c.base + static_cast<size_t>(k) * kTile] = static_cast<TO>(sk);
   }
 }
@@ -656,8 +737,8 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   // and the wave-uniform vertical vectors whenever needed (cheaper than
   // holding them: registers decide how many tiles a CU keeps in flight)
   auto e_of = [&](int i) -> T { return coef_excess<PM>(L, c, esum, k0 + i); };
-  auto l_of = [&](int i) -> T { return coef_face<PM>(L, c, k0 + i); };
-  auto m_of = [&](int i) -> T { return coef_face<PM>(L, c, k0 + i + 1); };
+  auto l_of = [&](int i) -> T { return coef_lower<PM>(L, c, k0 + i); };
+  auto m_of = [&](int i) -> T { return coef_upper<PM>(L, c, k0 + i); };
 
   // ---- residual of the wave's levels, in registers. All loads are issued
   // before any is used: their level indices are clamped into the column (the
@@ -717,7 +798,8 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     T s_prev = T(0), ip_prev = T(0);
     if (wave > 0) {
       s_prev = s_in;
-      ip_prev = rcp_of(s_prev + l_of(0));
+      // the pivot of the level below the block, s_{k0-1} + m_{k0-1}
+      ip_prev = rcp_of(s_prev + m_of(-1));
     }
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
@@ -796,13 +878,14 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   }
   __syncthreads();
   T x = at(wave, 5);
+  const bool upd = relaxes(L, col);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = KB - 1; i >= 0; --i) {
     if (i < nb) {
       x = mc[i] * x + r[i];
       const size_t o = c.base + static_cast<size_t>(k0 + i) * kTile;
-      const T uo = ZERO ? omega * x : uu[i] + omega * x;
+      const T uo = upd ? (ZERO ? omega * x : uu[i] + omega * x) : (ZERO ? T(0) : uu[i]);
       const TO zo = static_cast<TO>(uo);
       u_out[o] = zo;
       if (DOTS) {
@@ -1186,6 +1269,53 @@ __global__ __launch_bounds__(256) void k_pupdate(const TZ* __restrict__ z, doubl
   pupdate_body(z, p, sc, len, whole_grid());
 }
 
+__global__ __launch_bounds__(256) void k_dots2(const double* __restrict__ a, const double* __restrict__ b,
+                                               const double* __restrict__ c, const double* __restrict__ d,
+                                               size_t len, double* __restrict__ partials) {
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    acc[0] += a[i] * b[i];
+    acc[1] += c[i] * d[i];
+  }
+  block_sums(acc, partials, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_bicg_p(const double* __restrict__ r, double* __restrict__ p,
+                                                const double* __restrict__ v, const FcgScalars* __restrict__ sc,
+                                                size_t len) {
+  const double beta = sc->beta, w = sc->w;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = r[i] + beta * (p[i] - w * v[i]);
+}
+
+__global__ __launch_bounds__(256) void k_bicg_s(double* __restrict__ r, const double* __restrict__ v,
+                                                const FcgScalars* __restrict__ sc, size_t len) {
+  const double alpha = sc->alpha;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    r[i] = r[i] - alpha * v[i];
+}
+
+__global__ __launch_bounds__(256) void k_bicg_x(double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ y, const double* __restrict__ z,
+                                                const double* __restrict__ t, const double* __restrict__ rh,
+                                                const FcgScalars* __restrict__ sc, size_t len,
+                                                double* __restrict__ partials) {
+  const double alpha = sc->alpha, w = sc->w;
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    x[i] = x[i] + alpha * y[i] + w * z[i];
+    const double ri = r[i] - w * t[i];
+    r[i] = ri;
+    acc[0] += rh[i] * ri;
+    acc[1] += ri * ri;
+  }
+  block_sums(acc, partials, blockIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_add(double* __restrict__ x, const double* __restrict__ y, size_t len) {
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
        i += static_cast<size_t>(gridDim.x) * blockDim.x)
@@ -1418,6 +1548,7 @@ void profile_variant(int pm, Fn&& fn) {
   switch (pm) {
     case 1: fn(std::integral_constant<int, 1>{}); break;
     case 2: fn(std::integral_constant<int, 2>{}); break;
+    case 3: fn(std::integral_constant<int, 3>{}); break;
     default: fn(std::integral_constant<int, 0>{}); break;
   }
 }
@@ -1736,6 +1867,35 @@ hipError_t launch_pupdate(const void* z, bool z_double, double* p, const FcgScal
   else
     hipLaunchKernelGGL(k_pupdate<float>, dim3(pupdate_blocks(len)), dim3(256), 0, s, static_cast<const float*>(z), p,
                        sc, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots2(const double* a, const double* b, const double* c, const double* d, size_t len,
+                        double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots2, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, c, d, len, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_krylov_finalize(int stage, const double* partials, FcgScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, stage, partials, stage == kKInit ? 0 : kRedBlocks, sc,
+                     0.0, nullptr, kDefaultDiv2);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_p(const double* r, double* p, const double* v, const FcgScalars* sc, size_t len,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(pupdate_blocks(len)), dim3(256), 0, s, r, p, v, sc, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(double* r, const double* v, const FcgScalars* sc, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_s, dim3(pupdate_blocks(len)), dim3(256), 0, s, r, v, sc, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_x(double* x, double* r, const double* y, const double* z, const double* t, const double* rh,
+                         const FcgScalars* sc, size_t len, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_x, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, y, z, t, rh, sc, len, partials);
   return hipGetLastError();
 }
 

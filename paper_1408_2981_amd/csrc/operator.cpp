@@ -151,7 +151,23 @@ void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, co
   }
 }
 
-void build_full(Operator& op, const Grid& g, const double* alpha_r, const double* alpha_s, const double* beta) {
+std::vector<int8_t> greedy_colouring(const std::vector<int32_t>& nbr, int n) {
+  std::vector<int8_t> col(static_cast<size_t>(n), -1);
+  for (int t = 0; t < n; ++t) {
+    bool used[4] = {false, false, false, false};
+    for (int j = 0; j < 3; ++j) {
+      const int8_t c = col[nbr[3 * static_cast<size_t>(t) + j]];
+      if (c >= 0) used[c] = true;
+    }
+    int8_t c = 0;
+    while (used[c]) ++c;
+    col[t] = c;
+  }
+  return col;
+}
+
+void build_full(Operator& op, const Grid& g, const double* alpha_r, const double* alpha_s, const double* beta,
+                const double* xi_r) {
   const int nz = op.nz;
   if (g.nz != nz || g.refinement != op.refinement) throw std::runtime_error("grid and operator differ");
   const int fine_ref = g.refinement;
@@ -159,13 +175,14 @@ void build_full(Operator& op, const Grid& g, const double* alpha_r, const double
   const int coarse_ref = fine_ref - nl + 1;
   // per-level profiles [n][m], finest first; coarse = area-weighted means
   struct Prof {
-    std::vector<double> ar, as, b;
+    std::vector<double> ar, as, b, xi;
   };
   std::vector<Prof> pf(fine_ref + 1);
   const size_t nf = g.levels[fine_ref].n;
   pf[fine_ref].ar.assign(alpha_r, alpha_r + nf * (nz + 1));
   pf[fine_ref].as.assign(alpha_s, alpha_s + nf * nz);
   pf[fine_ref].b.assign(beta, beta + nf * nz);
+  if (xi_r) pf[fine_ref].xi.assign(xi_r, xi_r + nf * (nz + 1));
   for (int r = fine_ref; r > coarse_ref; --r) {
     const MeshLevel& F = g.levels[r];
     const int nc = g.levels[r - 1].n;
@@ -184,10 +201,19 @@ void build_full(Operator& op, const Grid& g, const double* alpha_r, const double
     restrict_rows(pf[r].ar, pf[r - 1].ar, nz + 1);
     restrict_rows(pf[r].as, pf[r - 1].as, nz);
     restrict_rows(pf[r].b, pf[r - 1].b, nz);
+    if (xi_r) restrict_rows(pf[r].xi, pf[r - 1].xi, nz + 1);
   }
   const double omega2 = op.omega2;
   std::vector<double> face(nz + 1, 0.0);
   for (int k = 1; k < nz; ++k) face[k] = 2.0 * g.r[k] * g.r[k] / (g.r[k + 1] - g.r[k - 1]);
+  // advection through cell k's lower and upper face: sigma_k r_k^2
+  // (r_{k+1}-r_k)/(r_{k+1}-r_{k-1}) and sigma_{k+1} r_{k+1}^2
+  // (r_{k+1}-r_k)/(r_{k+2}-r_k)
+  std::vector<double> adv_lo(nz, 0.0), adv_up(nz, 0.0);
+  for (int k = 0; k < nz; ++k) {
+    if (k > 0) adv_lo[k] = g.r[k] * g.r[k] * (g.r[k + 1] - g.r[k]) / (g.r[k + 1] - g.r[k - 1]);
+    if (k + 1 < nz) adv_up[k] = g.r[k + 1] * g.r[k + 1] * (g.r[k + 1] - g.r[k]) / (g.r[k + 2] - g.r[k]);
+  }
   for (int l = 0; l < nl; ++l) {
     const int r = coarse_ref + l;
     const MeshLevel& M = g.levels[r];
@@ -197,6 +223,7 @@ void build_full(Operator& op, const Grid& g, const double* alpha_r, const double
     C.fb.resize(n * nz);
     C.far.resize(n * (nz + 1));
     C.fas.resize(3 * n * nz);
+
     for (size_t t = 0; t < n; ++t) {
       for (int k = 0; k < nz; ++k) C.fb[t * nz + k] = M.area[t] * g.vk[k] * P.b[t * nz + k];
       for (int k = 0; k <= nz; ++k)
@@ -208,8 +235,26 @@ void build_full(Operator& op, const Grid& g, const double* alpha_r, const double
                                         (0.5 * (P.as[t * nz + k] + P.as[o * nz + k]));
       }
     }
+    // (after the diffusion coefficients, which the advection is checked against)
+    if (xi_r) {
+      C.fxl.resize(n * nz);
+      C.fxu.resize(n * nz);
+      for (size_t t = 0; t < n; ++t)
+        for (int k = 0; k < nz; ++k) {
+          C.fxl[t * nz + k] = omega2 * M.area[t] * adv_lo[k] * P.xi[t * (nz + 1) + k];
+          C.fxu[t * nz + k] = omega2 * M.area[t] * adv_up[k] * P.xi[t * (nz + 1) + k + 1];
+          // the column stays an M-matrix: both radial couplings positive
+          if ((k > 0 && !(C.far[t * (nz + 1) + k] - C.fxl[t * nz + k] > 0.0)) ||
+              (k + 1 < nz && !(C.far[t * (nz + 1) + k + 1] + C.fxu[t * nz + k] > 0.0)))
+            throw std::runtime_error("the vertical advection exceeds the vertical diffusion");
+        }
+    } else {
+      C.fxl.clear();
+      C.fxu.clear();
+    }
   }
   op.full = true;
+  op.adv = xi_r != nullptr;
 }
 
 }  // namespace tpmg

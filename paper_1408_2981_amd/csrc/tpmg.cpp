@@ -80,6 +80,14 @@ struct DevLevel {
   void* fb[2] = {nullptr, nullptr};
   void* far[2] = {nullptr, nullptr};
   void* fas[2] = {nullptr, nullptr};
+  // vertical advection: omega^2 times the coefficients of a cell's lower and
+  // upper face, tiled like a vector
+  void* fxl[2] = {nullptr, nullptr};
+  void* fxu[2] = {nullptr, nullptr};
+  // multicolour block-SOR: the colour of every column (padding -1) and the
+  // number of colours
+  int8_t* colour = nullptr;
+  int ncol = 0;
 };
 
 }  // namespace
@@ -93,6 +101,8 @@ struct tpmg_mg {
   // the operator of the equation has profiles that do not factorise
   int pm = 0;
   bool full_outer = false;
+  bool adv = false;                      // the operator has vertical advection (not symmetric)
+  bool sor = false;                      // multicolour block-SOR smoother (else block-Jacobi)
   hipStream_t stream = nullptr;
   std::vector<DevLevel> lv;
   void* bv[2] = {nullptr, nullptr};
@@ -144,6 +154,9 @@ struct tpmg_mg {
     v.fb = d.fb[i];
     v.far = d.far[i];
     v.fas = d.fas[i];
+    v.fxl = d.fxl[i];
+    v.fxu = d.fxu[i];
+    v.colour = d.colour;
     if (!tune.empty()) v.tune = tune[l];
     return v;
   }
@@ -152,7 +165,7 @@ struct tpmg_mg {
   // factorise
   tpmg::LevelView view_outer() const {
     tpmg::LevelView v = view64(nlev - 1);
-    v.pm = full_outer ? 2 : 0;
+    v.pm = adv ? 3 : full_outer ? 2 : 0;
     return v;
   }
   tpmg::LevelView view64(int l) const {
@@ -176,6 +189,9 @@ struct tpmg_mg {
     v.fb = d.fb[0];
     v.far = d.far[0];
     v.fas = d.fas[0];
+    v.fxl = d.fxl[0];
+    v.fxu = d.fxu[0];
+    v.colour = d.colour;
     if (!tune.empty()) v.tune = tune[l];
     return v;
   }
@@ -212,12 +228,17 @@ void carve(tpmg_mg& m, const tpmg::Operator& op, Carver& cv) {
     // whose FP64 view serves the relaxation after a learned guess
     d.margin[1] = m.fp32 ? cv.take(np * nz * 4) : nullptr;
     d.margin[0] = (!m.fp32 || finest) ? cv.take(np * nz * 8) : nullptr;
+    if (m.sor) d.colour = static_cast<int8_t*>(cv.take(np));
     if (op.full)
       for (int i = 0; i < (m.fp32 ? 2 : 1); ++i) {
         const size_t es = i == 0 ? 8 : 4;
         d.fb[i] = cv.take(np * nz * es);
         d.far[i] = cv.take(np * (nz + 1) * es);
         d.fas[i] = cv.take(3 * np * nz * es);
+        if (op.adv) {
+          d.fxl[i] = cv.take(np * nz * es);
+          d.fxu[i] = cv.take(np * nz * es);
+        }
       }
   }
   for (int i = 0; i < 2; ++i) {
@@ -299,6 +320,7 @@ tpmg_status check_params(const tpmg_mg_params* p) {
   if (p->stencil_chunk < 0 || p->stencil_chunk > 256) return fail(TPMG_ERR_ARG, "stencil_chunk must be in 0..256");
   if (p->precond_profiles < 0 || p->precond_profiles > 2)
     return fail(TPMG_ERR_ARG, "precond_profiles must be 0, 1 or 2");
+  if (p->smoother_order < 0 || p->smoother_order > 1) return fail(TPMG_ERR_ARG, "smoother_order must be 0 or 1");
   return TPMG_OK;
 }
 
@@ -382,7 +404,7 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
     return m.fp32 ? static_cast<const void*>(m.fcopy) : static_cast<const void*>(r_in);
   };
   auto sweep = [&](int o0, int o1, int o2, int o3, int l, const void* f, bool f_double, bool zero, void* out,
-                   bool out_double, bool fcopy, bool dots) {
+                   bool out_double, bool fcopy, bool dots, int pass = -1, const void* u_in = nullptr) {
     Op op;
     op.order[0] = o0;
     op.order[1] = o1;
@@ -397,8 +419,9 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
     op.dots = dots;
     op.omega = m.omega;
     op.L = m.view(l);
+    op.L.pass = pass;
     op.in0 = f;
-    op.in1 = m.lv[l].u[cur[l]];
+    op.in1 = u_in ? u_in : m.lv[l].u[cur[l]];
     op.out0 = out;
     op.out1 = fcopy ? m.fcopy : nullptr;
     op.q = dots ? q_dots : nullptr;
@@ -408,6 +431,32 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
     op.scratch_d = m.sd;
     op.scratch_c = m.sc;
     ops.push_back(op);
+  };
+  // A smoother sweep of level l: block-Jacobi in one pass; multicolour
+  // block-SOR in one pass per colour (ascending before the coarse-grid
+  // correction, descending after), each pass reading the previous one's
+  // output. final_out (or the level's other buffer) receives the sweep's
+  // result; the level's current buffer index follows it.
+  auto smooth_sweep = [&](int o0, int o1, int o2, int k, int l, const void* f, bool f_double, bool zero,
+                          void* final_out, bool out_double, bool fcopy, bool dots, bool post) {
+    if (!m.sor) {
+      void* out = final_out ? final_out : m.lv[l].u[zero ? cur[l] : 1 - cur[l]];
+      sweep(o0, o1, o2, k, l, f, f_double, zero, out, out_double, fcopy, dots);
+      if (!zero && !final_out) cur[l] = 1 - cur[l];
+      return;
+    }
+    const int nc = m.lv[l].ncol;
+    int src = cur[l];
+    for (int j = 0; j < nc; ++j) {
+      const bool first_pass = j == 0, last_pass = j + 1 == nc;
+      const int colour = post ? nc - 1 - j : j;
+      const int dst = (first_pass && zero) ? src : 1 - src;
+      void* out = (last_pass && final_out) ? final_out : m.lv[l].u[dst];
+      sweep(o0, o1, o2, k * 8 + j, l, f, f_double, zero && first_pass, out, last_pass && out_double,
+            fcopy && first_pass, dots && last_pass, colour, m.lv[l].u[src]);
+      src = dst;
+    }
+    if (!final_out) cur[l] = src;
   };
   for (int l = L; l >= 0; --l) {
     const int j = L - l;
@@ -420,10 +469,8 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
       const bool from32 = finest_first && m.fp32 && r32_ready && !dots;
       const void* f = from32 ? m.fcopy : (finest_first || dots) ? static_cast<const void*>(r_in) : rhs(l);
       const bool f_double = !from32 && (dots || ((l == L) && (finest_first || !m.fp32)));
-      void* out = last_of_cycle ? z_out : m.lv[l].u[first ? cur[l] : 1 - cur[l]];
-      sweep(0, j, 0, k, l, f, f_double, first, out, last_of_cycle && !z_float, finest_first && m.fp32 && !from32,
-            dots);
-      if (!first) cur[l] = 1 - cur[l];
+      smooth_sweep(0, j, 0, k, l, f, f_double, first, last_of_cycle ? z_out : nullptr, last_of_cycle && !z_float,
+                   finest_first && m.fp32 && !from32, dots, false);
     }
     if (l > 0) {
       Op op;
@@ -456,12 +503,10 @@ void vcycle_ops(tpmg_mg& m, const double* r_in, void* z_out, const double* q_dot
     ops.push_back(op);
     for (int k = 0; k < m.nu_post; ++k) {
       const bool last = l == L && k + 1 == m.nu_post;
-      void* out = last ? z_out : m.lv[l].u[1 - cur[l]];
       // the last sweep reads the FP64 residual when it also forms <z, q>, <z, r>
       const bool dots = last && q_dots;
-      sweep(1, -j, 1, k, l, dots ? static_cast<const void*>(r_in) : rhs(l), dots || (l == L && !m.fp32), false, out,
-            last && !z_float, false, dots);
-      if (!last) cur[l] = 1 - cur[l];
+      smooth_sweep(1, -j, 1, k, l, dots ? static_cast<const void*>(r_in) : rhs(l), dots || (l == L && !m.fp32), false,
+                   last ? z_out : nullptr, last && !z_float, false, dots, true);
     }
   }
 }
@@ -671,7 +716,7 @@ double op_model_bytes(const Op& op, int it) {
   // coefficients per (T, k) of profiles that do not factorise, read by every
   // stencil kernel: beta^, three alphaS^ and one new radial face per unknown
   // (all of them), or the radial face alone (the partial form)
-  const double coef = op.L.pm == 2 ? 5.0 : op.L.pm == 1 ? 1.0 : 0.0;
+  const double coef = op.L.pm == 3 ? 7.0 : op.L.pm == 2 ? 5.0 : op.L.pm == 1 ? 1.0 : 0.0;
   const double ring_x = flush ? 8.0 * (tpmg::kDirSlots + 2) : 0.0;
   switch (op.kind) {
     case tpmg::kOpSmooth: {
@@ -920,6 +965,7 @@ tpmg_status check_batch(tpmg_mg* const* problems, int n) {
     if (!m) return fail(TPMG_ERR_ARG, "NULL problem");
     if (m->nlev < 2) return fail(TPMG_ERR_ARG, "batched problems need at least 2 multigrid levels");
     if (m->full_outer) return fail(TPMG_ERR_ARG, "batched problems need factorising profiles");
+    if (m->sor) return fail(TPMG_ERR_ARG, "batched problems need the block-Jacobi smoother");
     for (const tpmg::LevelTune& t : m->tune)
       if (t.smoother != tpmg::kSmScan)
         return fail(TPMG_ERR_ARG, "batched problems need the scan smoother on every level (params.smoother = 1)");
@@ -1300,6 +1346,20 @@ tpmg_status tpmg_grid_geometry(const tpmg_grid* g, int level, double* centres, d
   return TPMG_OK;
 }
 
+tpmg_status tpmg_grid_colouring(const tpmg_grid* g, int level, int32_t* colours, int* n_colours) {
+  if (!g || !colours) return fail(TPMG_ERR_ARG, "NULL argument");
+  if (level < 0 || level > g->g.refinement) return fail(TPMG_ERR_ARG, "level out of range");
+  const tpmg::MeshLevel& M = g->g.levels[level];
+  const std::vector<int8_t> c = tpmg::greedy_colouring(M.nbr, M.n);
+  int nc = 0;
+  for (int t = 0; t < M.n; ++t) {
+    colours[t] = c[t];
+    nc = std::max(nc, c[t] + 1);
+  }
+  if (n_colours) *n_colours = nc;
+  return TPMG_OK;
+}
+
 tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk) {
   if (!g || !vk) return fail(TPMG_ERR_ARG, "NULL argument");
   std::copy(g->g.vk.begin(), g->g.vk.end(), vk);
@@ -1339,7 +1399,7 @@ tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, cons
 }
 
 tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const double* alpha_r, const double* alpha_s,
-                                      const double* beta) {
+                                      const double* beta, const double* xi_r) {
   if (!op || !g || !alpha_r || !alpha_s || !beta) return fail(TPMG_ERR_ARG, "NULL argument");
   const int ref = g->g.refinement, nz = g->g.nz;
   if (ref != op->op.refinement || nz != op->op.nz) return fail(TPMG_ERR_ARG, "op was not created on this grid");
@@ -1355,15 +1415,19 @@ tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const dou
   if (!positive(alpha_r, n * (nz + 1), nz + 1, 1, 1) || !positive(alpha_s, n * nz, nz, 0, 0) ||
       !positive(beta, n * nz, nz, 0, 0))
     return fail(TPMG_ERR_ARG, "full profiles must be positive and finite");
+  if (xi_r)
+    for (size_t i = 0; i < n * (nz + 1); ++i)
+      if (!std::isfinite(xi_r[i])) return fail(TPMG_ERR_ARG, "xi_r must be finite");
   try {
-    tpmg::build_full(op->op, g->g, alpha_r, alpha_s, beta);
+    tpmg::build_full(op->op, g->g, alpha_r, alpha_s, beta, xi_r);
   } catch (const std::exception& ex) {
     return fail(TPMG_ERR_ARG, ex.what());
   }
   return TPMG_OK;
 }
 
-tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta, double* alpha_s, double* alpha_r) {
+tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta, double* alpha_s, double* alpha_r,
+                                      double* adv_lo, double* adv_up) {
   if (!op) return fail(TPMG_ERR_ARG, "op is NULL");
   if (level < 0 || level >= static_cast<int>(op->op.levels.size())) return fail(TPMG_ERR_ARG, "level out of range");
   if (!op->op.full) return fail(TPMG_ERR_STATE, "the operator has no full profiles");
@@ -1371,6 +1435,15 @@ tpmg_status tpmg_op_coefficients_full(const tpmg_op* op, int level, double* beta
   if (beta) std::copy(C.fb.begin(), C.fb.end(), beta);
   if (alpha_s) std::copy(C.fas.begin(), C.fas.end(), alpha_s);
   if (alpha_r) std::copy(C.far.begin(), C.far.end(), alpha_r);
+  const size_t nn = static_cast<size_t>(C.n) * op->op.nz;
+  if (adv_lo) {
+    if (op->op.adv) std::copy(C.fxl.begin(), C.fxl.end(), adv_lo);
+    else std::fill(adv_lo, adv_lo + nn, 0.0);
+  }
+  if (adv_up) {
+    if (op->op.adv) std::copy(C.fxu.begin(), C.fxu.end(), adv_up);
+    else std::fill(adv_up, adv_up + nn, 0.0);
+  }
   return TPMG_OK;
 }
 
@@ -1415,6 +1488,7 @@ tpmg_status tpmg_mg_workspace_size(const tpmg_op* op, const tpmg_mg_params* para
   if (st != TPMG_OK) return st;
   tpmg_mg m;
   m.fp32 = params->precond_fp32 != 0;
+  m.sor = params->smoother_order == 1;
   Carver cv(nullptr);
   carve(m, op->op, cv);
   *bytes = cv.off + 256;
@@ -1452,12 +1526,16 @@ tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_
   m->nu_coarse = params->nu_coarse;
   m->omega = params->omega_relax;
   m->fp32 = params->precond_fp32 != 0;
+  m->sor = params->smoother_order == 1;
   m->full_outer = op->op.full;
   if (params->precond_profiles != 0 && !op->op.full) {
     delete m;
     return fail(TPMG_ERR_ARG, "precond_profiles 1 and 2 need an operator with full profiles (tpmg_op_set_full_profiles)");
   }
-  m->pm = !op->op.full ? 0 : params->precond_profiles == 0 ? 2 : params->precond_profiles == 1 ? 0 : 1;
+  m->adv = op->op.adv;
+  // (the V-cycle of the full profiles includes the advection; the factorised
+  // and partial ones are built without it)
+  m->pm = !op->op.full ? 0 : params->precond_profiles == 0 ? (op->op.adv ? 3 : 2) : params->precond_profiles == 1 ? 0 : 1;
   m->stream = static_cast<hipStream_t>(hip_stream);
   m->use_graph = params->use_graph != 0 && m->stream != nullptr;
   Carver cv(d_workspace);
@@ -1506,6 +1584,7 @@ tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_
   std::vector<std::vector<double>> keep64;
   std::vector<std::vector<float>> keep32;
   std::vector<std::vector<int32_t>> keepi;
+  std::vector<std::vector<int8_t>> keepc;
   const int nz = m->nz;
   for (int l = 0; l < m->nlev && e == hipSuccess; ++l) {
     const tpmg::LevelCoeffs& C = op->op.levels[l];
@@ -1518,8 +1597,15 @@ tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_
       (void)hipStreamSynchronize(m->stream);
       return cleanup_fail(TPMG_ERR_ARG, "a 64-column tile has more than 64 distinct out-of-tile neighbours");
     }
+    if (m->sor) {
+      std::vector<int8_t> col = tpmg::greedy_colouring(C.nbr, d.n);
+      d.ncol = 1 + *std::max_element(col.begin(), col.end());
+      col.resize(static_cast<size_t>(d.npad), static_cast<int8_t>(-1));
+      keepc.push_back(std::move(col));
+      if (e == hipSuccess) e = upload(d.colour, keepc.back(), m->stream);
+    }
     keepi.push_back(std::move(nb));
-    e = upload(d.nbr, keepi.back(), m->stream);
+    if (e == hipSuccess) e = upload(d.nbr, keepi.back(), m->stream);
     keepi.push_back(std::move(code));
     if (e == hipSuccess) e = upload(d.code, keepi.back(), m->stream);
     keepi.push_back(std::move(halo));
@@ -1545,11 +1631,11 @@ tpmg_status setup_impl(const tpmg_op* op, const tpmg_mg_params* params, void* d_
     }
     if (op->op.full) {
       // (padding columns: unit mass, no couplings)
-      const std::vector<double>* src[3] = {&C.fb, &C.far, &C.fas};
-      void* const* dst[3] = {d.fb, d.far, d.fas};
-      const int comps[3] = {1, 1, 3}, rows[3] = {nz, nz + 1, nz};
-      const double fill[3] = {1.0, 0.0, 0.0};
-      for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+      const std::vector<double>* src[5] = {&C.fb, &C.far, &C.fas, &C.fxl, &C.fxu};
+      void* const* dst[5] = {d.fb, d.far, d.fas, d.fxl, d.fxu};
+      const int comps[5] = {1, 1, 3, 1, 1}, rows[5] = {nz, nz + 1, nz, nz, nz};
+      const double fill[5] = {1.0, 0.0, 0.0, 0.0, 0.0};
+      for (int a = 0; a < (op->op.adv ? 5 : 3) && e == hipSuccess; ++a) {
         keep64.push_back(tiled<double>(*src[a], d.n, d.npad, comps[a], rows[a], fill[a]));
         e = upload(dst[a][0], keep64.back(), m->stream);
         if (e == hipSuccess && dst[a][1]) {
@@ -1746,6 +1832,9 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   if (!(rtol >= 0.0) || maxit < 0) return fail(TPMG_ERR_ARG, "rtol must be >= 0 and maxit >= 0");
   if (info && info->history_cap > 0 && !info->history) return fail(TPMG_ERR_ARG, "history_cap > 0 with NULL history");
   if (info && !(info->div_tol >= 0.0)) return fail(TPMG_ERR_ARG, "div_tol must be >= 0");
+  if (mg->adv)
+    return fail(TPMG_ERR_ARG, "the operator with vertical advection is not symmetric: use tpmg_solve_bicgstab or "
+                              "tpmg_solve_richardson");
   const bool timers = info && info->phase_timers != 0;
   const double div2 = info && info->div_tol > 0.0 ? info->div_tol * info->div_tol : tpmg::kDefaultDiv2;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1917,6 +2006,165 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   return result;
 }
 
+namespace {
+
+// The two outer solvers of the paper (Section 5.2), for any operator of the
+// handle (with vertical advection the only ones it accepts): the host reads
+// the residual norm after each iteration (one copy of the scalars).
+tpmg_status krylov_check(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
+                         const tpmg_solve_info* info) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_f || !d_u) return fail(TPMG_ERR_ARG, "NULL vector");
+  if (d_f == d_u) return fail(TPMG_ERR_ARG, "f and u must not alias");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(TPMG_ERR_ARG, "rtol must be >= 0 and maxit >= 0");
+  if (info && info->history_cap > 0 && !info->history) return fail(TPMG_ERR_ARG, "history_cap > 0 with NULL history");
+  if (info && info->phase_timers) return fail(TPMG_ERR_ARG, "phase timers are available with tpmg_solve only");
+  if (!mg->pinned) return fail(TPMG_ERR_STATE, "handle without pinned scalars");
+  return TPMG_OK;
+}
+
+hipError_t read_scalars(tpmg_mg& m) {
+  hipError_t e = hipMemcpyAsync(m.h_scal, m.scal, sizeof(tpmg::FcgScalars), hipMemcpyDeviceToHost, m.stream);
+  return e == hipSuccess ? hipStreamSynchronize(m.stream) : e;
+}
+
+}  // namespace
+
+tpmg_status tpmg_solve_richardson(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
+                                  tpmg_solve_info* info) {
+  tpmg_status st = krylov_check(mg, d_f, d_u, rtol, maxit, info);
+  if (st != TPMG_OK) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  tpmg_mg& m = *mg;
+  hipStream_t s = m.stream;
+  const tpmg::LevelView F = m.view_outer();
+  double fnorm = 0.0, rnorm = 0.0;
+  int it = 0;
+  tpmg_status result = TPMG_NOT_CONVERGED;
+  for (;; ++it) {
+    // r = f - A u, ||r||^2 and ||f||^2
+    TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, m.r, m.partials, tpmg::kFinInit, m.scal, s, rtol));
+    TPMG_HIP(read_scalars(m));
+    fnorm = std::sqrt(m.h_scal->ff);
+    rnorm = std::sqrt(m.h_scal->rr);
+    if (info && info->history && it < info->history_cap) info->history[it] = fnorm > 0 ? rnorm / fnorm : 0.0;
+    if (!std::isfinite(rnorm)) {
+      result = TPMG_ERR_BREAKDOWN;
+      break;
+    }
+    if (rnorm <= rtol * fnorm) {
+      result = TPMG_OK;
+      break;
+    }
+    if (it == maxit) break;
+    // u += M r
+    TPMG_HIP(vcycle(m, m.r, m.z));
+    TPMG_HIP(tpmg::launch_add(d_u, m.z, m.len, s));
+  }
+  TPMG_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = it;
+    info->relres = fnorm > 0 ? rnorm / fnorm : 0.0;
+    info->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->t_vcycle_ms = info->t_spmv_ms = info->t_blas_ms = 0.0;
+    std::vector<Op> vc;
+    vcycle_ops(m, m.r, m.z, nullptr, m.scal, vc);
+    double vb = 0.0;
+    for (const Op& op : vc) vb += op_model_bytes(op, 1);
+    const double n = static_cast<double>(m.len);
+    const double ab = (24.0 + (m.adv ? 56.0 : m.full_outer ? 40.0 : 0.0)) * n;   // r = f - A u
+    info->model_bytes = (it + 1) * ab + it * (vb + 24.0 * n);
+  }
+  if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite residual");
+  return result;
+}
+
+tpmg_status tpmg_solve_bicgstab(tpmg_mg* mg, const double* d_f, double* d_u, double rtol, int maxit,
+                                tpmg_solve_info* info) {
+  tpmg_status st = krylov_check(mg, d_f, d_u, rtol, maxit, info);
+  if (st != TPMG_OK) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  tpmg_mg& m = *mg;
+  hipStream_t s = m.stream;
+  const tpmg::LevelView F = m.view_outer();
+  const size_t len = m.len;
+  // vectors: r (then s) in r, p in p, v in q, y = M p in z, the shadow
+  // residual, z = M s and t in three slots of the direction ring
+  double* r = m.r;
+  double* p = m.p;
+  double* v = m.q;
+  double* y = m.z;
+  double* rh = m.dirs;
+  double* zs = m.dirs + len;
+  double* t = m.dirs + 2 * len;
+  TPMG_HIP(tpmg::launch_spmv64(F, 1, d_u, d_f, r, m.partials, tpmg::kFinInit, m.scal, s, rtol));
+  TPMG_HIP(hipMemcpyAsync(rh, r, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  TPMG_HIP(tpmg::launch_fill(p, len * sizeof(double), s));
+  TPMG_HIP(tpmg::launch_fill(v, len * sizeof(double), s));
+  TPMG_HIP(tpmg::launch_krylov_finalize(tpmg::kKInit, m.partials, m.scal, s));
+  TPMG_HIP(read_scalars(m));
+  const double fnorm = std::sqrt(m.h_scal->ff);
+  double rnorm = std::sqrt(m.h_scal->rr);
+  auto record = [&](int k) {
+    if (info && info->history && k < info->history_cap) info->history[k] = fnorm > 0 ? rnorm / fnorm : 0.0;
+  };
+  record(0);
+  int it = 0;
+  tpmg_status result = TPMG_NOT_CONVERGED;
+  if (!std::isfinite(rnorm)) {
+    result = TPMG_ERR_BREAKDOWN;
+  } else if (rnorm <= rtol * fnorm) {
+    result = TPMG_OK;
+  } else {
+    for (; it < maxit;) {
+      TPMG_HIP(tpmg::launch_bicg_p(r, p, v, m.scal, len, s));
+      TPMG_HIP(vcycle(m, p, y));
+      TPMG_HIP(tpmg::launch_spmv64(F, 0, y, nullptr, v, m.partials, tpmg::kFinNone, m.scal, s));
+      TPMG_HIP(tpmg::launch_dots2(rh, v, rh, v, len, m.partials, s));
+      TPMG_HIP(tpmg::launch_krylov_finalize(tpmg::kKAlpha, m.partials, m.scal, s));
+      TPMG_HIP(tpmg::launch_bicg_s(r, v, m.scal, len, s));
+      TPMG_HIP(vcycle(m, r, zs));
+      TPMG_HIP(tpmg::launch_spmv64(F, 0, zs, nullptr, t, m.partials, tpmg::kFinNone, m.scal, s));
+      TPMG_HIP(tpmg::launch_dots2(t, r, t, t, len, m.partials, s));
+      TPMG_HIP(tpmg::launch_krylov_finalize(tpmg::kKOmega, m.partials, m.scal, s));
+      TPMG_HIP(tpmg::launch_bicg_x(d_u, r, y, zs, t, rh, m.scal, len, m.partials, s));
+      TPMG_HIP(tpmg::launch_krylov_finalize(tpmg::kKRho, m.partials, m.scal, s));
+      TPMG_HIP(read_scalars(m));
+      ++it;
+      rnorm = std::sqrt(m.h_scal->rr);
+      record(it);
+      if (m.h_scal->status != 0 || !std::isfinite(rnorm)) {
+        result = TPMG_ERR_BREAKDOWN;
+        break;
+      }
+      if (rnorm <= rtol * fnorm) {
+        result = TPMG_OK;
+        break;
+      }
+    }
+  }
+  TPMG_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = it;
+    info->relres = fnorm > 0 ? rnorm / fnorm : 0.0;
+    info->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->t_vcycle_ms = info->t_spmv_ms = info->t_blas_ms = 0.0;
+    std::vector<Op> vc;
+    vcycle_ops(m, r, zs, nullptr, m.scal, vc);
+    double vb = 0.0;
+    for (const Op& op : vc) vb += op_model_bytes(op, 1);
+    const double n = static_cast<double>(len);
+    const double ab = (16.0 + (m.adv ? 56.0 : m.full_outer ? 40.0 : 0.0)) * n;   // v = A y, t = A z
+    // per iteration: p update 24, two V-cycles, two operators, dots 16 + 24,
+    // s update 24, x/r update 64
+    info->model_bytes = (32.0 + (m.adv ? 56.0 : m.full_outer ? 40.0 : 0.0)) * n +
+                        it * (2.0 * vb + 2.0 * ab + (24.0 + 16.0 + 24.0 + 24.0 + 64.0) * n);
+  }
+  if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: zero or non-finite BiCGStab scalar");
+  return result;
+}
+
 tpmg_status tpmg_richardson_rate(tpmg_mg* mg, double* d_u, int cycles, int skip, double* rate, double* norms) {
   tpmg_status st = check_mg(mg);
   if (st != TPMG_OK) return st;
@@ -2030,8 +2278,8 @@ tpmg_status tpmg_mg_time_kernel(tpmg_mg* mg, int kernel, int reps, double* avg_m
     const double n = static_cast<double>(mg->len);
     const double s_b = prec;
     // (coefficients per (T, k): five values per unknown, or the radial one)
-    const double cv = mg->pm == 2 ? 5.0 : mg->pm == 1 ? 1.0 : 0.0;
-    const double co = mg->full_outer ? 40.0 : 0.0;
+    const double cv = mg->pm == 3 ? 7.0 : mg->pm == 2 ? 5.0 : mg->pm == 1 ? 1.0 : 0.0;
+    const double co = mg->adv ? 56.0 : mg->full_outer ? 40.0 : 0.0;
     switch (kernel) {
       case 0: *model_bytes = (3.0 + cv) * s_b * n; break;
       case 1: *model_bytes = ((z_float ? 4.0 : 8.0) + 24.0 + co) * n; break;

@@ -18,11 +18,13 @@ from . import (
 class Problem:
     """Grid + operator on the host; call setup() to place it on the GPU."""
 
-    def __init__(self, refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0, full=None):
+    def __init__(self, refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0, full=None,
+                 advection: bool = False):
         """profiles: factorised profile factors (None: unit profiles). full:
         an object with alpha_r [n, nz+1], alpha_s, beta [n, nz], samples of
         profiles that do not factorise on the finest grid; the factorised
-        profiles then serve as their approximate factorisation."""
+        profiles then serve as their approximate factorisation. advection:
+        also take full.xi_r [n, nz+1], the vertical advection."""
         r_faces = np.asarray(r_faces, dtype=np.float64)
         self.refinement = refinement
         self.nz = len(r_faces) - 1
@@ -35,7 +37,8 @@ class Problem:
             h = (profiles.alpha_r_h, profiles.alpha_s_h, profiles.beta_h)
         self.op = tpmg_op_create(self.grid, n_levels, omega2, ar_v, as_v, b_v, *h)
         if full is not None:
-            tpmg_op_set_full_profiles(self.op, self.grid, full.alpha_r, full.alpha_s, full.beta)
+            tpmg_op_set_full_profiles(self.op, self.grid, full.alpha_r, full.alpha_s, full.beta,
+                                      getattr(full, "xi_r", None) if advection else None)
         self.n_levels = tpmg_op_levels(self.op)
         self.mg = None
         self.workspace = None

@@ -192,3 +192,47 @@ def test_full_profile_coefficients_match_oracle(ref, nz, seed):
     assert e.value.status == T.TPMG_ERR_ARG
     P.close()
     Q.close()
+
+
+def test_colouring_equals_oracle():
+    """The library's colouring of every level (multicolour block-SOR) is the
+    oracle's, cell for cell (both take the greedy rule in index order)."""
+    r = synth.vertical_faces(4, synth.H10KM)
+    g = T.tpmg_grid_icosahedral(6, 4, r)
+    from oracle import mesh
+
+    for lvl, m in enumerate(mesh.hierarchy(6)):
+        c, k = T.tpmg_grid_colouring(g, lvl)
+        o = otpmg.greedy_colouring(m.nbr)
+        assert np.array_equal(c, o) and k == o.max() + 1
+    T.tpmg_grid_destroy(g)
+
+
+def test_advection_coefficients_match_oracle():
+    """Vertical advection (Appendix A): the library's coefficients of every
+    cell's lower and upper face on every level equal the oracle's, for the
+    balanced flow (xi_r = Lambda rho d_r theta)."""
+    from oracle import mesh
+
+    ref, nz = 3, 16
+    r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+    om = synth.omega_for(ref)
+    bf = synth.balanced_flow(1.23, mesh.hierarchy(ref)[-1].centre, r, om)
+    P = T.Problem(ref, r, om * om, profiles=bf.factorised, full=bf, advection=True)
+    h = otpmg.build(ref, r, om * om, profiles=bf.factorised, full=bf, full_terms=otpmg.FULL_TERMS_ADV)
+    for lvl in range(P.n_levels):
+        c = T.tpmg_op_coefficients_full(P.op, lvl, nz)
+        o = h.ops[lvl]
+        assert np.allclose(c["adv_lo"], o.adv_lo, rtol=1e-13, atol=0)
+        assert np.allclose(c["adv_up"], o.adv_up, rtol=1e-13, atol=0)
+        assert np.allclose(c["alpha_r"], o.alpha_r, rtol=1e-13, atol=0)
+    Q = T.Problem(ref, r, om * om, profiles=bf.factorised, full=bf)
+    assert not np.any(T.tpmg_op_coefficients_full(Q.op, 0, nz)["adv_lo"])
+    # an advection stronger than the vertical diffusion is refused
+    with pytest.raises(T.TpmgError) as e:
+        T.Problem(ref, r, om * om, profiles=bf.factorised,
+                  full=type("F", (), dict(alpha_r=bf.alpha_r, alpha_s=bf.alpha_s, beta=bf.beta,
+                                          xi_r=bf.xi_r * 1e4))(), advection=True)
+    assert e.value.status == T.TPMG_ERR_ARG
+    P.close()
+    Q.close()
