@@ -33,22 +33,22 @@ def log(msg):
 
 
 def measured_traffic(path: str, key: str, instance: str):
-    """HBM bytes per dispatch of one kernel from a committed counter summary
-    under profiles/ (lines "traffic_<key>_bytes_per_dispatch: B"), or None
-    when kernels.hip has changed since the counters were taken or the timed
-    kernel is another instance than the one counted."""
+    """HBM bytes per dispatch of one kernel instance from a committed counter
+    summary under profiles/ (lines "traffic_<key>_<instance>_bytes_per_dispatch:
+    B"), or None when kernels.hip has changed since the counters were taken
+    or the timed instance was not counted."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1408_2981_amd", "csrc", "kernels.hip")
     try:
         vals = dict(l.strip().split(": ", 1) for l in open(os.path.join(ROOT, "profiles", path))
-                    if l.strip().startswith(("traffic_", "kernels_hip_", "instance_")))
+                    if l.strip().startswith(("traffic_", "kernels_hip_")))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if vals.get("kernels_hip_sha256") != digest or vals.get(f"instance_{key}") != instance:
+    if vals.get("kernels_hip_sha256") != digest:
         return None
-    v = vals.get(f"traffic_{key}_bytes_per_dispatch")
+    v = vals.get(f"traffic_{key}_{instance}_bytes_per_dispatch")
     return float(v) if v is not None else None
 
 
@@ -144,34 +144,53 @@ def roofline_workload(steps: int, reps: int) -> dict:
     return out
 
 
+# (scan levels per wave, stencil chunk) of the counter run: every sweep
+# instance (8 or 16 levels per wave; 4 holds at most 64 levels) and every
+# operator instance (1 .. 16 levels per wave) the autotuner chooses between
+# on the refinement-7 x 128-level grid
+PROFILE_INSTANCES = ((8, 4), (16, 16), (8, 8), (16, 2), (8, 1))
+
+
 def profile_kernels(reps: int):
     """Counter run on the HBM-bound workload (refinement 7 x 128 levels,
-    mixed): one solve, then `reps` finest-grid FP32 sweeps, `reps` launches of
-    q = A p with the direction update, then one copy of 1 GiB (a plain copy
-    kernel of known size, larger than the last-level cache, to calibrate
-    FETCH_SIZE and WRITE_SIZE)."""
+    mixed): for each (levels per wave, stencil chunk) of PROFILE_INSTANCES a
+    setup with that launch configuration, one solve, then `reps` + 1
+    back-to-back finest-grid FP32 sweeps and `reps` + 1 launches of q = A p
+    with the direction update; then one copy of 1 GiB (a plain copy kernel of
+    known size, larger than the last-level cache, to calibrate FETCH_SIZE and
+    WRITE_SIZE). A timed kernel is the only one launched that many times in a
+    row, which identifies its dispatches in the trace."""
     import torch
 
     import paper_1408_2981_amd as T
     import synth
 
     w = synth.workload("ico7_nz128_ar0.1")
-    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=False, autotune=1)
-    geo = P.geometry()
-    f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
-    u = P.device_vector()
-    st, it, rr, _, _ = P.solve(f, u)            # leaves realistic data in the buffers
-    sw_ms, sw_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_SWEEP, reps)
-    op_ms, op_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_OPERATOR_PRING, reps)
+    for scan, chunk in PROFILE_INSTANCES:
+        P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=False, autotune=0,
+                                                                 smoother=T.SMOOTHER_SCAN, scan_levels=scan,
+                                                                 stencil_chunk=chunk)
+        geo = P.geometry()
+        f = P.pack(synth.make_rhs(w, geo["centres"], geo["areas"], P.vk()))
+        u = P.device_vector()
+        st, it, rr, _, _ = P.solve(f, u)            # leaves realistic data in the buffers
+        sw_ms, sw_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_SWEEP, reps)
+        op_ms, op_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_OPERATOR_PRING, reps)
+        fine = P.tuning()[-1]
+        assert fine["scan_levels"] == scan and fine["chunk_spmv"] == chunk, fine
+        print(json.dumps({"workload": w.name, "sweep_instance": f"scan{scan}", "operator_instance": f"chunk{chunk}",
+                          "sweep_avg_us": sw_ms * 1000.0, "sweep_model_bytes": sw_b,
+                          "operator_avg_us": op_ms * 1000.0, "operator_model_bytes": op_b,
+                          "dispatches_each": reps + 1, "solve_iters": it}), flush=True)
+        P.close()
+        del P, f, u
+        torch.cuda.empty_cache()
     src = torch.ones(1024 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    fine = P.tuning()[-1]
-    print(json.dumps({"workload": w.name, "sweep_avg_us": sw_ms * 1000.0, "sweep_model_bytes": sw_b,
-                      "operator_avg_us": op_ms * 1000.0, "operator_model_bytes": op_b, "dispatches_each": reps + 1,
-                      "copy_bytes": 1024 * 1024 * 1024, "solve_iters": it, "tuning": fine}), flush=True)
+    print(json.dumps({"copy_bytes": 1024 * 1024 * 1024}), flush=True)
 
 
 def anisotropy_report(steps: int = 3):
