@@ -176,6 +176,7 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;   // fixed grid of the BLAS-1 reductions
 constexpr int kRedThreads = 256;
+constexpr int kFinThreads = 1024;  // one-block finalisation of the partial sums
 
 // Where a reduction's last block applies its sums to the FCG scalars.
 enum FinalizeSite { kFinInit = 0, kFinAlpha = 1, kFinRR = 2, kFinBeta = 3, kFinNone = 4 };

@@ -409,13 +409,27 @@ __device__ void fcg_scalars(int site, double s0, double s1, FcgScalars* __restri
 // back the whole L2).
 __device__ __forceinline__ void finalize_body(int site, const double* __restrict__ partials, int nblocks,
                                               FcgScalars* __restrict__ sc, double rtol, double div2 = kDefaultDiv2) {
+  // thread t adds the partials t, t + blockDim.x, ... in that order, eight
+  // pairs loaded ahead of their additions (the partials come from L2 or
+  // memory: one dependent load per pair would serialise the latencies)
   double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-    v[0] += partials[2 * b];
-    v[1] += partials[2 * b + 1];
+  const int nt = blockDim.x;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * nt) {
+    double a0[8], a1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int b = b0 + j * nt;
+      a0[j] = b < nblocks ? partials[2 * b] : 0.0;
+      a1[j] = b < nblocks ? partials[2 * b + 1] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      v[0] += a0[j];
+      v[1] += a1[j];
+    }
   }
-  __shared__ double red[4][2];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double red[16][2];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = nt >> 6;
   v[0] = wave_sum(v[0]);
   v[1] = wave_sum(v[1]);
   if (lane == 0) {
@@ -423,9 +437,14 @@ __device__ __forceinline__ void finalize_body(int site, const double* __restrict
     red[w][1] = v[1];
   }
   __syncthreads();
-  if (threadIdx.x == 0)
-    fcg_scalars(site, (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]),
-                (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]), sc, rtol, div2);
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int i = 0; i < nw; ++i) {
+      a += red[i][0];
+      c += red[i][1];
+    }
+    fcg_scalars(site, a, c, sc, rtol, div2);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1024,7 +1043,7 @@ __device__ __forceinline__ void pupdate_body(const TZ* __restrict__ z, double* _
 // they say done (an iteration queued ahead of the host's convergence test
 // then changes nothing the solve returns); the kFinRR site publishes the
 // iteration's record to the host ring when one is given.
-__global__ __launch_bounds__(256) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
+__global__ __launch_bounds__(kFinThreads) void k_finalize(int site, const double* __restrict__ partials, int nblocks,
                                                   FcgScalars* __restrict__ sc, double rtol,
                                                   FcgRecord* __restrict__ ring, double div2) {
   const bool iter_site = site == kFinAlpha || site == kFinRR || site == kFinBeta;
@@ -1445,7 +1464,7 @@ __global__ __launch_bounds__(256) void kb_rupdate(const Seg* __restrict__ segs, 
 }
 
 // one block per problem
-__global__ __launch_bounds__(256) void kb_finalize(const Seg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(kFinThreads) void kb_finalize(const Seg* __restrict__ segs, int nseg) {
   const Seg* sg = &segs[blockIdx.x];
   if (sg->sc->done) return;
   finalize_body(sg->site, sg->partials, sg->nblocks, sg->sc, 0.0);
@@ -1523,7 +1542,7 @@ LevelTune default_tune(int nz, int prec) {
 unsigned pupdate_blocks(size_t len) { return grid_for(len, 2048); }
 
 hipError_t launch_finalize(int site, const double* partials, int nblocks, FcgScalars* sc, double rtol, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, nblocks, sc, rtol, nullptr, kDefaultDiv2);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, site, partials, nblocks, sc, rtol, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1571,7 +1590,7 @@ hipError_t launch_spmv64(const LevelView& L, int mode, const double* x, const do
     });
   });
   if (site != kFinNone)
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, ring,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, site, partials, static_cast<int>(blocks), sc, rtol, ring,
                        div2);
   return hipGetLastError();
 }
@@ -1681,7 +1700,7 @@ static hipError_t smooth_t(const LevelView& Lg, bool f_double, bool zero, bool o
       });
     });
     if (dots)
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), a.partials,
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, static_cast<int>(kFinBeta), a.partials,
                          static_cast<int>(ntiles), a.scal, 0.0, nullptr, kDefaultDiv2);
     return hipGetLastError();
   }
@@ -1776,7 +1795,7 @@ hipError_t launch_margins(const LevelView& L64, int prec, void* margin, hipStrea
 hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* q, FcgScalars* sc, size_t len,
                              double* partials, FcgRecord* ring, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, p, q, sc, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
                      ring, kDefaultDiv2);
   return hipGetLastError();
 }
@@ -1804,7 +1823,7 @@ hipError_t launch_spmv_ring(const LevelView& L, const double* ring, size_t len, 
       hipLaunchKernelGGL((k_spmv_ring<CH, PM>), dim3(blocks), dim3(256), 0, s, V, chunk, ring, len, q, partials, sc);
     });
   });
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinAlpha), partials,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, static_cast<int>(kFinAlpha), partials,
                      static_cast<int>(blocks), sc, 0.0, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
@@ -1835,7 +1854,7 @@ hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, d
     });
   });
   if (site != kFinNone)
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, partials, static_cast<int>(blocks), sc, 0.0, nullptr,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, site, partials, static_cast<int>(blocks), sc, 0.0, nullptr,
                        kDefaultDiv2);
   return hipGetLastError();
 }
@@ -1843,7 +1862,7 @@ hipError_t launch_spmv_pring(const LevelView& L, const void* z, bool z_double, d
 hipError_t launch_rupdate(double* r, const double* q, FcgScalars* sc, size_t len, double* partials, FcgRecord* ring,
                           hipStream_t s, float* r32) {
   hipLaunchKernelGGL(k_rupdate, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, q, sc, len, partials, r32);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, static_cast<int>(kFinRR), partials, kRedBlocks, sc, 0.0,
                      ring, kDefaultDiv2);
   return hipGetLastError();
 }
@@ -1856,7 +1875,7 @@ hipError_t launch_flush(double* x, const double* ring, const FcgScalars* sc, siz
 hipError_t launch_dots(const double* z, const double* q, const double* r, size_t len, double* partials,
                        FcgScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, z, q, r, len, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0, nullptr, kDefaultDiv2);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, static_cast<int>(kFinBeta), partials, kRedBlocks, sc, 0.0, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
 
@@ -1877,7 +1896,7 @@ hipError_t launch_dots2(const double* a, const double* b, const double* c, const
 }
 
 hipError_t launch_krylov_finalize(int stage, const double* partials, FcgScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, stage, partials, stage == kKInit ? 0 : kRedBlocks, sc,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, stage, partials, stage == kKInit ? 0 : kRedBlocks, sc,
                      0.0, nullptr, kDefaultDiv2);
   return hipGetLastError();
 }
@@ -1992,7 +2011,7 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
       hipLaunchKernelGGL(kb_fcg_update, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       break;
     case kOpFinalize:
-      hipLaunchKernelGGL(kb_finalize, dim3(b.nseg), dim3(256), 0, s, b.segs, b.nseg);
+      hipLaunchKernelGGL(kb_finalize, dim3(b.nseg), dim3(kFinThreads), 0, s, b.segs, b.nseg);
       break;
     default:
       return hipErrorInvalidValue;
