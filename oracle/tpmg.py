@@ -214,13 +214,20 @@ FULL_TERMS_ADV = FULL_TERMS + ("xi_r",)
 
 def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0,
           meshes: list | None = None, vert: opmod.Vertical | None = None,
-          full: opmod.FullProfiles | None = None, full_terms=FULL_TERMS) -> Hierarchy:
+          full: opmod.FullProfiles | None = None, full_terms=FULL_TERMS,
+          level_factors: dict | None = None) -> Hierarchy:
     """Meshes, coefficients and transfer weights for TPMG on refinement `refinement`.
 
     profiles: object with alpha_r_v, alpha_s_v, beta_v and optional per-cell
     finest-grid alpha_r_h, alpha_s_h, beta_h (None = 1). vert replaces the
     radial factors derived from r_faces (used to pose the 2-D problems of the
     tensor decoupling).
+
+    level_factors: {refinement level: (alpha_r_h, alpha_s_h, beta_h)}, the
+    horizontal factors of that grid sampled by the caller (entries may be
+    None); where none is given, a coarse grid takes the area-weighted means
+    of its children's factors (the coarse operator is rediscretised on each
+    grid, Section 3.2.1).
 
     full: profiles that need not factorise, sampled on the finest grid
     (Section 4.2). The coefficients named in full_terms are then taken from
@@ -245,12 +252,20 @@ def build(refinement: int, r_faces, omega2: float, profiles=None, n_levels: int 
         ar_v, as_v, b_v = profiles.alpha_r_v, profiles.alpha_s_v, profiles.beta_v
         ar_h, as_h, b_h = profiles.alpha_r_h, profiles.alpha_s_h, profiles.beta_h
     nf = meshes[refinement].n
+    given = level_factors or {}
+
+    def sampled(ref, i):
+        v = given.get(ref, (None, None, None))[i]
+        return None if v is None else np.asarray(v, dtype=np.float64)
+
     h = [np.ones(nf) if x is None else np.asarray(x, dtype=np.float64) for x in (ar_h, as_h, b_h)]
+    h = [h[i] if sampled(refinement, i) is None else sampled(refinement, i) for i in range(3)]
     levels = list(range(refinement - n_levels + 1, refinement + 1))
     per_level = {refinement: h}
     for ref in range(refinement, levels[0], -1):
         fine_area = meshes[ref].area
-        per_level[ref - 1] = [opmod.restrict_cell_factor(x, fine_area) for x in per_level[ref]]
+        per_level[ref - 1] = [opmod.restrict_cell_factor(x, fine_area) if sampled(ref - 1, i) is None
+                              else sampled(ref - 1, i) for i, x in enumerate(per_level[ref])]
     full_level = {}
     if full is not None and full_terms:
         if "xi_r" in full_terms and getattr(full, "xi_r", None) is None:

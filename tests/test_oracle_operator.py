@@ -150,3 +150,36 @@ def test_coarse_coefficients_conserve_children():
     plain = ar_h.mean(axis=1) * h.meshes[-2].area
     weighted = (ar_h * h.meshes[-1].area.reshape(-1, 4)).sum(axis=1)
     assert not np.allclose(plain, weighted, rtol=1e-6)
+
+
+def test_caller_samples_on_coarse_grids():
+    """Horizontal factors sampled by the caller on a coarse grid (the
+    coarse operator is rediscretised on each grid, Section 3.2.1): giving
+    every grid exactly the area means of its children reproduces the default
+    hierarchy bit for bit; a sample given on refinement 2 makes that grid's
+    coefficients the cell integrals |T| x sample (mass: beta^S_T = |T|
+    beta_T, as in Appendix A) and refinement 1 their children's sums (the
+    conservation of the default hierarchy, now of the given samples), while
+    the finest grid is unchanged."""
+    nz = 4
+    r = synth.vertical_faces(nz, H, "quadratic")
+    prof = synth.profiles_random(nz, 1280, seed=23, tie_beta_to_alpha_r=False)
+    h0 = tpmg.build(3, r, OM2, profiles=prof, n_levels=4)
+    means = {3: (prof.alpha_r_h, prof.alpha_s_h, prof.beta_h)}
+    for ref in (3, 2, 1):
+        means[ref - 1] = tuple(opm.restrict_cell_factor(np.asarray(x), h0.meshes[ref].area) for x in means[ref])
+    h1 = tpmg.build(3, r, OM2, profiles=prof, n_levels=4, level_factors=means)
+    for a, b in zip(h0.ops, h1.ops):
+        for name in ("beta", "alpha_r", "alpha_s"):
+            assert np.array_equal(getattr(a, name), getattr(b, name)), name
+    rng = np.random.default_rng(24)
+    sample = rng.uniform(0.5, 2.0, 320)
+    h2 = tpmg.build(3, r, OM2, profiles=prof, n_levels=4, level_factors={2: (None, None, sample)})
+    m2 = h2.meshes[2]
+    assert np.allclose(h2.ops[2].beta, m2.area[:, None] * h2.vert.vk[None, :] * sample[:, None] *
+                       np.asarray(prof.beta_v)[None, :], rtol=1e-14, atol=0)
+    child_sum = h2.ops[2].beta.reshape(80, 4, nz).sum(axis=1)
+    assert np.allclose(h2.ops[1].beta, child_sum, rtol=1e-13, atol=0)
+    assert np.array_equal(h2.ops[3].beta, h0.ops[3].beta)
+    assert np.array_equal(h2.ops[2].alpha_r, h0.ops[2].alpha_r)
+    assert not np.allclose(h2.ops[2].beta, h0.ops[2].beta)
