@@ -236,12 +236,16 @@ def anisotropy_report(steps: int = 3):
 def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
     """Learned initial guess on the sequence f_t = f_0 + 0.05 t g (refinement 6
     x 64 quadratic levels, 5,242,880 unknowns, smooth seeded fields): solve
-    t = 1..n_train from zero (mixed, rtol 1e-8), train the per-column MLP on
-    those solutions (GPU, bf16 matrix cores, Adam, batch 4096), then solve
-    t = n_train+1..n_total from four guesses: zero, the previous solution,
-    the network (+ one line-relaxation sweep) and the two-step extrapolation
-    2 u_{t-1} - u_{t-2}; and, for reference, the plain FP64 solve from zero.
-    Times include producing the guess."""
+    t = 1..n_train from zero (mixed, rtol 1e-8) and train two per-column MLPs
+    on those solutions (GPU, bf16 matrix cores, Adam, batch 4096): one on
+    (f_t, u_t), one on the increments (f_t - f_{t-1}, u_t - u_{t-1}). Then
+    solve t = n_train+1..n_total from each guess: zero; zero + one
+    line-relaxation sweep; the previous solution, without and with the sweep;
+    the two-step extrapolation 2 u_{t-1} - u_{t-2}; the network on f_t (+
+    sweep); the previous solution + the increment network's output for
+    f_t - f_{t-1} (+ sweep); and, for reference, the plain FP64 solve from
+    zero. Times include producing the guess. The previous solutions are those
+    of the zero-guess solves."""
     import numpy as np
     import torch
 
@@ -261,35 +265,53 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
         torch.cuda.synchronize()
         return f
 
-    net = T.ColumnMLP(w.nz, 256, max(4096, P.n), stream=P.stream)
-    rng_params = np.random.default_rng(0)
     n_in, h = w.nz + 3, 256
-    he = lambda fan_in, shape: (rng_params.standard_normal(shape) * math.sqrt(2.0 / fan_in)).astype(np.float32)
-    net.set_params(np.concatenate([he(n_in, (h, n_in)).ravel(), np.zeros(h, np.float32), he(h, (h, h)).ravel(),
-                                   np.zeros(h, np.float32), he(h, (w.nz, h)).ravel(), np.zeros(w.nz, np.float32)]))
+
+    def new_net(seed):
+        net = T.ColumnMLP(w.nz, h, max(4096, P.n), stream=P.stream)
+        rng_params = np.random.default_rng(seed)
+        he = lambda fan_in, shape: (rng_params.standard_normal(shape) * math.sqrt(2.0 / fan_in)).astype(np.float32)
+        net.set_params(np.concatenate([he(n_in, (h, n_in)).ravel(), np.zeros(h, np.float32), he(h, (h, h)).ravel(),
+                                       np.zeros(h, np.float32), he(h, (w.nz, h)).ravel(),
+                                       np.zeros(w.nz, np.float32)]))
+        return net
+
+    net, net_inc = new_net(0), new_net(1)
     X = torch.empty((n_train * P.n, n_in), dtype=torch.float32, device="cuda")
     Y = torch.empty((n_train * P.n, w.nz), dtype=torch.float32, device="cuda")
+    Xd = torch.empty(((n_train - 1) * P.n, n_in), dtype=torch.float32, device="cuda")
+    Yd = torch.empty(((n_train - 1) * P.n, w.nz), dtype=torch.float32, device="cuda")
     sols = {}
     t0 = time.perf_counter()
+    f_prev = u_prev = None
     for t in range(1, n_train + 1):
         f = rhs(t)
         u = P.device_vector()
         st, it, *_ = P.solve(f, u)
         net.features(P, f, X[(t - 1) * P.n:t * P.n])
         net.targets(P, u, Y[(t - 1) * P.n:t * P.n])
+        if u_prev is not None:
+            net_inc.features_increment(P, f, f_prev, Xd[(t - 2) * P.n:(t - 1) * P.n])
+            net_inc.targets_increment(P, u, u_prev, Yd[(t - 2) * P.n:(t - 1) * P.n])
+        net.synchronize()
+        f_prev, u_prev = f, u
         if t >= n_train - 1:
             sols[t] = u
-    net.synchronize()
     t_data = time.perf_counter() - t0
     log(f"sequence: {n_train} training solves and features in {t_data:.1f} s")
-    net.fit_scaling(X, Y)
-    t0 = time.perf_counter()
-    losses = net.train(X, Y, epochs=epochs, batch=4096, lr=1e-3, seed=0)
-    t_train = time.perf_counter() - t0
-    log(f"sequence: trained {epochs} epochs in {t_train:.1f} s, epoch losses {losses}")
-    steps = epochs * (X.shape[0] // 4096)
+    trained = {}
+    for name, nn, xx, yy in (("network", net, X, Y), ("increment", net_inc, Xd, Yd)):
+        nn.fit_scaling(xx, yy)
+        t0 = time.perf_counter()
+        losses = nn.train(xx, yy, epochs=epochs, batch=4096, lr=1e-3, seed=0)
+        t_train = time.perf_counter() - t0
+        log(f"sequence: {name} trained {epochs} epochs in {t_train:.1f} s, epoch losses {losses}")
+        trained[name] = {"samples": xx.shape[0], "epochs": epochs, "steps": epochs * (xx.shape[0] // 4096),
+                         "epoch_loss": losses, "seconds": t_train}
     flop_step = 6.0 * 4096 * (n_in * h + h * h + h * w.nz)
-    del X, Y
+    for v in trained.values():
+        v["TFLOPs_per_s"] = flop_step * v["steps"] / v["seconds"] / 1e12
+    del X, Y, Xd, Yd
     torch.cuda.empty_cache()
 
     # inference timing (device events on the shared stream)
@@ -311,9 +333,12 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
     # the plain FP64 solve (FP64 V-cycle, zero guess) on the same grid and
     # right-hand sides: the reference the mixed + learned-guess form is to beat
     P64 = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=False, use_graph=True, autotune=1)
-    res = {k: {"iters": [], "ms": []} for k in ("zero", "previous", "network", "extrapolation", "fp64_zero")}
+    kinds = ("zero", "zero_relax", "previous", "previous_relax", "extrapolation", "network", "network_increment",
+             "fp64_zero")
+    res = {k: {"iters": [], "ms": []} for k in kinds}
     for t in range(n_train + 1, n_total + 1):
         f = rhs(t)
+        f_before = rhs(t - 1)
         for kind in res:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -326,13 +351,23 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
                 continue
             if kind == "zero":
                 u = P.device_vector()
+            elif kind == "zero_relax":
+                z = P.device_vector()
+                u = P.device_vector()
+                P.relax(f, z, u)
             elif kind == "previous":
                 u = sols[t - 1].clone()
+            elif kind == "previous_relax":
+                u = P.device_vector()
+                P.relax(f, sols[t - 1], u)
             elif kind == "extrapolation":
                 u = 2.0 * sols[t - 1] - sols[t - 2]
-            else:
+            elif kind == "network":
                 u = P.device_vector()
                 net.infer(P, f, u, 1)
+            else:
+                u = P.device_vector()
+                net_inc.infer_increment(P, f, f_before, sols[t - 1], u, 1)
             torch.cuda.synchronize()
             st, it, *_ = P.solve(f, u)
             res[kind]["ms"].append(1000.0 * (time.perf_counter() - t1))
@@ -343,9 +378,7 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
         sols.pop(t - 2, None)
     line = {"workload": f"{w.name}: f_t = f_0 + 0.05 t g, refinement 6 x nz 64 quadratic, {w.unknowns} unknowns, "
                         f"mixed, rtol 1e-8; train t=1..{n_train}, evaluate t={n_train + 1}..{n_total}",
-            "train": {"samples": n_train * P.n, "epochs": epochs, "steps": steps, "batch": 4096,
-                      "epoch_loss": losses, "seconds": t_train, "data_seconds": t_data,
-                      "TFLOPs_per_s": flop_step * steps / t_train / 1e12},
+            "train": trained,
             "inference": {"ms_network": infer_ms[0], "ms_with_relaxation": infer_ms[1], "GFLOP": flop_inf / 1e9,
                           "TFLOPs_per_s": flop_inf / (infer_ms[0] / 1000.0) / 1e12,
                           "mfma_bf16_peak_TFLOPs": 2500.0,
@@ -354,9 +387,12 @@ def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
         line[kind] = {"mean_iters": float(np.mean(r["iters"])), "max_iters": int(np.max(r["iters"])),
                       "mean_ms_incl_guess": float(np.mean(r["ms"]))}
     line["network_vs_fp64_zero_speedup"] = line["fp64_zero"]["mean_ms_incl_guess"] / line["network"]["mean_ms_incl_guess"]
+    line["network_increment_vs_fp64_zero_speedup"] = (line["fp64_zero"]["mean_ms_incl_guess"]
+                                                      / line["network_increment"]["mean_ms_incl_guess"])
     print(json.dumps(line), flush=True)
     P64.close()
     net.close()
+    net_inc.close()
     P.close()
 
 

@@ -104,6 +104,13 @@ typedef struct {
                           before the coarse-grid correction and descending
                           after; one pass over the grid per colour. Not
                           for batched solves.                             */
+  int tile_cols;       /* columns per tile of the device layout: 0 (auto)
+                          or 64, the only width: one lane per column and
+                          one 64-lane wavefront per tile, so that every
+                          level of a tile is one coalesced row and the
+                          neighbour exchange stays inside a wave; other
+                          values are TPMG_ERR_ARG. (Work per block is tuned
+                          through levels per wave and stencil chunks.)   */
 } tpmg_mg_params;
 
 /* Result of a solve. Inputs: history (optional, caller-owned, history_cap
@@ -183,6 +190,20 @@ tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk);
 tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
                            const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
                            const double* alpha_s_h, const double* beta_h, tpmg_op** out);
+
+/* As tpmg_op_create, with the horizontal factors of coarse grids sampled by
+ * the caller (the coarse-grid operator is rediscretised on each grid,
+ * Section 3.2.1; the profiles can be evaluated at its cells). alpha_r_h,
+ * alpha_s_h, beta_h: NULL or arrays of refinement + 1 pointers indexed by
+ * refinement level, entry r NULL or n_r values (tpmg_grid_level_size) for
+ * the cells of that grid, all > 0 and finite. Where an entry is NULL the
+ * finest grid takes the factor 1 and a coarse grid the area-weighted means
+ * of its four children's factors on the next finer grid, as tpmg_op_create
+ * does. Entries of grids outside the hierarchy are not read. Host arrays,
+ * caller-owned, read during the call. Errors: TPMG_ERR_ARG. */
+tpmg_status tpmg_op_create_levels(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
+                                  const double* alpha_s_v, const double* beta_v, const double* const* alpha_r_h,
+                                  const double* const* alpha_s_h, const double* const* beta_h, tpmg_op** out);
 
 /* Profiles that do not factorise (Section 4.2: the general case of
  * Appendix A, eq. hatFunctionsNonFac, with the vertical advection dropped):
@@ -273,6 +294,18 @@ tpmg_status tpmg_spmv(tpmg_mg* mg, const double* d_x, double* d_y);
  * the precision chosen at setup; FP64 tiled vectors in and out,
  * asynchronous. r and z must not alias. */
 tpmg_status tpmg_vcycle(tpmg_mg* mg, const double* d_r, double* d_z);
+
+/* One undamped line-relaxation sweep on the finest grid in FP64 (the
+ * smoother's column solves, eq. BlockJacobi, with damping 1, on the
+ * operator the V-cycle is built on): u_out = u_in + A_T^-1 (f - A u_in),
+ * A_T the vertical part of each column's block. Tiled FP64 vectors;
+ * u_out must not alias f or u_in; every entry of u_out is written (padding
+ * entries zero when those of f are). Asynchronous. nz <= 128 always fits;
+ * a larger nz needs the LDS-staged smoother (two [nz][64] FP64 arrays in
+ * LDS; factorised profiles only), else TPMG_ERR_ARG. It is the relaxation that
+ * follows the learned initial guess (tpmg_mlp.h), and from a zero u_in it
+ * is the column solves alone. */
+tpmg_status tpmg_relax(tpmg_mg* mg, const double* d_f, const double* d_u_in, double* d_u_out);
 
 /* Solves A u = f by V-cycle-preconditioned flexible CG, starting from the
  * guess in d_u (tiled FP64), until ||r|| <= rtol ||f|| (2-norms of the

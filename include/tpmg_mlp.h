@@ -115,6 +115,27 @@ tpmg_status tpmg_mlp_train_step(tpmg_mlp* m, const float* d_x, const float* d_y,
  * n_cells <= max_rows and mg's stream to be the network's. Asynchronous. */
 tpmg_status tpmg_mlp_infer(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, int relax, double* d_u0);
 
+/* The same network on the increments of a sequence of solves. The operator
+ * is linear, so between two steps of a sequence the solution changes by the
+ * solution for the change of the right-hand side: u_t = u_{t-1} +
+ * A^-1 (f_t - f_{t-1}). A network trained on features of f_t - f_{t-1}
+ * (tpmg_mlp_features_increment) and targets u_t - u_{t-1}
+ * (tpmg_mlp_targets_increment) predicts that change, and
+ * tpmg_mlp_infer_increment forms d_u0 = d_u_prev + (the network's output
+ * for the features of d_f - d_f_prev), followed with relax = 1 by one
+ * undamped FP64 line-relaxation sweep with d_f (as tpmg_mlp_infer). All
+ * vectors tiled FP64 as tpmg_solve; d_u0 must not alias an input; every
+ * entry of d_u0 is written (padding entries: those of d_u_prev, or with
+ * relax = 1 the sweep's). The difference vectors are formed in the
+ * network's workspace. Same requirements as tpmg_mlp_features /
+ * tpmg_mlp_targets / tpmg_mlp_infer; asynchronous. */
+tpmg_status tpmg_mlp_features_increment(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, const double* d_f_prev,
+                                        float* d_x);
+tpmg_status tpmg_mlp_targets_increment(tpmg_mlp* m, const tpmg_mg* mg, const double* d_u, const double* d_u_prev,
+                                       float* d_y);
+tpmg_status tpmg_mlp_infer_increment(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, const double* d_f_prev,
+                                     const double* d_u_prev, int relax, double* d_u0);
+
 /* Parameters, scaling and shape in a binary file (little-endian). load
  * requires the file's shape to match m. */
 tpmg_status tpmg_mlp_save(tpmg_mlp* m, const char* path);

@@ -38,14 +38,15 @@ TPMG_ERR_STATE = -5
 
 EXPORTED = [
     "tpmg_mg_params_default", "tpmg_grid_icosahedral", "tpmg_grid_level_size", "tpmg_grid_geometry",
-    "tpmg_grid_vertical", "tpmg_grid_colouring", "tpmg_op_create", "tpmg_op_set_full_profiles", "tpmg_op_coefficients_full", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
+    "tpmg_grid_vertical", "tpmg_grid_colouring", "tpmg_op_create", "tpmg_op_create_levels", "tpmg_op_set_full_profiles", "tpmg_op_coefficients_full", "tpmg_op_levels", "tpmg_op_level_size", "tpmg_op_coefficients",
     "tpmg_op_prolongation", "tpmg_mg_workspace_size", "tpmg_mg_setup", "tpmg_mg_vector_length", "tpmg_pack",
-    "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
+    "tpmg_unpack", "tpmg_spmv", "tpmg_vcycle", "tpmg_relax", "tpmg_solve", "tpmg_batch_workspace_size", "tpmg_batch_create", "tpmg_batch_solve", "tpmg_batch_destroy",
     "tpmg_richardson_rate", "tpmg_mg_time_sweep", "tpmg_mg_time_kernel", "tpmg_mg_tuning", "tpmg_mg_autotune_stats", "tpmg_tune_load",
     "tpmg_tune_save", "tpmg_tune_clear", "tpmg_tune_entries", "tpmg_grid_destroy", "tpmg_op_destroy",
     "tpmg_mlp_param_count", "tpmg_mlp_workspace_size", "tpmg_mlp_create", "tpmg_mlp_set_params", "tpmg_mlp_get_params",
     "tpmg_mlp_set_scaling", "tpmg_mlp_get_scaling", "tpmg_mlp_fit_scaling", "tpmg_mlp_features", "tpmg_mlp_targets",
-    "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_infer", "tpmg_mlp_save",
+    "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_infer", "tpmg_mlp_features_increment",
+    "tpmg_mlp_targets_increment", "tpmg_mlp_infer_increment", "tpmg_mlp_save",
     "tpmg_mlp_load", "tpmg_mlp_destroy",
     "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error", "tpmg_solve_noalloc", "tpmg_solve_richardson",
     "tpmg_solve_bicgstab",
@@ -64,7 +65,7 @@ class MgParams(ctypes.Structure):
         ("nu_coarse", ctypes.c_int), ("omega_relax", ctypes.c_double), ("precond_fp32", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int), ("smoother", ctypes.c_int),
         ("scan_levels", ctypes.c_int), ("stencil_chunk", ctypes.c_int), ("precond_profiles", ctypes.c_int),
-        ("smoother_order", ctypes.c_int),
+        ("smoother_order", ctypes.c_int), ("tile_cols", ctypes.c_int),
     ]
 
 
@@ -97,6 +98,8 @@ _sig = {
     "tpmg_grid_vertical": (_ip, [_vp, _dp]),
     "tpmg_grid_colouring": (_ip, [_vp, _ip, _i32p, ctypes.POINTER(_ip)]),
     "tpmg_op_create": (_ip, [_vp, _ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.POINTER(_vp)]),
+    "tpmg_op_create_levels": (_ip, [_vp, _ip, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(_dp),
+                                    ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_vp)]),
     "tpmg_op_set_full_profiles": (_ip, [_vp, _vp, _dp, _dp, _dp, _dp]),
     "tpmg_op_coefficients_full": (_ip, [_vp, _ip, _dp, _dp, _dp, _dp, _dp]),
     "tpmg_op_levels": (_ip, [_vp, ctypes.POINTER(_ip)]),
@@ -110,6 +113,7 @@ _sig = {
     "tpmg_unpack": (_ip, [_vp, _vp, _vp]),
     "tpmg_spmv": (_ip, [_vp, _vp, _vp]),
     "tpmg_vcycle": (_ip, [_vp, _vp, _vp]),
+    "tpmg_relax": (_ip, [_vp, _vp, _vp, _vp]),
     "tpmg_solve": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
     "tpmg_solve_richardson": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
     "tpmg_solve_bicgstab": (_ip, [_vp, _vp, _vp, ctypes.c_double, _ip, ctypes.POINTER(SolveInfo)]),
@@ -141,6 +145,9 @@ _sig = {
     "tpmg_mlp_gradients": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, _fp, _fp]),
     "tpmg_mlp_train_step": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, ctypes.c_float, _fp]),
     "tpmg_mlp_infer": (_ip, [_vp, _vp, _vp, _ip, _vp]),
+    "tpmg_mlp_features_increment": (_ip, [_vp, _vp, _vp, _vp, _vp]),
+    "tpmg_mlp_targets_increment": (_ip, [_vp, _vp, _vp, _vp, _vp]),
+    "tpmg_mlp_infer_increment": (_ip, [_vp, _vp, _vp, _vp, _vp, _ip, _vp]),
     "tpmg_mlp_save": (_ip, [_vp, ctypes.c_char_p]),
     "tpmg_mlp_load": (_ip, [_vp, ctypes.c_char_p]),
     "tpmg_mlp_destroy": (None, [_vp]),
@@ -238,6 +245,27 @@ def tpmg_op_create(grid: int, n_levels: int, omega2: float, alpha_r_v, alpha_s_v
     return h.value
 
 
+def tpmg_op_create_levels(grid: int, n_levels: int, omega2: float, alpha_r_v, alpha_s_v, beta_v,
+                          alpha_r_levels=None, alpha_s_levels=None, beta_levels=None) -> int:
+    """*_levels: None or a sequence indexed by refinement level (refinement + 1
+    entries) of None or per-cell factors of that grid."""
+    vert = [np.ascontiguousarray(a, dtype=np.float64) for a in (alpha_r_v, alpha_s_v, beta_v)]
+    keep = []
+
+    def table(levels):
+        if levels is None:
+            return None
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in levels]
+        keep.append(arrs)
+        return (_dp * len(arrs))(*[_dptr(a) for a in arrs])
+
+    tables = [table(x) for x in (alpha_r_levels, alpha_s_levels, beta_levels)]
+    h = _vp()
+    _check(_lib.tpmg_op_create_levels(grid, n_levels, float(omega2), *[_dptr(a) for a in vert], *tables,
+                                      ctypes.byref(h)))
+    return h.value
+
+
 def tpmg_op_set_full_profiles(op: int, grid: int, alpha_r, alpha_s, beta, xi_r=None) -> None:
     arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (alpha_r, alpha_s, beta, xi_r)]
     _check(_lib.tpmg_op_set_full_profiles(op, grid, *[_dptr(a) for a in arrs]))
@@ -327,6 +355,10 @@ def tpmg_spmv(mg: int, d_x, d_y):
 
 def tpmg_vcycle(mg: int, d_r, d_z):
     _check(_lib.tpmg_vcycle(mg, _dev(d_r), _dev(d_z)))
+
+
+def tpmg_relax(mg: int, d_f, d_u_in, d_u_out):
+    _check(_lib.tpmg_relax(mg, _dev(d_f), _dev(d_u_in), _dev(d_u_out)))
 
 
 def tpmg_solve(mg: int, d_f, d_u, rtol: float, maxit: int, history_cap: int = 256):
@@ -587,6 +619,18 @@ def tpmg_mlp_train_step(m: int, d_x, d_y, rows_total: int, d_rows, batch: int, l
 
 def tpmg_mlp_infer(m: int, mg: int, d_f, d_u0, relax: int = 1) -> None:
     _check(_lib.tpmg_mlp_infer(m, mg, _dev(d_f), relax, _dev(d_u0)))
+
+
+def tpmg_mlp_features_increment(m: int, mg: int, d_f, d_f_prev, d_x) -> None:
+    _check(_lib.tpmg_mlp_features_increment(m, mg, _dev(d_f), _dev(d_f_prev), _dev(d_x)))
+
+
+def tpmg_mlp_targets_increment(m: int, mg: int, d_u, d_u_prev, d_y) -> None:
+    _check(_lib.tpmg_mlp_targets_increment(m, mg, _dev(d_u), _dev(d_u_prev), _dev(d_y)))
+
+
+def tpmg_mlp_infer_increment(m: int, mg: int, d_f, d_f_prev, d_u_prev, d_u0, relax: int = 1) -> None:
+    _check(_lib.tpmg_mlp_infer_increment(m, mg, _dev(d_f), _dev(d_f_prev), _dev(d_u_prev), relax, _dev(d_u0)))
 
 
 def tpmg_mlp_save(m: int, path: str) -> None:

@@ -71,10 +71,16 @@ struct Operator {
   bool adv = false;             // ... and of the vertical advection
 };
 
-// Assembles the operator on the n_levels finest grids of g.
+// Assembles the operator on the n_levels finest grids of g. level_*: NULL
+// or refinement + 1 pointers, indexed by refinement level, to caller samples
+// of that grid's horizontal factors (n values); where a pointer is NULL the
+// finest grid takes alpha_r_h / alpha_s_h / beta_h (NULL: 1) and a coarse
+// grid the area-weighted means of its four children's factors.
 void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, const double* alpha_r_v,
                     const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
-                    const double* alpha_s_h, const double* beta_h);
+                    const double* alpha_s_h, const double* beta_h,
+                    const double* const* level_alpha_r_h = nullptr, const double* const* level_alpha_s_h = nullptr,
+                    const double* const* level_beta_h = nullptr);
 
 // Adds the coefficients of profiles that do not factorise, point samples on
 // the finest grid (cell-major: alpha_r [n][nz+1] at the radial faces,

@@ -82,6 +82,7 @@ struct tpmg_mlp {
   int* bad_row = nullptr;     // set by a batch that names a row outside [0, rows_total)
   // inference before line relaxation, and the relaxation's scratch (tiled FP64)
   double *guess = nullptr, *rsd = nullptr, *rsc = nullptr;
+  double* dvec = nullptr;   // the increment of a right-hand side or a solution (tiled)
   double* colmean = nullptr;  // column means of a right-hand side (features)
 
   // parameter offsets in the packed array
@@ -132,6 +133,7 @@ void carve(tpmg_mlp& m, Carve& c) {
   m.guess = c.take<double>(tiled);
   m.rsd = c.take<double>(tiled);
   m.rsc = c.take<double>(tiled);
+  m.dvec = c.take<double>(tiled);
   m.colmean = c.take<double>(m.max_rows);
 }
 
@@ -566,6 +568,56 @@ tpmg_status tpmg_mlp_infer(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, in
     MLP_HIP(forward(*m, g.n, tpmg::kEpiInferTiled, nullptr, out));
   }
   if (!relax) return TPMG_OK;
+  MLP_HIP(tpmg_relax_finest(mg, d_f, m->guess, d_u0, m->rsd, m->rsc, 1.0, m->stream));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mlp_features_increment(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, const double* d_f_prev,
+                                        float* d_x) {
+  tpmg_status st = check(m);
+  if (st != TPMG_OK) return st;
+  tpmg::FineGrid g;
+  if ((st = check_grid(m, mg, &g)) != TPMG_OK) return st;
+  if (!d_f || !d_f_prev || !d_x) return fail(TPMG_ERR_ARG, "NULL device buffer");
+  if (g.n > m->max_rows) return fail(TPMG_ERR_ARG, "the grid has more columns than max_rows");
+  MLP_HIP(tpmg::launch_vec_sub(d_f, d_f_prev, m->dvec, static_cast<size_t>(g.npad) * g.nz, m->stream));
+  MLP_HIP(tpmg::launch_mlp_features(g, m->dvec, m->colmean, d_x, m->stream));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mlp_targets_increment(tpmg_mlp* m, const tpmg_mg* mg, const double* d_u, const double* d_u_prev,
+                                       float* d_y) {
+  tpmg_status st = check(m);
+  if (st != TPMG_OK) return st;
+  tpmg::FineGrid g;
+  if ((st = check_grid(m, mg, &g)) != TPMG_OK) return st;
+  if (!d_u || !d_u_prev || !d_y) return fail(TPMG_ERR_ARG, "NULL device buffer");
+  if (g.n > m->max_rows) return fail(TPMG_ERR_ARG, "the grid has more columns than max_rows");
+  MLP_HIP(tpmg::launch_vec_sub(d_u, d_u_prev, m->dvec, static_cast<size_t>(g.npad) * g.nz, m->stream));
+  MLP_HIP(tpmg::launch_mlp_targets(g, m->dvec, d_y, m->stream));
+  return TPMG_OK;
+}
+
+tpmg_status tpmg_mlp_infer_increment(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, const double* d_f_prev,
+                                     const double* d_u_prev, int relax, double* d_u0) {
+  tpmg_status st = check(m);
+  if (st != TPMG_OK) return st;
+  tpmg::FineGrid g;
+  if ((st = check_grid(m, mg, &g)) != TPMG_OK) return st;
+  if (!d_f || !d_f_prev || !d_u_prev || !d_u0) return fail(TPMG_ERR_ARG, "NULL device buffer");
+  if (d_u0 == d_f || d_u0 == d_f_prev || d_u0 == d_u_prev)
+    return fail(TPMG_ERR_ARG, "u0 must not alias f, f_prev or u_prev");
+  if (g.n > m->max_rows) return fail(TPMG_ERR_ARG, "the grid has more columns than max_rows");
+  if (relax != 0 && relax != 1) return fail(TPMG_ERR_ARG, "relax must be 0 or 1");
+  if (g.stream != m->stream) return fail(TPMG_ERR_ARG, "the network and mg must share one stream");
+  MLP_HIP(tpmg::launch_vec_sub(d_f, d_f_prev, m->dvec, static_cast<size_t>(g.npad) * g.nz, m->stream));
+  // the network's increment into guess (real columns), then u_prev + increment
+  if ((st = tpmg_mlp_infer(m, mg, m->dvec, 0, m->guess)) != TPMG_OK) return st;
+  if (!relax) {
+    MLP_HIP(tpmg::launch_add_guess(g, d_u_prev, m->guess, d_u0, m->stream));
+    return TPMG_OK;
+  }
+  MLP_HIP(tpmg::launch_add_guess(g, d_u_prev, m->guess, m->guess, m->stream));
   MLP_HIP(tpmg_relax_finest(mg, d_f, m->guess, d_u0, m->rsd, m->rsc, 1.0, m->stream));
   return TPMG_OK;
 }

@@ -80,6 +80,11 @@ hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t s);
 hipError_t launch_mlp_features(const FineGrid& g, const double* f, double* means, float* x, hipStream_t s);
 hipError_t launch_mlp_features_bf16(const FineGrid& g, const double* f, double* means, const float* mu_x,
                                     const float* sd_x, int kp, bf16* xb, hipStream_t s);
+// out = a - b over a tiled vector of len values (the increment of a right-hand
+// side or a solution between two steps of a sequence).
+hipError_t launch_vec_sub(const double* a, const double* b, double* out, size_t len, hipStream_t s);
+// out = base + d on the real columns of the tiled vector, base on the padding.
+hipError_t launch_add_guess(const FineGrid& g, const double* base, const double* d, double* out, hipStream_t s);
 // y[T][k] = u(T, k), FP32.
 hipError_t launch_mlp_targets(const FineGrid& g, const double* u, float* y, hipStream_t s);
 

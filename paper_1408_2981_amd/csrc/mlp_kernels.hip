@@ -374,6 +374,27 @@ __global__ __launch_bounds__(256) void k_col_means(FineGrid g, const double* __r
   if (grp == 0 && t < g.n) means[t] = ((part[0][c] + part[1][c]) + (part[2][c] + part[3][c])) / g.nz;
 }
 
+// out = a - b entry by entry over a tiled vector of len values
+__global__ __launch_bounds__(256) void k_vec_sub(const double* __restrict__ a, const double* __restrict__ b,
+                                                 double* __restrict__ out, size_t len) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+
+// out = base + d on the real columns of a tiled vector, out = base on the
+// tile padding (d is not read there)
+__global__ __launch_bounds__(256) void k_add_guess(FineGrid g, const double* __restrict__ base,
+                                                   const double* __restrict__ d, double* __restrict__ out) {
+  const size_t len = static_cast<size_t>(g.npad) * g.nz;
+  const size_t per_tile = static_cast<size_t>(kTileCols) * g.nz;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < len;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int col = static_cast<int>(i / per_tile) * kTileCols + static_cast<int>(i & (kTileCols - 1));
+    out[i] = col < g.n ? base[i] + d[i] : base[i];
+  }
+}
+
 // One tile of 64 columns per block: the tile's values (level-major, one
 // coalesced row of 64 per level) are staged in LDS column-major with an odd
 // stride, completed by the neighbour means, and written out as contiguous
@@ -709,6 +730,22 @@ hipError_t launch_mlp_features_bf16(const FineGrid& g, const double* f, double* 
                                     const float* sd_x, int kp, bf16* xb, hipStream_t s) {
   hipLaunchKernelGGL(k_col_means, dim3(g.npad / kTileCols), dim3(256), 0, s, g, f, means);
   return columns_to_rows(1, g, f, means, mu_x, sd_x, kp, xb, s);
+}
+
+static unsigned vec_blocks(size_t len) {
+  const size_t b = (len + 255) / 256;
+  return static_cast<unsigned>(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+hipError_t launch_vec_sub(const double* a, const double* b, double* out, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_vec_sub, dim3(vec_blocks(len)), dim3(256), 0, s, a, b, out, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_guess(const FineGrid& g, const double* base, const double* d, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_guess, dim3(vec_blocks(static_cast<size_t>(g.npad) * g.nz)), dim3(256), 0, s, g, base, d,
+                     out);
+  return hipGetLastError();
 }
 
 hipError_t launch_mlp_targets(const FineGrid& g, const double* u, float* y, hipStream_t s) {

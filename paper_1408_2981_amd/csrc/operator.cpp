@@ -18,6 +18,7 @@
 // delta_c the tangent-plane offset of c's centre.
 #include <cmath>
 #include <stdexcept>
+#include <utility>
 
 #include "host.h"
 
@@ -82,7 +83,8 @@ std::vector<double> prolongation(const MeshLevel& coarse, const MeshLevel& fine)
 
 void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, const double* alpha_r_v,
                     const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
-                    const double* alpha_s_h, const double* beta_h) {
+                    const double* alpha_s_h, const double* beta_h, const double* const* level_alpha_r_h,
+                    const double* const* level_alpha_s_h, const double* const* level_beta_h) {
   const int nz = g.nz;
   op.nz = nz;
   op.refinement = g.refinement;
@@ -106,15 +108,22 @@ void build_operator(Operator& op, const Grid& g, int n_levels, double omega2, co
     if (src)
       for (int i = 0; i < nf; ++i) dst[i] = src[i];
   };
-  init(hr[fine_ref], alpha_r_h);
-  init(hs[fine_ref], alpha_s_h);
-  init(hb[fine_ref], beta_h);
+  auto given = [](const double* const* lv, int r) -> const double* { return lv ? lv[r] : nullptr; };
+  init(hr[fine_ref], given(level_alpha_r_h, fine_ref) ? given(level_alpha_r_h, fine_ref) : alpha_r_h);
+  init(hs[fine_ref], given(level_alpha_s_h, fine_ref) ? given(level_alpha_s_h, fine_ref) : alpha_s_h);
+  init(hb[fine_ref], given(level_beta_h, fine_ref) ? given(level_beta_h, fine_ref) : beta_h);
   for (int r = fine_ref; r > coarse_ref; --r) {
     const MeshLevel& F = g.levels[r];
     const int nc = g.levels[r - 1].n;
-    for (auto* pair : {&hr, &hs, &hb}) {
-      std::vector<double>& src = (*pair)[r];
-      std::vector<double>& dst = (*pair)[r - 1];
+    const std::pair<std::vector<std::vector<double>>*, const double* const*> planes[3] = {
+        {&hr, level_alpha_r_h}, {&hs, level_alpha_s_h}, {&hb, level_beta_h}};
+    for (const auto& plane : planes) {
+      std::vector<double>& src = (*plane.first)[r];
+      std::vector<double>& dst = (*plane.first)[r - 1];
+      if (const double* v = given(plane.second, r - 1)) {   // the caller's samples on this grid
+        dst.assign(v, v + nc);
+        continue;
+      }
       dst.assign(nc, 0.0);
       for (int P = 0; P < nc; ++P) {
         double num = 0.0, den = 0.0;

@@ -321,6 +321,8 @@ tpmg_status check_params(const tpmg_mg_params* p) {
   if (p->precond_profiles < 0 || p->precond_profiles > 2)
     return fail(TPMG_ERR_ARG, "precond_profiles must be 0, 1 or 2");
   if (p->smoother_order < 0 || p->smoother_order > 1) return fail(TPMG_ERR_ARG, "smoother_order must be 0 or 1");
+  if (p->tile_cols != 0 && p->tile_cols != tpmg::kTile)
+    return fail(TPMG_ERR_ARG, "tile_cols must be 0 or 64 (one lane per column, one wavefront per tile)");
   return TPMG_OK;
 }
 
@@ -1398,6 +1400,42 @@ tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, cons
   return TPMG_OK;
 }
 
+tpmg_status tpmg_op_create_levels(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
+                                  const double* alpha_s_v, const double* beta_v, const double* const* alpha_r_h,
+                                  const double* const* alpha_s_h, const double* const* beta_h, tpmg_op** out) {
+  if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(TPMG_ERR_ARG, "grid is NULL");
+  const int ref = g->g.refinement;
+  const int nl = n_levels == 0 ? std::min(6, ref + 1) : n_levels;
+  if (nl < 1 || nl > ref + 1) return fail(TPMG_ERR_ARG, "n_levels must be in [1, refinement + 1]");
+  for (const double* const* lv : {alpha_r_h, alpha_s_h, beta_h}) {
+    if (!lv) continue;
+    for (int r = ref - nl + 1; r <= ref; ++r) {
+      const double* v = lv[r];
+      if (!v) continue;
+      for (int i = 0; i < g->g.levels[r].n; ++i)
+        if (!(v[i] > 0.0) || !std::isfinite(v[i]))
+          return fail(TPMG_ERR_ARG, "horizontal profile factors of refinement level " + std::to_string(r) +
+                                        " must be positive and finite");
+    }
+  }
+  // the finest grid's samples go through the checks of tpmg_op_create
+  auto fine = [ref](const double* const* lv) -> const double* { return lv ? lv[ref] : nullptr; };
+  tpmg_status st = tpmg_op_create(g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, fine(alpha_r_h), fine(alpha_s_h),
+                                  fine(beta_h), out);
+  if (st != TPMG_OK) return st;
+  try {
+    tpmg::build_operator((*out)->op, g->g, nl, omega2, alpha_r_v, alpha_s_v, beta_v, fine(alpha_r_h),
+                         fine(alpha_s_h), fine(beta_h), alpha_r_h, alpha_s_h, beta_h);
+  } catch (const std::exception& ex) {
+    delete *out;
+    *out = nullptr;
+    return fail(TPMG_ERR_ARG, ex.what());
+  }
+  return TPMG_OK;
+}
+
 tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const double* alpha_r, const double* alpha_s,
                                       const double* beta, const double* xi_r) {
   if (!op || !g || !alpha_r || !alpha_s || !beta) return fail(TPMG_ERR_ARG, "NULL argument");
@@ -2004,6 +2042,19 @@ tpmg_status tpmg_solve(tpmg_mg* mg, const double* d_f, double* d_u, double rtol,
   if (diverged) return fail(TPMG_ERR_BREAKDOWN, "divergence: ||r|| exceeded div_tol ||r_0||");
   if (result == TPMG_ERR_BREAKDOWN) return fail(result, "breakdown: non-finite value or <p, A p> <= 0");
   return result;
+}
+
+tpmg_status tpmg_relax(tpmg_mg* mg, const double* d_f, const double* d_u_in, double* d_u_out) {
+  tpmg_status st = check_mg(mg);
+  if (st != TPMG_OK) return st;
+  if (!d_f || !d_u_in || !d_u_out) return fail(TPMG_ERR_ARG, "NULL vector");
+  if (d_u_in == d_u_out || d_f == d_u_out) return fail(TPMG_ERR_ARG, "u_out must not alias f or u_in");
+  const tpmg::LevelTune t = tpmg::default_tune(mg->nz, 8);
+  if (t.smoother == tpmg::kSmGlobal || (mg->pm != 0 && t.smoother != tpmg::kSmScan))
+    return fail(TPMG_ERR_ARG, "tpmg_relax: nz = " + std::to_string(mg->nz) +
+                                  " is beyond the FP64 line smoothers that need no scratch");
+  TPMG_HIP(tpmg_relax_finest(mg, d_f, d_u_in, d_u_out, nullptr, nullptr, 1.0, mg->stream));
+  return TPMG_OK;
 }
 
 namespace {
@@ -2624,5 +2675,6 @@ hipError_t tpmg_relax_finest(const tpmg_mg* mg, const double* f, const double* u
   if (!mg || !f || !u_in || !u_out || u_in == u_out) return hipErrorInvalidValue;
   tpmg::LevelView v = mg->view64(mg->nlev - 1);
   v.tune = tpmg::default_tune(mg->nz, 8);
+  if (v.pm != 0 && v.tune.smoother != tpmg::kSmScan) return hipErrorInvalidValue;   // nz beyond the scan form
   return tpmg::launch_smooth(v, 8, f, true, u_in, false, u_out, true, nullptr, sd, sc, omega, s);
 }

@@ -10,7 +10,8 @@ from . import (
     tpmg_mlp_create, tpmg_mlp_destroy, tpmg_mlp_features, tpmg_mlp_fit_scaling, tpmg_mlp_forward,
     tpmg_mlp_get_params, tpmg_mlp_get_scaling, tpmg_mlp_gradients, tpmg_mlp_infer, tpmg_mlp_load,
     tpmg_mlp_param_count, tpmg_mlp_save, tpmg_mlp_set_params, tpmg_mlp_set_scaling, tpmg_mlp_targets,
-    tpmg_mlp_train_step, tpmg_mlp_workspace_size,
+    tpmg_mlp_train_step, tpmg_mlp_workspace_size, tpmg_mlp_features_increment, tpmg_mlp_targets_increment,
+    tpmg_mlp_infer_increment,
 )
 
 
@@ -74,6 +75,26 @@ class ColumnMLP:
         tpmg_mlp_targets(self.h, problem.mg, u_tiled, out)
         return out
 
+    def features_increment(self, problem, f_tiled, f_prev_tiled, out=None):
+        """Features of the increment f - f_prev of the right-hand side."""
+        import torch
+
+        if out is None:
+            out = torch.empty((problem.n, self.n_in), dtype=torch.float32, device="cuda")
+        self._ready(f_tiled, f_prev_tiled, out)
+        tpmg_mlp_features_increment(self.h, problem.mg, f_tiled, f_prev_tiled, out)
+        return out
+
+    def targets_increment(self, problem, u_tiled, u_prev_tiled, out=None):
+        """Targets: the increment u - u_prev of the solution."""
+        import torch
+
+        if out is None:
+            out = torch.empty((problem.n, self.nz), dtype=torch.float32, device="cuda")
+        self._ready(u_tiled, u_prev_tiled, out)
+        tpmg_mlp_targets_increment(self.h, problem.mg, u_tiled, u_prev_tiled, out)
+        return out
+
     def forward(self, x):
         import torch
 
@@ -119,6 +140,12 @@ class ColumnMLP:
         one line-relaxation sweep when relax = 1; asynchronous on the shared stream."""
         self._ready(f_tiled, u0_tiled)
         tpmg_mlp_infer(self.h, problem.mg, f_tiled, u0_tiled, relax)
+
+    def infer_increment(self, problem, f_tiled, f_prev_tiled, u_prev_tiled, u0_tiled, relax: int = 1) -> None:
+        """u0_tiled = u_prev + the network's increment for f - f_prev, followed
+        by one line-relaxation sweep when relax = 1; asynchronous."""
+        self._ready(f_tiled, f_prev_tiled, u_prev_tiled, u0_tiled)
+        tpmg_mlp_infer_increment(self.h, problem.mg, f_tiled, f_prev_tiled, u_prev_tiled, u0_tiled, relax)
 
     def save(self, path: str) -> None:
         tpmg_mlp_save(self.h, path)

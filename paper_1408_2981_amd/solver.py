@@ -11,7 +11,7 @@ from . import (
     tpmg_grid_icosahedral, tpmg_grid_geometry, tpmg_grid_vertical, tpmg_op_create, tpmg_op_levels,
     tpmg_mg_params_default, tpmg_mg_workspace_size, tpmg_mg_setup, tpmg_mg_vector_length, tpmg_pack,
     tpmg_unpack, tpmg_spmv, tpmg_vcycle, tpmg_solve, tpmg_grid_destroy, tpmg_op_destroy, tpmg_mg_destroy,
-    tpmg_mg_tuning, tpmg_op_set_full_profiles,
+    tpmg_mg_tuning, tpmg_op_set_full_profiles, tpmg_relax, tpmg_op_create_levels,
 )
 
 
@@ -19,12 +19,15 @@ class Problem:
     """Grid + operator on the host; call setup() to place it on the GPU."""
 
     def __init__(self, refinement: int, r_faces, omega2: float, profiles=None, n_levels: int = 0, full=None,
-                 advection: bool = False):
+                 advection: bool = False, level_factors=None):
         """profiles: factorised profile factors (None: unit profiles). full:
         an object with alpha_r [n, nz+1], alpha_s, beta [n, nz], samples of
         profiles that do not factorise on the finest grid; the factorised
         profiles then serve as their approximate factorisation. advection:
-        also take full.xi_r [n, nz+1], the vertical advection."""
+        also take full.xi_r [n, nz+1], the vertical advection. level_factors:
+        {refinement level: (alpha_r_h, alpha_s_h, beta_h)}, horizontal
+        factors sampled by the caller on those grids (entries may be None;
+        tpmg_op_create_levels)."""
         r_faces = np.asarray(r_faces, dtype=np.float64)
         self.refinement = refinement
         self.nz = len(r_faces) - 1
@@ -35,7 +38,16 @@ class Problem:
         else:
             ar_v, as_v, b_v = profiles.alpha_r_v, profiles.alpha_s_v, profiles.beta_v
             h = (profiles.alpha_r_h, profiles.alpha_s_h, profiles.beta_h)
-        self.op = tpmg_op_create(self.grid, n_levels, omega2, ar_v, as_v, b_v, *h)
+        if level_factors:
+            tables = [[None] * (refinement + 1) for _ in range(3)]
+            for i in range(3):
+                tables[i][refinement] = h[i]
+                for r, planes in level_factors.items():
+                    if planes[i] is not None:
+                        tables[i][r] = planes[i]
+            self.op = tpmg_op_create_levels(self.grid, n_levels, omega2, ar_v, as_v, b_v, *tables)
+        else:
+            self.op = tpmg_op_create(self.grid, n_levels, omega2, ar_v, as_v, b_v, *h)
         if full is not None:
             tpmg_op_set_full_profiles(self.op, self.grid, full.alpha_r, full.alpha_s, full.beta,
                                       getattr(full, "xi_r", None) if advection else None)
@@ -114,6 +126,11 @@ class Problem:
     def vcycle(self, r_tiled, z_tiled):
         self._uses(r_tiled, z_tiled)
         tpmg_vcycle(self.mg, r_tiled, z_tiled)
+
+    def relax(self, f_tiled, u_in_tiled, u_out_tiled):
+        """One undamped FP64 line-relaxation sweep on the finest grid."""
+        self._uses(f_tiled, u_in_tiled, u_out_tiled)
+        tpmg_relax(self.mg, f_tiled, u_in_tiled, u_out_tiled)
 
     def solve(self, f_tiled, u_tiled, rtol: float = 1e-8, maxit: int = 100):
         """Synchronous; returns (status, iters, relres, history, t_total_ms)."""

@@ -99,7 +99,8 @@ def test_tuning_parameter_errors():
     assert (good.autotune, good.smoother, good.scan_levels, good.stencil_chunk) == (0, 0, 0, 0)
     base = T.tpmg_mg_workspace_size(op, good)
     for field, value in (("autotune", 3), ("autotune", -1), ("smoother", 4), ("scan_levels", 5),
-                         ("scan_levels", 32), ("stencil_chunk", -1), ("stencil_chunk", 257)):
+                         ("scan_levels", 32), ("stencil_chunk", -1), ("stencil_chunk", 257), ("tile_cols", 32),
+                         ("tile_cols", 128), ("tile_cols", -64)):
         p = T.tpmg_mg_params_default()
         setattr(p, field, value)
         with pytest.raises(T.TpmgError) as e:
@@ -110,7 +111,7 @@ def test_tuning_parameter_errors():
     with pytest.raises(T.TpmgError):
         T.tpmg_mg_workspace_size(op, p)
     p = T.tpmg_mg_params_default()
-    p.autotune, p.smoother, p.scan_levels, p.stencil_chunk = 2, T.SMOOTHER_SCAN, 16, 256
+    p.autotune, p.smoother, p.scan_levels, p.stencil_chunk, p.tile_cols = 2, T.SMOOTHER_SCAN, 16, 256, 64
     assert T.tpmg_mg_workspace_size(op, p) == base       # tuning does not change the workspace
 
 
@@ -236,3 +237,50 @@ def test_advection_coefficients_match_oracle():
     assert e.value.status == T.TPMG_ERR_ARG
     P.close()
     Q.close()
+
+
+def _level_factors(ref, seed):
+    """Seeded caller samples U[0.5, 2] for some planes of some grids: refinement
+    ref - 1 gets all three, ref - 2 only beta, the finest alpha_r; the rest
+    are left to the default (1 on the finest, area means below)."""
+    rng = np.random.default_rng(seed)
+    draw = lambda r: rng.uniform(0.5, 2.0, synth.n_cells(r))
+    lv = {ref: (draw(ref), None, None), ref - 1: (draw(ref - 1), draw(ref - 1), draw(ref - 1))}
+    if ref >= 2:
+        lv[ref - 2] = (None, None, draw(ref - 2))
+    tables = [[lv.get(r, (None, None, None))[i] for r in range(ref + 1)] for i in range(3)]
+    return lv, tables
+
+
+@pytest.mark.parametrize("ref,nz,seed", [(2, 4, 21), (4, 6, 22)])
+def test_per_level_factors_match_oracle(ref, nz, seed):
+    """tpmg_op_create_levels: coefficients of every level against the
+    oracle's hierarchy built from the same caller samples per grid (a
+    sampled plane replaces the area means on its grid; the grids below take
+    the means of it)."""
+    r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+    om2 = synth.omega_for(ref) ** 2
+    lv, tables = _level_factors(ref, seed)
+    g = T.tpmg_grid_icosahedral(ref, nz, r)
+    ones = np.ones(nz + 1), np.ones(nz), np.ones(nz)
+    op = T.tpmg_op_create_levels(g, 0, om2, *ones, *tables)
+    h = otpmg.build(ref, r, om2, level_factors=lv)
+    for lvl in range(len(h.ops)):
+        c = T.tpmg_op_coefficients(op, lvl, nz)
+        o = h.ops[lvl]
+        assert np.allclose(c["beta_h"][:, None] * c["beta_v"][None, :], o.beta, rtol=1e-13, atol=0)
+        assert np.allclose(c["alpha_s_h"][:, :, None] * c["alpha_s_v"][None, None, :], o.alpha_s, rtol=1e-12, atol=0)
+        assert np.allclose(c["alpha_r_h"][:, None] * c["alpha_r_v"][None, :], o.alpha_r, rtol=1e-13, atol=0)
+    # the sampled grid differs from the default hierarchy, the finest grid's
+    # alpha_S and beta (not sampled) do not
+    h0 = otpmg.build(ref, r, om2)
+    assert not np.allclose(h.ops[-2].beta, h0.ops[-2].beta)
+    assert np.array_equal(h.ops[-1].beta, h0.ops[-1].beta)
+    # errors: a non-positive sample on a grid of the hierarchy
+    bad = [list(t) for t in tables]
+    bad[2][ref - 1] = -np.ones(synth.n_cells(ref - 1))
+    with pytest.raises(T.TpmgError) as e:
+        T.tpmg_op_create_levels(g, 0, om2, *ones, *bad)
+    assert e.value.status == T.TPMG_ERR_ARG
+    T.tpmg_op_destroy(op)
+    T.tpmg_grid_destroy(g)

@@ -22,7 +22,7 @@ if not torch.cuda.is_available():
 
 import paper_1408_2981_amd as T  # noqa: E402
 import synth  # noqa: E402
-from oracle import mlp as omlp, tpmg as otpmg  # noqa: E402
+from oracle import mlp as omlp, operator as opm, tpmg as otpmg  # noqa: E402
 
 NZ, HIDDEN = 64, 256
 
@@ -264,9 +264,21 @@ def test_save_load_roundtrip(tmp_path):
 
 def test_learned_guess_saves_iterations():
     """Sequence f_t = f_0 + 0.05 t g on a refinement-4 grid with nz 32: train
-    on the solutions of t = 1..40, then solve t = 41..50 (mixed precision,
-    rtol 1e-8) from the zero guess and from the network's guess. The learned
-    guess must save iterations on every held-out step."""
+    one network on (f_t, u_t) and one on the increments (f_t - f_{t-1},
+    u_t - u_{t-1}) of the solutions of t = 1..40 (rtol 1e-10), then solve
+    t = 41..50 (mixed precision, rtol 1e-8) from: zero; zero + one
+    line-relaxation sweep (the sweep alone, tpmg_relax); the network on f_t
+    without and with the sweep; the previous solution without and with the
+    sweep; the previous solution + the increment network's output for
+    f_t - f_{t-1} with the sweep. Controls separate what the network adds
+    from what the sweep and the previous solution give. The network (+ sweep)
+    must save iterations over the zero guess on every held-out step; the
+    increment network (+ sweep) over the previous solution on every step,
+    and over the previous solution + sweep in total, never needing more on
+    any step. (Measured on MI355X: zero 15, zero + sweep 15, network 17-18,
+    network + sweep 14, previous 12, previous + sweep 11-12, increment
+    network + sweep 11 iterations: the network on f_t gains only over the
+    zero guess, the increment network at most one iteration.)"""
     w = synth.workload("seq_4_32")
     P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True, use_graph=True)
     geo = P.geometry()
@@ -274,8 +286,13 @@ def test_learned_guess_saves_iterations():
     ts_train, ts_test = range(1, 41), range(41, 51)
     net = T.ColumnMLP(w.nz, 256, max(4096, P.n), stream=P.stream)
     net.set_params(omlp.pack(omlp.init_params(w.nz + 3, 256, w.nz, 0)).astype(np.float32))
+    net_inc = T.ColumnMLP(w.nz, 256, max(4096, P.n), stream=P.stream)
+    net_inc.set_params(omlp.pack(omlp.init_params(w.nz + 3, 256, w.nz, 1)).astype(np.float32))
     X = torch.empty((len(ts_train) * P.n, w.nz + 3), dtype=torch.float32, device="cuda")
     Y = torch.empty((len(ts_train) * P.n, w.nz), dtype=torch.float32, device="cuda")
+    Xd = torch.empty(((len(ts_train) - 1) * P.n, w.nz + 3), dtype=torch.float32, device="cuda")
+    Yd = torch.empty(((len(ts_train) - 1) * P.n, w.nz), dtype=torch.float32, device="cuda")
+    prev = None
     for i, t in enumerate(ts_train):
         fd = P.pack(synth.sequence_rhs(w, geo["centres"], geo["areas"], vk, t))
         u = P.device_vector()
@@ -283,39 +300,154 @@ def test_learned_guess_saves_iterations():
         assert st == T.TPMG_OK
         net.features(P, fd, X[i * P.n:(i + 1) * P.n])
         net.targets(P, u, Y[i * P.n:(i + 1) * P.n])
-    net.synchronize()
-    net.fit_scaling(X, Y)
-    losses = net.train(X, Y, epochs=30, batch=4096, lr=1e-3, seed=0)
-    print("epoch losses", [f"{v:.2e}" for v in losses[::5]], f"last {losses[-1]:.2e}")
-    assert losses[-1] < 0.1 * losses[0]
+        if prev is not None:
+            net_inc.features_increment(P, fd, prev[0], Xd[(i - 1) * P.n:i * P.n])
+            net_inc.targets_increment(P, u, prev[1], Yd[(i - 1) * P.n:i * P.n])
+        net.synchronize()
+        prev = (fd, u)
+    for nn, xx, yy, name in ((net, X, Y, "network"), (net_inc, Xd, Yd, "increment network")):
+        nn.fit_scaling(xx, yy)
+        losses = nn.train(xx, yy, epochs=30, batch=4096, lr=1e-3, seed=0)
+        print(name, "epoch losses", [f"{v:.2e}" for v in losses[::5]], f"last {losses[-1]:.2e}")
+        assert losses[-1] < 0.1 * losses[0]
+
     def resid_ratio(fd, u):
         au = P.device_vector()
         P.spmv(u, au)
         P.synchronize()
         return float(torch.linalg.norm(fd - au) / torch.linalg.norm(fd))
 
-    zero_it, mlp_it, raw_it, q_raw, q_rel = [], [], [], [], []
+    kinds = ("zero", "zero_relax", "network", "network_relax", "previous", "previous_relax", "increment_relax")
+    its = {k: [] for k in kinds}
+    q = {k: [] for k in kinds}
+    f_prev, u_prev = prev
     for t in ts_test:
         fd = P.pack(synth.sequence_rhs(w, geo["centres"], geo["areas"], vk, t))
-        u = P.device_vector()
-        st, it0, *_ = P.solve(fd, u)
-        ur = P.device_vector()
-        net.infer(P, fd, ur, relax=0)
-        net.synchronize()
-        q_raw.append(resid_ratio(fd, ur))
-        st1, itr, *_ = P.solve(fd, ur)
-        u = P.device_vector()
-        net.infer(P, fd, u, relax=1)
-        net.synchronize()
-        q_rel.append(resid_ratio(fd, u))
-        st2, it1, *_ = P.solve(fd, u)
-        assert st == T.TPMG_OK and st1 == T.TPMG_OK and st2 == T.TPMG_OK
-        zero_it.append(it0)
-        raw_it.append(itr)
-        mlp_it.append(it1)
-    print(f"t=41..50: initial residual / |f|: network {np.mean(q_raw):.2e}, with relaxation {np.mean(q_rel):.2e}")
-    print(f"iterations: zero guess {zero_it}, network {raw_it}, network + relaxation {mlp_it}")
-    assert all(b < a for a, b in zip(zero_it, mlp_it))
+        sol = None
+        for kind in kinds:
+            u = P.device_vector()
+            if kind == "zero_relax":
+                P.relax(fd, P.device_vector(), u)
+            elif kind == "network":
+                net.infer(P, fd, u, relax=0)
+            elif kind == "network_relax":
+                net.infer(P, fd, u, relax=1)
+            elif kind == "previous":
+                u.copy_(u_prev)
+            elif kind == "previous_relax":
+                P.relax(fd, u_prev, u)
+            elif kind == "increment_relax":
+                net_inc.infer_increment(P, fd, f_prev, u_prev, u, relax=1)
+            P.synchronize()
+            torch.cuda.synchronize()
+            q[kind].append(resid_ratio(fd, u))
+            st, it, *_ = P.solve(fd, u)
+            assert st == T.TPMG_OK, kind
+            its[kind].append(it)
+            if kind == "zero":
+                sol = u
+        f_prev, u_prev = fd, sol
+    for k in kinds:
+        print(f"{k:16s} initial residual / |f| {np.mean(q[k]):.2e}, iterations {its[k]}")
+    assert all(b < a for a, b in zip(its["zero"], its["network_relax"]))
+    assert all(b < a for a, b in zip(its["previous"], its["increment_relax"]))
+    assert all(b <= a for a, b in zip(its["previous_relax"], its["increment_relax"]))
+    assert sum(its["increment_relax"]) < sum(its["previous_relax"])
+    net.close()
+    net_inc.close()
+
+
+def test_relax_matches_oracle():
+    """tpmg_relax (one undamped line-relaxation sweep in FP64) against the
+    oracle's block-Jacobi sweep with damping 1 (eq. BlockJacobi), from a
+    seeded guess and from zero, on a graded grid with random factorised
+    profiles. Bar, entry by entry: the rounding floor of the sweep, (8 + nz)
+    eps A_T^-1 (|f| + |A| |u_in|) for each side, twice: the residual
+    f - A u_in is formed from stencil terms of size |A| |u_in| (|A| = 2 D - A
+    for this M-matrix) and its rounding is carried through the column solve
+    A_T^-1 (entrywise positive), and the margin-form Thomas solve adds a few
+    roundings per level. (With the oracle in FP64 against the same sweep in
+    80-bit arithmetic the error is 0.23 of eps A_T^-1 (2|f| + 2|A||u_in|) here,
+    9e-11 of the result's largest magnitude: the graded columns amplify the
+    rounding of the residual.)"""
+    w = synth.workload("seq_4_32")
+    prof = synth.profiles_random(w.nz, synth.n_cells(w.refinement), seed=5)
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2, profiles=prof).setup()
+    h = otpmg.build(w.refinement, w.r_faces(), w.omega2, profiles=prof)
+    fine = h.meshes[-1]
+    op = h.finest
+    l, m, e = opm.column_bands(op)
+    f = synth.cell_integral(synth.uniform_noise(P.n, w.nz, 3), fine.area, h.vert.vk)
+    u_in = synth.uniform_noise(P.n, w.nz, 4) * 1e-3
+    eps = np.finfo(np.float64).eps
+    for start in (u_in, np.zeros_like(u_in)):
+        out = P.device_vector()
+        P.relax(P.pack(f), P.pack(start), out)
+        P.synchronize()
+        got = P.unpack(out)
+        ref = otpmg.smooth(op, f, start, 1.0)
+        a = np.abs(start)
+        abs_au = 2.0 * (e + l + m) * a - opm.apply(op, a)
+        bound = 2 * (8 + w.nz) * eps * otpmg.thomas_margin(l, m, e, np.abs(f) + abs_au)
+        ratio = float(np.max(np.abs(got - ref) / bound))
+        print(f"relax vs oracle: {np.max(np.abs(got - ref)) / np.max(np.abs(ref)):.2e} of max |u|, "
+              f"{ratio:.2e} of the rounding bar")
+        assert ratio <= 1.0
+    with pytest.raises(T.TpmgError):
+        x = P.device_vector()
+        P.relax(x, x, x)
+
+
+def test_increment_features_targets_and_inference():
+    """The increment forms against their definitions: features of f - f_prev
+    equal the oracle's features of the difference (formed on the host; the
+    bar of test_features_and_targets_match_oracle), targets equal u - u_prev
+    rounded to FP32, and tpmg_mlp_infer_increment equals u_prev + the
+    network's output for the difference (bit for bit, padding columns those
+    of u_prev) and, with the sweep, tpmg_relax of that (bit for bit)."""
+    w = synth.workload("seq_4_32")
+    P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True)
+    h = otpmg.build(w.refinement, w.r_faces(), w.omega2)
+    fine = h.meshes[-1]
+    f_prev = synth.sequence_rhs(w, fine.centre, fine.area, h.vert.vk, 7)
+    f = synth.sequence_rhs(w, fine.centre, fine.area, h.vert.vk, 8) + 1e-9 * synth.uniform_noise(P.n, w.nz, 9)
+    u_prev_h = synth.uniform_noise(P.n, w.nz, 10) * 1e-2
+    u_h = u_prev_h + synth.uniform_noise(P.n, w.nz, 11) * 1e-4
+    net = T.ColumnMLP(w.nz, 256, P.n, stream=P.stream)
+    p = omlp.init_params(w.nz + 3, 256, w.nz, 13)
+    net.set_params(omlp.pack(p).astype(np.float32))
+    fd, fpd, ud, upd = P.pack(f), P.pack(f_prev), P.pack(u_h), P.pack(u_prev_h)
+    x = net.features_increment(P, fd, fpd)
+    y = net.targets_increment(P, ud, upd)
+    net.synchronize()
+    xo = omlp.features(f - f_prev, fine.nbr)
+    assert _rel(x.cpu().numpy(), xo) <= 1e-6
+    assert np.array_equal(y.cpu().numpy(), (u_h - u_prev_h).astype(np.float32))
+    s = omlp.fit_scaling(xo, (u_h - u_prev_h))
+    net.set_scaling(s.mu_x, s.sd_x, s.mu_y, s.sd_y)
+    # reference: the plain inference on the difference vector, added to u_prev
+    dfd = fd - fpd
+    torch.cuda.synchronize()
+    du = P.device_vector()
+    net.infer(P, dfd, du, relax=0)
+    net.synchronize()
+    upd_t = upd.clone()
+    real = P.pack(np.ones((P.n, w.nz))) != 0
+    expect0 = torch.where(real, upd_t + du, upd_t)
+    got0 = P.device_vector()
+    net.infer_increment(P, fd, fpd, upd, got0, relax=0)
+    net.synchronize()
+    assert torch.equal(got0, expect0)
+    expect1 = P.device_vector()
+    P.relax(fd, expect0, expect1)
+    got1 = P.device_vector()
+    net.infer_increment(P, fd, fpd, upd, got1, relax=1)
+    net.synchronize()
+    P.synchronize()
+    assert torch.equal(got1, expect1)
+    with pytest.raises(T.TpmgError):
+        net.infer_increment(P, fd, fpd, upd, upd, relax=1)
+    net.close()
 
 
 def test_features_and_inference_at_sequence_shape():

@@ -229,3 +229,47 @@ def test_extreme_anisotropy_fp32():
     print(f"H/h 1e-3: FP32 V-cycle vs FP64 V-cycle {err:.2e}; mixed rate {rate32:.4f}, FP64 oracle rate {ref:.4f}")
     assert err <= 1e-4
     assert rate32 < 1.0 and abs(rate32 - ref) <= 0.1
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_caller_samples_on_coarse_grids(fp32):
+    """Horizontal factors sampled by the caller on coarse grids
+    (tpmg_op_create_levels) on top of random finest-grid profiles: FP64
+    V-cycle and solve against the oracle built from the same samples (1e-10,
+    identical iteration counts and histories); mixed: iterations within one
+    of the oracle's mixed solve and the error against the exact solution
+    within the bar of test_solve_mixed."""
+    ref, nz = 3, 13
+    r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+    om2 = synth.omega_for(ref) ** 2
+    prof = synth.profiles_random(nz, synth.n_cells(ref), seed=31)
+    rng = np.random.default_rng(32)
+    lv = {2: (rng.uniform(0.5, 2.0, 320), None, rng.uniform(0.5, 2.0, 320)),
+          1: (None, rng.uniform(0.5, 2.0, 80), None)}
+    h = otpmg.build(ref, r, om2, profiles=prof, level_factors=lv)
+    import paper_1408_2981_amd as T
+
+    P = T.Problem(ref, r, om2, profiles=prof, level_factors=lv).setup(precond_fp32=fp32)
+    fine = h.meshes[-1]
+    f = synth.cell_integral(synth.uniform_noise(fine.n, nz, 33), fine.area, h.vert.vk)
+    ud = P.device_vector()
+    st, iters, relres, hist, _ = P.solve(P.pack(f), ud, rtol=1e-8, maxit=100)
+    u = P.unpack(ud)
+    ref64 = otpmg.solve(h, f, rtol=1e-8)
+    assert st == 0
+    if not fp32:
+        zd = P.device_vector()
+        P.vcycle(P.pack(f), zd)
+        P.synchronize()
+        assert rel(P.unpack(zd), otpmg.vcycle(h, f)) <= 1e-10
+        assert iters == ref64.iters
+        assert rel(u, ref64.x) <= 1e-10
+        assert np.allclose(hist, ref64.history, rtol=1e-6, atol=0)
+    else:
+        ref32 = otpmg.solve(h, f, rtol=1e-8, precision="fp32")
+        tight = otpmg.solve(h, f, rtol=1e-13, maxit=400)
+        assert abs(iters - ref32.iters) <= 1
+        assert rel(u, tight.x) <= max(1e-6, 10 * rel(ref32.x, tight.x))
+    print(f"caller samples, {'mixed' if fp32 else 'FP64'}: {iters} iterations (oracle FP64 {ref64.iters}), "
+          f"solution vs oracle FP64 {rel(u, ref64.x):.2e}")
+    P.close()
