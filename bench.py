@@ -620,6 +620,8 @@ def main():
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the kernel timing loops on the refinement-7 grid (finest FP32 sweep and the operator "
                          "with the direction update) and a 1 GiB calibration copy, for hardware-counter runs")
+    ap.add_argument("--anisotropy", action="store_true",
+                    help="only the anisotropy sweep on refinement 7 x 128 levels (H/h = 1e-1, 1e-2, 1e-3)")
     ap.add_argument("--no-roofline-workload", action="store_true",
                     help="skip the refinement-7 solves and kernel timings that the roofline is taken on")
     args = ap.parse_args()
@@ -653,6 +655,9 @@ def main():
         return
     if args.batch:
         batch_report()
+        return
+    if args.anisotropy:
+        anisotropy_report()
         return
     if args.profiles:
         profiles_report()
