@@ -1368,9 +1368,9 @@ tpmg_status tpmg_grid_vertical(const tpmg_grid* g, double* vk) {
   return TPMG_OK;
 }
 
-tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
-                           const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
-                           const double* alpha_s_h, const double* beta_h, tpmg_op** out) {
+tpmg_status tpmg_op_create_levels(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
+                                  const double* alpha_s_v, const double* beta_v, const double* const* alpha_r_h,
+                                  const double* const* alpha_s_h, const double* const* beta_h, tpmg_op** out) {
   if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!g) return fail(TPMG_ERR_ARG, "grid is NULL");
@@ -1384,15 +1384,20 @@ tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, cons
       if (!(v[i] > 0.0) || !std::isfinite(v[i])) return false;
     return true;
   };
-  const size_t nf = g->g.levels[ref].n;
   if (!positive(alpha_r_v + 1, nz > 1 ? nz - 1 : 0) || !positive(alpha_s_v, nz) || !positive(beta_v, nz))
     return fail(TPMG_ERR_ARG, "vertical profile factors must be positive and finite");
-  if ((alpha_r_h && !positive(alpha_r_h, nf)) || (alpha_s_h && !positive(alpha_s_h, nf)) ||
-      (beta_h && !positive(beta_h, nf)))
-    return fail(TPMG_ERR_ARG, "horizontal profile factors must be positive and finite");
+  for (const double* const* lv : {alpha_r_h, alpha_s_h, beta_h}) {
+    if (!lv) continue;
+    for (int r = ref - n_levels + 1; r <= ref; ++r)
+      if (lv[r] && !positive(lv[r], g->g.levels[r].n))
+        return fail(TPMG_ERR_ARG, "horizontal profile factors of refinement level " + std::to_string(r) +
+                                      " must be positive and finite");
+  }
   try {
     auto* o = new tpmg_op();
-    tpmg::build_operator(o->op, g->g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, alpha_r_h, alpha_s_h, beta_h);
+    // (the finest grid's factors are entry ref of the tables)
+    tpmg::build_operator(o->op, g->g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, nullptr, nullptr, nullptr,
+                         alpha_r_h, alpha_s_h, beta_h);
     *out = o;
   } catch (const std::exception& ex) {
     return fail(TPMG_ERR_ARG, ex.what());
@@ -1400,40 +1405,18 @@ tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, cons
   return TPMG_OK;
 }
 
-tpmg_status tpmg_op_create_levels(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
-                                  const double* alpha_s_v, const double* beta_v, const double* const* alpha_r_h,
-                                  const double* const* alpha_s_h, const double* const* beta_h, tpmg_op** out) {
-  if (!out) return fail(TPMG_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (!g) return fail(TPMG_ERR_ARG, "grid is NULL");
-  const int ref = g->g.refinement;
-  const int nl = n_levels == 0 ? std::min(6, ref + 1) : n_levels;
-  if (nl < 1 || nl > ref + 1) return fail(TPMG_ERR_ARG, "n_levels must be in [1, refinement + 1]");
-  for (const double* const* lv : {alpha_r_h, alpha_s_h, beta_h}) {
-    if (!lv) continue;
-    for (int r = ref - nl + 1; r <= ref; ++r) {
-      const double* v = lv[r];
-      if (!v) continue;
-      for (int i = 0; i < g->g.levels[r].n; ++i)
-        if (!(v[i] > 0.0) || !std::isfinite(v[i]))
-          return fail(TPMG_ERR_ARG, "horizontal profile factors of refinement level " + std::to_string(r) +
-                                        " must be positive and finite");
-    }
-  }
-  // the finest grid's samples go through the checks of tpmg_op_create
-  auto fine = [ref](const double* const* lv) -> const double* { return lv ? lv[ref] : nullptr; };
-  tpmg_status st = tpmg_op_create(g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, fine(alpha_r_h), fine(alpha_s_h),
-                                  fine(beta_h), out);
-  if (st != TPMG_OK) return st;
-  try {
-    tpmg::build_operator((*out)->op, g->g, nl, omega2, alpha_r_v, alpha_s_v, beta_v, fine(alpha_r_h),
-                         fine(alpha_s_h), fine(beta_h), alpha_r_h, alpha_s_h, beta_h);
-  } catch (const std::exception& ex) {
-    delete *out;
-    *out = nullptr;
-    return fail(TPMG_ERR_ARG, ex.what());
-  }
-  return TPMG_OK;
+tpmg_status tpmg_op_create(const tpmg_grid* g, int n_levels, double omega2, const double* alpha_r_v,
+                           const double* alpha_s_v, const double* beta_v, const double* alpha_r_h,
+                           const double* alpha_s_h, const double* beta_h, tpmg_op** out) {
+  // the finest grid's factors as the only entries of the per-grid tables
+  if (!g) return tpmg_op_create_levels(g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, nullptr, nullptr, nullptr,
+                                       out);
+  std::vector<const double*> tr(g->g.refinement + 1, nullptr), ts(tr), tb(tr);
+  tr.back() = alpha_r_h;
+  ts.back() = alpha_s_h;
+  tb.back() = beta_h;
+  return tpmg_op_create_levels(g, n_levels, omega2, alpha_r_v, alpha_s_v, beta_v, tr.data(), ts.data(), tb.data(),
+                               out);
 }
 
 tpmg_status tpmg_op_set_full_profiles(tpmg_op* op, const tpmg_grid* g, const double* alpha_r, const double* alpha_s,
