@@ -140,3 +140,30 @@ def test_profile_mode_restrictions():
     P.close()
     Q.close()
     R.close()
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_relax_on_the_vcycle_operator(mode):
+    """tpmg_relax with profiles that do not factorise runs on the finest
+    operator of the V-cycle (full, factorised or partial): against the
+    oracle's sweep with damping 1 on that operator, entrywise within the
+    rounding bar of test_gpu_mlp.test_relax_matches_oracle."""
+    ref, r, om2, prof, full, f = _case("random")
+    code, terms = MODES[mode]
+    h = otpmg.build(ref, r, om2, profiles=prof, full=full if terms else None, full_terms=terms)
+    P = T.Problem(ref, r, om2, profiles=prof, full=full).setup(precond_profiles=code, precond_fp32=True)
+    op = h.finest
+    l, m, e = opm.column_bands(op)
+    u_in = synth.uniform_noise(f.shape[0], f.shape[1], 9) * 1e-3
+    out = P.device_vector()
+    P.relax(P.pack(f), P.pack(u_in), out)
+    P.synchronize()
+    got = P.unpack(out)
+    ref_u = otpmg.smooth(op, f, u_in, 1.0)
+    a = np.abs(u_in)
+    bound = 2 * (8 + f.shape[1]) * np.finfo(np.float64).eps * otpmg.thomas_margin(
+        l, m, e, np.abs(f) + 2.0 * (e + l + m) * a - opm.apply(op, a))
+    ratio = float(np.max(np.abs(got - ref_u) / bound))
+    print(f"{mode}: relax vs oracle {ratio:.2e} of the rounding bar")
+    assert ratio <= 1.0
+    P.close()
