@@ -92,6 +92,33 @@ __host__ __device__ Lv<T> view(const LevelView& L) {
                L.pass};
 }
 
+// The same view of a level descriptor held in the constant address space
+// (the segment tables of batched launches, below).
+template <typename T>
+__device__ __forceinline__ Lv<T> view(const __attribute__((address_space(4))) LevelView& L) {
+  return Lv<T>{L.n,
+               L.npad,
+               L.nz,
+               L.nbr,
+               L.code,
+               L.halo,
+               static_cast<const T*>(L.beta_h),
+               static_cast<const T*>(L.ar_h),
+               static_cast<const T*>(L.as_h),
+               static_cast<const T*>(L.pw),
+               static_cast<const T*>(L.beta_v),
+               static_cast<const T*>(L.as_v),
+               static_cast<const T*>(L.ar_v),
+               static_cast<const T*>(L.margin),
+               static_cast<const T*>(L.fb),
+               static_cast<const T*>(L.far),
+               static_cast<const T*>(L.fas),
+               static_cast<const T*>(L.fxl),
+               static_cast<const T*>(L.fxu),
+               L.colour,
+               L.pass};
+}
+
 // this block's index and the number of blocks of its problem's launch
 struct GridPos {
   int b;
@@ -1093,9 +1120,10 @@ constexpr int scan_waves_per_simd(bool wide) {
          : (sizeof(T) == 8 && KB == 16) ? 2
                                         : 4;
 }
-// the batched form also holds its segment's pointers: no FP32 bound beyond 4
+// profiles that do not factorise: the per-level coefficient loads need more
+// registers, no FP32 bound beyond 4
 template <int KB, typename T>
-constexpr int scan_waves_per_simd_batched() {
+constexpr int scan_waves_per_simd_full() {
   return (sizeof(T) == 8 && KB == 16) ? 2 : 4;
 }
 template <int KB, typename T>
@@ -1103,12 +1131,10 @@ constexpr int scan_max_threads() {
   return 64 * ((sizeof(T) == 8 && KB == 16) ? 8 : kScanWavesMax);
 }
 
-// (profiles that do not factorise load their coefficients per level: the
-// occupancy bound of the batched form)
 template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS, int PM>
 __global__ __launch_bounds__((scan_max_threads<KB, T>()),
                              (PM == 0 ? scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value)
-                                      : scan_waves_per_simd_batched<KB, T>())) void k_smooth_scan(
+                                      : scan_waves_per_simd_full<KB, T>())) void k_smooth_scan(
     Lv<T> L, const TF* __restrict__ f, const T* __restrict__ u_in, TO* __restrict__ u_out, T* __restrict__ fcopy,
     T omega, const double* __restrict__ q, double* __restrict__ partials) {
   smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS, PM>(L, f, u_in, u_out, fcopy, omega, q, partials, whole_grid());
@@ -1374,12 +1400,20 @@ __global__ __launch_bounds__(256) void k_unpack(const double* __restrict__ tiled
 // Problems whose scalars are marked done are skipped.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ const Seg* find_segment(const Seg* __restrict__ segs, int nseg, GridPos& g) {
+// The segment table is read through the constant address space: the table
+// does not change during a launch, so its fields become scalar loads the
+// compiler may repeat where they are used instead of holding every pointer
+// of a level descriptor in registers (which took the grouped sweep from the
+// 50 vector registers of the single one to 81, and its occupancy with it).
+using CSeg = const __attribute__((address_space(4))) Seg;
+
+__device__ __forceinline__ CSeg* find_segment(const Seg* __restrict__ segs_g, int nseg, GridPos& g) {
+  CSeg* segs = (CSeg*)segs_g;
   const int b = blockIdx.x;
   int s = 0;
   for (int i = 1; i < nseg; ++i)
     if (segs[i].start <= b) s = i;
-  const Seg* sg = &segs[s];
+  CSeg* sg = &segs[__builtin_amdgcn_readfirstlane(s)];
   g.b = b - sg->start;
   g.nb = sg->nblocks;
   if (g.b >= g.nb) return nullptr;                      // alignment padding
@@ -1387,13 +1421,13 @@ __device__ __forceinline__ const Seg* find_segment(const Seg* __restrict__ segs,
   return sg;
 }
 
-// (the segment lookup costs registers: the fused-dots variant keeps its
-// natural allocation rather than spilling under the FP32 bound)
+// (the occupancy bounds of the single sweep)
 template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
-__global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd_batched<KB, T>())) void kb_smooth_scan(const Seg* __restrict__ segs,
-                                                                                        int nseg, double omega) {
+__global__ __launch_bounds__((scan_max_threads<KB, T>()),
+                             (scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value))) void kb_smooth_scan(
+    const Seg* __restrict__ segs, int nseg, double omega) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(view<T>(sg->L), static_cast<const TF*>(sg->in0),
                                                      static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
@@ -1406,7 +1440,7 @@ __global__ __launch_bounds__((scan_max_threads<KB, T>()), (scan_waves_per_simd_b
 template <typename T, int CH>
 __global__ __launch_bounds__(256) void kb_residual_restrict(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   residual_restrict_body<T, CH>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
                              static_cast<const T*>(sg->in1), static_cast<T*>(sg->out0), g);
@@ -1415,7 +1449,7 @@ __global__ __launch_bounds__(256) void kb_residual_restrict(const Seg* __restric
 template <typename T>
 __global__ __launch_bounds__(256) void kb_prolong_add(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   prolong_add_body<T>(view<T>(sg->L), view<T>(sg->C), sg->chunk, static_cast<const T*>(sg->in0),
                       static_cast<T*>(sg->out0), g);
@@ -1424,7 +1458,7 @@ __global__ __launch_bounds__(256) void kb_prolong_add(const Seg* __restrict__ se
 template <int CH>
 __global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   spmv_body<0, CH>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
                    static_cast<double*>(sg->out0), sg->partials, g);
@@ -1433,14 +1467,14 @@ __global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, i
 template <typename TZ>
 __global__ __launch_bounds__(256) void kb_pupdate(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   pupdate_body(static_cast<const TZ*>(sg->in0), static_cast<double*>(sg->out0), sg->sc, sg->len, g);
 }
 
 __global__ __launch_bounds__(256) void kb_fcg_update(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   fcg_update_body(static_cast<double*>(sg->out0), static_cast<double*>(sg->out1), static_cast<const double*>(sg->in0),
                   static_cast<const double*>(sg->in1), sg->sc, sg->len, sg->partials, g);
@@ -1449,7 +1483,7 @@ __global__ __launch_bounds__(256) void kb_fcg_update(const Seg* __restrict__ seg
 template <int CH, typename TZ>
 __global__ __launch_bounds__(256) void kb_spmv_pring(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   spmv_pring_body<CH, TZ>(view<double>(sg->L), static_cast<const TZ*>(sg->in0), sg->aux, sg->len,
                           static_cast<double*>(sg->out1), static_cast<double*>(sg->out0), sg->partials, sg->sc, g);
@@ -1457,7 +1491,7 @@ __global__ __launch_bounds__(256) void kb_spmv_pring(const Seg* __restrict__ seg
 
 __global__ __launch_bounds__(256) void kb_rupdate(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
-  const Seg* sg = find_segment(segs, nseg, g);
+  CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
   rupdate_body(static_cast<double*>(sg->out1), static_cast<const double*>(sg->in1), sg->sc, sg->len, sg->partials,
                static_cast<float*>(sg->out0), g);
@@ -1465,7 +1499,7 @@ __global__ __launch_bounds__(256) void kb_rupdate(const Seg* __restrict__ segs, 
 
 // one block per problem
 __global__ __launch_bounds__(kFinThreads) void kb_finalize(const Seg* __restrict__ segs, int nseg) {
-  const Seg* sg = &segs[blockIdx.x];
+  CSeg* sg = &((CSeg*)segs)[blockIdx.x];
   if (sg->sc->done) return;
   finalize_body(sg->site, sg->partials, sg->nblocks, sg->sc, 0.0);
 }
