@@ -31,7 +31,11 @@ prolongation on constants and O(h^2) on linear fields; the tensor-decoupling
 of the V-cycle spectrum (Section 3.2.1, eq. EigenvalueEquation); a V-cycle
 rate bounded in h and anisotropy; FCG == textbook CG (scipy) for M = I,
 one step for M = A^-1, == PCG (scipy) for a symmetric M; the solve ==
-scipy.sparse.linalg.spsolve.
+scipy.sparse.linalg.spsolve; the V-cycle of Algorithm 1 == its dense
+composition from explicit matrices; the FP32 V-cycle (make_preconditioner)
+a float32 rounding of the FP64 one; the block-SOR sweep == the dense block
+SOR formula in colour order; Richardson and BiCGStab against their
+definitions (tests/test_oracle_sor.py, tests/test_oracle_advection.py).
 """
 from __future__ import annotations
 

@@ -342,3 +342,27 @@ def test_vcycle_schedule_dense_identity(levels):
         e[i] = 1.0
         got[:, i] = tpmg.vcycle(h, e.reshape(op.n, op.nz)).ravel()
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_fp32_vcycle_is_a_float32_rounding_of_the_fp64_one():
+    """make_preconditioner("fp32") is the V-cycle of Algorithm 1 (pinned in
+    FP64 by test_vcycle_schedule_dense_identity) evaluated in float32: every
+    coefficient array of its hierarchy is float32, and one V-cycle differs
+    from the FP64 one by a float32 rounding: more than 1e3 FP64 epsilons
+    (so float32 arithmetic is really used) and less than 100 float32
+    epsilons. Changing the algorithm moves it by orders of magnitude more
+    (one post-smoothing sweep fewer: 7e-2; damping 0.7 instead of 2/3:
+    3e-2), so the bar separates rounding from a different computation."""
+    import dataclasses
+
+    h, f = _small_problem(5)
+    h32 = h.astype(np.float32)
+    for op in h32.ops:
+        assert op.beta.dtype == np.float32 and op.alpha_r.dtype == np.float32 and op.alpha_s.dtype == np.float32
+    z64 = tpmg.vcycle(h, f)
+    z32 = tpmg.make_preconditioner(h, "fp32")(f)
+    d = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    assert 1e3 * np.finfo(np.float64).eps < d < 100 * np.finfo(np.float32).eps
+    for changed in (dataclasses.replace(h, nu_post=1), dataclasses.replace(h, omega=0.7)):
+        dc = np.linalg.norm(tpmg.vcycle(changed, f) - z64) / np.linalg.norm(z64)
+        assert dc > 1e3 * 100 * np.finfo(np.float32).eps
