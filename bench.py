@@ -102,7 +102,8 @@ def roofline_workload(steps: int, reps: int) -> dict:
     """The HBM-bound workload (icosahedral refinement 7 x 128 quadratic levels,
     41,943,040 unknowns, H = 0.1 x the horizontal spacing, seeded uniform
     right-hand side; at refinement 6 the FP32 fields fit the 256 MB
-    last-level cache): mixed and FP64 solve times, and the two dominant
+    last-level cache): mixed and FP64 solve times with the solve's
+    algorithmic bytes per second (tpmg_solve_info.model_bytes), and the two dominant
     kernels of the mixed solve timed alone with HIP events on the solver's
     stream (`reps` back-to-back launches each): the finest FP32 line-smoother
     sweep and q = A p with the direction update."""
@@ -130,7 +131,11 @@ def roofline_workload(steps: int, reps: int) -> dict:
             times.append(time.perf_counter() - t0)
             assert st == T.TPMG_OK, (name, st)
         ms = 1000.0 * float(np.median(times))
-        r = {"ms_per_solve": ms, "iters": it, "unknowns_per_s": w.unknowns / (ms / 1000.0)}
+        u.zero_()
+        torch.cuda.synchronize()
+        model_bytes = T.tpmg_solve_details(P.mg, f, u, 1e-8, 100)["model_bytes"]   # (not timed)
+        r = {"ms_per_solve": ms, "iters": it, "unknowns_per_s": w.unknowns / (ms / 1000.0),
+             "model_GBs": model_bytes / (ms / 1000.0) / 1e9}
         if fp32:
             fine = P.tuning()[-1]
             sw_ms, sw_b = T.tpmg_mg_time_kernel(P.mg, T.KERNEL_SWEEP, reps)
@@ -751,9 +756,9 @@ def main():
         out["config"]["roofline_workload"] = {
             "workload": rw["workload"],
             "mixed_unknowns_per_s": m3["unknowns_per_s"], "mixed_ms_per_solve": m3["ms_per_solve"],
-            "mixed_iters": m3["iters"],
+            "mixed_iters": m3["iters"], "mixed_model_GBs": m3["model_GBs"],
             "fp64_unknowns_per_s": rw["fp64"]["unknowns_per_s"], "fp64_ms_per_solve": rw["fp64"]["ms_per_solve"],
-            "fp64_iters": rw["fp64"]["iters"]}
+            "fp64_iters": rw["fp64"]["iters"], "fp64_model_GBs": rw["fp64"]["model_GBs"]}
         achieved = m3["sweep_bytes"] / (m3["sweep_us"] / 1e6) / 1e9
         out["roofline"] = {
             "kernel": "finest-grid line-smoother sweep (FP32, mixed solve), refinement 7 x 128 levels",
