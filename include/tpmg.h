@@ -102,8 +102,8 @@ typedef struct {
                           that neighbours differ (tpmg_grid_colouring),
                           the colours relaxed one after another, ascending
                           before the coarse-grid correction and descending
-                          after; one pass over the grid per colour. Not
-                          for batched solves.                             */
+                          after; one pass over the grid per colour. The
+                          problems of a batch share it.                   */
   int tile_cols;       /* columns per tile of the device layout: 0 (auto)
                           or 64, the only width: one lane per column and
                           one 64-lane wavefront per tile, so that every
@@ -349,8 +349,10 @@ tpmg_status tpmg_solve_bicgstab(tpmg_mg* mg, const double* d_f, double* d_u, dou
  * skipped). Each problem is computed with the block decomposition of its
  * own tpmg_solve, so its iterates and iteration count equal those of a
  * single solve. The problems must share one non-default stream, the
- * precision and the smoother parameters, have at least two levels and use
- * the scan smoother on every level (the default for nz <= 256). The batch workspace (device, 256-byte aligned) holds the
+ * precision and the smoother parameters (block-Jacobi or multicolour
+ * block-SOR, damping, sweep counts), have at least two levels, factorising
+ * profiles and the scan smoother on every level (the default for nz <=
+ * 256). The batch workspace (device, 256-byte aligned) holds the
  * per-problem scalars and the launch tables; problems must outlive the
  * batch. Errors: TPMG_ERR_ARG, TPMG_ERR_NOMEM. */
 tpmg_status tpmg_batch_workspace_size(tpmg_mg* const* problems, int n, size_t* bytes);

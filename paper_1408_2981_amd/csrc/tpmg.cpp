@@ -940,7 +940,7 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
     if (reduces) {
       F.nseg = static_cast<int>(fin.size());
       F.grid = static_cast<unsigned>(fin.size());
-      F.block = 256;
+      F.block = tpmg::kFinThreads;
       seg_offset.push_back(host.size());
       host.insert(host.end(), fin.begin(), fin.end());
       plan.push_back(F);
@@ -967,12 +967,11 @@ tpmg_status check_batch(tpmg_mg* const* problems, int n) {
     if (!m) return fail(TPMG_ERR_ARG, "NULL problem");
     if (m->nlev < 2) return fail(TPMG_ERR_ARG, "batched problems need at least 2 multigrid levels");
     if (m->full_outer) return fail(TPMG_ERR_ARG, "batched problems need factorising profiles");
-    if (m->sor) return fail(TPMG_ERR_ARG, "batched problems need the block-Jacobi smoother");
     for (const tpmg::LevelTune& t : m->tune)
       if (t.smoother != tpmg::kSmScan)
         return fail(TPMG_ERR_ARG, "batched problems need the scan smoother on every level (params.smoother = 1)");
     if (m->fp32 != a->fp32 || m->nu_pre != a->nu_pre || m->nu_post != a->nu_post || m->nu_coarse != a->nu_coarse ||
-        m->omega != a->omega)
+        m->omega != a->omega || m->sor != a->sor)
       return fail(TPMG_ERR_ARG, "batched problems must share precision and smoother parameters");
     if (m->stream != a->stream || m->stream == nullptr)
       return fail(TPMG_ERR_ARG, "batched problems must share one non-default stream");

@@ -168,3 +168,54 @@ def test_batch16_at_its_own_shape():
     T.tpmg_batch_destroy(batch)
     for P in probs:
         P.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_batch_with_block_sor(fp32):
+    """Batched solves with the multicolour block-SOR smoother (colour passes
+    of problems at the same schedule position grouped; refinement 1, whose
+    grid takes four colours, has a pass the others lack): bitwise equal to
+    the single SOR solves, and in FP64 the oracle's SOR solve (identical
+    iteration counts, 1e-10)."""
+    stream = torch.cuda.Stream()
+    probs = []
+    for ref, nz, grading, seed in PROBS[:4]:
+        r = synth.vertical_faces(nz, synth.H10KM, grading)
+        om2 = synth.omega_for(ref) ** 2
+        prof = synth.profiles_random(nz, synth.n_cells(ref), seed=seed + 100)
+        P = T.Problem(ref, r, om2, profiles=prof).setup(precond_fp32=fp32, use_graph=True, stream=stream,
+                                                        smoother_order=T.SMOOTHER_ORDER_SOR, omega_relax=1.0)
+        geo = P.geometry()
+        f = synth.cell_integral(synth.uniform_noise(P.n, nz, seed), geo["areas"], P.vk())
+        probs.append((P, f, (ref, r, om2, prof)))
+    fs = [P.pack(f) for P, f, _ in probs]
+    singles = []
+    for (P, f, _), fd in zip(probs, fs):
+        u = P.device_vector()
+        st, iters, relres, hist, _ = P.solve(fd, u, rtol=1e-8, maxit=200)
+        assert st == T.TPMG_OK
+        singles.append((iters, relres, hist, P.unpack(u)))
+    mgs = [P.mg for P, _, _ in probs]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, ws.data_ptr() + (-ws.data_ptr()) % 256, nbytes)
+    us = [P.device_vector() for P, _, _ in probs]
+    st, per, _ = T.tpmg_batch_solve(batch, fs, us, 1e-8, 200)
+    assert st == T.TPMG_OK
+    for (P, f, (ref, r, om2, prof)), u, (iters, relres, hist), (it_s, rr_s, hist_s, u_s) in zip(probs, us, per, singles):
+        assert iters == it_s and relres == rr_s
+        assert np.array_equal(P.unpack(u), u_s)
+        if not fp32:
+            h = otpmg.build(ref, r, om2, profiles=prof).with_sor(1.0)
+            o = otpmg.solve(h, f, rtol=1e-8)
+            assert o.iters == it_s
+            assert np.linalg.norm(u_s - o.x) <= 1e-10 * np.linalg.norm(o.x)
+    T.tpmg_batch_destroy(batch)
+    # problems that disagree on the smoother are refused
+    P0 = probs[0][0]
+    Pj = T.Problem(PROBS[0][0], synth.vertical_faces(PROBS[0][1], synth.H10KM, PROBS[0][2]),
+                   synth.omega_for(PROBS[0][0]) ** 2).setup(precond_fp32=fp32, stream=stream, omega_relax=1.0)
+    with pytest.raises(T.TpmgError) as e:
+        T.tpmg_batch_workspace_size([P0.mg, Pj.mg])
+    assert e.value.status == T.TPMG_ERR_ARG
