@@ -764,18 +764,31 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   const int nz = L.nz;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // waves that own levels; a batched launch may give the block more (idle) waves
+  // waves that own levels of one tile. A batched launch sizes its blocks for
+  // the deepest problem of the group: a block of a shallower problem then
+  // holds several tiles, one per nw waves (tpb of them; waves beyond those
+  // idle), except in the sweep that forms the dot products, whose partial
+  // sums are one per tile as in the single launches.
   const int nw = (nz + KB - 1) / KB;
+  const int tpb = DOTS ? 1 : max(1, static_cast<int>(blockDim.x >> 6) / nw);
+  const int slot = wave / nw;         // the wave's tile in the block
+  const int wt = wave - slot * nw;    // the wave's place in its tile
   // summaries: pivot map (4), elimination map (2), substitution map (2)
   T* __restrict__ sm = reinterpret_cast<T*>(smem);
   auto at = [&](int w, int q) -> T& { return sm[(static_cast<size_t>(w) * 8 + q) * kTile + lane]; };
   // after the summaries of all the block's waves: the exchange slices
   Exchange<T> xc{sm + static_cast<size_t>(blockDim.x >> 6) * 8 * kTile + static_cast<size_t>(wave) * 2 * kTile};
-  const int tile = xcd_tile(g.b, g.nb);
+  const int ntiles = L.npad / kTile;
+  const int tile_w = xcd_tile(g.b, g.nb) * tpb + slot;
+  // a wave without a tile (beyond the block's tpb tiles, or past the last
+  // tile) reads the last tile's column data, owns no level and stores nothing
+  const bool live = slot < tpb && tile_w < ntiles;
+  const int tile = live ? tile_w : ntiles - 1;
   const int col = tile * kTile + lane;
   const int kb = (nz + nw - 1) / nw;
-  const int k0 = min(nz, wave * kb);
+  const int k0 = live ? min(nz, wt * kb) : nz;
   const int nb = min(nz, k0 + kb) - k0;
+  const int w0 = slot * nw;           // the tile's first wave
   const Column<T> c = load_column(L, col);
   const T esum = c.a0 + c.a1 + c.a2;
 
@@ -842,7 +855,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   T la[KB], mc[KB];
   {
     T s_prev = T(0), ip_prev = T(0);
-    if (wave > 0) {
+    if (wt > 0) {
       s_prev = s_in;
       // the pivot of the level below the block, s_{k0-1} + m_{k0-1}
       ip_prev = rcp_of(s_prev + m_of(-1));
@@ -863,7 +876,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   }
 
   // ---- round 2, elimination d_k = la_k d_{k-1} + r_k: the block's map
-  // d_last = A d_in + B; wave 0 runs it up the column
+  // d_last = A d_in + B; the tile's first wave runs it up the column
   {
     T A = T(1), B = T(0);
 #pragma unroll
@@ -873,15 +886,15 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
         B = la[i] * B + r[i];
       }
     }
-    // (each wave overwrites only its own slots, which wave 0 filled before the
-    // last barrier and this wave has read)
+    // (each wave overwrites only its own slots, which the tile's first wave
+    // filled before the last barrier and this wave has read)
     at(wave, 0) = A;
     at(wave, 1) = B;
   }
   __syncthreads();
-  if (wave == 0) {
+  if (wt == 0 && slot < tpb) {
     T d = T(0);
-    for (int j = 0; j < nw; ++j) {
+    for (int j = w0; j < w0 + nw; ++j) {
       const T aj = at(j, 0), bj = at(j, 1);
       at(j, 2) = d;
       d = aj * d + bj;
@@ -900,7 +913,8 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   }
 
   // ---- round 3, back substitution x_k = mc_k x_{k+1} + d_k: the block's map
-  // x_first = C x_in + D from the block's own d; wave 0 runs it down the column
+  // x_first = C x_in + D from the block's own d; the tile's first wave runs it
+  // down the column
   {
     T C = T(1), D = T(0);
 #pragma unroll
@@ -914,9 +928,9 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
     at(wave, 4) = D;
   }
   __syncthreads();
-  if (wave == 0) {
+  if (wt == 0 && slot < tpb) {
     T x = T(0);
-    for (int j = nw - 1; j >= 0; --j) {
+    for (int j = w0 + nw - 1; j >= w0; --j) {
       const T cj = at(j, 3), dj = at(j, 4);
       at(j, 5) = x;
       x = cj * x + dj;

@@ -873,6 +873,11 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
     const size_t first = host.size();
     std::vector<tpmg::Seg> fin;
     unsigned start = 0;
+    // a grouped sweep's blocks hold the waves of the deepest problem's tile
+    if (o.kind == tpmg::kOpSmooth)
+      for (size_t k = i; k < j; ++k)
+        L.block = std::max(L.block,
+                           static_cast<unsigned>(64 * tpmg::scan_waves(items[k].op.L.nz, items[k].op.L.tune.scan_levels)));
     for (size_t k = i; k < j; ++k) {
       const Op& a = items[k].op;
       if (a.kind != o.kind || a.prec != o.prec || a.f_double != o.f_double || a.out_double != o.out_double ||
@@ -895,9 +900,12 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
       switch (a.kind) {
         case tpmg::kOpSmooth: {
           if (a.L.tune.smoother != tpmg::kSmScan) return hipErrorInvalidValue;
-          nb = a.L.npad / tpmg::kTile;
+          // tiles per block: as many as the block's waves hold, one in the
+          // sweep that forms the dot products (its partial sums are per tile)
           const int waves = tpmg::scan_waves(a.L.nz, a.L.tune.scan_levels);
-          L.block = std::max(L.block, static_cast<unsigned>(64 * waves));
+          const int tpb = a.dots ? 1 : std::max(1, static_cast<int>(L.block / 64) / waves);
+          const int ntiles = a.L.npad / tpmg::kTile;
+          nb = (ntiles + tpb - 1) / tpb;
           break;
         }
         case tpmg::kOpRestrict:
