@@ -788,6 +788,13 @@ hipError_t fcg_iteration(tpmg_mg& m, double* x) {
 
 }  // namespace
 
+// Branches of a batched iteration's graph: groups of problems whose grouped
+// launches form chains of their own, forked from the batch's stream and
+// joined before the scalars are copied, so that one group's latency-bound
+// coarse levels run beside another's bandwidth-bound fine ones. (Four: the
+// hardware queues a process gets by default.)
+constexpr int kBatchBranches = 4;
+
 struct tpmg_batch {
   std::vector<tpmg_mg*> probs;
   hipStream_t stream = nullptr;
@@ -796,17 +803,15 @@ struct tpmg_batch {
   hipEvent_t ev[2] = {nullptr, nullptr};   // each iteration's copy of the scalars has arrived
   tpmg::Seg* segs = nullptr;            // device segment tables
   size_t max_segs = 0;
-  std::vector<tpmg::BatchLaunch> plan;
+  std::vector<std::vector<tpmg::BatchLaunch>> plans;   // one launch chain per branch
+  hipStream_t aux[kBatchBranches - 1] = {};            // capture streams of branches 1, 2, ...
+  hipEvent_t fork = nullptr, join[kBatchBranches - 1] = {};
   std::vector<double*> plan_u;          // solution vectors the plan was built for
   hipGraphExec_t graph = nullptr;
 };
 
 namespace {
 
-// Groups the FCG-iteration operations of all problems by schedule position:
-// one grouped launch per position, followed by a grouped finalize where the
-// operation reduces. Returns the number of segments; with upload == false it
-// only counts them.
 // whether every problem of the batch has the fused operator instance
 bool batch_ring(const tpmg_batch& b) {
   for (const tpmg_mg* m : b.probs)
@@ -814,19 +819,46 @@ bool batch_ring(const tpmg_batch& b) {
   return true;
 }
 
-hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* nsegs_out) {
+// The problems of each branch: longest vectors first, each to the branch with
+// the least work so far (ties to the lower index), as many branches as
+// problems up to kBatchBranches.
+std::vector<std::vector<int>> batch_groups(const tpmg_batch& b) {
+  const int n = static_cast<int>(b.probs.size());
+  const int ng = std::min(n, kBatchBranches);
+  std::vector<int> order(n);
+  for (int p = 0; p < n; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b.probs[x]->len > b.probs[y]->len; });
+  std::vector<std::vector<int>> groups(ng);
+  std::vector<size_t> load(ng, 0);
+  for (int p : order) {
+    int g = 0;
+    for (int k = 1; k < ng; ++k)
+      if (load[k] < load[g]) g = k;
+    groups[g].push_back(p);
+    load[g] += b.probs[p]->len;
+  }
+  for (auto& gr : groups) std::sort(gr.begin(), gr.end());
+  return groups;
+}
+
+// Groups the FCG-iteration operations of a branch's problems by schedule
+// position: one grouped launch per position, followed by a grouped finalize
+// where the operation reduces. Appends the segments to host and the launches
+// (with the offsets of their segments) to plan.
+hipError_t plan_branch(tpmg_batch& b, const std::vector<int>& group, double* const* d_u, std::vector<tpmg::Seg>& host,
+                       std::vector<tpmg::BatchLaunch>& plan, std::vector<size_t>& seg_offset) {
   struct Item {
     Op op;
     int prob;
   };
   std::vector<Item> items;
   const bool ring = batch_ring(b);
-  for (size_t p = 0; p < b.probs.size(); ++p) {
+  for (int p : group) {
     std::vector<Op> ops;
     // (with the direction ring, as single solves; otherwise x and p are
     // updated in place in every iteration, with the same bits)
     fcg_ops(*b.probs[p], d_u ? d_u[p] : nullptr, b.scal ? b.scal + p : nullptr, ops, false, ring);
-    for (const Op& op : ops) items.push_back({op, static_cast<int>(p)});
+    for (const Op& op : ops) items.push_back({op, p});
   }
   // smoother sweeps of one position are grouped by levels per wave (one
   // kernel instance per launch)
@@ -847,9 +879,6 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
   };
   std::stable_sort(items.begin(), items.end(),
                    [&](const Item& a, const Item& c) { return group_less(a.op, c.op); });
-  std::vector<tpmg::Seg> host;
-  std::vector<tpmg::BatchLaunch> plan;
-  std::vector<size_t> seg_offset;   // first segment of each launch
   size_t i = 0;
   while (i < items.size()) {
     size_t j = i;
@@ -955,15 +984,31 @@ hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* ns
     }
     i = j;
   }
+  return hipSuccess;
+}
+
+// The launch chains of all branches over one segment table. Returns the
+// number of segments; with upload == false it only counts them.
+hipError_t build_plan(tpmg_batch& b, double* const* d_u, bool upload, size_t* nsegs_out) {
+  std::vector<tpmg::Seg> host;
+  std::vector<std::vector<tpmg::BatchLaunch>> plans;
+  std::vector<std::vector<size_t>> offsets;   // first segment of each launch
+  for (const std::vector<int>& group : batch_groups(b)) {
+    plans.emplace_back();
+    offsets.emplace_back();
+    hipError_t e = plan_branch(b, group, d_u, host, plans.back(), offsets.back());
+    if (e != hipSuccess) return e;
+  }
   if (nsegs_out) *nsegs_out = host.size();
   if (!upload) return hipSuccess;
   if (host.size() > b.max_segs) return hipErrorInvalidValue;
-  for (size_t k = 0; k < plan.size(); ++k) plan[k].segs = b.segs + seg_offset[k];
+  for (size_t g = 0; g < plans.size(); ++g)
+    for (size_t k = 0; k < plans[g].size(); ++k) plans[g][k].segs = b.segs + offsets[g][k];
   hipError_t e = hipMemcpyAsync(b.segs, host.data(), host.size() * sizeof(tpmg::Seg), hipMemcpyHostToDevice, b.stream);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(b.stream);
   if (e != hipSuccess) return e;
-  b.plan = std::move(plan);
+  b.plans = std::move(plans);
   return hipSuccess;
 }
 
@@ -2366,6 +2411,13 @@ tpmg_status tpmg_batch_create(tpmg_mg* const* problems, int n, void* d_workspace
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_scal), 3 * static_cast<size_t>(n) * sizeof(tpmg::FcgScalars),
                                hipHostMallocDefault);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+  // (the streams that capture the graph's branches; default priority)
+  const int nbr = std::min(n, kBatchBranches);
+  if (e == hipSuccess && nbr > 1) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int k = 0; k + 1 < nbr && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     tpmg_batch_destroy(b);
     return fail(TPMG_ERR_DEVICE, std::string("batch host buffers: ") + hipGetErrorString(e));
@@ -2406,9 +2458,24 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
     if (e != hipSuccess) return fail(TPMG_ERR_DEVICE, std::string("batch plan: ") + hipGetErrorString(e));
     hipGraph_t g = nullptr;
     TPMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = hipSuccess;
-    for (const tpmg::BatchLaunch& L : b->plan)
-      if ((ce = tpmg::launch_batched(L, s)) != hipSuccess) break;
+    // branch 0 on the batch's stream, the others forked from it and joined
+    // back (every branch is joined, also after a failed launch, so that the
+    // capture ends)
+    const int nbr = static_cast<int>(b->plans.size());
+    hipError_t ce = nbr > 1 ? hipEventRecord(b->fork, s) : hipSuccess;
+    int forked = 1;
+    for (; forked < nbr && ce == hipSuccess; ++forked) ce = hipStreamWaitEvent(b->aux[forked - 1], b->fork, 0);
+    if (ce != hipSuccess) --forked;
+    for (int k = 0; k < nbr && ce == hipSuccess; ++k) {
+      hipStream_t sk = k == 0 ? s : b->aux[k - 1];
+      for (const tpmg::BatchLaunch& L : b->plans[k])
+        if ((ce = tpmg::launch_batched(L, sk)) != hipSuccess) break;
+    }
+    for (int k = 1; k < forked; ++k) {
+      hipError_t je = hipEventRecord(b->join[k - 1], b->aux[k - 1]);
+      if (je == hipSuccess) je = hipStreamWaitEvent(s, b->join[k - 1], 0);
+      if (ce == hipSuccess) ce = je;
+    }
     hipError_t ee = hipStreamEndCapture(s, &g);
     if (ce != hipSuccess || ee != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
@@ -2511,6 +2578,11 @@ void tpmg_batch_destroy(tpmg_batch* b) {
   if (b->h_scal) (void)hipHostFree(b->h_scal);
   for (hipEvent_t ev : b->ev)
     if (ev) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (int k = 0; k + 1 < kBatchBranches; ++k) {
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    if (b->aux[k]) (void)hipStreamDestroy(b->aux[k]);
+  }
   delete b;
 }
 
