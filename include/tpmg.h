@@ -340,15 +340,20 @@ tpmg_status tpmg_solve_bicgstab(tpmg_mg* mg, const double* d_f, double* d_u, dou
 
 /* ----------------------------------------------------------- batched -- */
 
-/* Several independent solves of uneven size advanced together: every step
- * of the FCG iteration (each smoother sweep, transfer and BLAS-1 operation
- * of the V-cycle of Algorithm 1, taken level by level from the finest grid
- * down) is one grouped launch over all problems, the whole iteration is
- * replayed as one HIP graph, and each problem stops when its own relative
- * residual meets rtol (tested on the device; a finished problem's work is
- * skipped). Each problem is computed with the block decomposition of its
- * own tpmg_solve, so its iterates and iteration count equal those of a
- * single solve. The problems must share one non-default stream, the
+/* Several independent solves of uneven size advanced together. The problems
+ * fall into up to four groups (longest vectors first, each to the group
+ * with the least work so far); in each group every step of the FCG
+ * iteration (each smoother sweep, transfer and BLAS-1 operation of the
+ * V-cycle of Algorithm 1, taken level by level from the finest grid down)
+ * is one grouped launch over the group's problems. The whole iteration is
+ * replayed as one HIP graph whose branches, one per group, run
+ * concurrently, and each problem stops when its own relative residual
+ * meets rtol (tested on the device; a finished problem's work is skipped).
+ * Each problem is computed with the block decomposition of its own
+ * tpmg_solve, so its iterates and iteration count equal those of a single
+ * solve. tpmg_batch_create creates the streams and events that capture the
+ * branches (up to three of each, default priority; released by
+ * tpmg_batch_destroy). The problems must share one non-default stream, the
  * precision and the smoother parameters (block-Jacobi or multicolour
  * block-SOR, damping, sweep counts), have at least two levels, factorising
  * profiles and the scan smoother on every level (the default for nz <=
