@@ -755,7 +755,8 @@ __device__ __forceinline__ T rcp_of(T v) {
   return fast_rcp(v);
 }
 
-template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS, int PM = 0>
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS, int PM = 0,
+          bool PACK = false>
 __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __restrict__ f, const T* __restrict__ u_in,
                                                  TO* __restrict__ u_out, T* __restrict__ fcopy, T omega,
                                                  const double* __restrict__ q, double* __restrict__ partials,
@@ -765,14 +766,14 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // waves that own levels of one tile. A batched launch sizes its blocks for
-  // the deepest problem of the group: a block of a shallower problem then
-  // holds several tiles, one per nw waves (tpb of them; waves beyond those
-  // idle), except in the sweep that forms the dot products, whose partial
-  // sums are one per tile as in the single launches.
+  // the deepest problem of the group (waves beyond a tile's own idle). With
+  // PACK (batched sweeps without the dot products, whose partial sums are
+  // one per tile as in the single launches) such a block holds several
+  // tiles, one per nw waves (tpb of them; waves beyond those idle).
   const int nw = (nz + KB - 1) / KB;
-  const int tpb = DOTS ? 1 : max(1, static_cast<int>(blockDim.x >> 6) / nw);
-  const int slot = wave / nw;         // the wave's tile in the block
-  const int wt = wave - slot * nw;    // the wave's place in its tile
+  const int tpb = PACK ? max(1, static_cast<int>(blockDim.x >> 6) / nw) : 1;
+  const int slot = PACK ? wave / nw : 0;   // the wave's tile in the block
+  const int wt = wave - slot * nw;         // the wave's place in its tile
   // summaries: pivot map (4), elimination map (2), substitution map (2)
   T* __restrict__ sm = reinterpret_cast<T*>(smem);
   auto at = [&](int w, int q) -> T& { return sm[(static_cast<size_t>(w) * 8 + q) * kTile + lane]; };
@@ -782,7 +783,7 @@ __device__ __forceinline__ void smooth_scan_body(const Lv<T>& L, const TF* __res
   const int tile_w = xcd_tile(g.b, g.nb) * tpb + slot;
   // a wave without a tile (beyond the block's tpb tiles, or past the last
   // tile) reads the last tile's column data, owns no level and stores nothing
-  const bool live = slot < tpb && tile_w < ntiles;
+  const bool live = !PACK || (slot < tpb && tile_w < ntiles);
   const int tile = live ? tile_w : ntiles - 1;
   const int col = tile * kTile + lane;
   const int kb = (nz + nw - 1) / nw;
@@ -1443,10 +1444,9 @@ __global__ __launch_bounds__((scan_max_threads<KB, T>()),
   GridPos g;
   CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS>(view<T>(sg->L), static_cast<const TF*>(sg->in0),
-                                                     static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
-                                                     static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q,
-                                                     sg->partials, g);
+  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS, 0, !DOTS>(
+      view<T>(sg->L), static_cast<const TF*>(sg->in0), static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
+      static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q, sg->partials, g);
 }
 
 // (CH > 0: every segment's chunk is CH, the instance the single launches
