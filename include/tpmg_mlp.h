@@ -103,6 +103,19 @@ tpmg_status tpmg_mlp_gradients(tpmg_mlp* m, const float* d_x, const float* d_y, 
 tpmg_status tpmg_mlp_train_step(tpmg_mlp* m, const float* d_x, const float* d_y, size_t rows_total,
                                 const int32_t* d_rows, int batch, float lr, float* loss);
 
+/* steps Adam steps in one call, step k on the batch d_perm[k * batch ..
+ * (k + 1) * batch - 1] (device int32 row indices, steps * batch of them):
+ * the same launches, in the same order, as steps calls of
+ * tpmg_mlp_train_step, so the parameters end bit for bit the same, without
+ * a return to the caller between steps. With loss_every > 0, losses (host,
+ * at least (steps - 1) / loss_every + 2 floats) receives the batch loss
+ * before the step of every step k with k % loss_every == 0 and of the last
+ * step, in order; loss_every = 0 samples none (losses may be NULL).
+ * Synchronises the stream at the end; an out-of-range row index is reported
+ * then (TPMG_ERR_ARG). */
+tpmg_status tpmg_mlp_train_epoch(tpmg_mlp* m, const float* d_x, const float* d_y, size_t rows_total,
+                                 const int32_t* d_perm, int steps, int batch, float lr, int loss_every, float* losses);
+
 /* Initial guess for mg's solve with right-hand side d_f: features,
  * standardisation, forward pass and de-standardisation (u_hat). relax = 0:
  * u_hat is written into the real columns of d_u0 (tiled FP64; padding

@@ -45,7 +45,7 @@ EXPORTED = [
     "tpmg_tune_save", "tpmg_tune_clear", "tpmg_tune_entries", "tpmg_grid_destroy", "tpmg_op_destroy",
     "tpmg_mlp_param_count", "tpmg_mlp_workspace_size", "tpmg_mlp_create", "tpmg_mlp_set_params", "tpmg_mlp_get_params",
     "tpmg_mlp_set_scaling", "tpmg_mlp_get_scaling", "tpmg_mlp_fit_scaling", "tpmg_mlp_features", "tpmg_mlp_targets",
-    "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_infer", "tpmg_mlp_features_increment",
+    "tpmg_mlp_forward", "tpmg_mlp_gradients", "tpmg_mlp_train_step", "tpmg_mlp_train_epoch", "tpmg_mlp_infer", "tpmg_mlp_features_increment",
     "tpmg_mlp_targets_increment", "tpmg_mlp_infer_increment", "tpmg_mlp_save",
     "tpmg_mlp_load", "tpmg_mlp_destroy",
     "tpmg_mg_destroy", "tpmg_status_string", "tpmg_last_error", "tpmg_solve_noalloc", "tpmg_solve_richardson",
@@ -144,6 +144,7 @@ _sig = {
     "tpmg_mlp_forward": (_ip, [_vp, _vp, _ip, _vp]),
     "tpmg_mlp_gradients": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, _fp, _fp]),
     "tpmg_mlp_train_step": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, ctypes.c_float, _fp]),
+    "tpmg_mlp_train_epoch": (_ip, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _ip, _ip, ctypes.c_float, _ip, _fp]),
     "tpmg_mlp_infer": (_ip, [_vp, _vp, _vp, _ip, _vp]),
     "tpmg_mlp_features_increment": (_ip, [_vp, _vp, _vp, _vp, _vp]),
     "tpmg_mlp_targets_increment": (_ip, [_vp, _vp, _vp, _vp, _vp]),
@@ -615,6 +616,17 @@ def tpmg_mlp_train_step(m: int, d_x, d_y, rows_total: int, d_rows, batch: int, l
     _check(_lib.tpmg_mlp_train_step(m, _dev(d_x), _dev(d_y), rows_total, _dev(d_rows), batch, lr,
                                     ctypes.byref(loss) if want_loss else None))
     return loss.value if want_loss else None
+
+
+def tpmg_mlp_train_epoch(m: int, d_x, d_y, rows_total: int, d_perm, steps: int, batch: int, lr: float,
+                         loss_every: int = 0) -> np.ndarray:
+    n = (steps - 1) // loss_every + 2 if loss_every > 0 else 0
+    losses = np.zeros(max(n, 1), dtype=np.float32)
+    ptr = losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if loss_every > 0 else None
+    _check(_lib.tpmg_mlp_train_epoch(m, _dev(d_x), _dev(d_y), rows_total, _dev(d_perm), steps, batch, lr, loss_every,
+                                     ptr))
+    k = len(range(0, steps, loss_every)) + (1 if (steps - 1) % loss_every else 0) if loss_every > 0 else 0
+    return losses[:k]
 
 
 def tpmg_mlp_infer(m: int, mg: int, d_f, d_u0, relax: int = 1) -> None:

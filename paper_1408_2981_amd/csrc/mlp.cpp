@@ -40,7 +40,7 @@ struct Carve {
   }
 };
 
-constexpr int kSplitMax = 128;   // K slices of the weight-gradient products
+constexpr int kSplitMax = 64;   // K slices of the weight-gradient products
 constexpr uint32_t kFileMagic = 0x504c4d54u;   // file tag of saved networks
 
 size_t param_count(int nz, int h) {
@@ -73,8 +73,7 @@ struct tpmg_mlp {
   bf16 *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *dh2 = nullptr, *dh1 = nullptr;
   float *y = nullptr, *yt = nullptr;
   // reductions
-  float* gpart = nullptr;     // kSplitMax x largest weight matrix
-  float* cpart = nullptr;     // column-sum chunks x hidden
+  float* gpart = nullptr;     // kSplitMax x (largest weight matrix + its bias)
   double* lpart = nullptr;    // loss partials
   float* loss = nullptr;
   double* mpart = nullptr;    // moment partials
@@ -120,10 +119,9 @@ void carve(tpmg_mlp& m, Carve& c) {
   m.dh1 = c.take<bf16>(R * m.h);
   m.y = c.take<float>(R * m.nz);
   m.yt = c.take<float>(R * m.nz);
-  const size_t wmax = std::max({static_cast<size_t>(m.h) * m.nin, static_cast<size_t>(m.h) * m.h,
-                                static_cast<size_t>(m.nz) * m.h});
+  const size_t wmax = std::max({static_cast<size_t>(m.h) * (m.nin + 1), static_cast<size_t>(m.h) * (m.h + 1),
+                                static_cast<size_t>(m.nz) * (m.h + 1)});
   m.gpart = c.take<float>(kSplitMax * wmax);
-  m.cpart = c.take<float>(static_cast<size_t>(tpmg::colsum_chunks(m.max_rows)) * std::max(m.h, m.nz));
   m.lpart = c.take<double>(1024);
   m.loss = c.take<float>(1);
   m.mpart = c.take<double>(static_cast<size_t>(tpmg::kMomentChunksMax) * m.nin);
@@ -165,6 +163,12 @@ hipError_t upload_scaling(tpmg_mlp& m) {
 
 hipError_t refresh(tpmg_mlp& m) {
   return tpmg::launch_refresh_weights(m.params, m.nin, m.h, m.nz, m.kp, m.w1b, m.w2b, m.w3b, m.w2t, m.w3t, m.stream);
+}
+
+// one Adam step on m.grads, with the bf16 weight copies refreshed in it
+hipError_t adam_step(tpmg_mlp& m, float lr) {
+  return tpmg::launch_adam_copies(m.params, m.grads, m.am, m.av, m.np, lr, m.adam_t, m.nin, m.h, m.nz, m.kp, m.w1b,
+                                  m.w2b, m.w3b, m.w2t, m.w3t, m.stream);
 }
 
 // forward pass over n prepared rows (m.xb): h1, h2, then the third product
@@ -214,6 +218,11 @@ hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out) {
 
 // weight gradient dW [M][N] = sum over the batch of a(b, m) c(b, n), a and c
 // row-major [batch][lda] and [batch][ldc], written to grads + off
+// gradient of a layer's weights W [M][N] and bias b [M], which follows W in
+// the packed parameters: the product a^T c over the batch (a: the layer's
+// output gradients [batch][M], c: its inputs [batch][N]) in K slices with
+// the row sums of a (the bias gradient) beside each slice's partial, then
+// one sum over the slices
 hipError_t weight_grad(tpmg_mlp& m, const bf16* a, int lda, int M, const bf16* c, int ldc, int N, int batch,
                        size_t off) {
   // slices of the batch: about 256 workgroups in all, at least 32 rows each
@@ -233,16 +242,11 @@ hipError_t weight_grad(tpmg_mlp& m, const bf16* a, int lda, int M, const bf16* c
   g.K = batch;
   g.ksplit = ksplit;
   g.epi = tpmg::kEpiPartialF32;
+  g.row_sums = true;
   g.out_f32 = m.gpart;
   hipError_t e = tpmg::launch_gemm(g, m.stream);
   if (e != hipSuccess) return e;
-  return tpmg::launch_sum_parts(m.gpart, nsplit, static_cast<size_t>(M) * N, m.grads + off, m.stream);
-}
-
-hipError_t bias_grad(tpmg_mlp& m, const bf16* a, int rows, int cols, size_t off) {
-  hipError_t e = tpmg::launch_colsum_partial(a, rows, cols, m.cpart, m.stream);
-  if (e != hipSuccess) return e;
-  return tpmg::launch_sum_parts(m.cpart, tpmg::colsum_chunks(rows), cols, m.grads + off, m.stream);
+  return tpmg::launch_sum_parts(m.gpart, nsplit, static_cast<size_t>(M) * N + M, m.grads + off, m.stream);
 }
 
 // loss and gradients of the batch into m.grads and m.loss
@@ -254,7 +258,6 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
   if (e != hipSuccess) return e;
   // output layer
   e = weight_grad(m, m.dy, m.nz, m.nz, m.h2, m.h, m.h, batch, m.oW3());
-  if (e == hipSuccess) e = bias_grad(m, m.dy, batch, m.nz, m.ob3());
   // dh2 = (dy W3) * [h2 > 0]
   tpmg::GemmArgs g;
   g.A = m.dy;
@@ -270,7 +273,6 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
   g.ldc = m.h;
   if (e == hipSuccess) e = tpmg::launch_gemm(g, m.stream);
   if (e == hipSuccess) e = weight_grad(m, m.dh2, m.h, m.h, m.h1, m.h, m.h, batch, m.oW2());
-  if (e == hipSuccess) e = bias_grad(m, m.dh2, batch, m.h, m.ob2());
   // dh1 = (dh2 W2) * [h1 > 0]
   g.A = m.dh2;
   g.lda = m.h;
@@ -281,7 +283,6 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
   g.out_bf16 = m.dh1;
   if (e == hipSuccess) e = tpmg::launch_gemm(g, m.stream);
   if (e == hipSuccess) e = weight_grad(m, m.dh1, m.h, m.h, m.xb, m.kp, m.nin, batch, m.oW1());
-  if (e == hipSuccess) e = bias_grad(m, m.dh1, batch, m.h, m.ob1());
   return e;
 }
 
@@ -519,14 +520,33 @@ tpmg_status tpmg_mlp_train_step(tpmg_mlp* m, const float* d_x, const float* d_y,
   if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(TPMG_ERR_ARG, "lr must be finite and > 0");
   MLP_HIP(backprop(*m, d_x, d_y, rows_total, d_rows, batch));
   m->adam_t += 1;
-  MLP_HIP(tpmg::launch_adam(m->params, m->grads, m->am, m->av, m->np, lr, m->adam_t, m->stream));
-  MLP_HIP(refresh(*m));
+  MLP_HIP(adam_step(*m, lr));
   if (loss) {
     MLP_HIP(hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
     MLP_HIP(hipStreamSynchronize(m->stream));
     return check_bad_row(*m);
   }
   return TPMG_OK;
+}
+
+tpmg_status tpmg_mlp_train_epoch(tpmg_mlp* m, const float* d_x, const float* d_y, size_t rows_total,
+                                 const int32_t* d_perm, int steps, int batch, float lr, int loss_every, float* losses) {
+  tpmg_status st = check(m);
+  if (st != TPMG_OK) return st;
+  if (steps < 1) return fail(TPMG_ERR_ARG, "steps must be >= 1");
+  if ((st = check_batch_args(m, d_x, d_y, rows_total, d_perm, batch)) != TPMG_OK) return st;
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(TPMG_ERR_ARG, "lr must be finite and > 0");
+  if (loss_every < 0 || (loss_every > 0 && !losses)) return fail(TPMG_ERR_ARG, "loss_every > 0 needs losses");
+  int sampled = 0;
+  for (int k = 0; k < steps; ++k) {
+    MLP_HIP(backprop(*m, d_x, d_y, rows_total, d_perm + static_cast<size_t>(k) * batch, batch));
+    if (loss_every > 0 && (k % loss_every == 0 || k == steps - 1))
+      MLP_HIP(hipMemcpyAsync(losses + sampled++, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    m->adam_t += 1;
+    MLP_HIP(adam_step(*m, lr));
+  }
+  MLP_HIP(hipStreamSynchronize(m->stream));
+  return check_bad_row(*m);
 }
 
 tpmg_status tpmg_mlp_infer(tpmg_mlp* m, const tpmg_mg* mg, const double* d_f, int relax, double* d_u0) {

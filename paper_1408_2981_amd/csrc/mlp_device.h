@@ -36,6 +36,11 @@ struct GemmArgs {
   int lda = 0, ldb = 0;
   int M = 0, N = 0, K = 0;
   int ksplit = 0;            // kEpiPartialF32: k values per slice (multiple of 32); else K
+  // kEpiPartialF32 with transposed operands: also the sums over k of each row
+  // of A (a layer's bias gradient beside its weight gradient); the partials
+  // of slice z are then out_f32[z (M N + M) + m N + n] and, for the row sums,
+  // out_f32[z (M N + M) + M N + m]
+  bool row_sums = false;
   bool ta = false, tb = false;
   int epi = kEpiBiasF32;
   const float* bias = nullptr;
@@ -102,14 +107,15 @@ hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* 
                           float* loss, hipStream_t s);
 int mlp_mse_blocks(int n, int nz);
 
-// out_part[c][j] = sum of a[r][j] over the c-th chunk of 64 rows (FP32).
-hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_part, hipStream_t s);
-int colsum_chunks(int rows);
 // out[i] = sum_p part[p * len + i] (fixed order), FP32.
 hipError_t launch_sum_parts(const float* part, int nparts, size_t len, float* out, hipStream_t s);
 
-// Adam over n parameters (moments m, v; step t >= 1), FP32.
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s);
+// Adam (t: the step count from 1) on the n packed parameters, also writing
+// the bf16 copies of the weights the products read (as
+// launch_refresh_weights, whose zero padding of w1b it keeps)
+hipError_t launch_adam_copies(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, int n_in,
+                              int hidden, int nz, int kp, bf16* w1b, bf16* w2b, bf16* w3b, bf16* w2t, bf16* w3t,
+                              hipStream_t s);
 
 // bf16 copies of the weights: w1b [hidden][kp] (zero beyond n_in), w2b, w3b,
 // and the transposes w2t [hidden][hidden], w3t [hidden][nz].

@@ -24,26 +24,31 @@ __device__ __forceinline__ size_t tiled_index(int col, int k, int nz) {
 // ---------------------------------------------------------------------------
 // GEMM: one workgroup of 4 waves computes a (64 WM) x (64 WN) tile of C; each
 // wave a 64 x 64 block as 2 x 2 matrix-core products of 32 x 32 x 16 (bf16
-// operands, FP32 accumulators). K advances in steps of 32 through LDS
-// (rows padded by 8 bf16 so the 16-byte operand reads spread over the banks).
+// operands, FP32 accumulators). K advances through LDS in slices of BK
+// (rows padded by 8 bf16 so the 16-byte operand reads spread over the
+// banks); with K-contiguous operands the next slice's loads are in flight
+// while the current one computes. Within a slice the 16-wide K chunks are
+// taken in ascending order, so the accumulation order is that of K itself,
+// whatever BK. Split-K partitions are multiples of kBK.
 // Operand layout of the 32 x 32 x 16 product: lane l supplies row l % 32 of A
 // (column l % 32 of B) at k = 8 (l / 32) .. 8 (l / 32) + 7; accumulator r of
 // lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 // ---------------------------------------------------------------------------
 constexpr int kBK = 32;
-constexpr int kLdsRow = kBK + 8;
+constexpr int kGemmBK = 64;   // K slice of the GEMM kernel
 
-// Stages rows [r0, r0 + ROWS) x k [k0, k0 + 32) of a K-contiguous (T false)
+// Stages rows [r0, r0 + ROWS) x k [k0, k0 + BK) of a K-contiguous (T false)
 // or R-contiguous (T true) operand into LDS as [row][k]; entries outside
 // r < R, k < kend are zero.
-template <int ROWS, bool T>
+template <int ROWS, bool T, int BK>
 __device__ __forceinline__ void stage(const bf16* __restrict__ src, int ld, int r0, int R, int k0, int kend,
-                                      bf16 (*dst)[kLdsRow]) {
-  constexpr int kChunks = ROWS * kBK / 8;   // 16-byte chunks of 8 bf16
+                                      bf16 (*dst)[BK + 8]) {
+  constexpr int kChunks = ROWS * BK / 8;   // 16-byte chunks of 8 bf16
+  constexpr int kPerRow = BK / 8;
 #pragma unroll
   for (int c = threadIdx.x; c < kChunks; c += 256) {
     if (!T) {
-      const int row = c >> 2, kc = (c & 3) * 8;
+      const int row = c / kPerRow, kc = (c % kPerRow) * 8;
       const int r = r0 + row, k = k0 + kc;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (r < R && k < kend) v = *reinterpret_cast<const uint4*>(src + static_cast<size_t>(r) * ld + k);
@@ -65,37 +70,39 @@ __device__ __forceinline__ void stage(const bf16* __restrict__ src, int ld, int 
 }
 
 // The staging of a K-contiguous operand split in two, so that the next
-// step's loads are in flight while the current step computes: fetch takes
-// this thread's 16-byte chunks of rows [0, ROWS) x k [k0, k0 + 32) into
+// slice's loads are in flight while the current slice computes: fetch takes
+// this thread's 16-byte chunks of rows [0, ROWS) x k [k0, k0 + BK) into
 // registers (zero outside r < R, k < kend), put stores them as [row][k].
-template <int ROWS>
+template <int ROWS, int BK>
 struct StageRegs {
-  static constexpr int kPer = (ROWS * kBK / 8 + 255) / 256;
+  static constexpr int kChunks = ROWS * BK / 8;
+  static constexpr int kPerRow = BK / 8;
+  static constexpr int kPer = (kChunks + 255) / 256;
   uint4 v[kPer];
   __device__ __forceinline__ void fetch(const bf16* __restrict__ src, int ld, int R, int k0, int kend) {
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int c = threadIdx.x + 256 * i;
-      const int row = c >> 2, kc = (c & 3) * 8;
+      const int row = c / kPerRow, kc = (c % kPerRow) * 8;
       v[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (c < ROWS * kBK / 8 && row < R && k0 + kc < kend)
+      if (c < kChunks && row < R && k0 + kc < kend)
         v[i] = *reinterpret_cast<const uint4*>(src + static_cast<size_t>(row) * ld + k0 + kc);
     }
   }
-  __device__ __forceinline__ void put(bf16 (*dst)[kLdsRow]) const {
+  __device__ __forceinline__ void put(bf16 (*dst)[BK + 8]) const {
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int c = threadIdx.x + 256 * i;
-      if (c < ROWS * kBK / 8) *reinterpret_cast<uint4*>(&dst[c >> 2][(c & 3) * 8]) = v[i];
+      if (c < kChunks) *reinterpret_cast<uint4*>(&dst[c / kPerRow][(c % kPerRow) * 8]) = v[i];
     }
   }
 };
 
 template <int WM, int WN, bool TR, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  constexpr int BM = 64 * WM, BN = 64 * WN;
-  __shared__ __align__(16) bf16 As[BM][kLdsRow];
-  __shared__ __align__(16) bf16 Bs[BN][kLdsRow];
+  constexpr int BM = 64 * WM, BN = 64 * WN, BK = kGemmBK;
+  __shared__ __align__(16) bf16 As[BM][BK + 8];
+  __shared__ __align__(16) bf16 Bs[BN][BK + 8];
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int kbeg = blockIdx.z * g.ksplit;
   const int kend = min(g.K, kbeg + g.ksplit);
@@ -110,12 +117,55 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
   const int lr = lane & 31, lk = 8 * (lane >> 5);
-  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-    stage<BM, TR>(g.A, g.lda, m0, g.M, k0, kend, As);
-    stage<BN, TR>(g.B, g.ldb, n0, g.N, k0, kend, Bs);
-    __syncthreads();
+  // output element (i, j, r) of this lane
+  auto out_row = [&](int i, int r) { return m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); };
+  auto out_col = [&](int j) { return n0 + wn + 32 * j + lr; };
+  // the ReLU mask of the outputs, loaded before the products so that its
+  // latency hides behind them
+  bf16 mk[2][2][16];
+  if (EPI == kEpiMaskBf16)
 #pragma unroll
-    for (int ks = 0; ks < kBK; ks += 16) {
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = out_row(i, r), n = out_col(j);
+          mk[i][j][r] = (m < g.M && n < g.N) ? g.mask[static_cast<size_t>(m) * g.ldc + n] : static_cast<bf16>(0.0f);
+        }
+  // row sums of A (bias gradient): the first column tile's threads, one row each
+  const bool rsum = EPI == kEpiPartialF32 && g.row_sums && blockIdx.y == 0 && threadIdx.x < BM;
+  float rs = 0.0f;
+  StageRegs<BM, BK> ra;
+  StageRegs<BN, BK> rb;
+  const bf16* a0 = g.A + static_cast<size_t>(m0) * g.lda;
+  const bf16* b0 = g.B + static_cast<size_t>(n0) * g.ldb;
+  if (!TR && kbeg < kend) {
+    ra.fetch(a0, g.lda, g.M - m0, kbeg, kend);
+    rb.fetch(b0, g.ldb, g.N - n0, kbeg, kend);
+  }
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    if (TR) {
+      stage<BM, TR, BK>(g.A, g.lda, m0, g.M, k0, kend, As);
+      stage<BN, TR, BK>(g.B, g.ldb, n0, g.N, k0, kend, Bs);
+    } else {
+      ra.put(As);
+      rb.put(Bs);
+    }
+    __syncthreads();
+    if (!TR && k0 + BK < kend) {
+      ra.fetch(a0, g.lda, g.M - m0, k0 + BK, kend);
+      rb.fetch(b0, g.ldb, g.N - n0, k0 + BK, kend);
+    }
+    if (rsum)
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 8) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(&As[threadIdx.x][kk]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rs += static_cast<float>(v[q]);
+      }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + lr][ks + lk]);
@@ -129,14 +179,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __syncthreads();
   }
 
+  const size_t pstride = static_cast<size_t>(g.M) * g.N + (g.row_sums ? g.M : 0);
+  if (rsum && m0 + static_cast<int>(threadIdx.x) < g.M)
+    g.out_f32[static_cast<size_t>(blockIdx.z) * pstride + static_cast<size_t>(g.M) * g.N + m0 + threadIdx.x] = rs;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int n = n0 + wn + 32 * j + lr;
+        const int m = out_row(i, r), n = out_col(j);
         if (m >= g.M || n >= g.N) continue;
         const float c = acc[i][j][r];
         const size_t o = static_cast<size_t>(m) * g.ldc + n;
@@ -145,9 +197,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         } else if (EPI == kEpiBiasF32) {
           g.out_f32[o] = c + g.bias[n];
         } else if (EPI == kEpiMaskBf16) {
-          g.out_bf16[o] = static_cast<float>(g.mask[o]) > 0.0f ? static_cast<bf16>(c) : static_cast<bf16>(0.0f);
+          g.out_bf16[o] = static_cast<float>(mk[i][j][r]) > 0.0f ? static_cast<bf16>(c) : static_cast<bf16>(0.0f);
         } else if (EPI == kEpiPartialF32) {
-          g.out_f32[static_cast<size_t>(blockIdx.z) * g.M * g.N + static_cast<size_t>(m) * g.N + n] = c;
+          g.out_f32[static_cast<size_t>(blockIdx.z) * pstride + static_cast<size_t>(m) * g.N + n] = c;
         } else {
           g.out_f64[tiled_index(m, n, g.N)] = static_cast<double>((c + g.bias[n]) * g.sd[n] + g.mu[n]);
         }
@@ -509,27 +561,6 @@ __global__ __launch_bounds__(256) void k_mlp_loss(const double* __restrict__ par
   if (threadIdx.x == 0) loss[0] = static_cast<float>(s * inv_total);
 }
 
-// partial column sums of 64 rows per chunk: 64 columns x 4 row groups per block
-__global__ __launch_bounds__(256) void k_colsum_partial(const bf16* __restrict__ a, int rows, int cols, int chunks,
-                                                        float* __restrict__ out) {
-  __shared__ float red[4][64];
-  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + c;
-  for (int chunk = blockIdx.y; chunk < chunks; chunk += gridDim.y) {
-    const int r0 = chunk * 64;
-    float s = 0.0f;
-    if (j < cols)
-      for (int i = 0; i < 16; ++i) {
-        const int r = r0 + grp + 4 * i;
-        if (r < rows) s += static_cast<float>(a[static_cast<size_t>(r) * cols + j]);
-      }
-    red[grp][c] = s;
-    __syncthreads();
-    if (grp == 0 && j < cols) out[static_cast<size_t>(chunk) * cols + j] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-    __syncthreads();
-  }
-}
-
 // out[i] = sum over p of part[p][i]: 64 elements x 4 groups of parts per
 // block, the groups combined in a fixed order
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nparts, size_t len,
@@ -552,9 +583,19 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
 // optimiser and weight copies
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                                              float* __restrict__ v, size_t n, float lr, float bc1, float bc2) {
+// Adam on every parameter, and for the weights the bf16 copies the products
+// read (as k_refresh_weights writes them; the zero padding of the first
+// layer's copy beyond nin is left as k_refresh_weights wrote it)
+__global__ __launch_bounds__(256) void k_adam_copies(float* __restrict__ p, const float* __restrict__ g,
+                                                     float* __restrict__ m, float* __restrict__ v, size_t n, float lr,
+                                                     float bc1, float bc2, int nin, int h, int nz, int kp,
+                                                     bf16* __restrict__ w1b, bf16* __restrict__ w2b,
+                                                     bf16* __restrict__ w3b, bf16* __restrict__ w2t,
+                                                     bf16* __restrict__ w3t) {
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const size_t oW2 = static_cast<size_t>(h) * nin + h, oW3 = oW2 + static_cast<size_t>(h) * h + h;
+  const size_t eW1 = static_cast<size_t>(h) * nin, eW2 = oW2 + static_cast<size_t>(h) * h,
+               eW3 = oW3 + static_cast<size_t>(nz) * h;
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const float gi = g[i];
@@ -562,7 +603,21 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+    const float pi = p[i] - lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+    p[i] = pi;
+    const bf16 w = static_cast<bf16>(pi);
+    if (i < eW1) {
+      const size_t o = i / nin;
+      w1b[o * kp + (i - o * nin)] = w;
+    } else if (i >= oW2 && i < eW2) {
+      const size_t q = i - oW2, r = q / h, c = q - r * h;
+      w2b[q] = w;
+      w2t[c * h + r] = w;
+    } else if (i >= oW3 && i < eW3) {
+      const size_t q = i - oW3, r = q / h, c = q - r * h;
+      w3b[q] = w;
+      w3t[c * nz + r] = w;
+    }
   }
 }
 
@@ -677,6 +732,7 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
   auto up8 = [](int v) { return (v + 7) / 8 * 8; };
   if (!g.ta && (g.lda < g.K || g.ldb < g.K)) return hipErrorInvalidValue;
   if (g.ta && (g.lda < up8(g.M) || g.ldb < up8(g.N))) return hipErrorInvalidValue;
+  if (g.row_sums && (g.epi != kEpiPartialF32 || !g.ta)) return hipErrorInvalidValue;
   if (g.epi == kEpiPartialF32) {
     if (g.ksplit <= 0 || g.ksplit % kBK) return hipErrorInvalidValue;
   } else {
@@ -773,26 +829,18 @@ hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* 
   return hipGetLastError();
 }
 
-int colsum_chunks(int rows) { return (rows + 63) / 64; }
-
-hipError_t launch_colsum_partial(const bf16* a, int rows, int cols, float* out_part, hipStream_t s) {
-  const int chunks = colsum_chunks(rows);
-  hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 63) / 64, std::min(chunks, 65535)), dim3(256), 0, s, a, rows, cols,
-                     chunks, out_part);
-  return hipGetLastError();
-}
-
 hipError_t launch_sum_parts(const float* part, int nparts, size_t len, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_parts, dim3(static_cast<unsigned>(std::min<size_t>((len + 63) / 64, 4096))), dim3(256), 0, s,
                      part, nparts, len, out);
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s) {
-  const double bc1 = 1.0 / (1.0 - std::pow(0.9, t));
-  const double bc2 = 1.0 / (1.0 - std::pow(0.999, t));
-  hipLaunchKernelGGL(k_adam, dim3(grid_of(n)), dim3(256), 0, s, p, g, m, v, n, lr, static_cast<float>(bc1),
-                     static_cast<float>(bc2));
+hipError_t launch_adam_copies(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, int n_in,
+                              int hidden, int nz, int kp, bf16* w1b, bf16* w2b, bf16* w3b, bf16* w2t, bf16* w3t,
+                              hipStream_t s) {
+  const double bc1 = 1.0 / (1.0 - std::pow(0.9, t)), bc2 = 1.0 / (1.0 - std::pow(0.999, t));
+  hipLaunchKernelGGL(k_adam_copies, dim3(grid_of(n)), dim3(256), 0, s, p, g, m, v, n, lr, static_cast<float>(bc1),
+                     static_cast<float>(bc2), n_in, hidden, nz, kp, w1b, w2b, w3b, w2t, w3t);
   return hipGetLastError();
 }
 

@@ -10,8 +10,8 @@ from . import (
     tpmg_mlp_create, tpmg_mlp_destroy, tpmg_mlp_features, tpmg_mlp_fit_scaling, tpmg_mlp_forward,
     tpmg_mlp_get_params, tpmg_mlp_get_scaling, tpmg_mlp_gradients, tpmg_mlp_infer, tpmg_mlp_load,
     tpmg_mlp_param_count, tpmg_mlp_save, tpmg_mlp_set_params, tpmg_mlp_set_scaling, tpmg_mlp_targets,
-    tpmg_mlp_train_step, tpmg_mlp_workspace_size, tpmg_mlp_features_increment, tpmg_mlp_targets_increment,
-    tpmg_mlp_infer_increment,
+    tpmg_mlp_train_step, tpmg_mlp_train_epoch, tpmg_mlp_workspace_size, tpmg_mlp_features_increment,
+    tpmg_mlp_targets_increment, tpmg_mlp_infer_increment,
 )
 
 
@@ -113,26 +113,23 @@ class ColumnMLP:
         return tpmg_mlp_train_step(self.h, x, y, x.shape[0], rows, rows.shape[0], lr, want_loss)
 
     def train(self, x, y, epochs: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0, loss_every: int = 50):
-        """Adam over shuffled mini-batches (a seeded permutation per epoch,
-        drawn on the host); returns the mean sampled batch loss per epoch."""
+        """Adam over shuffled mini-batches (a permutation per epoch, drawn on
+        the GPU from a generator seeded with seed); returns the mean sampled
+        batch loss per epoch."""
         import torch
 
         rows_total = x.shape[0]
-        rng = np.random.default_rng(seed)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
         per_epoch = []
         self._ready(x, y)
         for _ in range(epochs):
-            perm = torch.from_numpy(rng.permutation(rows_total).astype(np.int32)).to("cuda")
+            perm = torch.randperm(rows_total, generator=gen, device="cuda", dtype=torch.int32)
             self._ready(perm)
-            losses = []
             nb = rows_total // batch
-            for b in range(nb):
-                want = (b % loss_every == 0) or b == nb - 1
-                out = tpmg_mlp_train_step(self.h, x, y, rows_total, perm[b * batch:(b + 1) * batch], batch, lr, want)
-                if want:
-                    losses.append(out)
-            self.stream.synchronize()
-            per_epoch.append(float(np.mean(losses)) if losses else float("nan"))
+            # the epoch's steps in one call (the launches of nb train_step calls)
+            losses = tpmg_mlp_train_epoch(self.h, x, y, rows_total, perm, nb, batch, lr, loss_every) if nb else []
+            per_epoch.append(float(np.mean(losses)) if len(losses) else float("nan"))
         return per_epoch
 
     def infer(self, problem, f_tiled, u0_tiled, relax: int = 1) -> None:

@@ -149,6 +149,43 @@ def test_adam_steps_match_oracle():
     assert _rel(dg, do) <= 5e-2
 
 
+def test_train_epoch_equals_train_steps():
+    """tpmg_mlp_train_epoch runs the launches of its steps' train_step calls
+    in the same order: the parameters after 7 steps (batch 1,000 of a
+    seeded permutation of 7,500 rows) and the sampled losses (steps 0, 3, 6)
+    are bit for bit those of seven train_step calls; an out-of-range row is
+    reported and its flag cleared, and bad arguments are refused."""
+    x, y = _data(7_500, seed=21)
+    xd, yd = _cuda(x), _cuda(y)
+    perm = np.random.default_rng(22).permutation(len(x)).astype(np.int32)
+    pd = _cuda(perm)
+    steps, batch = 7, 1000
+    a, _ = _net(max_rows=batch, seed=3)
+    a.fit_scaling(xd, yd)
+    want = []
+    for k in range(steps):
+        loss = a.train_step(xd, yd, _cuda(perm[k * batch:(k + 1) * batch]), 2e-3, want_loss=True)
+        if k % 3 == 0 or k == steps - 1:
+            want.append(loss)
+    b, _ = _net(max_rows=batch, seed=3)
+    b.fit_scaling(xd, yd)
+    b._ready(xd, yd, pd)
+    losses = T.tpmg_mlp_train_epoch(b.h, xd, yd, len(x), pd, steps, batch, 2e-3, 3)
+    assert np.array_equal(losses, np.array(want, dtype=np.float32))
+    assert np.array_equal(a.get_params(), b.get_params())
+    # loss_every 0 samples nothing; an index out of range is reported after the epoch
+    bad = perm.copy()
+    bad[1500] = len(x)
+    assert len(T.tpmg_mlp_train_epoch(b.h, xd, yd, len(x), pd, 2, batch, 2e-3, 0)) == 0
+    with pytest.raises(T.TpmgError) as e:
+        T.tpmg_mlp_train_epoch(b.h, xd, yd, len(x), _cuda(bad), 2, batch, 2e-3, 0)
+    assert e.value.status == T.TPMG_ERR_ARG
+    T.tpmg_mlp_train_epoch(b.h, xd, yd, len(x), pd, 1, batch, 2e-3, 0)      # flag cleared
+    for args in ((0, batch, 2e-3), (2, batch + 1, 2e-3), (2, batch, 0.0)):
+        with pytest.raises(T.TpmgError):
+            T.tpmg_mlp_train_epoch(b.h, xd, yd, len(x), pd, *args, 0)
+
+
 def test_infer_into_solver_layout():
     w = synth.workload("seq_4_32")
     P = T.Problem(w.refinement, w.r_faces(), w.omega2).setup(precond_fp32=True)
