@@ -219,3 +219,32 @@ def test_batch_with_block_sor(fp32):
     with pytest.raises(T.TpmgError) as e:
         T.tpmg_batch_workspace_size([P0.mg, Pj.mg])
     assert e.value.status == T.TPMG_ERR_ARG
+
+
+@pytest.mark.parametrize("count", [1, 2])
+def test_small_batches_one_branch_per_problem(count):
+    """A batch of one problem (a graph of one branch) and of two (two
+    branches, one problem each) solve bit for bit as the single solves, also
+    on a second call that replays the cached graph."""
+    stream = torch.cuda.Stream()
+    probs = _setup(True, stream)[1:1 + count]
+    fs = [P.pack(f) for P, f, _ in probs]
+    singles = []
+    for (P, _, _), fd in zip(probs, fs):
+        u = P.device_vector()
+        st, iters, relres, hist, _ = P.solve(fd, u, rtol=1e-8, maxit=200)
+        assert st == T.TPMG_OK
+        singles.append((iters, relres, P.unpack(u)))
+    mgs = [P.mg for P, _, _ in probs]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, ws.data_ptr() + (-ws.data_ptr()) % 256, nbytes)
+    for rep in range(2):
+        us = [P.device_vector() for P, _, _ in probs]
+        st, per, _ = T.tpmg_batch_solve(batch, fs, us, 1e-8, 200)
+        assert st == T.TPMG_OK
+        for (P, _, _), u, (iters, relres, _h), (it_s, rr_s, u_s) in zip(probs, us, per, singles):
+            assert iters == it_s and relres == rr_s
+            assert np.array_equal(P.unpack(u), u_s)
+    T.tpmg_batch_destroy(batch)
