@@ -37,9 +37,20 @@ __device__ __forceinline__ size_t tiled_index(int col, int k, int nz) {
 constexpr int kBK = 32;
 constexpr int kGemmBK = 64;   // K slice of the GEMM kernel
 
+// LDS column of element (row, k) of a staged slice. A transposed operand is
+// staged by scattering each lane's 8 consecutive rows (one k) into their
+// rows, so the lanes of one store hit rows 8 apart, all in the same two of
+// the 64 banks whatever the row padding; its 8-wide K groups are therefore
+// placed at group XOR (row / 8) mod 8, which spreads those stores over the
+// banks and keeps every group contiguous for the 16-byte operand reads.
+template <bool T>
+__device__ __forceinline__ int lds_col(int row, int k) {
+  return T ? ((((k >> 3) ^ (row >> 3)) & 7) << 3 | (k & ~63) | (k & 7)) : k;
+}
+
 // Stages rows [r0, r0 + ROWS) x k [k0, k0 + BK) of a K-contiguous (T false)
-// or R-contiguous (T true) operand into LDS as [row][k]; entries outside
-// r < R, k < kend are zero.
+// or R-contiguous (T true) operand into LDS as [row][lds_col(row, k)];
+// entries outside r < R, k < kend are zero.
 template <int ROWS, bool T, int BK>
 __device__ __forceinline__ void stage(const bf16* __restrict__ src, int ld, int r0, int R, int k0, int kend,
                                       bf16 (*dst)[BK + 8]) {
@@ -64,7 +75,7 @@ __device__ __forceinline__ void stage(const bf16* __restrict__ src, int ld, int 
       v.u = make_uint4(0u, 0u, 0u, 0u);
       if (k < kend && r < R) v.u = *reinterpret_cast<const uint4*>(src + static_cast<size_t>(k) * ld + r);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) dst[rc + i][kk] = v.h[i];
+      for (int i = 0; i < 8; ++i) dst[rc + i][lds_col<true>(rc + i, kk)] = v.h[i];
     }
   }
 }
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     if (rsum)
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 8) {
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(&As[threadIdx.x][kk]);
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(&As[threadIdx.x][lds_col<TR>(threadIdx.x, kk)]);
 #pragma unroll
         for (int q = 0; q < 8; ++q) rs += static_cast<float>(v[q]);
       }
@@ -168,9 +179,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int ks = 0; ks < BK; ks += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + lr][ks + lk]);
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + 32 * i + lr;
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[row][lds_col<TR>(row, ks + lk)]);
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 32 * j + lr][ks + lk]);
+      for (int j = 0; j < 2; ++j) {
+        const int row = wn + 32 * j + lr;
+        b[j] = *reinterpret_cast<const bf16x8*>(&Bs[row][lds_col<TR>(row, ks + lk)]);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
