@@ -73,7 +73,7 @@ struct tpmg_mlp {
   bf16 *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *dh2 = nullptr, *dh1 = nullptr;
   float *y = nullptr, *yt = nullptr;
   // reductions
-  float* gpart = nullptr;     // kSplitMax x (largest weight matrix + its bias)
+  float* gpart = nullptr;     // kSplitMax x np: partial gradients of the K slices
   double* lpart = nullptr;    // loss partials
   float* loss = nullptr;
   double* mpart = nullptr;    // moment partials
@@ -119,9 +119,7 @@ void carve(tpmg_mlp& m, Carve& c) {
   m.dh1 = c.take<bf16>(R * m.h);
   m.y = c.take<float>(R * m.nz);
   m.yt = c.take<float>(R * m.nz);
-  const size_t wmax = std::max({static_cast<size_t>(m.h) * (m.nin + 1), static_cast<size_t>(m.h) * (m.h + 1),
-                                static_cast<size_t>(m.nz) * (m.h + 1)});
-  m.gpart = c.take<float>(kSplitMax * wmax);
+  m.gpart = c.take<float>(kSplitMax * m.np);
   m.lpart = c.take<double>(1024);
   m.loss = c.take<float>(1);
   m.mpart = c.take<double>(static_cast<size_t>(tpmg::kMomentChunksMax) * m.nin);
@@ -218,19 +216,21 @@ hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out) {
 
 // weight gradient dW [M][N] = sum over the batch of a(b, m) c(b, n), a and c
 // row-major [batch][lda] and [batch][ldc], written to grads + off
-// gradient of a layer's weights W [M][N] and bias b [M], which follows W in
-// the packed parameters: the product a^T c over the batch (a: the layer's
-// output gradients [batch][M], c: its inputs [batch][N]) in K slices with
-// the row sums of a (the bias gradient) beside each slice's partial, then
-// one sum over the slices
+// K slices of the weight-gradient products: about 256 workgroups for the
+// largest layer, at least 32 rows each; the same for every layer, so that
+// one sum over the slices forms all the gradients
+int grad_ksplit(int batch) {
+  int ksplit = (batch + kSplitMax - 1) / kSplitMax;
+  return std::max(32, (ksplit + 31) / 32 * 32);
+}
+
+// partial gradients of a layer's weights W [M][N] and bias b [M], which
+// follows W in the packed parameters: the product a^T c over each K slice of
+// the batch (a: the layer's output gradients [batch][M], c: its inputs
+// [batch][N]) with the row sums of a (the bias gradient) beside it, at
+// offset off of that slice's row of m.gpart (rows of np entries)
 hipError_t weight_grad(tpmg_mlp& m, const bf16* a, int lda, int M, const bf16* c, int ldc, int N, int batch,
                        size_t off) {
-  // slices of the batch: about 256 workgroups in all, at least 32 rows each
-  const long tiles = std::max(1L, (static_cast<long>(M) * N) / (128L * 128L));
-  const int want = static_cast<int>(std::min<long>(kSplitMax, std::max(1L, 256L / tiles)));
-  int ksplit = (batch + want - 1) / want;
-  ksplit = std::max(32, (ksplit + 31) / 32 * 32);
-  const int nsplit = (batch + ksplit - 1) / ksplit;
   tpmg::GemmArgs g;
   g.A = a;
   g.lda = lda;
@@ -240,13 +240,12 @@ hipError_t weight_grad(tpmg_mlp& m, const bf16* a, int lda, int M, const bf16* c
   g.M = M;
   g.N = N;
   g.K = batch;
-  g.ksplit = ksplit;
+  g.ksplit = grad_ksplit(batch);
   g.epi = tpmg::kEpiPartialF32;
   g.row_sums = true;
-  g.out_f32 = m.gpart;
-  hipError_t e = tpmg::launch_gemm(g, m.stream);
-  if (e != hipSuccess) return e;
-  return tpmg::launch_sum_parts(m.gpart, nsplit, static_cast<size_t>(M) * N + M, m.grads + off, m.stream);
+  g.pstride = m.np;
+  g.out_f32 = m.gpart + off;
+  return tpmg::launch_gemm(g, m.stream);
 }
 
 // loss and gradients of the batch into m.grads and m.loss
@@ -283,6 +282,9 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
   g.out_bf16 = m.dh1;
   if (e == hipSuccess) e = tpmg::launch_gemm(g, m.stream);
   if (e == hipSuccess) e = weight_grad(m, m.dh1, m.h, m.h, m.xb, m.kp, m.nin, batch, m.oW1());
+  // every parameter's gradient: the sum over the K slices
+  const int ksplit = grad_ksplit(batch);
+  if (e == hipSuccess) e = tpmg::launch_sum_parts(m.gpart, (batch + ksplit - 1) / ksplit, m.np, m.grads, m.stream);
   return e;
 }
 

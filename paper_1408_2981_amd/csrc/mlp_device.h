@@ -38,9 +38,12 @@ struct GemmArgs {
   int ksplit = 0;            // kEpiPartialF32: k values per slice (multiple of 32); else K
   // kEpiPartialF32 with transposed operands: also the sums over k of each row
   // of A (a layer's bias gradient beside its weight gradient); the partials
-  // of slice z are then out_f32[z (M N + M) + m N + n] and, for the row sums,
-  // out_f32[z (M N + M) + M N + m]
+  // of slice z are then out_f32[z S + m N + n] and, for the row sums,
+  // out_f32[z S + M N + m], S the partial stride
   bool row_sums = false;
+  // kEpiPartialF32: the distance between the partials of consecutive K slices
+  // (0: M N, + M with row_sums)
+  size_t pstride = 0;
   bool ta = false, tb = false;
   int epi = kEpiBiasF32;
   const float* bias = nullptr;

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __syncthreads();
   }
 
-  const size_t pstride = static_cast<size_t>(g.M) * g.N + (g.row_sums ? g.M : 0);
+  const size_t pstride = g.pstride ? g.pstride : static_cast<size_t>(g.M) * g.N + (g.row_sums ? g.M : 0);
   if (rsum && m0 + static_cast<int>(threadIdx.x) < g.M)
     g.out_f32[static_cast<size_t>(blockIdx.z) * pstride + static_cast<size_t>(g.M) * g.N + m0 + threadIdx.x] = rs;
 #pragma unroll
