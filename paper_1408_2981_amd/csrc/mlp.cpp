@@ -249,11 +249,14 @@ hipError_t weight_grad(tpmg_mlp& m, const bf16* a, int lda, int M, const bf16* c
 }
 
 // loss and gradients of the batch into m.grads and m.loss
-hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_total, const int32_t* rows, int batch) {
+hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_total, const int32_t* rows, int batch,
+                    bool want_loss = true) {
   hipError_t e = tpmg::launch_mlp_prep(x, yv, rows, rows_total, m.bad_row, batch, m.nin, m.kp, m.nz, m.mu_x, m.sd_x,
                                        m.mu_y, m.sd_y, m.xb, m.yt, m.stream);
   if (e == hipSuccess) e = forward(m, batch, tpmg::kEpiBiasF32, m.y, nullptr);
-  if (e == hipSuccess) e = tpmg::launch_mlp_mse(m.y, m.yt, batch, m.nz, m.dy, m.lpart, m.loss, m.stream);
+  // (the batch loss, into m.loss, only when it is read)
+  if (e == hipSuccess)
+    e = tpmg::launch_mlp_mse(m.y, m.yt, batch, m.nz, m.dy, m.lpart, want_loss ? m.loss : nullptr, m.stream);
   if (e != hipSuccess) return e;
   // output layer
   e = weight_grad(m, m.dy, m.nz, m.nz, m.h2, m.h, m.h, batch, m.oW3());
@@ -520,7 +523,7 @@ tpmg_status tpmg_mlp_train_step(tpmg_mlp* m, const float* d_x, const float* d_y,
   if (st != TPMG_OK) return st;
   if ((st = check_batch_args(m, d_x, d_y, rows_total, d_rows, batch)) != TPMG_OK) return st;
   if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(TPMG_ERR_ARG, "lr must be finite and > 0");
-  MLP_HIP(backprop(*m, d_x, d_y, rows_total, d_rows, batch));
+  MLP_HIP(backprop(*m, d_x, d_y, rows_total, d_rows, batch, loss != nullptr));
   m->adam_t += 1;
   MLP_HIP(adam_step(*m, lr));
   if (loss) {
@@ -541,8 +544,9 @@ tpmg_status tpmg_mlp_train_epoch(tpmg_mlp* m, const float* d_x, const float* d_y
   if (loss_every < 0 || (loss_every > 0 && !losses)) return fail(TPMG_ERR_ARG, "loss_every > 0 needs losses");
   int sampled = 0;
   for (int k = 0; k < steps; ++k) {
-    MLP_HIP(backprop(*m, d_x, d_y, rows_total, d_perm + static_cast<size_t>(k) * batch, batch));
-    if (loss_every > 0 && (k % loss_every == 0 || k == steps - 1))
+    const bool sample = loss_every > 0 && (k % loss_every == 0 || k == steps - 1);
+    MLP_HIP(backprop(*m, d_x, d_y, rows_total, d_perm + static_cast<size_t>(k) * batch, batch, sample));
+    if (sample)
       MLP_HIP(hipMemcpyAsync(losses + sampled++, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
     m->adam_t += 1;
     MLP_HIP(adam_step(*m, lr));

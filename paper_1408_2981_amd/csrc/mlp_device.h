@@ -105,7 +105,7 @@ hipError_t launch_mlp_prep(const float* x, const float* y, const int32_t* rows, 
                            const float* sd_y, bf16* xb, float* yt, hipStream_t s);
 
 // d = y - yt; dy = bf16(scale d); loss_partials[b] = sum of d^2 per block
-// (FP64), then loss[0] = sum over blocks / (n nz), FP32.
+// (FP64), then (loss not NULL) loss[0] = sum over blocks / (n nz), FP32.
 hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* dy, double* partials,
                           float* loss, hipStream_t s);
 int mlp_mse_blocks(int n, int nz);

@@ -842,7 +842,8 @@ hipError_t launch_mlp_mse(const float* y, const float* yt, int n, int nz, bf16* 
   const int nb = mlp_mse_blocks(n, nz);
   hipLaunchKernelGGL(k_mlp_mse, dim3(nb), dim3(256), 0, s, y, yt, total, 2.0f / static_cast<float>(total), dy,
                      partials);
-  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, partials, nb, 1.0 / static_cast<double>(total), loss);
+  if (loss)
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, partials, nb, 1.0 / static_cast<double>(total), loss);
   return hipGetLastError();
 }
 
