@@ -71,6 +71,8 @@ struct tpmg_mlp {
   std::vector<double> h_mu_x, h_sd_x, h_mu_y, h_sd_y;
   // activations of up to max_rows rows
   bf16 *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *dh2 = nullptr, *dh1 = nullptr;
+  // ReLU masks of h1 and h2 as bits, written by the training forward pass
+  uint64_t *bits1 = nullptr, *bits2 = nullptr;
   float *y = nullptr, *yt = nullptr;
   // reductions
   float* gpart = nullptr;     // kSplitMax x np: partial gradients of the K slices
@@ -117,6 +119,10 @@ void carve(tpmg_mlp& m, Carve& c) {
   m.dy = c.take<bf16>(R * m.nz);
   m.dh2 = c.take<bf16>(R * m.h);
   m.dh1 = c.take<bf16>(R * m.h);
+  // (at most one word per thread of 4 waves per 64 x 64 outputs, whatever the tile)
+  const size_t words = (R + 63) / 64 * ((static_cast<size_t>(m.h) + 63) / 64) * 256;
+  m.bits1 = c.take<uint64_t>(words);
+  m.bits2 = c.take<uint64_t>(words);
   m.y = c.take<float>(R * m.nz);
   m.yt = c.take<float>(R * m.nz);
   m.gpart = c.take<float>(kSplitMax * m.np);
@@ -171,7 +177,7 @@ hipError_t adam_step(tpmg_mlp& m, float lr) {
 
 // forward pass over n prepared rows (m.xb): h1, h2, then the third product
 // with the given epilogue
-hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out) {
+hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out, bool mask_bits = false) {
   const float* P = m.params;
   tpmg::GemmArgs g;
   g.A = m.xb;
@@ -185,6 +191,7 @@ hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out) {
   g.bias = P + m.ob1();
   g.out_bf16 = m.h1;
   g.ldc = m.h;
+  g.mask_bits = mask_bits ? m.bits1 : nullptr;
   hipError_t e = tpmg::launch_gemm(g, m.stream);
   if (e != hipSuccess) return e;
   g.A = m.h1;
@@ -194,6 +201,7 @@ hipError_t forward(tpmg_mlp& m, int n, int epi3, float* y_out, double* u_out) {
   g.K = m.h;
   g.bias = P + m.ob2();
   g.out_bf16 = m.h2;
+  g.mask_bits = mask_bits ? m.bits2 : nullptr;
   e = tpmg::launch_gemm(g, m.stream);
   if (e != hipSuccess) return e;
   tpmg::GemmArgs g3;
@@ -253,7 +261,7 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
                     bool want_loss = true) {
   hipError_t e = tpmg::launch_mlp_prep(x, yv, rows, rows_total, m.bad_row, batch, m.nin, m.kp, m.nz, m.mu_x, m.sd_x,
                                        m.mu_y, m.sd_y, m.xb, m.yt, m.stream);
-  if (e == hipSuccess) e = forward(m, batch, tpmg::kEpiBiasF32, m.y, nullptr);
+  if (e == hipSuccess) e = forward(m, batch, tpmg::kEpiBiasF32, m.y, nullptr, true);
   // (the batch loss, into m.loss, only when it is read)
   if (e == hipSuccess)
     e = tpmg::launch_mlp_mse(m.y, m.yt, batch, m.nz, m.dy, m.lpart, want_loss ? m.loss : nullptr, m.stream);
@@ -270,7 +278,7 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
   g.N = m.h;
   g.K = m.nz;
   g.epi = tpmg::kEpiMaskBf16;
-  g.mask = m.h2;
+  g.mask_bits = m.bits2;   // (this product's M and N are those of layer 2's)
   g.out_bf16 = m.dh2;
   g.ldc = m.h;
   if (e == hipSuccess) e = tpmg::launch_gemm(g, m.stream);
@@ -281,7 +289,7 @@ hipError_t backprop(tpmg_mlp& m, const float* x, const float* yv, size_t rows_to
   g.B = m.w2t;
   g.ldb = m.h;
   g.K = m.h;
-  g.mask = m.h1;
+  g.mask_bits = m.bits1;
   g.out_bf16 = m.dh1;
   if (e == hipSuccess) e = tpmg::launch_gemm(g, m.stream);
   if (e == hipSuccess) e = weight_grad(m, m.dh1, m.h, m.h, m.xb, m.kp, m.nin, batch, m.oW1());

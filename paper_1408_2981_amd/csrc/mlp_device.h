@@ -47,7 +47,12 @@ struct GemmArgs {
   bool ta = false, tb = false;
   int epi = kEpiBiasF32;
   const float* bias = nullptr;
-  const bf16* mask = nullptr;
+  // ReLU masks as bits: kEpiBiasReluBf16 (optional) writes, for every thread
+  // of every workgroup, one 64-bit word whose bit 32 i + 16 j + r is set when
+  // its output (i, j, r) is > 0 after the bf16 rounding; kEpiMaskBf16 reads the
+  // words a kEpiBiasReluBf16 product of the same M and N wrote (same tiles,
+  // so the same output positions per thread) as its mask
+  uint64_t* mask_bits = nullptr;
   bf16* out_bf16 = nullptr;
   float* out_f32 = nullptr;
   int ldc = 0;

@@ -131,19 +131,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   // output element (i, j, r) of this lane
   auto out_row = [&](int i, int r) { return m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); };
   auto out_col = [&](int j) { return n0 + wn + 32 * j + lr; };
-  // the ReLU mask of the outputs, loaded before the products so that its
-  // latency hides behind them
-  bf16 mk[2][2][16];
-  if (EPI == kEpiMaskBf16)
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = out_row(i, r), n = out_col(j);
-          mk[i][j][r] = (m < g.M && n < g.N) ? g.mask[static_cast<size_t>(m) * g.ldc + n] : static_cast<bf16>(0.0f);
-        }
+  // this thread's word of ReLU mask bits (loaded before the products)
+  const size_t mword = (static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
+  const uint64_t mk = EPI == kEpiMaskBf16 ? g.mask_bits[mword] : 0;
+  uint64_t mb = 0;
   // row sums of A (bias gradient): the first column tile's threads, one row each
   const bool rsum = EPI == kEpiPartialF32 && g.row_sums && blockIdx.y == 0 && threadIdx.x < BM;
   float rs = 0.0f;
@@ -209,18 +200,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         if (m >= g.M || n >= g.N) continue;
         const float c = acc[i][j][r];
         const size_t o = static_cast<size_t>(m) * g.ldc + n;
+        const int bit = 32 * i + 16 * j + r;
         if (EPI == kEpiBiasReluBf16) {
-          g.out_bf16[o] = static_cast<bf16>(fmaxf(c + g.bias[n], 0.0f));
+          const bf16 h = static_cast<bf16>(fmaxf(c + g.bias[n], 0.0f));
+          g.out_bf16[o] = h;
+          if (static_cast<float>(h) > 0.0f) mb |= uint64_t(1) << bit;
         } else if (EPI == kEpiBiasF32) {
           g.out_f32[o] = c + g.bias[n];
         } else if (EPI == kEpiMaskBf16) {
-          g.out_bf16[o] = static_cast<float>(mk[i][j][r]) > 0.0f ? static_cast<bf16>(c) : static_cast<bf16>(0.0f);
+          g.out_bf16[o] = ((mk >> bit) & 1) ? static_cast<bf16>(c) : static_cast<bf16>(0.0f);
         } else if (EPI == kEpiPartialF32) {
           g.out_f32[static_cast<size_t>(blockIdx.z) * pstride + static_cast<size_t>(m) * g.N + n] = c;
         } else {
           g.out_f64[tiled_index(m, n, g.N)] = static_cast<double>((c + g.bias[n]) * g.sd[n] + g.mu[n]);
         }
       }
+  if (EPI == kEpiBiasReluBf16 && g.mask_bits) g.mask_bits[mword] = mb;
 }
 
 // ---------------------------------------------------------------------------
@@ -760,7 +755,7 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
     case kEpiMaskBf16:
       if (!g.out_bf16 || g.ldc < g.N) return hipErrorInvalidValue;
       if (g.epi == kEpiBiasReluBf16 && !g.bias) return hipErrorInvalidValue;
-      if (g.epi == kEpiMaskBf16 && !g.mask) return hipErrorInvalidValue;
+      if (g.epi == kEpiMaskBf16 && !g.mask_bits) return hipErrorInvalidValue;
       break;
     case kEpiBiasF32:
       if (!g.out_f32 || !g.bias || g.ldc < g.N) return hipErrorInvalidValue;
