@@ -135,6 +135,23 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const size_t mword = (static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
   const uint64_t mk = EPI == kEpiMaskBf16 ? g.mask_bits[mword] : 0;
   uint64_t mb = 0;
+  // this lane's bias (and de-standardisation) of its two output columns, in
+  // registers before the products: read in the epilogue, each load would
+  // wait behind the output stores the compiler cannot prove apart from it
+  constexpr bool kBias = EPI == kEpiBiasReluBf16 || EPI == kEpiBiasF32 || EPI == kEpiInferTiled;
+  float bj[2] = {0.0f, 0.0f}, sj[2] = {0.0f, 0.0f}, uj[2] = {0.0f, 0.0f};
+  if (kBias)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = out_col(j);
+      if (n < g.N) {
+        bj[j] = g.bias[n];
+        if (EPI == kEpiInferTiled) {
+          sj[j] = g.sd[n];
+          uj[j] = g.mu[n];
+        }
+      }
+    }
   // row sums of A (bias gradient): the first column tile's threads, one row each
   const bool rsum = EPI == kEpiPartialF32 && g.row_sums && blockIdx.y == 0 && threadIdx.x < BM;
   float rs = 0.0f;
@@ -202,17 +219,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const size_t o = static_cast<size_t>(m) * g.ldc + n;
         const int bit = 32 * i + 16 * j + r;
         if (EPI == kEpiBiasReluBf16) {
-          const bf16 h = static_cast<bf16>(fmaxf(c + g.bias[n], 0.0f));
+          const bf16 h = static_cast<bf16>(fmaxf(c + bj[j], 0.0f));
           g.out_bf16[o] = h;
           if (static_cast<float>(h) > 0.0f) mb |= uint64_t(1) << bit;
         } else if (EPI == kEpiBiasF32) {
-          g.out_f32[o] = c + g.bias[n];
+          g.out_f32[o] = c + bj[j];
         } else if (EPI == kEpiMaskBf16) {
           g.out_bf16[o] = ((mk >> bit) & 1) ? static_cast<bf16>(c) : static_cast<bf16>(0.0f);
         } else if (EPI == kEpiPartialF32) {
           g.out_f32[static_cast<size_t>(blockIdx.z) * pstride + static_cast<size_t>(m) * g.N + n] = c;
         } else {
-          g.out_f64[tiled_index(m, n, g.N)] = static_cast<double>((c + g.bias[n]) * g.sd[n] + g.mu[n]);
+          g.out_f64[tiled_index(m, n, g.N)] = static_cast<double>((c + bj[j]) * sj[j] + uj[j]);
         }
       }
   if (EPI == kEpiBiasReluBf16 && g.mask_bits) g.mask_bits[mword] = mb;
