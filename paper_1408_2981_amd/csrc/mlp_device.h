@@ -25,8 +25,8 @@ using bf16 = __bf16;
 enum GemmEpilogue {
   kEpiBiasReluBf16 = 0,  // out_bf16[m ldc + n] = bf16(max(C + bias[n], 0))
   kEpiBiasF32 = 1,       // out_f32[m ldc + n] = C + bias[n]
-  kEpiMaskBf16 = 2,      // out_bf16[m ldc + n] = mask[m ldc + n] > 0 ? bf16(C) : 0
-  kEpiPartialF32 = 3,    // out_f32[z M N + m N + n] = C over the z-th slice of ksplit values of k
+  kEpiMaskBf16 = 2,      // out_bf16[m ldc + n] = (ReLU mask bit of (m, n), mask_bits) ? bf16(C) : 0
+  kEpiPartialF32 = 3,    // out_f32[z S + m N + n] = C over the z-th slice of ksplit values of k (S: pstride)
   kEpiInferTiled = 4,    // out_f64 tiled (column m, level n) = (C + bias[n]) sd[n] + mu[n]
 };
 
