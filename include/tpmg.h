@@ -355,9 +355,10 @@ tpmg_status tpmg_solve_bicgstab(tpmg_mg* mg, const double* d_f, double* d_u, dou
  * branches (up to three of each, default priority; released by
  * tpmg_batch_destroy). The problems must share one non-default stream, the
  * precision and the smoother parameters (block-Jacobi or multicolour
- * block-SOR, damping, sweep counts), have at least two levels, factorising
- * profiles and the scan smoother on every level (the default for nz <=
- * 256). The batch workspace (device, 256-byte aligned) holds the
+ * block-SOR, damping, sweep counts), have at least two levels, a symmetric
+ * operator (no vertical advection; profiles that factorise or not, with any
+ * of the three V-cycles) and the scan smoother on every level (the default
+ * for nz <= 256). The batch workspace (device, 256-byte aligned) holds the
  * per-problem scalars and the launch tables; problems must outlive the
  * batch. Errors: TPMG_ERR_ARG, TPMG_ERR_NOMEM. */
 tpmg_status tpmg_batch_workspace_size(tpmg_mg* const* problems, int n, size_t* bytes);

@@ -166,6 +166,7 @@ struct BatchLaunch {
   int chunk;        // residual + restriction, operator: the levels-per-wave instance of every
                     // segment (1, 2, 4, 8, 16), or 0 for the per-segment runtime chunk
   bool f_double, out_double, zero, fcopy, dots;   // smoother variant
+  int pm;           // profile mode of every segment's level (0, 1, 2; LevelView::pm)
   double omega;
   unsigned grid, block;
   size_t lds;

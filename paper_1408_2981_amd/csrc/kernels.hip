@@ -1437,26 +1437,27 @@ __device__ __forceinline__ CSeg* find_segment(const Seg* __restrict__ segs_g, in
 }
 
 // (the occupancy bounds of the single sweep)
-template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS>
+template <int KB, typename T, typename TF, typename TO, bool ZERO, bool FCOPY, bool DOTS, int PM>
 __global__ __launch_bounds__((scan_max_threads<KB, T>()),
-                             (scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value))) void kb_smooth_scan(
+                             (PM == 0 ? scan_waves_per_simd<KB, T>(DOTS || std::is_same<TF, double>::value)
+                                      : scan_waves_per_simd_full<KB, T>())) void kb_smooth_scan(
     const Seg* __restrict__ segs, int nseg, double omega) {
   GridPos g;
   CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS, 0, !DOTS>(
+  smooth_scan_body<KB, T, TF, TO, ZERO, FCOPY, DOTS, PM, !DOTS>(
       view<T>(sg->L), static_cast<const TF*>(sg->in0), static_cast<const T*>(sg->in1), static_cast<TO*>(sg->out0),
       static_cast<T*>(sg->out1), static_cast<T>(omega), sg->q, sg->partials, g);
 }
 
 // (CH > 0: every segment's chunk is CH, the instance the single launches
 // use for that chunk, so a batch forms the same bits)
-template <typename T, int CH>
+template <typename T, int CH, int PM>
 __global__ __launch_bounds__(256) void kb_residual_restrict(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
   CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  residual_restrict_body<T, CH>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
+  residual_restrict_body<T, CH, PM>(view<T>(sg->L), sg->chunk, sg->C.n, static_cast<const T*>(sg->in0),
                              static_cast<const T*>(sg->in1), static_cast<T*>(sg->out0), g);
 }
 
@@ -1469,12 +1470,12 @@ __global__ __launch_bounds__(256) void kb_prolong_add(const Seg* __restrict__ se
                       static_cast<T*>(sg->out0), g);
 }
 
-template <int CH>
+template <int CH, int PM>
 __global__ __launch_bounds__(256) void kb_spmv64(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
   CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  spmv_body<0, CH>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
+  spmv_body<0, CH, PM>(view<double>(sg->L), sg->chunk, static_cast<const double*>(sg->in0), nullptr,
                    static_cast<double*>(sg->out0), sg->partials, g);
 }
 
@@ -1494,12 +1495,12 @@ __global__ __launch_bounds__(256) void kb_fcg_update(const Seg* __restrict__ seg
                   static_cast<const double*>(sg->in1), sg->sc, sg->len, sg->partials, g);
 }
 
-template <int CH, typename TZ>
+template <int CH, typename TZ, int PM>
 __global__ __launch_bounds__(256) void kb_spmv_pring(const Seg* __restrict__ segs, int nseg) {
   GridPos g;
   CSeg* sg = find_segment(segs, nseg, g);
   if (!sg) return;
-  spmv_pring_body<CH, TZ>(view<double>(sg->L), static_cast<const TZ*>(sg->in0), sg->aux, sg->len,
+  spmv_pring_body<CH, TZ, PM>(view<double>(sg->L), static_cast<const TZ*>(sg->in0), sg->aux, sg->len,
                           static_cast<double*>(sg->out1), static_cast<double*>(sg->out0), sg->partials, sg->sc, g);
 }
 
@@ -1991,34 +1992,56 @@ hipError_t launch_unpack(const double* tiled, double* cm, int n, int npad, int n
 
 // ---- batched launches -----------------------------------------------------
 
+// Calls fn(std::integral_constant<int, PM>) for the profile modes a batch can
+// hold (0 factorised, 1 radial couplings per (T, k), 2 all coefficients per
+// (T, k); the advective mode needs the non-symmetric solvers, not batched).
+template <typename Fn>
+void batch_profile_variant(int pm, Fn&& fn) {
+  switch (pm) {
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    default: fn(std::integral_constant<int, 0>{}); break;
+  }
+}
+
 template <typename T>
 static hipError_t batched_smooth_t(const BatchLaunch& b, hipStream_t s) {
   const dim3 grid(b.grid), block(b.block);
   if (!smoother_fits(kSmScan, b.scan_levels, 1, static_cast<int>(sizeof(T)))) return hipErrorInvalidValue;
+  if (b.pm < 0 || b.pm > 2) return hipErrorInvalidValue;
   scan_levels_variant(b.scan_levels, [&](auto kbc) {
     constexpr int KB = decltype(kbc)::value;
-    smoother_variant<T>(b.f_double, b.out_double, b.zero, b.fcopy, b.dots, [&](auto tf, auto to, auto z, auto fcp, auto dt) {
-      using TF = typename decltype(tf)::type;
-      using TO = typename decltype(to)::type;
-      hipLaunchKernelGGL((kb_smooth_scan<KB, T, TF, TO, decltype(z)::value, decltype(fcp)::value, decltype(dt)::value>),
-                         grid, block, b.lds, s, b.segs, b.nseg, b.omega);
+    batch_profile_variant(b.pm, [&](auto pmc) {
+      constexpr int PM = decltype(pmc)::value;
+      smoother_variant<T>(b.f_double, b.out_double, b.zero, b.fcopy, b.dots,
+                          [&](auto tf, auto to, auto z, auto fcp, auto dt) {
+                            using TF = typename decltype(tf)::type;
+                            using TO = typename decltype(to)::type;
+                            hipLaunchKernelGGL((kb_smooth_scan<KB, T, TF, TO, decltype(z)::value, decltype(fcp)::value,
+                                                               decltype(dt)::value, PM>),
+                                               grid, block, b.lds, s, b.segs, b.nseg, b.omega);
+                          });
     });
   });
   return hipGetLastError();
 }
 
 hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
+  if (b.pm < 0 || b.pm > 2) return hipErrorInvalidValue;
   switch (b.kind) {
     case kOpSmooth:
       if (b.prec == 8) return batched_smooth_t<double>(b, s);
       return batched_smooth_t<float>(b, s);
     case kOpRestrict:
-      chunk_variant(b.chunk, [&](auto chc) {
-        constexpr int CH = decltype(chc)::value;
-        if (b.prec == 8)
-          hipLaunchKernelGGL((kb_residual_restrict<double, CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
-        else
-          hipLaunchKernelGGL((kb_residual_restrict<float, CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      batch_profile_variant(b.pm, [&](auto pmc) {
+        constexpr int PM = decltype(pmc)::value;
+        chunk_variant(b.chunk, [&](auto chc) {
+          constexpr int CH = decltype(chc)::value;
+          if (b.prec == 8)
+            hipLaunchKernelGGL((kb_residual_restrict<double, CH, PM>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+          else
+            hipLaunchKernelGGL((kb_residual_restrict<float, CH, PM>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+        });
       });
       break;
     case kOpProlong:
@@ -2028,22 +2051,28 @@ hipError_t launch_batched(const BatchLaunch& b, hipStream_t s) {
         hipLaunchKernelGGL(kb_prolong_add<float>, dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
       break;
     case kOpSpmv:
-      chunk_variant(b.chunk, [&](auto chc) {
-        constexpr int CH = decltype(chc)::value;
-        hipLaunchKernelGGL((kb_spmv64<CH>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+      batch_profile_variant(b.pm, [&](auto pmc) {
+        constexpr int PM = decltype(pmc)::value;
+        chunk_variant(b.chunk, [&](auto chc) {
+          constexpr int CH = decltype(chc)::value;
+          hipLaunchKernelGGL((kb_spmv64<CH, PM>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+        });
       });
       break;
     case kOpSpmvPRing:
       // (the plan only forms it for chunks with an instance)
       if (b.chunk == 0) return hipErrorInvalidValue;
-      chunk_variant(b.chunk, [&](auto chc) {
-        constexpr int CH = decltype(chc)::value;
-        if constexpr (CH > 0) {
-          if (b.f_double)
-            hipLaunchKernelGGL((kb_spmv_pring<CH, double>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
-          else
-            hipLaunchKernelGGL((kb_spmv_pring<CH, float>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
-        }
+      batch_profile_variant(b.pm, [&](auto pmc) {
+        constexpr int PM = decltype(pmc)::value;
+        chunk_variant(b.chunk, [&](auto chc) {
+          constexpr int CH = decltype(chc)::value;
+          if constexpr (CH > 0) {
+            if (b.f_double)
+              hipLaunchKernelGGL((kb_spmv_pring<CH, double, PM>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+            else
+              hipLaunchKernelGGL((kb_spmv_pring<CH, float, PM>), dim3(b.grid), dim3(256), 0, s, b.segs, b.nseg);
+          }
+        });
       });
       break;
     case kOpRupdate:

@@ -871,9 +871,12 @@ hipError_t plan_branch(tpmg_batch& b, const std::vector<int>& group, double* con
                                         o.L.npad, o.L.nz);
     return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) ? c : 0;
   };
+  // (a launch holds one profile mode: problems whose V-cycle or outer operator
+  // rebuilds coefficients differently launch apart)
   auto group_less = [&](const Op& a, const Op& c) {
     if (order_less(a, c)) return true;
     if (order_less(c, a)) return false;
+    if (a.L.pm != c.L.pm) return a.L.pm < c.L.pm;
     if (kb_of(a) != kb_of(c)) return kb_of(a) < kb_of(c);
     return ch_of(a) < ch_of(c);
   };
@@ -895,6 +898,7 @@ hipError_t plan_branch(tpmg_batch& b, const std::vector<int>& group, double* con
     L.fcopy = o.fcopy;
     L.dots = o.dots;
     L.omega = o.omega;
+    L.pm = o.L.pm;
     L.block = 256;
     tpmg::BatchLaunch F{};
     F.kind = tpmg::kOpFinalize;
@@ -1019,7 +1023,7 @@ tpmg_status check_batch(tpmg_mg* const* problems, int n) {
     const tpmg_mg* m = problems[i];
     if (!m) return fail(TPMG_ERR_ARG, "NULL problem");
     if (m->nlev < 2) return fail(TPMG_ERR_ARG, "batched problems need at least 2 multigrid levels");
-    if (m->full_outer) return fail(TPMG_ERR_ARG, "batched problems need factorising profiles");
+    if (m->adv) return fail(TPMG_ERR_ARG, "batched problems need a symmetric operator (no vertical advection)");
     for (const tpmg::LevelTune& t : m->tune)
       if (t.smoother != tpmg::kSmScan)
         return fail(TPMG_ERR_ARG, "batched problems need the scan smoother on every level (params.smoother = 1)");
@@ -2445,8 +2449,8 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
   const bool ring = batch_ring(*b);
   for (int p = 0; p < n; ++p) {
     tpmg_mg& m = *b->probs[p];
-    TPMG_HIP(tpmg::launch_spmv64(m.view64(m.nlev - 1), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit,
-                                  b->scal + p, s, rtol, ring && m.fp32 ? static_cast<float*>(m.fcopy) : nullptr));
+    TPMG_HIP(tpmg::launch_spmv64(m.view_outer(), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit, b->scal + p, s,
+                                  rtol, ring && m.fp32 ? static_cast<float*>(m.fcopy) : nullptr));
     if (!ring) TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
   }
   const bool rebuild = b->plan_u.size() != static_cast<size_t>(n) || !std::equal(b->plan_u.begin(), b->plan_u.end(), d_u);
@@ -2563,7 +2567,8 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
       infos[p].t_vcycle_ms = infos[p].t_spmv_ms = infos[p].t_blas_ms = 0.0;
       std::vector<Op> ops;
       fcg_ops(*b->probs[p], d_u[p], b->scal + p, ops, false, ring);
-      infos[p].model_bytes = solve_model_bytes(ops, c.iters, b->probs[p]->len, b->probs[p]->fp32, ring);
+      infos[p].model_bytes =
+          solve_model_bytes(ops, c.iters, b->probs[p]->len, b->probs[p]->fp32, ring, b->probs[p]->full_outer);
     }
     if (st == TPMG_ERR_BREAKDOWN) worst = st;
     else if (st == TPMG_NOT_CONVERGED && worst == TPMG_OK) worst = st;

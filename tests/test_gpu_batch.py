@@ -248,3 +248,72 @@ def test_small_batches_one_branch_per_problem(count):
             assert iters == it_s and relres == rr_s
             assert np.array_equal(P.unpack(u), u_s)
     T.tpmg_batch_destroy(batch)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_batch_with_profiles_that_do_not_factorise(fp32):
+    """Problems whose operator has coefficients per (T, k), preconditioned by
+    the V-cycle of the full operator (TPMG^(full)), of the approximate
+    factorisation (TPMG^(x)) or of the partial one (TPMG^(partial)), batched
+    with a factorising problem: each launch holds one profile mode, and every
+    problem's iterates equal its single solve's bit for bit; in FP64 the
+    TPMG^(full) problem also matches the oracle's solve (identical iteration
+    count, 1e-10)."""
+    from oracle import mesh, operator as opm
+
+    stream = torch.cuda.Stream()
+    cases = []
+    for ref, nz, seed, code in ((3, 13, 42, T.PRECOND_FULL), (3, 13, 42, T.PRECOND_FACTORISED),
+                                (3, 13, 42, T.PRECOND_PARTIAL), (2, 8, 52, T.PRECOND_FULL)):
+        r = synth.vertical_faces(nz, synth.H10KM, "quadratic")
+        om2 = synth.omega_for(ref) ** 2
+        n = synth.n_cells(ref)
+        rng = np.random.default_rng(seed)
+        full = opm.FullProfiles(rng.uniform(0.5, 2.0, (n, nz + 1)), rng.uniform(0.5, 2.0, (n, nz)),
+                                rng.uniform(0.5, 2.0, (n, nz)))
+        prof = synth.profiles_random(nz, n, seed=seed + 1)
+        P = T.Problem(ref, r, om2, profiles=prof, full=full).setup(precond_fp32=fp32, use_graph=True, stream=stream,
+                                                                   precond_profiles=code)
+        m = mesh.hierarchy(ref)[-1]
+        f = synth.cell_integral(synth.uniform_noise(n, nz, seed + 2), m.area, opm.vertical(r).vk)
+        cases.append((P, f, (ref, r, om2, prof, full, code)))
+    ref, nz, grading, seed = PROBS[1]
+    r = synth.vertical_faces(nz, synth.H10KM, grading)
+    P = T.Problem(ref, r, synth.omega_for(ref) ** 2).setup(precond_fp32=fp32, use_graph=True, stream=stream)
+    geo = P.geometry()
+    cases.append((P, synth.cell_integral(synth.uniform_noise(P.n, nz, seed), geo["areas"], P.vk()), None))
+    fs = [P.pack(f) for P, f, _ in cases]
+    singles = []
+    for (P, _, _), fd in zip(cases, fs):
+        u = P.device_vector()
+        st, iters, relres, hist, _ = P.solve(fd, u, rtol=1e-8, maxit=200)
+        assert st == T.TPMG_OK
+        singles.append((iters, relres, P.unpack(u)))
+    mgs = [P.mg for P, _, _ in cases]
+    nbytes = T.tpmg_batch_workspace_size(mgs)
+    ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    batch = T.tpmg_batch_create(mgs, ws.data_ptr() + (-ws.data_ptr()) % 256, nbytes)
+    us = [P.device_vector() for P, _, _ in cases]
+    st, per, _ = T.tpmg_batch_solve(batch, fs, us, 1e-8, 200)
+    assert st == T.TPMG_OK
+    for (P, _, _), u, (iters, relres, _h), (it_s, rr_s, u_s) in zip(cases, us, per, singles):
+        assert iters == it_s and relres == rr_s
+        assert np.array_equal(P.unpack(u), u_s)
+    T.tpmg_batch_destroy(batch)
+    if not fp32:
+        P, f, (ref, r, om2, prof, full, code) = cases[0]
+        A = otpmg.build(ref, r, om2, profiles=prof, full=full).finest
+        h = otpmg.build(ref, r, om2, profiles=prof, full=full, full_terms=otpmg.FULL_TERMS)
+        o = otpmg.solve(h, f, rtol=1e-8, maxit=200, outer=A)
+        assert o.iters == singles[0][0]
+        assert np.linalg.norm(singles[0][2] - o.x) <= 1e-10 * np.linalg.norm(o.x)
+        # an operator with vertical advection is not symmetric: refused
+        m = mesh.hierarchy(2)[-1]
+        r2 = synth.vertical_faces(8, synth.H10KM, "quadratic")
+        bf = synth.balanced_flow(0.5, m.centre, r2, synth.omega_for(2))
+        Q = T.Problem(2, r2, synth.omega_for(2) ** 2, profiles=bf.factorised, full=bf, advection=True).setup(
+            stream=stream)
+        with pytest.raises(T.TpmgError) as e:
+            T.tpmg_batch_workspace_size([Q.mg])
+        assert e.value.status == T.TPMG_ERR_ARG

@@ -123,11 +123,10 @@ def test_profile_mode_restrictions():
     P.setup(precond_fp32=True, use_graph=True, precond_profiles=T.PRECOND_FULL)
     tun = P.tuning()
     assert all(t["smoother"] == T.SMOOTHER_SCAN and t["scan_levels"] in (8, 16) for t in tun)
+    # a batch takes problems of either kind together (test_gpu_batch solves one)
     stream = P.stream
     Q = T.Problem(ref, r, om2, profiles=prof).setup(precond_fp32=True, use_graph=True, stream=stream)
-    with pytest.raises(T.TpmgError) as e:
-        T.tpmg_batch_workspace_size([P.mg, Q.mg])
-    assert e.value.status == T.TPMG_ERR_ARG
+    assert T.tpmg_batch_workspace_size([P.mg, Q.mg]) > 0
     # graph replay and the autotuner with full profiles: the same result as
     # launches one by one with the built-in choices
     u1 = P.device_vector()

@@ -100,14 +100,12 @@ def test_sor_with_full_profiles():
     err = rel(P.unpack(u), ref_s.x)
     print(f"full profiles + SOR: {iters} iterations (oracle {ref_s.iters}), solution {err:.2e}")
     assert st == T.TPMG_OK and iters == ref_s.iters and err <= 1e-10
-    # batches take SOR problems with factorising profiles (test_gpu_batch), not
-    # profiles that do not factorise
+    # batches take SOR problems, with profiles that factorise or not
+    # (test_gpu_batch runs them)
     stream = P.stream
     Q = T.Problem(ref, r, om2).setup(precond_fp32=True, use_graph=True, stream=stream,
                                      smoother_order=T.SMOOTHER_ORDER_SOR, omega_relax=1.0)
     assert T.tpmg_batch_workspace_size([Q.mg]) > 0
-    with pytest.raises(T.TpmgError) as e:
-        T.tpmg_batch_workspace_size([P.mg])
-    assert e.value.status == T.TPMG_ERR_ARG
+    assert T.tpmg_batch_workspace_size([P.mg]) > 0
     P.close()
     Q.close()
