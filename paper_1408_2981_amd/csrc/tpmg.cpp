@@ -2447,12 +2447,35 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
   // V-cycle; the first iteration takes beta = 0 (p = 0 for the in-place
   // form, whose update reads it)
   const bool ring = batch_ring(*b);
-  for (int p = 0; p < n; ++p) {
-    tpmg_mg& m = *b->probs[p];
-    TPMG_HIP(tpmg::launch_spmv64(m.view_outer(), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit, b->scal + p, s,
-                                  rtol, ring && m.fp32 ? static_cast<float*>(m.fcopy) : nullptr));
-    if (!ring) TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, s));
+  // (each problem's start and end run on its branch's stream, forked from
+  // the batch's stream and joined back, so that they overlap as the
+  // iterations do)
+  const std::vector<std::vector<int>> groups = batch_groups(*b);
+  auto fork = [&]() -> hipError_t {
+    if (groups.size() < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (size_t k = 1; k < groups.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->aux[k - 1], b->fork, 0);
+    return e;
+  };
+  auto join = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (size_t k = 1; k < groups.size() && e == hipSuccess; ++k) {
+      e = hipEventRecord(b->join[k - 1], b->aux[k - 1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[k - 1], 0);
+    }
+    return e;
+  };
+  TPMG_HIP(fork());
+  for (size_t k = 0; k < groups.size(); ++k) {
+    hipStream_t sk = k == 0 ? s : b->aux[k - 1];
+    for (int p : groups[k]) {
+      tpmg_mg& m = *b->probs[p];
+      TPMG_HIP(tpmg::launch_spmv64(m.view_outer(), 1, d_u[p], d_f[p], m.r, m.partials, tpmg::kFinInit, b->scal + p,
+                                    sk, rtol, ring && m.fp32 ? static_cast<float*>(m.fcopy) : nullptr));
+      if (!ring) TPMG_HIP(tpmg::launch_fill(m.p, m.len * 8, sk));
+    }
   }
+  TPMG_HIP(join());
   const bool rebuild = b->plan_u.size() != static_cast<size_t>(n) || !std::equal(b->plan_u.begin(), b->plan_u.end(), d_u);
   if (rebuild || b->graph == nullptr) {
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -2551,9 +2574,15 @@ tpmg_status tpmg_batch_solve(tpmg_batch* b, const double* const* d_f, double* co
   }
   // x += alpha p of each problem's iterations not yet added (after an
   // iteration queued ahead, which changes neither); drains the stream
-  if (ring)
-    for (int p = 0; p < n; ++p)
-      TPMG_HIP(tpmg::launch_flush(d_u[p], b->probs[p]->dirs, b->scal + p, b->probs[p]->len, s));
+  if (ring) {
+    TPMG_HIP(fork());
+    for (size_t k = 0; k < groups.size(); ++k) {
+      hipStream_t sk = k == 0 ? s : b->aux[k - 1];
+      for (int p : groups[k])
+        TPMG_HIP(tpmg::launch_flush(d_u[p], b->probs[p]->dirs, b->scal + p, b->probs[p]->len, sk));
+    }
+    TPMG_HIP(join());
+  }
   TPMG_HIP(hipStreamSynchronize(s));
   const auto t1 = std::chrono::steady_clock::now();
   tpmg_status worst = TPMG_OK;
