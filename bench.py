@@ -238,7 +238,7 @@ def anisotropy_report(steps: int = 3):
         print(json.dumps(line), flush=True)
 
 
-def sequence_report(epochs: int = 4, n_train: int = 150, n_total: int = 200):
+def sequence_report(epochs: int = 16, n_train: int = 150, n_total: int = 200):
     """Learned initial guess on the sequence f_t = f_0 + 0.05 t g (refinement 6
     x 64 quadratic levels, 5,242,880 unknowns, smooth seeded fields): solve
     t = 1..n_train from zero (mixed, rtol 1e-8) and train two per-column MLPs
@@ -607,7 +607,7 @@ def main():
     ap.add_argument("--sweep-reps", type=int, default=50)
     ap.add_argument("--sequence", action="store_true",
                     help="only the learned-initial-guess sequence report (refinement 6 x nz 64, 200 solves)")
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
                     help="choose kernels by timed trials at setup (excluded from the timed solves)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
